@@ -1,0 +1,96 @@
+"""CPU oracle for GLCM counts and Haralick statistics (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  The library and its Python binding never do: the oracle shares
+no code with the HIP path.  The arithmetic lives in ``glcm_oracle.c`` (plain C,
+built with gcc); this module only builds it and marshals numpy arrays.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "glcm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    global _lib
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+        _lib = None
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_quantize.restype = ctypes.c_uint32
+        lib.oracle_quantize.argtypes = [ctypes.c_uint32] * 4
+        lib.oracle_glcm_rows.restype = ctypes.c_int
+        lib.oracle_glcm_rows.argtypes = [
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+            ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_features.restype = None
+        lib.oracle_features.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def quantize(v: int, N: int, lo: int, hi: int) -> int:
+    return int(_load().oracle_quantize(v, N, lo, hi))
+
+
+def quantize_array(values, N: int, lo: int, hi: int) -> np.ndarray:
+    q = _load().oracle_quantize
+    return np.array([q(int(v), N, lo, hi) for v in np.asarray(values).ravel()],
+                    dtype=np.int64).reshape(np.shape(values))
+
+
+def glcm(img: np.ndarray, N: int, lo: int, hi: int, offsets, rows=None) -> np.ndarray:
+    """Counts P[k][i][j] (uint32) of a 2-D uint8/uint16 image for offsets (dx, dy).
+
+    ``img`` may be a strided view (row stride in elements, unit column stride).
+    ``rows=(y0, y1)`` restricts the FIRST pixel to rows y0..y1-1."""
+    img = np.asarray(img)
+    if img.ndim != 2 or img.dtype not in (np.uint8, np.uint16):
+        raise ValueError("img must be a 2-D uint8 or uint16 array")
+    if img.strides[1] != img.itemsize:
+        img = np.ascontiguousarray(img)
+    H, W = img.shape
+    stride = img.strides[0] // img.itemsize
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 2))
+    K = offs.shape[0]
+    out = np.zeros((K, N, N), dtype=np.uint32)
+    y0, y1 = (0, H) if rows is None else rows
+    rc = _load().oracle_glcm_rows(img.ctypes.data, W, H, stride, img.itemsize, N, lo, hi,
+                                  offs.ctypes.data, K, y0, y1, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_glcm_rows rejected its arguments or a count overflowed")
+    return out
+
+
+def features(P: np.ndarray) -> np.ndarray:
+    """Five statistics per GLCM in float64: contrast, energy, entropy,
+    homogeneity, correlation.  ``P`` has shape [K, N, N] (or [N, N])."""
+    P = np.ascontiguousarray(P, dtype=np.uint32)
+    squeeze = P.ndim == 2
+    if squeeze:
+        P = P[None]
+    K, N, _ = P.shape
+    out = np.zeros((K, 5), dtype=np.float64)
+    _load().oracle_features(P.ctypes.data, K, N, out.ctypes.data)
+    return out[0] if squeeze else out
