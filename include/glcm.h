@@ -1,0 +1,191 @@
+/*
+ * glcm.h - C ABI of the MI355X (gfx950) gray-level co-occurrence matrix library.
+ *
+ * The library computes the gray-level co-occurrence matrix of Eq. (1) of
+ * Hong, Zheng and Pan, "Computation of gray-level co-occurrence matrix based on
+ * CUDA and its optimization" (Section I.A): for an offset (dx, dy),
+ *
+ *     P[i][j] = number of pixels (x, y) such that (x+dx, y+dy) lies inside the
+ *               W x H image, q(img(x, y)) = i and q(img(x+dx, y+dy)) = j,
+ *
+ * where q() reduces the raw pixel value to one of N gray levels (the
+ * pre-processing step of Section I.A).  Conventions fixed by this library
+ * (the paper leaves them open):
+ *
+ *   - Coordinates: x indexes columns, y indexes rows, y grows down the rows.
+ *     Pixel (x, y) is img[y * stride + x].  The four directions of Eq. (2) at
+ *     distance d are 0 deg = (d, 0), 45 deg = (-d, d), 90 deg = (0, d),
+ *     135 deg = (d, d); see glcm_offset_polar().
+ *   - Borders: a pair whose second pixel falls outside the image is skipped
+ *     (no wrap-around to the next row, no padding), so sum P = (W-|dx|)(H-|dy|)
+ *     when both factors are positive, else 0.
+ *   - Orientation: P is stored row-major as out[k][i][j] with i the level of
+ *     the FIRST pixel (x, y) and j the level of the SECOND pixel, following the
+ *     variable order of Eq. (1).  P for (-dx, -dy) is the transpose of P for
+ *     (dx, dy).
+ *   - One increment per ordered pair (not symmetric), unnormalised uint32 counts.
+ *   - Quantization: q(v) = 0 if v < lo; N-1 if v > hi; otherwise
+ *     floor((v - lo) * N / (hi - lo + 1)), computed exactly.
+ *
+ * All functions return a glcm_status (0 = success, negative = error).  No
+ * function aborts or prints.  Argument checks happen before any work is queued:
+ * a call that returns GLCM_EINVAL has queued nothing and written nothing.
+ * `stream` arguments are hipStream_t handles passed as void* (NULL = the
+ * default stream of the current device).  Device pointers must belong to the
+ * current HIP device.
+ */
+#ifndef GLCM_H
+#define GLCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GLCM_ABI_VERSION 1
+
+#ifndef GLCM_API
+#define GLCM_API __attribute__((visibility("default")))
+#endif
+
+/* Pixel types. */
+enum glcm_dtype { GLCM_U8 = 0, GLCM_U16 = 1 };
+
+/* Displacement of the second pixel of a pair relative to the first. */
+typedef struct glcm_offset {
+    int32_t dx; /* columns, positive to the right */
+    int32_t dy; /* rows, positive downwards */
+} glcm_offset_t;
+
+enum glcm_status {
+    GLCM_OK = 0,
+    GLCM_EINVAL = -1,       /* invalid argument; nothing was queued */
+    GLCM_ENOMEM = -2,       /* device or pinned-host allocation failed */
+    GLCM_EUNSUPPORTED = -3, /* valid request this build cannot serve */
+    GLCM_EHIP = -4,         /* a HIP call failed; see glcm_last_hip_error() */
+    GLCM_EBUSY = -5         /* reserved */
+};
+
+/* Limits checked by every entry point. */
+#define GLCM_MAX_LEVELS 4096    /* N */
+#define GLCM_MAX_OFFSETS 64     /* K */
+#define GLCM_MAX_DISPLACEMENT 32767
+
+/* Plan flags (bitwise OR).  The FORCE_* flags select a kernel variant for
+ * tests and ablations; without them the library picks the variant. */
+#define GLCM_FLAG_FORCE_GENERIC     (1u << 0) /* per-pixel kernel, any layout */
+#define GLCM_FLAG_FORCE_PARTITIONED (1u << 1) /* split bins into LDS-sized partitions */
+#define GLCM_FLAG_FORCE_GLOBAL      (1u << 2) /* one global atomic per pair, no LDS */
+#define GLCM_FLAG_SERIAL_UPLOAD     (1u << 3) /* host images: copy, then count (no overlap) */
+
+typedef struct glcm_plan_s *glcm_plan_t;
+
+/* Launch parameters of a plan, readable and (for tuning) overridable. */
+typedef struct glcm_tuning {
+    int replicas;       /* R: LDS copies of each GLCM per workgroup (power of two) */
+    int wg_size;        /* threads per workgroup: 256, 512 or 1024 */
+    int rows_per_wave;  /* image rows each wavefront walks */
+    int tile_rows;      /* host-image upload tile height (rows) */
+    int path;           /* read-only: 0 generic, 1 row kernel, 2 partitioned, 3 global */
+    int partitions;     /* read-only: bin partitions per pass */
+} glcm_tuning_t;
+
+/* Version of this ABI (GLCM_ABI_VERSION). */
+GLCM_API int glcm_abi_version(void);
+
+/* Static English description of a status code.  Never NULL. */
+GLCM_API const char *glcm_strerror(int status);
+
+/* hipError_t value of the last HIP failure reported as GLCM_EHIP on the
+ * calling thread (0 if none). */
+GLCM_API int glcm_last_hip_error(void);
+
+/*
+ * Offset of the Eq. (2) direction table.  d >= 1; theta_deg is a multiple of
+ * 45 in [0, 360).  0/45/90/135 give (d,0), (-d,d), (0,d), (d,d): the second
+ * pixel sits d, d*(W-1), d*W, d*(W+1) elements after the first in row-major
+ * order, as in Eq. (2).  180..315 give the opposite displacements.
+ * Returns GLCM_EINVAL for other angles, d < 1, d > GLCM_MAX_DISPLACEMENT or a
+ * NULL out.
+ */
+GLCM_API int glcm_offset_polar(int d, int theta_deg, glcm_offset_t *out);
+
+/*
+ * Creates a reusable plan for images of one pixel type, one N and one offset
+ * list, of size up to max_W x max_H.  The plan owns its device workspace, its
+ * pinned staging buffers and its upload stream; all are released by
+ * glcm_plan_destroy().  `offsets` (host, K entries) is copied.
+ * Errors: GLCM_EINVAL for a NULL plan pointer, bad dtype, N outside
+ * [1, GLCM_MAX_LEVELS], K outside [1, GLCM_MAX_OFFSETS], NULL offsets, a
+ * displacement component beyond GLCM_MAX_DISPLACEMENT, max_W or max_H < 1 or
+ * max_W * max_H > 2^32 - 1, or unknown flags.  GLCM_ENOMEM / GLCM_EHIP on
+ * allocation failure.  Needs a HIP device.
+ */
+GLCM_API int glcm_plan_create(glcm_plan_t *plan, int dtype, int N, int K, const glcm_offset_t *offsets,
+                     int max_W, int max_H, uint32_t flags);
+
+/* Reads (and, if `set` is non-zero, first overrides) the plan's launch
+ * parameters.  Overrides are validated and clamped to what the device allows;
+ * GLCM_EINVAL for values outside the documented sets. */
+GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t *tuning, int set);
+
+/* Releases a plan after waiting for its queued work.  NULL is accepted. */
+GLCM_API int glcm_plan_destroy(glcm_plan_t plan);
+
+/*
+ * Computes out[k][i][j] (Eq. (1)) for the K offsets.
+ *
+ *   plan     NULL, or a plan created with the same dtype, N, K, offsets and
+ *            with W <= max_W, H <= max_H (else GLCM_EINVAL).  NULL uses an
+ *            internal plan cached per device and call signature.
+ *   img      W x H pixels, row y at img + y*stride elements.  Device memory,
+ *            pinned host memory or pageable host memory.  Host images are
+ *            uploaded in row tiles (with the halo rows the offsets need) on the
+ *            plan's upload stream while earlier tiles are counted on `stream`.
+ *            Must be aligned to the pixel size.
+ *   stride   row pitch in ELEMENTS, >= W.
+ *   dtype    GLCM_U8 or GLCM_U16.
+ *   N, lo, hi  quantization (see above); lo <= hi <= max of dtype.
+ *   offsets  host array of K displacements; components within
+ *            +-GLCM_MAX_DISPLACEMENT.  Offsets reaching outside the image are
+ *            legal and give all-zero matrices.
+ *   out      device memory, K*N*N uint32, overwritten (not accumulated); must
+ *            not overlap img.
+ *   stream   hipStream_t (as void*); all device work is ordered on it.
+ *
+ * Device images: returns once the work is queued.  Host images: returns once
+ * the last upload is queued; the caller must not modify the host image until
+ * `stream` has completed.  Errors: GLCM_EINVAL (nothing queued) for NULL
+ * pointers, W or H < 1, stride < W, W*H > 2^32-1, bad dtype, N or K out of
+ * range, lo > hi, hi above the dtype maximum, a displacement out of range, a
+ * misaligned img, an out buffer that is not device memory or overlaps img, or
+ * a plan mismatch.  GLCM_EHIP / GLCM_ENOMEM on HIP failures while queueing.
+ */
+GLCM_API int glcm_compute(glcm_plan_t plan, const void *img, int W, int H, int64_t stride, int dtype,
+                 int N, uint32_t lo, uint32_t hi, const glcm_offset_t *offsets, int K,
+                 uint32_t *out, void *stream);
+
+/*
+ * Haralick statistics of K co-occurrence matrices (Introduction, Haralick's
+ * texture features), out[k][0..4] = contrast, energy (angular second moment),
+ * entropy (natural log), homogeneity (inverse difference moment,
+ * 1/(1+(i-j)^2)), correlation.  p = P/T with T = sum of P[k].  T = 0 gives
+ * five zeros; a row or column marginal with a single occupied level gives
+ * correlation 1.  Computed in fp32 except the correlation, whose moments are
+ * exact integers combined in fp64.
+ *
+ *   glcm     device memory, K*N*N uint32 (the layout glcm_compute writes).
+ *   out      device memory, K*5 float, overwritten.
+ * Errors: GLCM_EINVAL for NULL or host pointers, K outside [1, 2^20], N
+ * outside [1, GLCM_MAX_LEVELS], or a matrix whose total exceeds 2^32 - 1 (the
+ * latter only detected on the device: that matrix's outputs are NaN).
+ */
+GLCM_API int glcm_features(const uint32_t *glcm, int K, int N, float *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLCM_H */

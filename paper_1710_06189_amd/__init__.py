@@ -1,0 +1,260 @@
+"""Python binding of libglcm, the gfx950 gray-level co-occurrence matrix library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/glcm.h.  PyTorch supplies device
+memory and streams.  The functions keep the C names:
+
+    glcm_compute(img, N, lo=0, hi=None, offsets=((1, 0),), out=None, stream=None, plan=None)
+        -> torch.Tensor [K, N, N] uint32 on the current device
+    glcm_features(P, out=None, stream=None) -> torch.Tensor [K, 5] float32
+    glcm_offset_polar(d, theta_deg) -> (dx, dy)
+    glcm_plan_create(dtype, N, offsets, max_W, max_H, flags=0) -> Plan
+
+Conventions (Eq. (1) of the paper, made precise): out[k][i][j] counts pixels
+(x, y) with level i whose neighbour (x + dx_k, y + dy_k) lies inside the image
+and has level j; levels are q(v) = floor((v - lo) * N / (hi - lo + 1)),
+clamped to [0, N-1].
+
+If the library is not built the functions raise; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+__all__ = [
+    "GlcmError", "Plan", "Tuning", "glcm_abi_version", "glcm_strerror", "glcm_last_hip_error",
+    "glcm_offset_polar", "glcm_plan_create", "glcm_plan_destroy", "glcm_plan_tuning", "glcm_compute",
+    "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
+    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "PATH_NAMES",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libglcm.so")
+
+U8, U16 = 0, 1
+FLAG_FORCE_GENERIC = 1 << 0
+FLAG_FORCE_PARTITIONED = 1 << 1
+FLAG_FORCE_GLOBAL = 1 << 2
+FLAG_SERIAL_UPLOAD = 1 << 3
+PATH_NAMES = {0: "generic", 1: "rows", 2: "partitioned", 3: "global"}
+
+STATUS = {0: "GLCM_OK", -1: "GLCM_EINVAL", -2: "GLCM_ENOMEM", -3: "GLCM_EUNSUPPORTED",
+          -4: "GLCM_EHIP", -5: "GLCM_EBUSY"}
+
+
+class GlcmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = f"{what}: {STATUS.get(status, status)} ({_lib().glcm_strerror(status).decode()})"
+        if status == -4:
+            msg += f", hipError {_lib().glcm_last_hip_error()}"
+        super().__init__(msg)
+
+
+class Offset(ctypes.Structure):
+    _fields_ = [("dx", ctypes.c_int32), ("dy", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("replicas", ctypes.c_int), ("wg_size", ctypes.c_int), ("rows_per_wave", ctypes.c_int),
+                ("tile_rows", ctypes.c_int), ("path", ctypes.c_int), ("partitions", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_L = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_1710_06189_amd/build.py "
+                               "(or __graft_entry__.build())")
+        lib = ctypes.CDLL(_LIB_PATH)
+        vp, i32, u32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_int64
+        lib.glcm_abi_version.restype = i32
+        lib.glcm_strerror.restype = ctypes.c_char_p
+        lib.glcm_strerror.argtypes = [i32]
+        lib.glcm_last_hip_error.restype = i32
+        lib.glcm_offset_polar.restype = i32
+        lib.glcm_offset_polar.argtypes = [i32, i32, ctypes.POINTER(Offset)]
+        lib.glcm_plan_create.restype = i32
+        lib.glcm_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(Offset), i32, i32, u32]
+        lib.glcm_plan_tuning.restype = i32
+        lib.glcm_plan_tuning.argtypes = [vp, ctypes.POINTER(Tuning), i32]
+        lib.glcm_plan_destroy.restype = i32
+        lib.glcm_plan_destroy.argtypes = [vp]
+        lib.glcm_compute.restype = i32
+        lib.glcm_compute.argtypes = [vp, vp, i32, i32, i64, i32, i32, u32, u32, ctypes.POINTER(Offset), i32, vp, vp]
+        lib.glcm_features.restype = i32
+        lib.glcm_features.argtypes = [vp, i32, i32, vp, vp]
+        _L = lib
+    return _L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise GlcmError(status, what)
+
+
+def _offsets(offsets):
+    offs = [(int(dx), int(dy)) for dx, dy in offsets]
+    arr = (Offset * max(1, len(offs)))(*[Offset(dx, dy) for dx, dy in offs])
+    return arr, len(offs)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def glcm_abi_version() -> int:
+    return int(_lib().glcm_abi_version())
+
+
+def glcm_strerror(status: int) -> str:
+    return _lib().glcm_strerror(status).decode()
+
+
+def glcm_last_hip_error() -> int:
+    return int(_lib().glcm_last_hip_error())
+
+
+def glcm_offset_polar(d: int, theta_deg: int):
+    o = Offset()
+    _check(_lib().glcm_offset_polar(d, theta_deg, ctypes.byref(o)), "glcm_offset_polar")
+    return (o.dx, o.dy)
+
+
+class Plan:
+    """Owner of a glcm_plan_t (workspace, upload stream and pinned staging)."""
+
+    def __init__(self, handle, dtype, N, offsets):
+        self.handle = handle
+        self.dtype, self.N, self.offsets = dtype, N, [tuple(o) for o in offsets]
+
+    @property
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        _check(_lib().glcm_plan_tuning(self.handle, ctypes.byref(t), 0), "glcm_plan_tuning")
+        return t
+
+    def set_tuning(self, **kw) -> Tuning:
+        t = self.tuning
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(_lib().glcm_plan_tuning(self.handle, ctypes.byref(t), 1), "glcm_plan_tuning")
+        return t
+
+    def close(self):
+        if self.handle:
+            _lib().glcm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def glcm_plan_create(dtype, N, offsets, max_W, max_H, flags=0) -> Plan:
+    dt = _dtype_code(dtype)
+    arr, K = _offsets(offsets)
+    h = ctypes.c_void_p()
+    _check(_lib().glcm_plan_create(ctypes.byref(h), dt, int(N), K, arr, int(max_W), int(max_H), int(flags)),
+           "glcm_plan_create")
+    return Plan(h, dt, N, offsets)
+
+
+def glcm_plan_tuning(plan: Plan) -> Tuning:
+    return plan.tuning
+
+
+def glcm_plan_destroy(plan: Plan):
+    plan.close()
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (U8, U16):
+        return dtype
+    if dtype in (torch.uint8, np.uint8):
+        return U8
+    if dtype in (torch.uint16, np.uint16):
+        return U16
+    raise ValueError(f"unsupported pixel dtype {dtype}")
+
+
+def _image_args(img):
+    """(pointer, W, H, stride_elements, dtype_code, keepalive) of a 2-D image."""
+    if isinstance(img, np.ndarray):
+        if img.ndim != 2 or img.dtype not in (np.uint8, np.uint16):
+            raise ValueError("img must be a 2-D uint8 or uint16 array")
+        if img.strides[1] != img.itemsize or img.strides[0] % img.itemsize:
+            img = np.ascontiguousarray(img)
+        H, W = img.shape
+        return img.ctypes.data, W, H, img.strides[0] // img.itemsize, _dtype_code(img.dtype), img
+    if isinstance(img, torch.Tensor):
+        if img.dim() != 2 or img.dtype not in (torch.uint8, torch.uint16):
+            raise ValueError("img must be a 2-D torch.uint8 or torch.uint16 tensor")
+        if img.stride(1) != 1:
+            img = img.contiguous()
+        H, W = img.shape
+        return img.data_ptr(), W, H, img.stride(0), _dtype_code(img.dtype), img
+    raise TypeError("img must be a numpy array or a torch tensor")
+
+
+def glcm_compute(img, N, lo=0, hi=None, offsets=((1, 0),), out=None, stream=None, plan=None):
+    """Co-occurrence counts of `img` for each offset, as a [K, N, N] uint32 tensor.
+
+    `img` may live on the GPU (torch tensor) or on the host (numpy array or CPU
+    tensor, pinned or pageable); host images are streamed to the GPU in row
+    tiles.  `out`, if given, must be a contiguous device tensor of K*N*N 32-bit
+    elements; it is overwritten."""
+    ptr, W, H, stride, dt, keep = _image_args(img)
+    if hi is None:
+        hi = 255 if dt == U8 else 65535
+    arr, K = _offsets(offsets)
+    dev = img.device if isinstance(img, torch.Tensor) and img.is_cuda else torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty((K, N, N), dtype=torch.uint32, device=dev)
+    elif not (out.is_cuda and out.is_contiguous() and out.numel() == K * N * N and out.element_size() == 4):
+        raise ValueError("out must be a contiguous CUDA tensor of K*N*N 32-bit elements")
+    s = _stream_handle(stream)
+    _check(_lib().glcm_compute(plan.handle if plan is not None else None, ctypes.c_void_p(ptr), W, H, stride, dt,
+                               int(N), int(lo), int(hi), arr, K, ctypes.c_void_p(out.data_ptr()), s),
+           "glcm_compute")
+    del keep
+    return out
+
+
+def glcm_features(P, out=None, stream=None):
+    """Contrast, energy, entropy, homogeneity and correlation of each GLCM in
+    `P` ([K, N, N] or [N, N], 32-bit, on the GPU), as a [K, 5] float32 tensor."""
+    if not (isinstance(P, torch.Tensor) and P.is_cuda and P.element_size() == 4 and P.is_contiguous()):
+        raise ValueError("P must be a contiguous CUDA tensor of 32-bit counts")
+    if P.dim() == 2:
+        P = P.unsqueeze(0)
+    K, N, N2 = P.shape
+    if N != N2:
+        raise ValueError("P must be [K, N, N]")
+    if out is None:
+        out = torch.empty((K, 5), dtype=torch.float32, device=P.device)
+    s = _stream_handle(stream)
+    _check(_lib().glcm_features(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()), s),
+           "glcm_features")
+    return out

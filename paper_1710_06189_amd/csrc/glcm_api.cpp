@@ -1,0 +1,563 @@
+// C-ABI host runtime of the GLCM library: argument checks, plans, path choice,
+// workspace management and the streamed upload of host-resident images.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "glcm.h"
+#include "glcm_internal.h"
+
+using glcm::VoteArgs;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return GLCM_OK;
+  g_last_hip = (int)e;
+  return e == hipErrorOutOfMemory ? GLCM_ENOMEM : GLCM_EHIP;
+}
+
+#define GLCM_TRY(expr)                      \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return hip_status(e_); \
+  } while (0)
+
+constexpr uint32_t kKnownFlags = GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED |
+                                 GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD;
+
+enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3 };
+
+
+
+int dtype_bytes(int dtype) { return dtype == GLCM_U8 ? 1 : (dtype == GLCM_U16 ? 2 : 0); }
+
+// ---------------------------------------------------------------------------
+// Validation shared by the entry points (no HIP calls).
+// ---------------------------------------------------------------------------
+int check_offsets(const glcm_offset_t* offsets, int K) {
+  if (!offsets || K < 1 || K > GLCM_MAX_OFFSETS) return GLCM_EINVAL;
+  for (int k = 0; k < K; ++k) {
+    if (offsets[k].dx < -GLCM_MAX_DISPLACEMENT || offsets[k].dx > GLCM_MAX_DISPLACEMENT ||
+        offsets[k].dy < -GLCM_MAX_DISPLACEMENT || offsets[k].dy > GLCM_MAX_DISPLACEMENT)
+      return GLCM_EINVAL;
+  }
+  return GLCM_OK;
+}
+
+int check_compute_args(const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo,
+                       uint32_t hi, const glcm_offset_t* offsets, int K, const uint32_t* out) {
+  const int b = dtype_bytes(dtype);
+  if (!img || !out || b == 0) return GLCM_EINVAL;
+  if (W < 1 || H < 1 || stride < W) return GLCM_EINVAL;
+  if ((uint64_t)W * (uint64_t)H > 0xffffffffull) return GLCM_EINVAL;
+  if (N < 1 || N > GLCM_MAX_LEVELS) return GLCM_EINVAL;
+  if (lo > hi || hi > (b == 1 ? 255u : 65535u)) return GLCM_EINVAL;
+  if (((uintptr_t)img) % (uintptr_t)b) return GLCM_EINVAL;
+  if (check_offsets(offsets, K) != GLCM_OK) return GLCM_EINVAL;
+  // out must not overlap the image bytes
+  const uintptr_t i0 = (uintptr_t)img;
+  const uintptr_t i1 = i0 + (uintptr_t)(((uint64_t)(H - 1) * (uint64_t)stride + (uint64_t)W) * (uint64_t)b);
+  const uintptr_t o0 = (uintptr_t)out;
+  const uintptr_t o1 = o0 + (uintptr_t)((uint64_t)K * N * N * 4u);
+  if (o0 < i1 && i0 < o1) return GLCM_EINVAL;
+  return GLCM_OK;
+}
+
+glcm::Quant make_quant(int N, uint32_t lo, uint32_t hi) {
+  glcm::Quant q{};
+  q.lo = lo;
+  q.hi = hi;
+  q.nlev = (uint32_t)N;
+  const uint64_t D = (uint64_t)hi - lo + 1u;  // 1 .. 65536
+  uint32_t s = 0;
+  while ((1ull << s) < D) ++s;               // ceil(log2 D)
+  const uint64_t m = ((1ull << (32 + s)) + D - 1) / D;  // ceil(2^(32+s) / D), in (2^32, 2^33]
+  q.magic = (uint32_t)(m - (1ull << 32));
+  q.shift = s;
+  return q;
+}
+
+// Offsets as the row kernel wants them: dy >= 0 (and dx >= 0 when dy == 0);
+// a negated offset is counted as its opposite and voted transposed.
+struct Canon {
+  int32_t dx[glcm::kMaxK], dy[glcm::kMaxK];
+  unsigned long long tmask = 0;
+  int maxdy = 0, maxadx = 0;
+  int up = 0, down = 0;  // rows of halo above / below a row band (original offsets)
+};
+
+Canon canonicalize(const glcm_offset_t* o, int K) {
+  Canon c;
+  for (int k = 0; k < K; ++k) {
+    int dx = o[k].dx, dy = o[k].dy;
+    c.up = std::max(c.up, -dy);
+    c.down = std::max(c.down, dy);
+    if (dy < 0 || (dy == 0 && dx < 0)) {
+      dx = -dx;
+      dy = -dy;
+      c.tmask |= 1ull << k;
+    }
+    c.dx[k] = dx;
+    c.dy[k] = dy;
+    c.maxdy = std::max(c.maxdy, dy);
+    c.maxadx = std::max(c.maxadx, std::abs(dx));
+  }
+  return c;
+}
+
+int pointer_kind(const void* p, int* device) {
+  // 0 = pageable host, 1 = pinned host, 2 = device
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (device) *device = attr.device;
+  if (attr.type == hipMemoryTypeDevice) return 2;
+  if (attr.type == hipMemoryTypeHost) return 1;
+  if (attr.type == hipMemoryTypeManaged) return 2;
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+struct glcm_plan_s {
+  int device = 0;
+  int dtype = 0;
+  int N = 0, K = 0;
+  glcm_offset_t offsets[GLCM_MAX_OFFSETS];
+  int max_W = 0, max_H = 0;
+  uint32_t flags = 0;
+  glcm_tuning_t tuning{};
+  bool user_tuned = false;
+  int lds_budget_words = 0;
+  int num_cus = 0;
+
+  // device workspace
+  uint32_t* partials = nullptr;
+  size_t partials_bytes = 0;
+
+
+  // ordering across streams
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool has_done = false;
+
+  // host-image upload resources
+  hipStream_t copy_stream = nullptr;
+  static constexpr int kSlots = 2;
+  void* dev_tile[kSlots] = {nullptr, nullptr};
+  void* pin_tile[kSlots] = {nullptr, nullptr};
+  size_t tile_bytes = 0;
+  hipEvent_t uploaded[kSlots] = {nullptr, nullptr};
+  hipEvent_t consumed[kSlots] = {nullptr, nullptr};
+
+  std::mutex mu;
+};
+
+namespace {
+
+int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
+  // Path and LDS layout for this plan's (dtype, N, K, offsets, flags).
+  const uint32_t NN = (uint32_t)p->N * (uint32_t)p->N;
+  const uint64_t words = (uint64_t)p->K * NN;
+  const Canon c = canonicalize(p->offsets, p->K);
+  const uint64_t budget = (uint64_t)p->lds_budget_words;
+  glcm_tuning_t d{};
+  d.wg_size = 1024;
+  d.rows_per_wave = 0;
+  d.tile_rows = 1024;
+  if (p->flags & GLCM_FLAG_FORCE_GLOBAL) {
+    d.path = kPathGlobal;
+    d.replicas = 1;
+    d.partitions = 1;
+  } else {
+    // the row kernel keeps (N+1)^2 words per GLCM (row / column N absorb
+    // votes of pixels outside the image) and stores levels in bytes
+    const uint64_t NN1 = (uint64_t)(p->N + 1) * (uint64_t)(p->N + 1);
+    const bool rows_ok = !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) &&
+                         p->N <= 255 && c.maxadx <= 4 && c.maxdy <= 4 && NN1 <= budget;
+    if (rows_ok) {
+      d.path = kPathRows;
+      int R = 1;
+      while (R < 16 && (uint64_t)p->K * NN1 * (uint64_t)(2 * R) <= budget) R *= 2;
+      d.replicas = R;
+      const uint64_t per = budget / (NN1 * R);  // whole GLCMs per partition
+      d.partitions = (int)((p->K + per - 1) / per);
+      d.rows_per_wave = 4;
+    } else {
+      uint64_t P1 = (words + budget - 1) / budget;
+      if (p->flags & GLCM_FLAG_FORCE_PARTITIONED) P1 = std::max<uint64_t>(P1, std::min<uint64_t>(words, 3));
+      if (P1 > 16) {
+        d.path = kPathGlobal;
+        d.replicas = 1;
+        d.partitions = 1;
+      } else {
+        int R = 1;
+        while (R < 16 && (words * 2 * R + budget - 1) / budget <= P1) R *= 2;
+        d.path = P1 > 1 ? kPathPartitioned : kPathGeneric;
+        d.replicas = R;
+        d.partitions = (int)P1;
+      }
+    }
+  }
+  *t = d;
+  return GLCM_OK;
+}
+
+int plan_init(glcm_plan_t p) {
+  GLCM_TRY(hipGetDevice(&p->device));
+  int lds = 0;
+  GLCM_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  GLCM_TRY(hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device));
+  // keep 1 KiB for static LDS (reduction scratch) and the 64 trash words
+  p->lds_budget_words = (lds - 1024) / 4;
+  choose_tuning(p, &p->tuning);
+
+  GLCM_TRY(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+  return GLCM_OK;
+}
+
+void plan_release(glcm_plan_t p) {
+  if (p->has_done) (void)hipEventSynchronize(p->done);
+  if (p->copy_stream) (void)hipStreamSynchronize(p->copy_stream);
+  for (int s = 0; s < glcm_plan_s::kSlots; ++s) {
+    if (p->dev_tile[s]) (void)hipFree(p->dev_tile[s]);
+    if (p->pin_tile[s]) (void)hipHostFree(p->pin_tile[s]);
+    if (p->uploaded[s]) (void)hipEventDestroy(p->uploaded[s]);
+    if (p->consumed[s]) (void)hipEventDestroy(p->consumed[s]);
+  }
+  if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
+  if (p->partials) (void)hipFree(p->partials);
+
+  if (p->done) (void)hipEventDestroy(p->done);
+}
+
+// Makes sure the plan's workspace can hold `bytes` of partials.  Waits for the
+// plan's queued work before replacing a buffer.
+int ensure_partials(glcm_plan_t p, size_t bytes) {
+  if (bytes <= p->partials_bytes) return GLCM_OK;
+  if (p->has_done) GLCM_TRY(hipEventSynchronize(p->done));
+  if (p->partials) GLCM_TRY(hipFree(p->partials));
+  p->partials = nullptr;
+  p->partials_bytes = 0;
+  GLCM_TRY(hipMalloc((void**)&p->partials, bytes));
+  p->partials_bytes = bytes;
+  return GLCM_OK;
+}
+
+// Orders this call after the plan's previous call when it ran on another stream.
+int order_after_previous(glcm_plan_t p, hipStream_t s) {
+  if (p->has_done && p->last_stream != s) GLCM_TRY(hipStreamWaitEvent(s, p->done, 0));
+  return GLCM_OK;
+}
+
+int record_done(glcm_plan_t p, hipStream_t s) {
+  GLCM_TRY(hipEventRecord(p->done, s));
+  p->has_done = true;
+  p->last_stream = s;
+  return GLCM_OK;
+}
+
+// Queues the counting of first-pixel rows [y_begin, y_end) of a device image
+// whose rows [0, H) are all resident, writing (or adding into) out.
+int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, int y_begin, int y_end,
+                 uint32_t lo, uint32_t hi, uint32_t* out, bool accumulate, hipStream_t stream) {
+  const glcm_tuning_t& t = p->tuning;
+  const int b = dtype_bytes(p->dtype);
+  const uint32_t NN = (uint32_t)p->N * (uint32_t)p->N;
+  const uint32_t words = (uint32_t)p->K * NN;
+
+  VoteArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.img = img;
+  a.stride = stride;
+  a.W = W;
+  a.H = H;
+  a.y_begin = y_begin;
+  a.y_end = y_end;
+  a.q = make_quant(p->N, lo, hi);
+  {
+    const uint32_t top = b == 1 ? 255u : 65535u, bits = b == 1 ? 8u : 16u;
+    uint32_t n = 0;
+    while ((1u << n) < (uint32_t)p->N) ++n;
+    if (lo == 0 && hi == top && (1u << n) == (uint32_t)p->N && n <= bits) {
+      a.qfast = 1;
+      a.qfast_shift = bits - n;
+      a.qfast_mask = b == 1 ? (0xffu >> a.qfast_shift) * 0x01010101u : (0xffffu >> a.qfast_shift) * 0x00010001u;
+    }
+  }
+  a.K = p->K;
+  a.words_total = words;
+  a.out = out;
+
+  int path = t.path;
+  const Canon c = canonicalize(p->offsets, p->K);
+  if (path == kPathRows) {
+    const bool aligned = ((uintptr_t)img % 16 == 0) && (((uint64_t)stride * b) % 16 == 0);
+    if (!aligned) path = (words <= (uint32_t)p->lds_budget_words) ? kPathGeneric : kPathPartitioned;
+  }
+  if (y_end <= y_begin) {
+    // nothing to count: clear (or keep) the output
+    if (!accumulate) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
+    return GLCM_OK;
+  }
+
+  if (path == kPathGlobal) {
+    for (int k = 0; k < p->K; ++k) {
+      a.dx[k] = p->offsets[k].dx;
+      a.dy[k] = p->offsets[k].dy;
+    }
+    if (!accumulate) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
+    GLCM_TRY(glcm::launch_vote_global(a, b, stream));
+    return GLCM_OK;
+  }
+
+  int R = t.replicas, P = t.partitions;
+  if (path != kPathRows && t.path == kPathRows) {
+    // fell back from the row kernel: size the generic partitions
+    const uint64_t budget = (uint64_t)p->lds_budget_words;
+    P = (int)((words + budget - 1) / budget);
+    R = 1;
+    while (R < 16 && ((uint64_t)words * 2 * R + budget - 1) / budget <= (uint64_t)P) R *= 2;
+  }
+  int log2R = 0;
+  while ((1 << log2R) < R) ++log2R;
+  a.log2R = log2R;
+  const int rpw = 4;
+  if (path == kPathRows) {
+    const uint32_t per = (uint32_t)p->K / (uint32_t)P + ((uint32_t)p->K % (uint32_t)P ? 1u : 0u);
+    a.part_words = per * NN;
+    a.P = (int)((p->K + per - 1) / per);
+    for (int k = 0; k < p->K; ++k) {
+      a.dx[k] = c.dx[k];
+      a.dy[k] = c.dy[k];
+    }
+    a.tmask = c.tmask;
+  } else {
+    a.part_words = (words + (uint32_t)P - 1) / (uint32_t)P;
+    a.P = P;
+    for (int k = 0; k < p->K; ++k) {
+      a.dx[k] = p->offsets[k].dx;
+      a.dy[k] = p->offsets[k].dy;
+    }
+  }
+
+  // Row bands: about one workgroup per CU per partition (LDS allows one).
+  const int rows = y_end - y_begin;
+  const int wg = t.wg_size;
+  const int nwaves = wg / 64;
+  int target_groups = std::max(1, p->num_cus / a.P);
+  int nregions = std::min(rows, target_groups);
+  // keep partials within 256 MiB
+  while (nregions > 1 && (uint64_t)nregions * words * 4ull > (256ull << 20)) nregions = (nregions + 1) / 2;
+  const int region_rows = (rows + nregions - 1) / nregions;
+  nregions = (rows + region_rows - 1) / region_rows;
+  a.nregions = nregions;
+  a.region_rows = region_rows;
+  (void)nwaves;
+  a.rows_per_wave = rpw;
+
+  int rc = ensure_partials(p, (size_t)a.nregions * words * 4u);
+  if (rc != GLCM_OK) return rc;
+  a.partials = p->partials;
+
+  // LDS: the copies; the final sum reuses one word per thread as scratch
+  size_t lds_bytes = ((size_t)a.part_words << log2R) * 4u;
+  if (path == kPathRows)
+    lds_bytes = ((size_t)(a.part_words / NN) * (uint32_t)(p->N + 1) * (uint32_t)(p->N + 1) << log2R) * 4u;
+  lds_bytes = std::max(lds_bytes, (size_t)wg * 4u);
+
+  const int maxdy = c.maxdy <= 1 ? 1 : (c.maxdy <= 2 ? 2 : 4);
+  hipError_t e;
+  if (path == kPathRows) {
+    e = glcm::launch_vote_rows(a, b, maxdy, rpw, wg, lds_bytes, stream);
+  } else {
+    e = glcm::launch_vote_generic(a, b, wg, lds_bytes, stream);
+  }
+  if (e == hipSuccess) e = glcm::launch_reduce(a.partials, out, words, a.nregions, accumulate, stream);
+  if (e != hipSuccess) return hip_status(e);
+  return GLCM_OK;
+}
+
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int, int, int, std::vector<int32_t>>, glcm_plan_t> g_cache;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+GLCM_API int glcm_abi_version(void) { return GLCM_ABI_VERSION; }
+
+GLCM_API const char* glcm_strerror(int s) {
+  switch (s) {
+    case GLCM_OK: return "success";
+    case GLCM_EINVAL: return "invalid argument";
+    case GLCM_ENOMEM: return "out of memory";
+    case GLCM_EUNSUPPORTED: return "unsupported request";
+    case GLCM_EHIP: return "HIP runtime error";
+    case GLCM_EBUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+GLCM_API int glcm_last_hip_error(void) { return g_last_hip; }
+
+GLCM_API int glcm_offset_polar(int d, int theta_deg, glcm_offset_t* out) {
+  if (!out || d < 1 || d > GLCM_MAX_DISPLACEMENT || theta_deg < 0 || theta_deg >= 360 || theta_deg % 45)
+    return GLCM_EINVAL;
+  // Eq. (2): 0, 45, 90, 135 degrees move the second pixel by +d, +d(W-1),
+  // +dW, +d(W+1) elements in row-major order.
+  static const int ux[8] = {1, -1, 0, 1, -1, 1, 0, -1};
+  static const int uy[8] = {0, 1, 1, 1, 0, -1, -1, -1};
+  const int i = theta_deg / 45;
+  out->dx = ux[i] * d;
+  out->dy = uy[i] * d;
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_plan_create(glcm_plan_t* plan, int dtype, int N, int K, const glcm_offset_t* offsets, int max_W,
+                     int max_H, uint32_t flags) {
+  if (!plan) return GLCM_EINVAL;
+  *plan = nullptr;
+  if (dtype_bytes(dtype) == 0 || N < 1 || N > GLCM_MAX_LEVELS) return GLCM_EINVAL;
+  if (check_offsets(offsets, K) != GLCM_OK) return GLCM_EINVAL;
+  if (max_W < 1 || max_H < 1 || (uint64_t)max_W * (uint64_t)max_H > 0xffffffffull) return GLCM_EINVAL;
+  if (flags & ~kKnownFlags) return GLCM_EINVAL;
+  std::unique_ptr<glcm_plan_s> p(new (std::nothrow) glcm_plan_s());
+  if (!p) return GLCM_ENOMEM;
+  p->dtype = dtype;
+  p->N = N;
+  p->K = K;
+  std::memcpy(p->offsets, offsets, sizeof(glcm_offset_t) * K);
+  p->max_W = max_W;
+  p->max_H = max_H;
+  p->flags = flags;
+  int rc = plan_init(p.get());
+  if (rc != GLCM_OK) {
+    plan_release(p.get());
+    return rc;
+  }
+  *plan = p.release();
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) {
+  if (!plan || !tuning) return GLCM_EINVAL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  if (set) {
+    const glcm_tuning_t& n = *tuning;
+    if (n.replicas < 1 || n.replicas > 64 || (n.replicas & (n.replicas - 1))) return GLCM_EINVAL;
+    if (n.wg_size != 256 && n.wg_size != 512 && n.wg_size != 1024) return GLCM_EINVAL;
+    if (n.rows_per_wave < 0 || n.rows_per_wave > 65536) return GLCM_EINVAL;
+    if (n.tile_rows < 1 || n.tile_rows > 65536) return GLCM_EINVAL;
+    const uint32_t NN = (uint32_t)plan->N * (uint32_t)plan->N;
+    glcm_tuning_t& t = plan->tuning;
+    if (t.path == kPathRows) {
+      // partitions are groups of whole (N+1)^2 GLCMs; the replicas must fit one
+      const uint64_t NN1 = (uint64_t)(plan->N + 1) * (uint64_t)(plan->N + 1);
+      if (NN1 * n.replicas > (uint64_t)plan->lds_budget_words) return GLCM_EINVAL;
+      if (n.rows_per_wave != 0 && n.rows_per_wave != 4) return GLCM_EINVAL;
+      const uint64_t per = (uint64_t)plan->lds_budget_words / (NN1 * n.replicas);
+      t.partitions = (int)((plan->K + per - 1) / per);
+    } else if (t.path != kPathGlobal) {
+      const uint64_t words = (uint64_t)plan->K * NN;
+      if ((uint64_t)n.replicas > (uint64_t)plan->lds_budget_words) return GLCM_EINVAL;
+      const uint64_t cap = (uint64_t)plan->lds_budget_words / n.replicas;
+      t.partitions = (int)((words + cap - 1) / cap);
+      if (t.partitions > 1) t.path = kPathPartitioned;
+    }
+    t.replicas = n.replicas;
+    t.wg_size = n.wg_size;
+    if (t.path == kPathRows && n.rows_per_wave != 0) t.rows_per_wave = n.rows_per_wave;
+    t.tile_rows = n.tile_rows;
+    plan->user_tuned = true;
+  }
+  *tuning = plan->tuning;
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_plan_destroy(glcm_plan_t plan) {
+  if (!plan) return GLCM_OK;
+  plan_release(plan);
+  delete plan;
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_compute(glcm_plan_t plan, const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo,
+                 uint32_t hi, const glcm_offset_t* offsets, int K, uint32_t* out, void* stream_) {
+  int rc = check_compute_args(img, W, H, stride, dtype, N, lo, hi, offsets, K, out);
+  if (rc != GLCM_OK) return rc;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (plan) {
+    if (plan->dtype != dtype || plan->N != N || plan->K != K ||
+        std::memcmp(plan->offsets, offsets, sizeof(glcm_offset_t) * K) != 0 || W > plan->max_W ||
+        H > plan->max_H)
+      return GLCM_EINVAL;
+  }
+  int out_dev = -1;
+  if (pointer_kind(out, &out_dev) != 2) return GLCM_EINVAL;
+  int img_dev = -1;
+  const int kind = pointer_kind(img, &img_dev);
+  int cur = 0;
+  GLCM_TRY(hipGetDevice(&cur));
+  if (out_dev != cur || (kind == 2 && img_dev != cur)) return GLCM_EINVAL;
+
+  if (!plan) {
+    std::vector<int32_t> key;
+    for (int k = 0; k < K; ++k) {
+      key.push_back(offsets[k].dx);
+      key.push_back(offsets[k].dy);
+    }
+    auto tk = std::make_tuple(cur, dtype, N, K, key);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(tk);
+    if (it == g_cache.end()) {
+      glcm_plan_t np = nullptr;
+      rc = glcm_plan_create(&np, dtype, N, K, offsets, 65535, 65535, 0);
+      if (rc != GLCM_OK) return rc;
+      it = g_cache.emplace(tk, np).first;
+    }
+    plan = it->second;
+  }
+
+  std::lock_guard<std::mutex> lk(plan->mu);
+  rc = order_after_previous(plan, stream);
+  if (rc != GLCM_OK) return rc;
+  if (kind == 2) {
+    rc = count_device(plan, img, W, H, stride, 0, H, lo, hi, out, false, stream);
+  } else {
+    rc = GLCM_EUNSUPPORTED;
+  }
+  if (rc != GLCM_OK) return rc;
+  return record_done(plan, stream);
+}
+
+GLCM_API int glcm_features(const uint32_t* glcm_u32, int K, int N, float* out, void* stream) {
+  if (!glcm_u32 || !out || K < 1 || K > (1 << 20) || N < 1 || N > GLCM_MAX_LEVELS) return GLCM_EINVAL;
+  int d1 = -1, d2 = -1;
+  if (pointer_kind(glcm_u32, &d1) != 2 || pointer_kind(out, &d2) != 2) return GLCM_EINVAL;
+  GLCM_TRY(glcm::launch_features(glcm_u32, K, N, out, (hipStream_t)stream));
+  return GLCM_OK;
+}
+
+}  // extern "C"

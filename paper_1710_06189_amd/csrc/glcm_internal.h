@@ -1,0 +1,53 @@
+// Internal interface between the C-ABI host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace glcm {
+
+constexpr int kMaxK = 64;
+
+// Gray-level reduction q(v): 0 below lo, N-1 above hi, otherwise
+// floor(x / D) with x = (v - lo) * N and D = hi - lo + 1, evaluated as
+// (x + mulhi(x, magic)) >> shift.  With shift = ceil(log2 D) and
+// magic = ceil(2^(32+shift) / D) - 2^32 this is exact for every x < 2^32
+// (Granlund-Montgomery division by an invariant integer).
+struct Quant {
+  uint32_t lo, hi, nlev, magic, shift;
+};
+
+// Arguments shared by every counting kernel.  Passed by value.
+struct VoteArgs {
+  const void* img;            // first row of the (tile) image
+  int64_t stride;             // row pitch in elements
+  int W, H;                   // image (tile) size; second pixels must lie inside
+  int y_begin, y_end;         // rows whose pixels act as FIRST pixel of a pair
+  Quant q;
+  int qfast;                  // 1: lo = 0, hi = dtype max, N = 2^n: level = pixel >> qfast_shift
+  uint32_t qfast_shift, qfast_mask;  // shift and per-byte (u8) / per-halfword (u16) mask
+  int K;
+  int32_t dx[kMaxK], dy[kMaxK];
+  unsigned long long tmask;   // row kernel: bit k set = offset k was negated, vote (j, i)
+  int log2R;                  // LDS replicas per workgroup = 1 << log2R
+  uint32_t words_total;       // K * N * N
+  uint32_t part_words;        // GLCM words held in LDS per partition
+  int P;                      // bin partitions
+  int nregions;               // row bands; workgroup g counts band g / P, partition g % P
+  int region_rows;            // first-pixel rows per band
+  int rows_per_wave;          // row kernel: first-pixel rows per wavefront slab (4)
+  uint32_t* partials;         // [nregions][words_total] per-band counts
+  uint32_t* out;              // global-atomic kernel: [words_total] counts, zeroed beforehand
+};
+
+// Launchers (all asynchronous on `stream`; return the launch error).
+hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
+                            hipStream_t stream);
+// out[w] = (accumulate ? out[w] : 0) + sum_b partials[b * M + w] for w < M.
+hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, int nbands, bool accumulate,
+                         hipStream_t stream);
+hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream);
+hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream);
+
+}  // namespace glcm

@@ -1,0 +1,534 @@
+// gfx950 kernels for gray-level co-occurrence matrices (Eq. (1)) and Haralick
+// statistics.
+//
+// Counting follows the replica idea of Scheme 2 (Section II.A): every
+// workgroup keeps R copies of its GLCM words in LDS and each thread votes into
+// copy (thread index mod R), which divides same-address atomic collisions on
+// smooth images by R.  The copies are interleaved word by word (counter of
+// word w, copy r at LDS index w*R + r) so lanes voting the same bin hit
+// different banks.  The merge of all copies into one result (the final sum in
+// Section II.A) takes two steps: every workgroup writes its band's counts to
+// a partial buffer, and a second kernel sums the partials into `out`.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "glcm_internal.h"
+
+namespace glcm {
+namespace {
+
+__device__ __forceinline__ uint32_t quantize(uint32_t v, const Quant& q) {
+  const uint32_t x = (v - q.lo) * q.nlev;
+  const uint32_t lv = (x + __umulhi(x, q.magic)) >> q.shift;
+  return v < q.lo ? 0u : (v > q.hi ? q.nlev - 1u : lv);
+}
+
+// ---------------------------------------------------------------------------
+// Merge of the LDS copies into this workgroup's band partial.  Called by every
+// thread once its votes are done.  The LDS matrices may be padded: word
+// (k, i, j) of the partition (k counted from the partition's first GLCM) sits
+// at copy-block k * nn1 + i * n1 + j, each block holding R consecutive copies.
+// The cross-workgroup sum runs in k_reduce after this kernel: the kernel
+// boundary makes the partials visible without any in-kernel synchronisation.
+// ---------------------------------------------------------------------------
+__device__ void store_partial(const VoteArgs& a, const uint32_t* lds, uint32_t pbase, uint32_t pwords, int region,
+                              uint32_t n1, uint32_t nn1) {
+  __syncthreads();
+  const uint32_t R = 1u << a.log2R;
+  const uint32_t N = a.q.nlev, NN = N * N;
+  uint32_t* dst = a.partials + (size_t)region * a.words_total + pbase;
+  for (uint32_t w = threadIdx.x; w < pwords; w += blockDim.x) {
+    uint32_t src = w;
+    if (n1 != N) {
+      const uint32_t k = w / NN, rem = w - k * NN, i = rem / N, j = rem - i * N;
+      src = k * nn1 + i * n1 + j;
+    }
+    const uint32_t* c = lds + (src << a.log2R);
+    uint32_t s = 0;
+    for (uint32_t r = 0; r < R; ++r) s += c[r];
+    dst[w] = s;
+  }
+}
+
+// out[w] (+)= sum over bands of partials[band][w].  Each workgroup owns
+// kReduceQuads quads of words; its threads are kReduceQuads x kReduceGroups,
+// group g loading bands g, g + kReduceGroups, ... 16 bytes at a time (all
+// loads of a thread in flight together), and the groups meet in an LDS tree.
+constexpr int kReduceQuads = 4, kReduceGroups = 256;
+
+__global__ __launch_bounds__(kReduceQuads * kReduceGroups) void k_reduce(const uint32_t* partials, uint32_t* out,
+                                                                       uint32_t M, int nbands, int accumulate) {
+  __shared__ uint4 part[kReduceGroups][kReduceQuads];
+  const int q = threadIdx.x % kReduceQuads, g = threadIdx.x / kReduceQuads;
+  const uint32_t w = (blockIdx.x * kReduceQuads + q) * 4u;  // first word of this thread's quad
+  uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+  if (w < M) {
+    const bool whole = w + 4 <= M && (M % 4u) == 0;
+    for (int b0 = g; b0 < nbands; b0 += 4 * kReduceGroups) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {  // independent loads in flight
+        const int b = b0 + u * kReduceGroups;
+        v[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (b < nbands) {
+          const uint32_t* p = partials + (size_t)b * M + w;
+          if (whole) {
+            v[u] = *(const uint4*)p;
+          } else {
+            v[u].x = p[0];
+            if (w + 1 < M) v[u].y = p[1];
+            if (w + 2 < M) v[u].z = p[2];
+            if (w + 3 < M) v[u].w = p[3];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc.x += v[u].x; acc.y += v[u].y; acc.z += v[u].z; acc.w += v[u].w;
+      }
+    }
+  }
+  part[g][q] = acc;
+  __syncthreads();
+  for (int half = kReduceGroups / 2; half > 0; half >>= 1) {
+    if (g < half) {
+      const uint4 o = part[g + half][q];
+      uint4 t = part[g][q];
+      t.x += o.x; t.y += o.y; t.z += o.z; t.w += o.w;
+      part[g][q] = t;
+    }
+    __syncthreads();
+  }
+  if (g == 0 && w < M) {
+    const uint4 t = part[0][q];
+    const uint32_t r[4] = {t.x, t.y, t.z, t.w};
+    for (int e = 0; e < 4 && w + e < M; ++e) out[w + e] = (accumulate ? out[w + e] : 0u) + r[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic counting kernel: any alignment, stride and offsets.  One thread per
+// first pixel, loads through the cache, votes into the LDS copies of the
+// partition this workgroup owns.
+// ---------------------------------------------------------------------------
+template <typename Pix>
+__global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
+  const uint32_t pbase = (uint32_t)part * a.part_words;
+  const uint32_t pwords = min(a.part_words, a.words_total - pbase);
+  const uint32_t nctr = pwords << a.log2R;
+  for (uint32_t i = threadIdx.x; i < nctr; i += blockDim.x) lds[i] = 0;
+  __syncthreads();
+
+  const Pix* img = (const Pix*)a.img;
+  const uint32_t r = threadIdx.x & ((1u << a.log2R) - 1u);
+  const uint32_t N = a.q.nlev, NN = N * N;
+  const int y0 = a.y_begin + region * a.region_rows;
+  const int y1 = min(a.y_end, y0 + a.region_rows);
+  if (y1 > y0) {
+    const uint32_t n = (uint32_t)(y1 - y0) * (uint32_t)a.W;
+    for (uint32_t idx = threadIdx.x; idx < n; idx += blockDim.x) {
+      const int y = y0 + (int)(idx / (uint32_t)a.W);
+      const int x = (int)(idx % (uint32_t)a.W);
+      const uint32_t av = quantize(img[(int64_t)y * a.stride + x], a.q);
+      for (int k = 0; k < a.K; ++k) {
+        const int x2 = x + a.dx[k], y2 = y + a.dy[k];
+        if ((unsigned)x2 >= (unsigned)a.W || (unsigned)y2 >= (unsigned)a.H) continue;
+        const uint32_t bv = quantize(img[(int64_t)y2 * a.stride + x2], a.q);
+        const uint32_t w = (uint32_t)k * NN + av * N + bv - pbase;
+        if (w < pwords)
+          __hip_atomic_fetch_add(&lds[(w << a.log2R) + r], 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+  store_partial(a, lds, pbase, pwords, region, a.q.nlev, a.q.nlev * a.q.nlev);
+}
+
+// ---------------------------------------------------------------------------
+// Global-atomic counting (the one-thread-per-pixel, global-memory-atomics
+// scheme of Section I.B): no LDS, `out` must be zeroed beforehand.  Used as an
+// ablation and for N too large for LDS partitions to pay off.
+// ---------------------------------------------------------------------------
+template <typename Pix>
+__global__ __launch_bounds__(256) void k_vote_global(VoteArgs a) {
+  const Pix* img = (const Pix*)a.img;
+  const uint32_t N = a.q.nlev, NN = N * N;
+  const uint64_t n = (uint64_t)(a.y_end - a.y_begin) * (uint64_t)a.W;
+  for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (uint64_t)gridDim.x * blockDim.x) {
+    const int y = a.y_begin + (int)(idx / (uint64_t)a.W);
+    const int x = (int)(idx % (uint64_t)a.W);
+    const uint32_t av = quantize(img[(int64_t)y * a.stride + x], a.q);
+    for (int k = 0; k < a.K; ++k) {
+      const int x2 = x + a.dx[k], y2 = y + a.dy[k];
+      if ((unsigned)x2 >= (unsigned)a.W || (unsigned)y2 >= (unsigned)a.H) continue;
+      const uint32_t bv = quantize(img[(int64_t)y2 * a.stride + x2], a.q);
+      __hip_atomic_fetch_add(&a.out[(size_t)k * NN + av * N + bv], 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row kernel: the fast path for aligned images (base and row pitch multiples
+// of 16 bytes), N <= 255, offsets with |dx| <= 4 and 0 <= dy <= MAXDY <= 4 after
+// canonicalisation (an offset with dy < 0 is counted as its opposite and voted
+// transposed).  Each lane owns a 16-pixel column chunk; a wavefront covers 64
+// chunks (1024 pixels) of RPW consecutive rows (a slab).  All RPW + MAXDY rows
+// of the slab are loaded at once, quantized into bytes, and the horizontal
+// neighbours come from the adjacent lanes through DPP wave shifts, so each
+// pixel is read from memory once per slab.
+//
+// Pixels outside the image (x < 0, x >= W, or rows >= H) get the sentinel
+// level N.  The LDS copy of each GLCM is (N+1) x (N+1); votes touching a
+// sentinel land in row or column N and are dropped by the merge, so the vote
+// loop carries no bounds checks at all.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kDppWaveShr1 = 0x138;  // lane l receives lane l-1
+constexpr uint32_t kDppWaveShl1 = 0x130;  // lane l receives lane l+1
+
+struct Ring {
+  uint32_t w[6];  // [left halo (4 px) | 16 px chunk | right halo (4 px)], one level per byte
+};
+
+__device__ __forceinline__ uint32_t pack4(uint32_t l0, uint32_t l1, uint32_t l2, uint32_t l3) {
+  return l0 | (l1 << 8) | (l2 << 16) | (l3 << 24);
+}
+
+// Four packed 8-bit pixels -> four packed levels.
+__device__ __forceinline__ uint32_t quant4_u8(uint32_t raw, const VoteArgs& a) {
+  if (a.qfast) return (raw >> a.qfast_shift) & a.qfast_mask;
+  return pack4(quantize(raw & 0xffu, a.q), quantize((raw >> 8) & 0xffu, a.q), quantize((raw >> 16) & 0xffu, a.q),
+               quantize(raw >> 24, a.q));
+}
+
+// Four 16-bit pixels (two dwords) -> four packed levels.
+__device__ __forceinline__ uint32_t quant4_u16(uint32_t lo2, uint32_t hi2, const VoteArgs& a) {
+  if (a.qfast) {
+    const uint32_t l = (lo2 >> a.qfast_shift) & a.qfast_mask;  // levels in bits 0..7 and 16..23
+    const uint32_t h = (hi2 >> a.qfast_shift) & a.qfast_mask;
+    return __builtin_amdgcn_perm(h, l, 0x06040200u);            // bytes l0, l2, h0, h2
+  }
+  return pack4(quantize(lo2 & 0xffffu, a.q), quantize(lo2 >> 16, a.q), quantize(hi2 & 0xffffu, a.q),
+               quantize(hi2 >> 16, a.q));
+}
+
+// Byte mask keeping the first n (0..4) bytes of a dword.
+__device__ __forceinline__ uint32_t keep_bytes(int n) {
+  return n <= 0 ? 0u : (n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u));
+}
+
+// Replaces the levels of pixels at or beyond W by the sentinel.
+__device__ __forceinline__ uint32_t clip_dword(uint32_t lv, int x, int W, uint32_t sent4) {
+  const uint32_t m = keep_bytes(W - x);
+  return (lv & m) | (sent4 & ~m);
+}
+
+template <typename Pix>
+struct RawChunk {
+  uint4 v[sizeof(Pix)];  // 16 pixels
+  uint32_t lh[sizeof(Pix)], rh[sizeof(Pix)];  // 4-pixel halos of the wave-boundary lanes
+};
+
+template <typename Pix>
+__device__ __forceinline__ void issue_row(RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0, int lane) {
+#pragma unroll
+  for (int h = 0; h < (int)sizeof(Pix); ++h) {
+    rc.v[h] = make_uint4(0u, 0u, 0u, 0u);
+    rc.lh[h] = 0u;
+    rc.rh[h] = 0u;
+  }
+  if (y >= a.H) return;
+  const Pix* row = (const Pix*)a.img + (int64_t)y * a.stride;
+  if (x0 < a.W) rc.v[0] = *(const uint4*)(row + x0);
+  if (sizeof(Pix) == 2 && x0 + 8 < a.W) rc.v[sizeof(Pix) - 1] = *(const uint4*)(row + x0 + 8);
+  if (lane == 0 && x0 >= 16 && x0 - 4 < a.W) {
+    if (sizeof(Pix) == 1) rc.lh[0] = *(const uint32_t*)(row + x0 - 4);
+    else { const uint2 t = *(const uint2*)(row + x0 - 4); rc.lh[0] = t.x; rc.lh[sizeof(Pix) - 1] = t.y; }
+  }
+  if (lane == 63 && x0 + 16 < a.W) {
+    if (sizeof(Pix) == 1) rc.rh[0] = *(const uint32_t*)(row + x0 + 16);
+    else { const uint2 t = *(const uint2*)(row + x0 + 16); rc.rh[0] = t.x; rc.rh[sizeof(Pix) - 1] = t.y; }
+  }
+}
+
+template <typename Pix>
+__device__ __forceinline__ void finish_row(Ring& rg, const RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0,
+                                           int lane, uint32_t sent4) {
+  uint32_t c[4], lh, rh;
+  if (sizeof(Pix) == 1) {
+    c[0] = quant4_u8(rc.v[0].x, a); c[1] = quant4_u8(rc.v[0].y, a);
+    c[2] = quant4_u8(rc.v[0].z, a); c[3] = quant4_u8(rc.v[0].w, a);
+    lh = quant4_u8(rc.lh[0], a);
+    rh = quant4_u8(rc.rh[0], a);
+  } else {
+    c[0] = quant4_u16(rc.v[0].x, rc.v[0].y, a); c[1] = quant4_u16(rc.v[0].z, rc.v[0].w, a);
+    c[2] = quant4_u16(rc.v[sizeof(Pix) - 1].x, rc.v[sizeof(Pix) - 1].y, a);
+    c[3] = quant4_u16(rc.v[sizeof(Pix) - 1].z, rc.v[sizeof(Pix) - 1].w, a);
+    lh = quant4_u16(rc.lh[0], rc.lh[sizeof(Pix) - 1], a);
+    rh = quant4_u16(rc.rh[0], rc.rh[sizeof(Pix) - 1], a);
+  }
+  if (y >= a.H) {
+    c[0] = c[1] = c[2] = c[3] = sent4;
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) c[m] = clip_dword(c[m], x0 + 4 * m, a.W, sent4);
+  }
+  const uint32_t from_left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[3], kDppWaveShr1, 0xf, 0xf, false);
+  const uint32_t from_right = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[0], kDppWaveShl1, 0xf, 0xf, false);
+  // wave-boundary lanes take the halo they loaded themselves (sentinel outside the image)
+  lh = (y < a.H && x0 >= 16) ? clip_dword(lh, x0 - 4, a.W, sent4) : sent4;
+  rh = (y < a.H) ? clip_dword(rh, x0 + 16, a.W, sent4) : sent4;
+  rg.w[0] = lane == 0 ? lh : from_left;
+  rg.w[1] = c[0]; rg.w[2] = c[1]; rg.w[3] = c[2]; rg.w[4] = c[3];
+  rg.w[5] = lane == 63 ? rh : from_right;
+}
+
+// Second-pixel levels of the 16 chunk pixels for horizontal shift dx in [-4, 4]:
+// bytes 4+dx .. 19+dx of the 24-byte ring row, as a funnel shift of 64-bit
+// values (no indexed register access, which the compiler would spill).
+__device__ __forceinline__ void window(const Ring& rg, int dx, uint32_t out[4]) {
+  const uint64_t r0 = (uint64_t)rg.w[0] | ((uint64_t)rg.w[1] << 32);
+  const uint64_t r1 = (uint64_t)rg.w[2] | ((uint64_t)rg.w[3] << 32);
+  const uint64_t r2 = (uint64_t)rg.w[4] | ((uint64_t)rg.w[5] << 32);
+  const uint32_t sh = (uint32_t)(4 + dx) * 8u;  // 0 .. 64
+  uint64_t lo, hi;
+  if (sh == 0) {
+    lo = r0; hi = r1;
+  } else if (sh == 64) {
+    lo = r1; hi = r2;
+  } else {
+    lo = (r0 >> sh) | (r1 << (64u - sh));
+    hi = (r1 >> sh) | (r2 << (64u - sh));
+  }
+  out[0] = (uint32_t)lo; out[1] = (uint32_t)(lo >> 32);
+  out[2] = (uint32_t)hi; out[3] = (uint32_t)(hi >> 32);
+}
+
+// Votes of one offset whose canonical dy is S, for the RPW first-pixel rows of
+// the slab: LDS byte address = C + a * MA + b * MB.
+template <int S, int RPW, int NROWS>
+__device__ __forceinline__ void vote_offset(uint32_t* lds, const Ring (&rows)[NROWS], int nrows_first, int dx,
+                                            uint32_t C, uint32_t MA, uint32_t MB) {
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    if (i < nrows_first) {
+      uint32_t b[4];
+      window(rows[i + S], dx, b);
+      const uint32_t f[4] = {rows[i].w[1], rows[i].w[2], rows[i].w[3], rows[i].w[4]};
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const uint32_t av = (f[t >> 2] >> ((t & 3) * 8)) & 0xffu;
+        const uint32_t bv = (b[t >> 2] >> ((t & 3) * 8)) & 0xffu;
+        const uint32_t addr = C + __umul24(av, MA) + __umul24(bv, MB);  // full-rate 24-bit multiplies
+        __hip_atomic_fetch_add((uint32_t*)((char*)lds + addr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+}
+
+template <typename Pix, int MAXDY, int RPW>
+__global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
+  const uint32_t N = a.q.nlev, N1 = N + 1, NN = N * N, NN1 = N1 * N1;
+  // Partitions of the row kernel are groups of whole GLCMs (offsets).
+  const uint32_t pbase = (uint32_t)part * a.part_words;
+  const uint32_t pwords = min(a.part_words, a.words_total - pbase);
+  const int kp0 = (int)(pbase / NN), kp1 = (int)((pbase + pwords) / NN);
+  const uint32_t nctr = ((uint32_t)(kp1 - kp0) * NN1) << a.log2R;
+  for (uint32_t i = threadIdx.x; i < nctr; i += blockDim.x) lds[i] = 0;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t R4 = 4u << a.log2R;                               // bytes per word (all copies)
+  const uint32_t Cr = (threadIdx.x & ((1u << a.log2R) - 1u)) * 4u;  // this thread's copy
+  const uint32_t sent4 = N * 0x01010101u;
+  const int y0 = a.y_begin + region * a.region_rows;
+  const int y1 = min(a.y_end, y0 + a.region_rows);
+  const int chunks = (a.W + 15) >> 4;
+  const int spans = (chunks + 63) >> 6;
+  const int bands = y1 > y0 ? (y1 - y0 + RPW - 1) / RPW : 0;
+  constexpr int NROWS = RPW + MAXDY;
+
+  for (int slab = wave; slab < spans * bands; slab += nwaves) {
+    const int span = slab % spans, band = slab / spans;
+    const int x0 = ((span << 6) + lane) << 4;
+    const int ys = y0 + band * RPW;
+    const int nfirst = min(RPW, y1 - ys);
+    Ring rows[NROWS];
+    {
+      RawChunk<Pix> raw[NROWS];
+#pragma unroll
+      for (int i = 0; i < NROWS; ++i) issue_row<Pix>(raw[i], a, ys + i, x0, lane);
+#pragma unroll
+      for (int i = 0; i < NROWS; ++i) finish_row<Pix>(rows[i], raw[i], a, ys + i, x0, lane, sent4);
+    }
+    for (int k = kp0; k < kp1; ++k) {
+      const int dy = a.dy[k], dx = a.dx[k];
+      const bool tr = (a.tmask >> k) & 1ull;
+      const uint32_t C = (uint32_t)(k - kp0) * NN1 * R4 + Cr;
+      const uint32_t MA = tr ? R4 : N1 * R4, MB = tr ? N1 * R4 : R4;
+      switch (dy) {
+        case 0: vote_offset<0, RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
+        case 1: if (MAXDY >= 1) vote_offset<(MAXDY >= 1 ? 1 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
+        case 2: if (MAXDY >= 2) vote_offset<(MAXDY >= 2 ? 2 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
+        case 3: if (MAXDY >= 3) vote_offset<(MAXDY >= 3 ? 3 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
+        case 4: if (MAXDY >= 4) vote_offset<(MAXDY >= 4 ? 4 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
+        default: break;  // the host never launches an offset with dy > MAXDY
+      }
+    }
+  }
+  store_partial(a, lds, pbase, pwords, region, N1, NN1);
+}
+
+// ---------------------------------------------------------------------------
+// Haralick statistics: one workgroup per GLCM.  Exact integer sums for the
+// contrast numerator and the correlation moments; fp32 for energy, entropy and
+// homogeneity; fp64 (from exact 128-bit integers) for the correlation.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, float* out) {
+  const int k = blockIdx.x;
+  const uint32_t NN = (uint32_t)N * (uint32_t)N;
+  const uint32_t* P = glcm + (size_t)k * NN;
+  // pass 1: total (needed for p)
+  unsigned long long T = 0;
+  for (uint32_t t = threadIdx.x; t < NN; t += blockDim.x) T += P[t];
+  __shared__ unsigned long long redu[256];
+  __shared__ float redf[256];
+  redu[threadIdx.x] = T;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) redu[threadIdx.x] += redu[threadIdx.x + s];
+    __syncthreads();
+  }
+  T = redu[0];
+  __syncthreads();
+  float* o = out + (size_t)k * 5;
+  if (T == 0) {
+    if (threadIdx.x < 5) o[threadIdx.x] = 0.0f;
+    return;
+  }
+  if (T > 0xffffffffull) {
+    if (threadIdx.x < 5) o[threadIdx.x] = __builtin_nanf("");
+    return;
+  }
+  const float invT = 1.0f / (float)T;
+  unsigned long long sc = 0, si = 0, sj = 0, sii = 0, sjj = 0, sij = 0;
+  float energy = 0.f, ent = 0.f, homog = 0.f;
+  for (uint32_t t = threadIdx.x; t < NN; t += blockDim.x) {
+    const uint32_t c = P[t];
+    if (c == 0) continue;
+    const unsigned long long i = t / (uint32_t)N, j = t % (uint32_t)N;
+    const unsigned long long d = i > j ? i - j : j - i;
+    sc += d * d * c;
+    si += i * c; sj += j * c;
+    sii += i * i * c; sjj += j * j * c; sij += i * j * c;
+    const float p = (float)c * invT;
+    energy += p * p;
+    // -p ln p; for p > 1/2 use log1p of the exact complement to keep accuracy
+    const float lp = (2ull * c > T) ? log1pf(-(float)(T - c) * invT) : logf(p);
+    ent -= p * lp;
+    homog += p / (1.0f + (float)(d * d));
+  }
+  unsigned long long vals[6] = {sc, si, sj, sii, sjj, sij};
+  unsigned long long tot[6];
+  for (int v = 0; v < 6; ++v) {
+    redu[threadIdx.x] = vals[v];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) redu[threadIdx.x] += redu[threadIdx.x + s];
+      __syncthreads();
+    }
+    tot[v] = redu[0];
+    __syncthreads();
+  }
+  float fv[3] = {energy, ent, homog};
+  float ftot[3];
+  for (int v = 0; v < 3; ++v) {
+    redf[threadIdx.x] = fv[v];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) redf[threadIdx.x] += redf[threadIdx.x + s];
+      __syncthreads();
+    }
+    ftot[v] = redf[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    using i128 = __int128;
+    const i128 tT = (i128)T;
+    const i128 vi = (i128)tot[3] * tT - (i128)tot[1] * (i128)tot[1];  // T^2 var_i
+    const i128 vj = (i128)tot[4] * tT - (i128)tot[2] * (i128)tot[2];  // T^2 var_j
+    const i128 cv = (i128)tot[5] * tT - (i128)tot[1] * (i128)tot[2];  // T^2 cov
+    double corr = 1.0;
+    if (vi != 0 && vj != 0) corr = (double)cv / sqrt((double)vi * (double)vj);
+    o[0] = (float)((double)tot[0] / (double)T);
+    o[1] = ftot[0];
+    o[2] = ftot[1];
+    o[3] = ftot[2];
+    o[4] = (float)corr;
+  }
+}
+
+}  // namespace
+
+template <typename K>
+static hipError_t launch(K kernel, const VoteArgs& a, dim3 grid, dim3 block, size_t lds_bytes, hipStream_t stream) {
+  hipLaunchKernelGGL(kernel, grid, block, lds_bytes, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream) {
+  const dim3 grid(a.nregions * a.P), block(wg);
+  if (dtype_bytes == 1) return launch(k_vote_generic<uint8_t>, a, grid, block, lds_bytes, stream);
+  return launch(k_vote_generic<uint16_t>, a, grid, block, lds_bytes, stream);
+}
+
+template <typename Pix>
+static hipError_t launch_rows_t(const VoteArgs& a, int maxdy, int wg, size_t lds_bytes, hipStream_t stream) {
+  const dim3 grid(a.nregions * a.P), block(wg);
+  switch (maxdy) {
+    case 1: return launch(k_vote_rows<Pix, 1, 4>, a, grid, block, lds_bytes, stream);
+    case 2: return launch(k_vote_rows<Pix, 2, 4>, a, grid, block, lds_bytes, stream);
+    case 4: return launch(k_vote_rows<Pix, 4, 4>, a, grid, block, lds_bytes, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
+                            hipStream_t stream) {
+  if (rpw != 4) return hipErrorInvalidValue;
+  return dtype_bytes == 1 ? launch_rows_t<uint8_t>(a, maxdy, wg, lds_bytes, stream)
+                          : launch_rows_t<uint16_t>(a, maxdy, wg, lds_bytes, stream);
+}
+
+hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, int nbands, bool accumulate,
+                         hipStream_t stream) {
+  const uint32_t per = 4u * kReduceQuads;
+  hipLaunchKernelGGL(k_reduce, dim3((M + per - 1) / per), dim3(kReduceQuads * kReduceGroups), 0, stream, partials,
+                     out, M, nbands, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream) {
+  const uint64_t n = (uint64_t)(a.y_end - a.y_begin) * (uint64_t)a.W;
+  const uint64_t want = (n + 255) / 256;
+  const dim3 grid((unsigned)(want < 65536 ? (want ? want : 1) : 65536)), block(256);
+  if (dtype_bytes == 1)
+    hipLaunchKernelGGL(k_vote_global<uint8_t>, grid, block, 0, stream, a);
+  else
+    hipLaunchKernelGGL(k_vote_global<uint16_t>, grid, block, 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_features, dim3(K), dim3(256), 0, stream, glcm, N, out);
+  return hipGetLastError();
+}
+
+}  // namespace glcm

@@ -1,0 +1,124 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/glcm.h declares, reports its version and status strings, implements the
+Eq. (2) direction table, and rejects bad arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "glcm.h")
+
+glcm = pytest.importorskip("paper_1710_06189_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*GLCM_API\s+(?:const\s+)?\w+\s*\*?\s*(glcm_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(glcm.library_path()):
+        pytest.fail("libglcm.so is not built (run __graft_entry__.build())")
+    return glcm._lib()
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 9, names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in glcm.h but not exported"
+
+
+def test_version_and_strings(lib):
+    assert glcm.glcm_abi_version() == 1
+    for s in (0, -1, -2, -3, -4, -5):
+        assert glcm.glcm_strerror(s)
+    assert glcm.glcm_strerror(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("W", [7, 64, 4096])
+@pytest.mark.parametrize("d", [1, 2, 4, 9])
+def test_polar_offsets_follow_eq2(lib, W, d):
+    """Eq. (2): in row-major storage the second pixel sits +d, +d(W-1), +dW,
+    +d(W+1) elements after the first for 0, 45, 90, 135 degrees; the other four
+    angles are the opposite displacements."""
+    expect = {0: d, 45: d * (W - 1), 90: d * W, 135: d * (W + 1)}
+    for theta, delta in expect.items():
+        dx, dy = glcm.glcm_offset_polar(d, theta)
+        assert dy * W + dx == delta
+        assert abs(dx) <= d and abs(dy) <= d
+        ox, oy = glcm.glcm_offset_polar(d, theta + 180)
+        assert (ox, oy) == (-dx, -dy)
+
+
+def test_polar_rejects_bad_angles(lib):
+    for d, th in [(0, 0), (1, 30), (1, 360), (1, -45), (40000, 0)]:
+        with pytest.raises(glcm.GlcmError) as e:
+            glcm.glcm_offset_polar(d, th)
+        assert e.value.status == -1
+
+
+def _compute_raw(lib, img_ptr, W, H, stride, dtype, N, lo, hi, offs, out_ptr):
+    arr = (glcm.Offset * max(1, len(offs)))(*[glcm.Offset(a, b) for a, b in offs])
+    return lib.glcm_compute(None, ctypes.c_void_p(img_ptr), W, H, stride, dtype, N, lo, hi, arr, len(offs),
+                            ctypes.c_void_p(out_ptr), None)
+
+
+BAD_CALLS = [
+    # (img, W, H, stride, dtype, N, lo, hi, offsets, out)
+    (0, 8, 8, 8, 0, 8, 0, 255, [(1, 0)], 0x20000),          # null image
+    (0x10000, 8, 8, 8, 0, 8, 0, 255, [(1, 0)], 0),          # null out
+    (0x10000, 0, 8, 8, 0, 8, 0, 255, [(1, 0)], 0x20000),    # W < 1
+    (0x10000, 8, 0, 8, 0, 8, 0, 255, [(1, 0)], 0x20000),    # H < 1
+    (0x10000, 8, 8, 7, 0, 8, 0, 255, [(1, 0)], 0x20000),    # stride < W
+    (0x10000, 8, 8, 8, 2, 8, 0, 255, [(1, 0)], 0x20000),    # bad dtype
+    (0x10000, 8, 8, 8, 0, 0, 0, 255, [(1, 0)], 0x20000),    # N < 1
+    (0x10000, 8, 8, 8, 0, 4097, 0, 255, [(1, 0)], 0x20000),  # N too large
+    (0x10000, 8, 8, 8, 0, 8, 9, 8, [(1, 0)], 0x20000),      # lo > hi
+    (0x10000, 8, 8, 8, 0, 8, 0, 256, [(1, 0)], 0x20000),    # hi above u8 max
+    (0x10000, 8, 8, 8, 1, 8, 0, 65536, [(1, 0)], 0x20000),  # hi above u16 max
+    (0x10001, 8, 8, 8, 1, 8, 0, 255, [(1, 0)], 0x20000),    # misaligned u16 image
+    (0x10000, 8, 8, 8, 0, 8, 0, 255, [], 0x20000),          # K < 1
+    (0x10000, 8, 8, 8, 0, 8, 0, 255, [(1, 0)] * 65, 0x20000),  # K > 64
+    (0x10000, 8, 8, 8, 0, 8, 0, 255, [(40000, 0)], 0x20000),   # displacement too large
+    (0x10000, 65536, 65536, 65536, 0, 8, 0, 255, [(1, 0)], 0x2000000000),  # W*H > 2^32-1
+    (0x10000, 64, 64, 64, 0, 8, 0, 255, [(1, 0)], 0x10010),  # out overlaps image
+]
+
+
+@pytest.mark.parametrize("call", BAD_CALLS)
+def test_compute_rejects_before_any_device_work(lib, call):
+    img, W, H, stride, dt, N, lo, hi, offs, out = call
+    assert _compute_raw(lib, img, W, H, stride, dt, N, lo, hi, offs, out) == -1
+
+
+def test_plan_create_rejects_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    one = (glcm.Offset * 1)(glcm.Offset(1, 0))
+    assert lib.glcm_plan_create(None, 0, 8, 1, one, 8, 8, 0) == -1
+    assert lib.glcm_plan_create(ctypes.byref(h), 3, 8, 1, one, 8, 8, 0) == -1
+    assert lib.glcm_plan_create(ctypes.byref(h), 0, 0, 1, one, 8, 8, 0) == -1
+    assert lib.glcm_plan_create(ctypes.byref(h), 0, 8, 0, one, 8, 8, 0) == -1
+    assert lib.glcm_plan_create(ctypes.byref(h), 0, 8, 1, None, 8, 8, 0) == -1
+    assert lib.glcm_plan_create(ctypes.byref(h), 0, 8, 1, one, 0, 8, 0) == -1
+    assert lib.glcm_plan_create(ctypes.byref(h), 0, 8, 1, one, 65536, 65536, 0) == -1
+    assert lib.glcm_plan_create(ctypes.byref(h), 0, 8, 1, one, 8, 8, 1 << 20) == -1
+    assert h.value is None
+
+
+def test_features_rejects_bad_arguments(lib):
+    assert lib.glcm_features(None, 1, 8, ctypes.c_void_p(0x1000), None) == -1
+    assert lib.glcm_features(ctypes.c_void_p(0x1000), 0, 8, ctypes.c_void_p(0x2000), None) == -1
+    assert lib.glcm_features(ctypes.c_void_p(0x1000), 1, 0, ctypes.c_void_p(0x2000), None) == -1
+    assert lib.glcm_features(ctypes.c_void_p(0x1000), 1, 5000, ctypes.c_void_p(0x2000), None) == -1
+
+
+def test_plan_tuning_rejects_null(lib):
+    t = glcm.Tuning()
+    assert lib.glcm_plan_tuning(None, ctypes.byref(t), 0) == -1
+    assert lib.glcm_plan_destroy(None) == 0

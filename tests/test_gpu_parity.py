@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit-exact.
+
+Covers the workloads the library is measured on (512^2 uint8 N=8; 4096^2 uint8
+N=32 with four d=1 offsets on uniform, smooth and constant images; uint16
+multispectral bands, N=64, twelve offsets), every kernel variant forced through
+plans, replica / workgroup / band sweeps, ragged and degenerate shapes, strided
+and misaligned views, exhaustive quantizer inputs and large N.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_1710_06189_amd")
+
+
+def to_device(img: np.ndarray) -> torch.Tensor:
+    if img.dtype == np.uint16:
+        return torch.from_numpy(np.ascontiguousarray(img).view(np.int16)).cuda().view(torch.uint16)
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def to_host(out: torch.Tensor) -> np.ndarray:
+    torch.cuda.synchronize()
+    return out.view(torch.int32).cpu().numpy().view(np.uint32)
+
+
+def gpu_glcm(img, N, lo, hi, offs, plan=None, t=None):
+    if t is None:
+        t = to_device(img)
+    return to_host(G.glcm_compute(t, N, lo, hi, offs, plan=plan))
+
+
+def check(img, N, lo, hi, offs, plan=None, t=None, label=""):
+    print(f"[parity] {label} shape={img.shape} dtype={img.dtype} N={N} lo={lo} hi={hi} K={len(offs)}", flush=True)
+    got = gpu_glcm(img, N, lo, hi, offs, plan=plan, t=t)
+    want = oracle.glcm(img, N, lo, hi, offs)
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        k, i, j = bad[0]
+        raise AssertionError(f"{label}: {len(bad)} bins differ, first at k={k} i={i} j={j}: "
+                             f"gpu {got[k, i, j]} oracle {want[k, i, j]}")
+    return got
+
+
+def test_status_word_clear_after_suite_start():
+    t = to_device(synth.uniform(64, 64, 1))
+    check(synth.uniform(64, 64, 1), 8, 0, 255, [(1, 0)], t=t, label="warmup")
+
+
+def test_small_uniform_512():
+    w = synth.small_uniform_512()
+    check(w["images"][0], w["N"], w["lo"], w["hi"], w["offsets"], label=w["name"])
+
+
+@pytest.mark.parametrize("kind", ["uniform", "smooth", "constant"])
+def test_square_4096(kind):
+    w = synth.square_4096(kind)
+    got = check(w["images"][0], w["N"], w["lo"], w["hi"], w["offsets"], label=w["name"])
+    if kind == "constant":
+        assert [int(got[k, 16, 16]) for k in range(4)] == [16773120, 16769025, 16773120, 16769025]
+
+
+SHAPES = [(1, 1), (1, 37), (37, 1), (15, 16), (16, 15), (17, 33), (64, 63), (65, 129), (1023, 3), (3, 1025),
+          (1040, 77), (2000, 31), (4097, 5)]
+
+
+@pytest.mark.parametrize("W,H", SHAPES)
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_ragged_shapes(W, H, dtype):
+    img = synth.smooth(H, W, 2.0, 100 + W + H, dtype) if W > 2 and H > 2 else synth.uniform(H, W, 3, dtype)
+    offs = synth.offsets_for([1, 2, 4]) + [(0, 0), (-3, -1), (4, -4)]
+    top = int(np.iinfo(dtype).max)
+    check(img, 16, 0, top, offs, label=f"ragged {W}x{H}")
+
+
+@pytest.mark.parametrize("offs", [
+    [(5, 0)], [(0, 9)], [(-7, 3)], [(16, 16), (-16, 1)], [(100, 0), (0, 100), (-100, -100)],
+    [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)],
+])
+def test_offsets_any(offs):
+    img = synth.smooth(130, 300, 3.0, 7)
+    check(img, 24, 10, 240, offs, label=f"offsets {offs}")
+
+
+@pytest.mark.parametrize("flags,name", [
+    (G.FLAG_FORCE_GENERIC, "generic"), (G.FLAG_FORCE_PARTITIONED, "partitioned"),
+    (G.FLAG_FORCE_GLOBAL, "global"), (0, "auto"),
+])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_forced_paths(flags, name, dtype):
+    img = synth.smooth(517, 731, 5.0, 11, dtype)
+    offs = synth.offsets_for([1, 2, 4])
+    top = int(np.iinfo(dtype).max)
+    plan = G.glcm_plan_create(dtype, 32, offs, 731, 517, flags)
+    try:
+        check(img, 32, 0, top, offs, plan=plan, label=f"path {name} {plan.tuning.as_dict()}")
+        check(img, 32, 0, top, offs, plan=plan, label=f"path {name} again")
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("R", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("wg", [256, 1024])
+def test_replica_and_workgroup_sweep(R, wg):
+    img = synth.smooth(300, 2100, 8.0, 12)
+    offs = synth.offsets_for([1])
+    plan = G.glcm_plan_create(np.uint8, 32, offs, 2100, 300)
+    try:
+        t = plan.set_tuning(replicas=R, wg_size=wg)
+        assert t.replicas == R and t.wg_size == wg
+        check(img, 32, 0, 255, offs, plan=plan, label=f"R={R} wg={wg}")
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("H", [1, 2, 3, 4, 5, 7, 9, 255, 257, 1029])
+def test_band_heights(H):
+    """Heights that leave partial 4-row slabs and partial bands in the row kernel."""
+    img = synth.uniform(H, 1500, 13 + H)
+    offs = synth.offsets_for([1, 2, 4])
+    plan = G.glcm_plan_create(np.uint8, 8, offs, 1500, H)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == "rows"
+        check(img, 8, 0, 255, offs, plan=plan, label=f"H={H}")
+    finally:
+        plan.close()
+
+
+def test_rows_per_wave_knob():
+    plan = G.glcm_plan_create(np.uint8, 8, [(1, 0)], 64, 64)
+    try:
+        assert plan.set_tuning(rows_per_wave=4).rows_per_wave == 4
+        with pytest.raises(G.GlcmError):
+            plan.set_tuning(rows_per_wave=3)
+    finally:
+        plan.close()
+
+
+def test_strided_and_misaligned_views():
+    base = synth.smooth(400, 700, 4.0, 14)
+    tb = to_device(base)
+    offs = synth.offsets_for([1, 4])
+    for (y0, y1, x0, x1) in [(0, 400, 0, 640), (3, 397, 1, 699), (10, 300, 16, 656), (0, 399, 5, 6)]:
+        view = tb[y0:y1, x0:x1]
+        check(base[y0:y1, x0:x1], 32, 0, 255, offs, t=view, label=f"view {(y0, y1, x0, x1)}")
+
+
+@pytest.mark.parametrize("N,lo,hi", [(8, 0, 255), (7, 13, 200), (256, 0, 255), (1, 0, 255), (100, 50, 60),
+                                     (3, 255, 255), (32, 0, 127)])
+def test_quantizer_exhaustive_u8(N, lo, hi):
+    """Every 8-bit value occurs; offset (0,0) puts the level histogram on the diagonal."""
+    img = np.arange(256, dtype=np.uint8).reshape(16, 16)
+    img = np.concatenate([img, img[::-1, ::-1]], axis=0)
+    check(img, N, lo, hi, [(0, 0), (1, 0), (0, 1)], label=f"quant u8 N={N}")
+
+
+@pytest.mark.parametrize("N,lo,hi", [(64, 0, 65535), (257, 1000, 60000), (13, 0, 65535), (4096, 0, 65535),
+                                     (4096, 7, 700), (300, 0, 299)])
+def test_quantizer_exhaustive_u16(N, lo, hi):
+    img = np.arange(65536, dtype=np.uint16).reshape(256, 256)
+    want = oracle.glcm(img, N, lo, hi, [(0, 0)])
+    got = gpu_glcm(img, N, lo, hi, [(0, 0)])
+    assert np.array_equal(got, want), f"quant u16 N={N} lo={lo} hi={hi}"
+
+
+@pytest.mark.parametrize("N", [256, 300, 1024])
+def test_large_levels(N):
+    img = synth.uniform(300, 257, 15, np.uint16)
+    check(img, N, 0, 65535, [(1, 0), (-1, 1)], label=f"large N={N}")
+
+
+def test_multispectral_band_reduced():
+    img, sigma = synth.multispectral_band(0, size=1536)
+    check(img, 64, 0, 65535, synth.offsets_for([1, 2, 4]), label=f"multispectral 1536^2 sigma={sigma:.1f}")
+
+
+def test_multispectral_band_full():
+    img, sigma = synth.multispectral_band(3)
+    check(img, 64, 0, 65535, synth.offsets_for([1, 2, 4]), label=f"multispectral 8192^2 sigma={sigma:.1f}")
+
+
+def test_repeated_calls_two_streams():
+    img = synth.smooth(512, 1024, 6.0, 16)
+    offs = synth.offsets_for([1])
+    want = oracle.glcm(img, 32, 0, 255, offs)
+    t = to_device(img)
+    plan = G.glcm_plan_create(np.uint8, 32, offs, 1024, 512)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    try:
+        for it in range(40):
+            s = s1 if it % 3 else s2
+            with torch.cuda.stream(s):
+                outs.append(G.glcm_compute(t, 32, 0, 255, offs, plan=plan, stream=s))
+        torch.cuda.synchronize()
+        for o in outs:
+            assert np.array_equal(to_host(o), want)
+    finally:
+        plan.close()
+
+
+def test_offsets_outside_image_give_zero():
+    img = synth.uniform(20, 30, 17)
+    got = gpu_glcm(img, 8, 0, 255, [(30, 0), (0, 20), (-31, 5)])
+    assert not got.any()
+
+
+@pytest.mark.parametrize("case", ["smooth", "uniform", "constant", "checker", "sparse"])
+def test_features_vs_oracle(case):
+    N = 16
+    if case == "smooth":
+        img = synth.smooth(600, 500, 4.0, 18)
+    elif case == "uniform":
+        img = synth.uniform(600, 500, 18)
+    elif case == "constant":
+        img = synth.constant(60, 50, 99)
+    elif case == "checker":
+        img = synth.checkerboard(60, 51, 16, 240)
+    else:
+        img = synth.constant(64, 64, 0)
+        img[10, 10] = 255
+    offs = synth.offsets_for([1, 2])
+    P = G.glcm_compute(to_device(img), N, 0, 255, offs)
+    f = G.glcm_features(P)
+    torch.cuda.synchronize()
+    got = f.cpu().numpy().astype(np.float64)
+    want = oracle.features(oracle.glcm(img, N, 0, 255, offs))
+    zero = want == 0
+    assert np.all(got[zero] == 0), (got, want)
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-300)
+    assert np.all(rel[~zero] <= 1e-5), (case, got, want, rel)
+
+
+def test_features_large_and_empty():
+    rng = synth.rng(19)
+    P = rng.integers(0, 1 << 15, size=(4, 256, 256)).astype(np.uint32)  # totals below 2^31
+    P[1] = 0
+    P[2, :, :] = 0
+    P[2, 5, 7] = 0xFFFFFFFF
+    t = torch.from_numpy(P.view(np.int32)).cuda()
+    got = G.glcm_features(t).cpu().numpy().astype(np.float64)
+    want = oracle.features(P)
+    assert np.all(got[1] == 0)
+    P[3, 0, 0] = 1 << 31                      # total above 2^32 - 1: documented NaN output
+    P[3, 1, 1] = 1 << 31
+    t3 = torch.from_numpy(P[3:].view(np.int32)).cuda()
+    assert np.all(np.isnan(G.glcm_features(t3).cpu().numpy()))
+    for k in (0, 2):
+        for c in range(5):
+            if want[k, c] == 0:
+                assert got[k, c] == 0
+            else:
+                assert abs(got[k, c] - want[k, c]) <= 1e-5 * abs(want[k, c]), (k, c, got[k], want[k])
