@@ -86,8 +86,10 @@ typedef struct glcm_plan_s *glcm_plan_t;
 typedef struct glcm_tuning {
     int replicas;       /* R: LDS copies of each GLCM per workgroup (power of two) */
     int wg_size;        /* threads per workgroup: 256, 512 or 1024 */
-    int rows_per_wave;  /* image rows each wavefront walks */
+    int rows_per_wave;  /* row kernel: first-pixel rows per wavefront slab (4) */
     int tile_rows;      /* host-image upload tile height (rows) */
+    int counter_bits;   /* row kernel LDS counters: 16 (two copies per dword, used only
+                           when no count can overflow) or 32; 0 keeps the current value */
     int path;           /* read-only: 0 generic, 1 row kernel, 2 partitioned, 3 global */
     int partitions;     /* read-only: bin partitions per pass */
 } glcm_tuning_t;

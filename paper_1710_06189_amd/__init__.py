@@ -62,7 +62,8 @@ class Offset(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("replicas", ctypes.c_int), ("wg_size", ctypes.c_int), ("rows_per_wave", ctypes.c_int),
-                ("tile_rows", ctypes.c_int), ("path", ctypes.c_int), ("partitions", ctypes.c_int)]
+                ("tile_rows", ctypes.c_int), ("counter_bits", ctypes.c_int), ("path", ctypes.c_int),
+                ("partitions", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

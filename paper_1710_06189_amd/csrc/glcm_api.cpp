@@ -166,12 +166,37 @@ struct glcm_plan_s {
   void* pin_tile[kSlots] = {nullptr, nullptr};
   size_t tile_bytes = 0;
   hipEvent_t uploaded[kSlots] = {nullptr, nullptr};
+  bool pin_pending[kSlots] = {false, false};  // a staging slot's upload may still be running
   hipEvent_t consumed[kSlots] = {nullptr, nullptr};
 
   std::mutex mu;
 };
 
 namespace {
+
+// Row pitch of the LDS copy of a GLCM in the row kernel: at least N + 1 (row
+// and column N take the votes of pixels outside the image) and 2 mod 4, so
+// that the bins of the diagonal, where smooth images put most of their pairs,
+// spread over all banks of a copy group (bank = bin index mod 4 there).
+uint32_t row_pitch(int N) {
+  uint32_t n1 = (uint32_t)N + 1u;
+  while (n1 % 4u != 2u) ++n1;
+  return n1;
+}
+
+// LDS dwords of one GLCM in the row kernel for R copies of `bits`-bit counters.
+uint64_t row_glcm_dwords(int N, int R, int bits) {
+  const uint64_t p = row_pitch(N);
+  return p * p * (uint64_t)(bits == 16 ? R / 2 : R);
+}
+
+// Partitions (groups of whole GLCMs) the row kernel needs; 0 if one GLCM
+// does not fit.
+int row_partitions(const glcm_plan_s* p, int R, int bits) {
+  const uint64_t per = (uint64_t)p->lds_budget_words / row_glcm_dwords(p->N, R, bits);
+  if (per == 0) return 0;
+  return (int)(((uint64_t)p->K + per - 1) / per);
+}
 
 int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   // Path and LDS layout for this plan's (dtype, N, K, offsets, flags).
@@ -183,24 +208,30 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   d.wg_size = 1024;
   d.rows_per_wave = 0;
   d.tile_rows = 1024;
+  d.counter_bits = 32;
   if (p->flags & GLCM_FLAG_FORCE_GLOBAL) {
     d.path = kPathGlobal;
     d.replicas = 1;
     d.partitions = 1;
   } else {
-    // the row kernel keeps (N+1)^2 words per GLCM (row / column N absorb
-    // votes of pixels outside the image) and stores levels in bytes
-    const uint64_t NN1 = (uint64_t)(p->N + 1) * (uint64_t)(p->N + 1);
     const bool rows_ok = !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) &&
-                         p->N <= 255 && c.maxadx <= 4 && c.maxdy <= 4 && NN1 <= budget;
+                         p->N <= 255 && c.maxadx <= 4 && c.maxdy <= 4 && row_partitions(p, 1, 32) > 0;
     if (rows_ok) {
       d.path = kPathRows;
-      int R = 1;
-      while (R < 16 && (uint64_t)p->K * NN1 * (uint64_t)(2 * R) <= budget) R *= 2;
-      d.replicas = R;
-      const uint64_t per = budget / (NN1 * R);  // whole GLCMs per partition
-      d.partitions = (int)((p->K + per - 1) / per);
       d.rows_per_wave = 4;
+      // Most copies for the fewest partitions; 16-bit counters double the
+      // copies in the same LDS (checked against the count bound per call).
+      const int Pmin = row_partitions(p, 1, 32);
+      static const int cand[][2] = {{16, 16}, {8, 16}, {8, 32}, {4, 16}, {4, 32}, {2, 16}, {2, 32}, {1, 32}};
+      for (const auto& cr : cand) {
+        const int P = row_partitions(p, cr[0], cr[1]);
+        if (P == Pmin) {
+          d.replicas = cr[0];
+          d.counter_bits = cr[1];
+          d.partitions = P;
+          break;
+        }
+      }
     } else {
       uint64_t P1 = (words + budget - 1) / budget;
       if (p->flags & GLCM_FLAG_FORCE_PARTITIONED) P1 = std::max<uint64_t>(P1, std::min<uint64_t>(words, 3));
@@ -293,6 +324,10 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   a.y_begin = y_begin;
   a.y_end = y_end;
   a.q = make_quant(p->N, lo, hi);
+  // x / N and x / N^2 as multiply-high + shift: make_quant(1, 0, d - 1) has
+  // D = d and the same division constants
+  a.div_n = make_quant(1, 0, (uint32_t)p->N - 1);
+  a.div_nn = make_quant(1, 0, NN - 1);
   {
     const uint32_t top = b == 1 ? 255u : 65535u, bits = b == 1 ? 8u : 16u;
     uint32_t n = 0;
@@ -329,7 +364,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     return GLCM_OK;
   }
 
-  int R = t.replicas, P = t.partitions;
+  int R = t.replicas, P = t.partitions;  // R may drop below if 16-bit counters cannot be used
   if (path != kPathRows && t.path == kPathRows) {
     // fell back from the row kernel: size the generic partitions
     const uint64_t budget = (uint64_t)p->lds_budget_words;
@@ -378,10 +413,23 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   if (rc != GLCM_OK) return rc;
   a.partials = p->partials;
 
-  // LDS: the copies; the final sum reuses one word per thread as scratch
+  // LDS: the copies (at least one word per thread)
   size_t lds_bytes = ((size_t)a.part_words << log2R) * 4u;
-  if (path == kPathRows)
-    lds_bytes = ((size_t)(a.part_words / NN) * (uint32_t)(p->N + 1) * (uint32_t)(p->N + 1) << log2R) * 4u;
+  if (path == kPathRows) {
+    // 16-bit counters only when no count can reach 2^16: each slab gives a
+    // copy at most 64 lanes / R x 16 pixels x 4 rows votes into one bin.
+    int bits = t.counter_bits == 16 && R >= 2 ? 16 : 32;
+    const uint64_t chunks = ((uint64_t)W + 15) / 16, spans = (chunks + 63) / 64;
+    const uint64_t slabs = spans * (((uint64_t)a.region_rows + rpw - 1) / rpw);
+    if (bits == 16 && slabs * 4096u / (uint64_t)R > 65535u) {
+      bits = 32;  // same LDS footprint with half the copies
+      R /= 2;
+      a.log2R -= 1;
+    }
+    a.c16 = bits == 16 ? 1 : 0;
+    a.pitch = row_pitch(p->N);
+    lds_bytes = (size_t)(a.part_words / NN) * row_glcm_dwords(p->N, R, bits) * 4u;
+  }
   lds_bytes = std::max(lds_bytes, (size_t)wg * 4u);
 
   const int maxdy = c.maxdy <= 1 ? 1 : (c.maxdy <= 2 ? 2 : 4);
@@ -393,6 +441,83 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   }
   if (e == hipSuccess) e = glcm::launch_reduce(a.partials, out, words, a.nregions, accumulate, stream);
   if (e != hipSuccess) return hip_status(e);
+  return GLCM_OK;
+}
+
+// Host-resident image: uploads it in tiles of `tile_rows` first-pixel rows,
+// each with the halo rows its offsets reach (the 2-D form of the chunk bounds
+// of Eq. (7)-(9): a tile owns the pairs whose first pixel lies in its rows),
+// through two pinned staging slots and two device tile buffers.  Copies run on
+// the plan's upload stream and counting on `stream`, so the upload of tile
+// t+1 overlaps the counting of tile t (Section III); tile results are summed
+// into `out` by the reduce step.  With GLCM_FLAG_SERIAL_UPLOAD everything runs
+// on `stream` (no overlap).  Returns once the last upload is queued.
+int count_host(glcm_plan_t p, const void* img, bool pinned, int W, int H, int64_t stride, uint32_t lo, uint32_t hi,
+               uint32_t* out, hipStream_t stream) {
+  const int b = dtype_bytes(p->dtype);
+  const Canon c = canonicalize(p->offsets, p->K);
+  const int up = std::min(c.up, H), down = std::min(c.down, H);
+  const int T = std::max(1, p->tuning.tile_rows);
+  const bool serial = (p->flags & GLCM_FLAG_SERIAL_UPLOAD) != 0;
+  // device rows padded to 256 bytes so the row kernel's alignment holds
+  const size_t pitch_bytes = (((size_t)W * b) + 255) / 256 * 256;
+  const int max_rows = std::min(H, T + up + down);
+  const size_t slot_bytes = pitch_bytes * (size_t)max_rows;
+  if (slot_bytes > p->tile_bytes) {
+    if (p->has_done) GLCM_TRY(hipEventSynchronize(p->done));
+    if (p->copy_stream) GLCM_TRY(hipStreamSynchronize(p->copy_stream));
+    for (int s = 0; s < glcm_plan_s::kSlots; ++s) {
+      if (p->dev_tile[s]) GLCM_TRY(hipFree(p->dev_tile[s]));
+      if (p->pin_tile[s]) GLCM_TRY(hipHostFree(p->pin_tile[s]));
+      p->dev_tile[s] = p->pin_tile[s] = nullptr;
+      p->pin_pending[s] = false;
+    }
+    p->tile_bytes = 0;
+    for (int s = 0; s < glcm_plan_s::kSlots; ++s) {
+      GLCM_TRY(hipMalloc(&p->dev_tile[s], slot_bytes));
+      GLCM_TRY(hipHostMalloc(&p->pin_tile[s], slot_bytes, hipHostMallocDefault));
+      if (!p->uploaded[s]) GLCM_TRY(hipEventCreateWithFlags(&p->uploaded[s], hipEventDisableTiming));
+      if (!p->consumed[s]) GLCM_TRY(hipEventCreateWithFlags(&p->consumed[s], hipEventDisableTiming));
+    }
+    p->tile_bytes = slot_bytes;
+  }
+  if (!p->copy_stream) GLCM_TRY(hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking));
+  hipStream_t cs = serial ? stream : p->copy_stream;
+  // the previous call on this plan may still read the device tile buffers
+  if (p->has_done && !serial) GLCM_TRY(hipStreamWaitEvent(cs, p->done, 0));
+  const char* src = (const char*)img;
+  const size_t row_bytes = (size_t)W * b, src_pitch = (size_t)stride * b;
+  bool slot_used[glcm_plan_s::kSlots] = {false, false};
+  int tile = 0;
+  for (int r0 = 0; r0 < H; r0 += T, ++tile) {
+    const int r1 = std::min(H, r0 + T);
+    const int ra = std::max(0, r0 - up), rb = std::min(H, r1 + down);
+    const int rows = rb - ra;
+    const int s = tile % glcm_plan_s::kSlots;
+    char* dev = (char*)p->dev_tile[s];
+    // the device slot is free once the count that read it has run
+    if (slot_used[s] && !serial) GLCM_TRY(hipStreamWaitEvent(cs, p->consumed[s], 0));
+    if (pinned) {
+      GLCM_TRY(hipMemcpy2DAsync(dev, pitch_bytes, src + (size_t)ra * src_pitch, src_pitch, row_bytes, rows,
+                                hipMemcpyHostToDevice, cs));
+    } else {
+      // the staging slot is free once its previous upload (of this call or of
+      // an earlier one) has completed
+      if (p->pin_pending[s]) GLCM_TRY(hipEventSynchronize(p->uploaded[s]));
+      char* pin = (char*)p->pin_tile[s];
+      for (int y = 0; y < rows; ++y)
+        std::memcpy(pin + (size_t)y * pitch_bytes, src + (size_t)(ra + y) * src_pitch, row_bytes);
+      GLCM_TRY(hipMemcpyAsync(dev, pin, pitch_bytes * rows, hipMemcpyHostToDevice, cs));
+    }
+    GLCM_TRY(hipEventRecord(p->uploaded[s], cs));
+    p->pin_pending[s] = !pinned;
+    if (!serial) GLCM_TRY(hipStreamWaitEvent(stream, p->uploaded[s], 0));
+    int rc = count_device(p, dev, W, rows, (int64_t)(pitch_bytes / b), r0 - ra, r1 - ra, lo, hi, out, tile > 0,
+                          stream);
+    if (rc != GLCM_OK) return rc;
+    GLCM_TRY(hipEventRecord(p->consumed[s], stream));
+    slot_used[s] = true;
+  }
   return GLCM_OK;
 }
 
@@ -472,20 +597,24 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
     if (n.tile_rows < 1 || n.tile_rows > 65536) return GLCM_EINVAL;
     const uint32_t NN = (uint32_t)plan->N * (uint32_t)plan->N;
     glcm_tuning_t& t = plan->tuning;
+    if (n.counter_bits != 0 && n.counter_bits != 16 && n.counter_bits != 32) return GLCM_EINVAL;
+    int bits = n.counter_bits == 0 ? t.counter_bits : n.counter_bits;
     if (t.path == kPathRows) {
-      // partitions are groups of whole (N+1)^2 GLCMs; the replicas must fit one
-      const uint64_t NN1 = (uint64_t)(plan->N + 1) * (uint64_t)(plan->N + 1);
-      if (NN1 * n.replicas > (uint64_t)plan->lds_budget_words) return GLCM_EINVAL;
+      // partitions are groups of whole GLCMs; the copies must fit one
+      if (bits == 16 && n.replicas < 2) return GLCM_EINVAL;
       if (n.rows_per_wave != 0 && n.rows_per_wave != 4) return GLCM_EINVAL;
-      const uint64_t per = (uint64_t)plan->lds_budget_words / (NN1 * n.replicas);
-      t.partitions = (int)((plan->K + per - 1) / per);
+      const int P = row_partitions(plan, n.replicas, bits);
+      if (P == 0) return GLCM_EINVAL;
+      t.partitions = P;
     } else if (t.path != kPathGlobal) {
+      bits = 32;
       const uint64_t words = (uint64_t)plan->K * NN;
       if ((uint64_t)n.replicas > (uint64_t)plan->lds_budget_words) return GLCM_EINVAL;
       const uint64_t cap = (uint64_t)plan->lds_budget_words / n.replicas;
       t.partitions = (int)((words + cap - 1) / cap);
       if (t.partitions > 1) t.path = kPathPartitioned;
     }
+    t.counter_bits = bits;
     t.replicas = n.replicas;
     t.wg_size = n.wg_size;
     if (t.path == kPathRows && n.rows_per_wave != 0) t.rows_per_wave = n.rows_per_wave;
@@ -546,7 +675,7 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void* img, int W, int H, int64
   if (kind == 2) {
     rc = count_device(plan, img, W, H, stride, 0, H, lo, hi, out, false, stream);
   } else {
-    rc = GLCM_EUNSUPPORTED;
+    rc = count_host(plan, img, kind == 1, W, H, stride, lo, hi, out, stream);
   }
   if (rc != GLCM_OK) return rc;
   return record_done(plan, stream);

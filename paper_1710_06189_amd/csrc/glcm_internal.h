@@ -36,6 +36,9 @@ struct VoteArgs {
   int nregions;               // row bands; workgroup g counts band g / P, partition g % P
   int region_rows;            // first-pixel rows per band
   int rows_per_wave;          // row kernel: first-pixel rows per wavefront slab (4)
+  uint32_t pitch;             // row kernel: LDS row pitch of a GLCM, >= N + 1 (row/column N: sentinel)
+  Quant div_n, div_nn;        // magic/shift for dividing by N and by N*N (only those fields used)
+  int c16;                    // row kernel: 16-bit counters, two copies per dword
   uint32_t* partials;         // [nregions][words_total] per-band counts
   uint32_t* out;              // global-atomic kernel: [words_total] counts, zeroed beforehand
 };

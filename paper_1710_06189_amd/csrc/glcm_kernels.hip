@@ -18,6 +18,19 @@
 namespace glcm {
 namespace {
 
+// floor(x / d) for x < 2^32 with (magic, shift) from the host (see Quant).
+__device__ __forceinline__ uint32_t divide(uint32_t x, uint32_t magic, uint32_t shift) {
+  return (uint32_t)(((uint64_t)x + __umulhi(x, magic)) >> shift);
+}
+
+// Zeroes n dwords of LDS starting at a 16-byte aligned address.
+__device__ __forceinline__ void zero_lds(uint32_t* lds, uint32_t n) {
+  uint4* v = (uint4*)lds;
+  const uint32_t n4 = n / 4u;
+  for (uint32_t i = threadIdx.x; i < n4; i += blockDim.x) v[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (uint32_t i = n4 * 4u + threadIdx.x; i < n; i += blockDim.x) lds[i] = 0u;
+}
+
 __device__ __forceinline__ uint32_t quantize(uint32_t v, const Quant& q) {
   const uint32_t x = (v - q.lo) * q.nlev;
   const uint32_t lv = (x + __umulhi(x, q.magic)) >> q.shift;
@@ -33,20 +46,33 @@ __device__ __forceinline__ uint32_t quantize(uint32_t v, const Quant& q) {
 // boundary makes the partials visible without any in-kernel synchronisation.
 // ---------------------------------------------------------------------------
 __device__ void store_partial(const VoteArgs& a, const uint32_t* lds, uint32_t pbase, uint32_t pwords, int region,
-                              uint32_t n1, uint32_t nn1) {
+                              uint32_t n1, uint32_t nn1, bool c16) {
   __syncthreads();
   const uint32_t R = 1u << a.log2R;
+  const uint32_t D = c16 ? R / 2u : R;  // dwords per bin (a multiple of 4 when D >= 4)
   const uint32_t N = a.q.nlev, NN = N * N;
   uint32_t* dst = a.partials + (size_t)region * a.words_total + pbase;
   for (uint32_t w = threadIdx.x; w < pwords; w += blockDim.x) {
     uint32_t src = w;
     if (n1 != N) {
-      const uint32_t k = w / NN, rem = w - k * NN, i = rem / N, j = rem - i * N;
+      const uint32_t k = divide(w, a.div_nn.magic, a.div_nn.shift), rem = w - k * NN;
+      const uint32_t i = divide(rem, a.div_n.magic, a.div_n.shift), j = rem - i * N;
       src = k * nn1 + i * n1 + j;
     }
-    const uint32_t* c = lds + (src << a.log2R);
+    const uint32_t* c = lds + src * D;
     uint32_t s = 0;
-    for (uint32_t r = 0; r < R; ++r) s += c[r];
+    if (D >= 4) {
+      for (uint32_t d = 0; d < D; d += 4) {
+        const uint4 v = *(const uint4*)(c + d);
+        s += c16 ? (v.x & 0xffffu) + (v.x >> 16) + (v.y & 0xffffu) + (v.y >> 16) + (v.z & 0xffffu) + (v.z >> 16) +
+                       (v.w & 0xffffu) + (v.w >> 16)
+                 : (v.x + v.y) + (v.z + v.w);
+      }
+    } else if (c16) {
+      for (uint32_t d = 0; d < D; ++d) s += (c[d] & 0xffffu) + (c[d] >> 16);
+    } else {
+      for (uint32_t d = 0; d < D; ++d) s += c[d];
+    }
     dst[w] = s;
   }
 }
@@ -114,12 +140,11 @@ __global__ __launch_bounds__(kReduceQuads * kReduceGroups) void k_reduce(const u
 // ---------------------------------------------------------------------------
 template <typename Pix>
 __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
   const uint32_t pbase = (uint32_t)part * a.part_words;
   const uint32_t pwords = min(a.part_words, a.words_total - pbase);
-  const uint32_t nctr = pwords << a.log2R;
-  for (uint32_t i = threadIdx.x; i < nctr; i += blockDim.x) lds[i] = 0;
+  zero_lds(lds, pwords << a.log2R);
   __syncthreads();
 
   const Pix* img = (const Pix*)a.img;
@@ -144,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
       }
     }
   }
-  store_partial(a, lds, pbase, pwords, region, a.q.nlev, a.q.nlev * a.q.nlev);
+  store_partial(a, lds, pbase, pwords, region, a.q.nlev, a.q.nlev * a.q.nlev, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -312,7 +337,7 @@ __device__ __forceinline__ void window(const Ring& rg, int dx, uint32_t out[4]) 
 // the slab: LDS byte address = C + a * MA + b * MB.
 template <int S, int RPW, int NROWS>
 __device__ __forceinline__ void vote_offset(uint32_t* lds, const Ring (&rows)[NROWS], int nrows_first, int dx,
-                                            uint32_t C, uint32_t MA, uint32_t MB) {
+                                            uint32_t C, uint32_t MA, uint32_t MB, uint32_t inc) {
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     if (i < nrows_first) {
@@ -324,7 +349,7 @@ __device__ __forceinline__ void vote_offset(uint32_t* lds, const Ring (&rows)[NR
         const uint32_t av = (f[t >> 2] >> ((t & 3) * 8)) & 0xffu;
         const uint32_t bv = (b[t >> 2] >> ((t & 3) * 8)) & 0xffu;
         const uint32_t addr = C + __umul24(av, MA) + __umul24(bv, MB);  // full-rate 24-bit multiplies
-        __hip_atomic_fetch_add((uint32_t*)((char*)lds + addr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add((uint32_t*)((char*)lds + addr), inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
   }
@@ -332,21 +357,26 @@ __device__ __forceinline__ void vote_offset(uint32_t* lds, const Ring (&rows)[NR
 
 template <typename Pix, int MAXDY, int RPW>
 __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
-  const uint32_t N = a.q.nlev, N1 = N + 1, NN = N * N, NN1 = N1 * N1;
+  const uint32_t N = a.q.nlev, N1 = a.pitch, NN = N * N, NN1 = N1 * N1;
   // Partitions of the row kernel are groups of whole GLCMs (offsets).
   const uint32_t pbase = (uint32_t)part * a.part_words;
   const uint32_t pwords = min(a.part_words, a.words_total - pbase);
   const int kp0 = (int)(pbase / NN), kp1 = (int)((pbase + pwords) / NN);
-  const uint32_t nctr = ((uint32_t)(kp1 - kp0) * NN1) << a.log2R;
-  for (uint32_t i = threadIdx.x; i < nctr; i += blockDim.x) lds[i] = 0;
+  // Counters: R copies per bin, 32 bits each, or 16 bits each (copies 2m and
+  // 2m+1 share a dword) when the host has bounded every count below 2^16.
+  const uint32_t R = 1u << a.log2R;
+  const uint32_t dwords_per_bin = a.c16 ? R / 2u : R;
+  zero_lds(lds, (uint32_t)(kp1 - kp0) * NN1 * dwords_per_bin);
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const uint32_t R4 = 4u << a.log2R;                               // bytes per word (all copies)
-  const uint32_t Cr = (threadIdx.x & ((1u << a.log2R) - 1u)) * 4u;  // this thread's copy
+  const uint32_t r = threadIdx.x & (R - 1u);                // this thread's copy
+  const uint32_t B = dwords_per_bin * 4u;                   // bytes per bin (all copies)
+  const uint32_t Cr = a.c16 ? (r >> 1) * 4u : r * 4u;
+  const uint32_t inc = a.c16 ? (1u << ((r & 1u) * 16u)) : 1u;
   const uint32_t sent4 = N * 0x01010101u;
   const int y0 = a.y_begin + region * a.region_rows;
   const int y1 = min(a.y_end, y0 + a.region_rows);
@@ -371,19 +401,19 @@ __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
     for (int k = kp0; k < kp1; ++k) {
       const int dy = a.dy[k], dx = a.dx[k];
       const bool tr = (a.tmask >> k) & 1ull;
-      const uint32_t C = (uint32_t)(k - kp0) * NN1 * R4 + Cr;
-      const uint32_t MA = tr ? R4 : N1 * R4, MB = tr ? N1 * R4 : R4;
+      const uint32_t C = (uint32_t)(k - kp0) * NN1 * B + Cr;
+      const uint32_t MA = tr ? B : N1 * B, MB = tr ? N1 * B : B;
       switch (dy) {
-        case 0: vote_offset<0, RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
-        case 1: if (MAXDY >= 1) vote_offset<(MAXDY >= 1 ? 1 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
-        case 2: if (MAXDY >= 2) vote_offset<(MAXDY >= 2 ? 2 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
-        case 3: if (MAXDY >= 3) vote_offset<(MAXDY >= 3 ? 3 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
-        case 4: if (MAXDY >= 4) vote_offset<(MAXDY >= 4 ? 4 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB); break;
+        case 0: vote_offset<0, RPW>(lds, rows, nfirst, dx, C, MA, MB, inc); break;
+        case 1: if (MAXDY >= 1) vote_offset<(MAXDY >= 1 ? 1 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB, inc); break;
+        case 2: if (MAXDY >= 2) vote_offset<(MAXDY >= 2 ? 2 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB, inc); break;
+        case 3: if (MAXDY >= 3) vote_offset<(MAXDY >= 3 ? 3 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB, inc); break;
+        case 4: if (MAXDY >= 4) vote_offset<(MAXDY >= 4 ? 4 : 0), RPW>(lds, rows, nfirst, dx, C, MA, MB, inc); break;
         default: break;  // the host never launches an offset with dy > MAXDY
       }
     }
   }
-  store_partial(a, lds, pbase, pwords, region, N1, NN1);
+  store_partial(a, lds, pbase, pwords, region, N1, NN1, a.c16 != 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -33,7 +33,8 @@ def to_host(out: torch.Tensor) -> np.ndarray:
 def gpu_glcm(img, N, lo, hi, offs, plan=None, t=None):
     if t is None:
         t = to_device(img)
-    return to_host(G.glcm_compute(t, N, lo, hi, offs, plan=plan))
+    out = torch.empty((len(offs), N, N), dtype=torch.uint32, device="cuda")
+    return to_host(G.glcm_compute(t, N, lo, hi, offs, plan=plan, out=out))
 
 
 def check(img, N, lo, hi, offs, plan=None, t=None, label=""):
@@ -105,18 +106,33 @@ def test_forced_paths(flags, name, dtype):
         plan.close()
 
 
-@pytest.mark.parametrize("R", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("R,bits", [(1, 32), (2, 32), (4, 32), (8, 32), (16, 32), (2, 16), (4, 16), (8, 16),
+                                    (16, 16), (32, 16)])
 @pytest.mark.parametrize("wg", [256, 1024])
-def test_replica_and_workgroup_sweep(R, wg):
+def test_replica_counter_and_workgroup_sweep(R, bits, wg):
     img = synth.smooth(300, 2100, 8.0, 12)
     offs = synth.offsets_for([1])
     plan = G.glcm_plan_create(np.uint8, 32, offs, 2100, 300)
     try:
-        t = plan.set_tuning(replicas=R, wg_size=wg)
-        assert t.replicas == R and t.wg_size == wg
-        check(img, 32, 0, 255, offs, plan=plan, label=f"R={R} wg={wg}")
+        t = plan.set_tuning(replicas=R, wg_size=wg, counter_bits=bits)
+        assert t.replicas == R and t.wg_size == wg and t.counter_bits == bits
+        check(img, 32, 0, 255, offs, plan=plan, label=f"R={R} bits={bits} wg={wg} P={t.partitions}")
     finally:
         plan.close()
+
+
+def test_sixteen_bit_counters_near_the_bound():
+    """A constant image puts every vote of a copy into one bin: the largest
+    band the 16-bit counters accept, and one just beyond (falls back to 32)."""
+    for H in (4096, 8192):  # 16 and 32 slabs of 2048 same-bin votes per copy: 32768, then 65536
+        img = synth.constant(H, 4096, 77)
+        offs = synth.offsets_for([1])
+        plan = G.glcm_plan_create(np.uint8, 16, offs, 4096, H)
+        try:
+            plan.set_tuning(replicas=2, counter_bits=16)
+            check(img, 16, 0, 255, offs, plan=plan, label=f"c16 bound H={H}")
+        finally:
+            plan.close()
 
 
 @pytest.mark.parametrize("H", [1, 2, 3, 4, 5, 7, 9, 255, 257, 1029])
@@ -257,3 +273,41 @@ def test_features_large_and_empty():
                 assert got[k, c] == 0
             else:
                 assert abs(got[k, c] - want[k, c]) <= 1e-5 * abs(want[k, c]), (k, c, got[k], want[k])
+
+
+# ---------------------------------------------------------------- host-resident images (streamed tiles)
+
+@pytest.mark.parametrize("tile_rows", [1, 7, 64, 1024])
+@pytest.mark.parametrize("pinned", [False, True])
+@pytest.mark.parametrize("serial", [False, True])
+def test_host_image_tiles(tile_rows, pinned, serial):
+    """Host images go up in row tiles with halo rows; each tile owns the pairs
+    whose first pixel lies in its rows, so the sum over tiles is exact."""
+    img = synth.smooth(301, 517, 3.0, 31, np.uint16, noise_frac=0.05)
+    offs = synth.offsets_for([1, 2, 4]) + [(-2, -3), (3, -1)]
+    flags = G.FLAG_SERIAL_UPLOAD if serial else 0
+    plan = G.glcm_plan_create(np.uint16, 64, offs, 517, 301, flags)
+    try:
+        plan.set_tuning(tile_rows=tile_rows)
+        src = torch.from_numpy(img.view(np.int16)).view(torch.uint16)
+        if pinned:
+            src = src.pin_memory()
+        check(img, 64, 0, 65535, offs, plan=plan, t=src,
+              label=f"host tiles={tile_rows} pinned={pinned} serial={serial}")
+        check(img, 64, 0, 65535, offs, plan=plan, t=src, label="host again")
+    finally:
+        plan.close()
+
+
+def test_host_numpy_strided_view():
+    base = synth.uniform(200, 300, 32)
+    view = base[5:190, 7:290]
+    offs = synth.offsets_for([1])
+    check(np.ascontiguousarray(view), 16, 0, 255, offs, t=view, label="numpy strided view")
+
+
+def test_host_multispectral_band_streamed():
+    img, sigma = synth.multispectral_band(1, size=2048)
+    offs = synth.offsets_for([1, 2, 4])
+    src = torch.from_numpy(img.view(np.int16)).view(torch.uint16).pin_memory()
+    check(img, 64, 0, 65535, offs, t=src, label=f"multispectral 2048^2 streamed sigma={sigma:.1f}")
