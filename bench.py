@@ -4,18 +4,28 @@
 Workload: one 4096x4096 uint8 image (smooth: Gaussian noise blurred with
 sigma = 8 px, min-max rescaled), N = 32 levels over [0, 255], the four d = 1
 offsets of Eq. (2); output [4, 32, 32] uint32.  A step is one glcm_compute
-call on a device-resident image.  Timed steps rotate over enough device copies
-of the image (> 256 MiB in total) that every step reads its input from HBM
-rather than from the Infinity Cache.  Every copy's result is checked bit-exact
-against the CPU oracle.
+call on a device-resident image (quantize, pair visit, LDS vote, merge).
+Timed steps rotate over enough device copies of the image (> 256 MiB in
+total) that every step reads its input from HBM rather than from the
+Infinity Cache.  Every copy's result is checked bit-exact against the CPU
+oracle.  The plan's LDS layout is picked by glcm_plan_autotune first
+(untimed).
 
-Prints one JSON line (see the keys below).  The CPU-baseline leg times the
-oracle (plain C, one thread) on a bounded sample of the same workload.
+Prints one JSON line.  `value` is pairs per second over the timed steps
+(wall clock, both kernels of each call).  `roofline` prices the dominant
+kernel (the vote kernel) against HBM: algorithmic bytes per launch (image
+once + output counts) over that kernel's average duration, from HIP events
+recorded around each launch on its stream (a second, identically tuned plan
+with FLAG_TIMING).  `traffic` comes from a committed rocprofv3 counter
+summary of the same kernel, used only while the kernel source and layout
+still match it.  The CPU-baseline leg times the oracle (plain C, one thread)
+on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,10 +36,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpairs/s & % HBM roofline (bit-exact); batched vs per-image; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1710_06189_amd", "csrc", "glcm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vote_rows_4096x4096_u8_smooth_traffic.json")
+TUNING_KEYS = ("replicas", "wg_size", "counter_bits", "merge", "partitions")
 
 
 def pairs_of(W, H, offsets):
     return sum(max(0, W - abs(dx)) * max(0, H - abs(dy)) for dx, dy in offsets)
+
+
+def kernel_source_sha256():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic(tuning):
+    """HBM bytes per vote-kernel launch from the committed counter summary,
+    or None when the kernel source or the layout differ from what was measured."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    if any(rec.get("tuning", {}).get(k) != tuning.get(k) for k in TUNING_KEYS):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -42,7 +75,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--others", action="store_true", help="also time the uniform and constant images")
-    ap.add_argument("--sweep", action="store_true", help="time replica counts R = 1..16 on all three images")
+    ap.add_argument("--sweep", action="store_true", help="time the LDS layouts on all three images")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the plan's default layout instead of timing the candidates first")
+    ap.add_argument("--layout", default=None,
+                    help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
@@ -58,73 +95,104 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    oracle_cache, image_cache = {}, {}
+    fixed = None
+    if args.layout:
+        R, bits, wg = (int(v) for v in args.layout.split(","))
+        fixed = {"replicas": R, "counter_bits": bits, "wg_size": wg}
 
-    def measure(kind, tuning=None):
-        w = synth.square_4096(kind)
+    def timed_loop(plan, copies, outs, N, lo, hi, offs, steps, warmup):
+        stream = torch.cuda.current_stream()
+        for i in range(warmup):
+            j = i % len(copies)
+            G.glcm_compute(copies[j], N, lo, hi, offs, out=outs[j], plan=plan, stream=stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for i in range(steps):
+            j = i % len(copies)
+            G.glcm_compute(copies[j], N, lo, hi, offs, out=outs[j], plan=plan, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ev0.elapsed_time(ev1) / max(1, steps)
+
+    def measure(kind, tuning=None, vote_timing=False):
+        w = image_cache.get(kind)
+        if w is None:
+            w = image_cache[kind] = synth.square_4096(kind)
         img, N, lo, hi, offs = w["images"][0], w["N"], w["lo"], w["hi"], w["offsets"]
         H, W = img.shape
         K = len(offs)
-        pairs = pairs_of(W, H, offs)
-        algo_bytes = W * H * img.itemsize + K * N * N * 4
-        want = oracle.glcm(img, N, lo, hi, offs)
+        want = oracle_cache.get(kind)
+        if want is None:
+            want = oracle_cache[kind] = oracle.glcm(img, N, lo, hi, offs)
         base = torch.from_numpy(img).to(dev)
         copies = [base.clone() for _ in range(args.copies)]
         outs = [torch.empty((K, N, N), dtype=torch.uint32, device=dev) for _ in range(args.copies)]
         plan = G.glcm_plan_create(np.uint8, N, offs, W, H)
         if tuning:
             plan.set_tuning(**tuning)
-        stream = torch.cuda.current_stream()
-        for i in range(args.warmup):
-            j = i % args.copies
-            G.glcm_compute(copies[j], N, lo, hi, offs, out=outs[j], plan=plan, stream=stream)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        for i in range(args.steps):
-            j = i % args.copies
-            G.glcm_compute(copies[j], N, lo, hi, offs, out=outs[j], plan=plan, stream=stream)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        kern_ms = ev0.elapsed_time(ev1) / args.steps
+        elif fixed:
+            plan.set_tuning(**fixed)
+        elif args.autotune:
+            plan.autotune(copies[0], lo, hi, repeats=10)
+        wall, step_ms = timed_loop(plan, copies, outs, N, lo, hi, offs, args.steps, args.warmup)
         for j in range(min(args.copies, args.steps)):
             got = outs[j].view(torch.int32).cpu().numpy().view(np.uint32)
             if not np.array_equal(got, want):
                 raise SystemExit(f"bench: result of copy {j} differs from the oracle ({kind})")
-        tuning = plan.tuning.as_dict()
+        t = plan.tuning.as_dict()
+        vote_ms = None
+        if vote_timing:
+            tp = G.glcm_plan_create(np.uint8, N, offs, W, H, G.FLAG_TIMING)
+            tp.set_tuning(**{k: t[k] for k in ("replicas", "counter_bits", "wg_size", "merge")})
+            timed_loop(tp, copies, outs, N, lo, hi, offs, args.warmup, 0)
+            tp.kernel_time()  # drop the warm-up launches
+            timed_loop(tp, copies, outs, N, lo, hi, offs, args.steps, 0)
+            total, n = tp.kernel_time()
+            vote_ms = total / n
+            tp.close()
         plan.close()
-        return dict(name=w["name"], pairs=pairs, bytes=algo_bytes, wall_s=wall, kern_ms=kern_ms,
-                    tuning=tuning, img=img, N=N, lo=lo, hi=hi, offs=offs)
+        return dict(name=w["name"], pairs=pairs_of(W, H, offs), bytes=W * H * img.itemsize + K * N * N * 4,
+                    wall_s=wall, step_ms=step_ms, vote_ms=vote_ms, tuning=t, img=img, N=N, lo=lo, hi=hi,
+                    offs=offs)
 
     if args.sweep:
+        grid = [(R, bits, wg) for R, bits in ((2, 32), (4, 32), (8, 32), (16, 32), (32, 32), (16, 16), (32, 16))
+                for wg in (256, 512, 1024)]
         for kind in ("smooth", "uniform", "constant"):
-            for R in (1, 2, 4, 8, 16):
+            for R, bits, wg in grid:
+                cfg = {"replicas": R, "counter_bits": bits, "wg_size": wg}
                 try:
-                    r = measure(kind, {"replicas": R})
-                except Exception as e:  # an R the LDS cannot hold
-                    print(json.dumps({"sweep": kind, "replicas": R, "error": str(e)}), flush=True)
+                    r = measure(kind, cfg)
+                except Exception as e:  # a layout the LDS cannot hold
+                    print(json.dumps({"sweep": kind, **cfg, "error": str(e)}), flush=True)
                     continue
-                print(json.dumps({"sweep": kind, "replicas": R, "us_per_step": r["kern_ms"] * 1e3,
-                                  "gpairs_s": r["pairs"] / (r["kern_ms"] * 1e-3) / 1e9}), flush=True)
+                print(json.dumps({"sweep": kind, **cfg, "partitions": r["tuning"]["partitions"],
+                                  "us_per_step": round(r["step_ms"] * 1e3, 2),
+                                  "gpairs_s": round(r["pairs"] / (r["step_ms"] * 1e-3) / 1e9, 1)}), flush=True)
         return
 
-    main_res = measure(args.kind)
+    main_res = measure(args.kind, vote_timing=True)
     steps = args.steps
     ms_per_step = main_res["wall_s"] * 1e3 / steps
     value = main_res["pairs"] / (main_res["wall_s"] / steps) / 1e9
-    achieved_gbs = main_res["bytes"] / (main_res["kern_ms"] * 1e-3) / 1e9
+    achieved_gbs = main_res["bytes"] / (main_res["vote_ms"] * 1e-3) / 1e9
+    traffic = recorded_traffic(main_res["tuning"])
 
-    extra = {"kernel_ms_per_step": main_res["kern_ms"], "pairs_per_step": main_res["pairs"],
-             "algorithmic_bytes_per_step": main_res["bytes"], "tuning": main_res["tuning"],
-             "copies_rotated": args.copies, "rotated_bytes": args.copies * 4096 * 4096}
+    extra = {"step_ms_events": main_res["step_ms"], "vote_kernel_ms": main_res["vote_ms"],
+             "pairs_per_step": main_res["pairs"], "algorithmic_bytes_per_step": main_res["bytes"],
+             "tuning": main_res["tuning"], "copies_rotated": args.copies,
+             "rotated_bytes": args.copies * 4096 * 4096,
+             "lds_vote_rate_tvotes_s": main_res["pairs"] / (main_res["vote_ms"] * 1e-3) / 1e12}
     if args.others:
         for kind in ("uniform", "constant", "smooth"):
             if kind == args.kind:
                 continue
             r = measure(kind)
             extra[f"{kind}_gpairs_s"] = r["pairs"] / (r["wall_s"] / steps) / 1e9
-            extra[f"{kind}_kernel_ms"] = r["kern_ms"]
+            extra[f"{kind}_tuning"] = r["tuning"]
 
     cpu = None
     if not args.no_cpu:
@@ -147,7 +215,7 @@ def main():
         "config": {"workload": main_res["name"], "image": "4096x4096 uint8", "levels": 32,
                    "offsets": [list(o) for o in main_res["offs"]], "resident": "device"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -79,6 +79,8 @@ enum glcm_status {
 #define GLCM_FLAG_FORCE_PARTITIONED (1u << 1) /* split bins into LDS-sized partitions */
 #define GLCM_FLAG_FORCE_GLOBAL      (1u << 2) /* one global atomic per pair, no LDS */
 #define GLCM_FLAG_SERIAL_UPLOAD     (1u << 3) /* host images: copy, then count (no overlap) */
+#define GLCM_FLAG_TIMING            (1u << 4) /* record HIP events around each counting-kernel
+                                                 launch; read with glcm_plan_kernel_time() */
 
 typedef struct glcm_plan_s *glcm_plan_t;
 
@@ -90,6 +92,9 @@ typedef struct glcm_tuning {
     int tile_rows;      /* host-image upload tile height (rows) */
     int counter_bits;   /* row kernel LDS counters: 16 (two copies per dword, used only
                            when no count can overflow) or 32; 0 keeps the current value */
+    int merge;          /* 0: workgroups add their counts into per-XCD accumulators in L2,
+                           a small kernel sums the 8 slices; 1: per-band partial counts,
+                           summed by a reduce kernel */
     int path;           /* read-only: 0 generic, 1 row kernel, 2 partitioned, 3 global */
     int partitions;     /* read-only: bin partitions per pass */
 } glcm_tuning_t;
@@ -132,6 +137,28 @@ GLCM_API int glcm_plan_create(glcm_plan_t *plan, int dtype, int N, int K, const 
  * parameters.  Overrides are validated and clamped to what the device allows;
  * GLCM_EINVAL for values outside the documented sets. */
 GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t *tuning, int set);
+
+/*
+ * Picks the plan's launch parameters by timing the candidate layouts (LDS
+ * copies, counter width, workgroup size) on a representative DEVICE image:
+ * each candidate counts the image `repeats` times after two warm-up runs, on
+ * `stream`; the fastest is kept and written to *chosen (may be NULL).  The
+ * call blocks until the timing is done and leaves the plan's results
+ * unchanged in meaning (every candidate computes the same counts).
+ * Errors: GLCM_EINVAL for a NULL plan or image, a host image, sizes beyond the
+ * plan's maxima, lo > hi, repeats outside [1, 1000]; GLCM_EHIP / GLCM_ENOMEM.
+ */
+GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void *img, int W, int H, int64_t stride, uint32_t lo,
+                                uint32_t hi, int repeats, void *stream, glcm_tuning_t *chosen);
+
+/*
+ * For plans created with GLCM_FLAG_TIMING: waits for the recorded launches and
+ * returns the summed duration (ms) of the counting kernel (the vote kernel,
+ * without the merge step) over the launches since the previous call, as
+ * measured by HIP events on each launch's stream; then forgets them.
+ * Errors: GLCM_EINVAL for NULL arguments; GLCM_EHIP.
+ */
+GLCM_API int glcm_plan_kernel_time(glcm_plan_t plan, double *ms_total, int *launches);
 
 /* Releases a plan after waiting for its queued work.  NULL is accepted. */
 GLCM_API int glcm_plan_destroy(glcm_plan_t plan);

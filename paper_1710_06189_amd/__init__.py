@@ -28,9 +28,10 @@ import torch
 
 __all__ = [
     "GlcmError", "Plan", "Tuning", "glcm_abi_version", "glcm_strerror", "glcm_last_hip_error",
-    "glcm_offset_polar", "glcm_plan_create", "glcm_plan_destroy", "glcm_plan_tuning", "glcm_compute",
+    "glcm_offset_polar", "glcm_plan_create", "glcm_plan_destroy", "glcm_plan_tuning", "glcm_plan_autotune",
+    "glcm_compute",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
-    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "PATH_NAMES",
+    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "PATH_NAMES", "glcm_plan_kernel_time",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,6 +42,7 @@ FLAG_FORCE_GENERIC = 1 << 0
 FLAG_FORCE_PARTITIONED = 1 << 1
 FLAG_FORCE_GLOBAL = 1 << 2
 FLAG_SERIAL_UPLOAD = 1 << 3
+FLAG_TIMING = 1 << 4
 PATH_NAMES = {0: "generic", 1: "rows", 2: "partitioned", 3: "global"}
 
 STATUS = {0: "GLCM_OK", -1: "GLCM_EINVAL", -2: "GLCM_ENOMEM", -3: "GLCM_EUNSUPPORTED",
@@ -62,8 +64,8 @@ class Offset(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("replicas", ctypes.c_int), ("wg_size", ctypes.c_int), ("rows_per_wave", ctypes.c_int),
-                ("tile_rows", ctypes.c_int), ("counter_bits", ctypes.c_int), ("path", ctypes.c_int),
-                ("partitions", ctypes.c_int)]
+                ("tile_rows", ctypes.c_int), ("counter_bits", ctypes.c_int), ("merge", ctypes.c_int),
+                ("path", ctypes.c_int), ("partitions", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -94,6 +96,10 @@ def _lib():
         lib.glcm_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(Offset), i32, i32, u32]
         lib.glcm_plan_tuning.restype = i32
         lib.glcm_plan_tuning.argtypes = [vp, ctypes.POINTER(Tuning), i32]
+        lib.glcm_plan_autotune.restype = i32
+        lib.glcm_plan_autotune.argtypes = [vp, vp, i32, i32, i64, u32, u32, i32, vp, ctypes.POINTER(Tuning)]
+        lib.glcm_plan_kernel_time.restype = i32
+        lib.glcm_plan_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         lib.glcm_plan_destroy.restype = i32
         lib.glcm_plan_destroy.argtypes = [vp]
         lib.glcm_compute.restype = i32
@@ -161,6 +167,26 @@ class Plan:
         _check(_lib().glcm_plan_tuning(self.handle, ctypes.byref(t), 1), "glcm_plan_tuning")
         return t
 
+    def autotune(self, img, lo=0, hi=None, repeats=5, stream=None) -> Tuning:
+        """Times the candidate layouts on `img` (a device tensor) and keeps the fastest."""
+        ptr, W, H, stride, dt, keep = _image_args(img)
+        if dt != self.dtype:
+            raise ValueError("image dtype differs from the plan's")
+        if hi is None:
+            hi = 255 if dt == U8 else 65535
+        t = Tuning()
+        _check(_lib().glcm_plan_autotune(self.handle, ctypes.c_void_p(ptr), W, H, stride, int(lo), int(hi),
+                                         int(repeats), _stream_handle(stream), ctypes.byref(t)),
+               "glcm_plan_autotune")
+        del keep
+        return t
+
+    def kernel_time(self):
+        """(total ms, launches) of the counting kernel since the last read (plans made with FLAG_TIMING)."""
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        _check(_lib().glcm_plan_kernel_time(self.handle, ctypes.byref(ms), ctypes.byref(n)), "glcm_plan_kernel_time")
+        return ms.value, n.value
+
     def close(self):
         if self.handle:
             _lib().glcm_plan_destroy(self.handle)
@@ -184,6 +210,14 @@ def glcm_plan_create(dtype, N, offsets, max_W, max_H, flags=0) -> Plan:
 
 def glcm_plan_tuning(plan: Plan) -> Tuning:
     return plan.tuning
+
+
+def glcm_plan_autotune(plan: Plan, img, lo=0, hi=None, repeats=5, stream=None) -> Tuning:
+    return plan.autotune(img, lo, hi, repeats, stream)
+
+
+def glcm_plan_kernel_time(plan: Plan):
+    return plan.kernel_time()
 
 
 def glcm_plan_destroy(plan: Plan):

@@ -34,7 +34,7 @@ int hip_status(hipError_t e) {
   } while (0)
 
 constexpr uint32_t kKnownFlags = GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED |
-                                 GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD;
+                                 GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD | GLCM_FLAG_TIMING;
 
 enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3 };
 
@@ -152,6 +152,7 @@ struct glcm_plan_s {
   // device workspace
   uint32_t* partials = nullptr;
   size_t partials_bytes = 0;
+  uint32_t* xbuf = nullptr;  // [kXcdSlots][K*N*N] per-XCD accumulators, kept zero between calls
 
 
   // ordering across streams
@@ -168,6 +169,9 @@ struct glcm_plan_s {
   hipEvent_t uploaded[kSlots] = {nullptr, nullptr};
   bool pin_pending[kSlots] = {false, false};  // a staging slot's upload may still be running
   hipEvent_t consumed[kSlots] = {nullptr, nullptr};
+
+  // GLCM_FLAG_TIMING: events around every counting-kernel launch
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
 
   std::mutex mu;
 };
@@ -209,6 +213,7 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   d.rows_per_wave = 0;
   d.tile_rows = 1024;
   d.counter_bits = 32;
+  d.merge = 0;
   if (p->flags & GLCM_FLAG_FORCE_GLOBAL) {
     d.path = kPathGlobal;
     d.replicas = 1;
@@ -219,15 +224,16 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
     if (rows_ok) {
       d.path = kPathRows;
       d.rows_per_wave = 4;
-      // Most copies for the fewest partitions; 16-bit counters double the
-      // copies in the same LDS (checked against the count bound per call).
+      // The most dwords per bin (copies spread same-bin votes over more
+      // addresses and banks) that costs at most max(2, minimum) partitions:
+      // measured on MI355X, fewer LDS conflicts are worth reading the image
+      // twice, not more.
       const int Pmin = row_partitions(p, 1, 32);
-      static const int cand[][2] = {{16, 16}, {8, 16}, {8, 32}, {4, 16}, {4, 32}, {2, 16}, {2, 32}, {1, 32}};
-      for (const auto& cr : cand) {
-        const int P = row_partitions(p, cr[0], cr[1]);
-        if (P == Pmin) {
-          d.replicas = cr[0];
-          d.counter_bits = cr[1];
+      for (int R = 16; R >= 1; R /= 2) {
+        const int P = row_partitions(p, R, 32);
+        if (P > 0 && P <= std::max(2, Pmin)) {
+          d.replicas = R;
+          d.counter_bits = 32;
           d.partitions = P;
           break;
         }
@@ -260,6 +266,15 @@ int plan_init(glcm_plan_t p) {
   // keep 1 KiB for static LDS (reduction scratch) and the 64 trash words
   p->lds_budget_words = (lds - 1024) / 4;
   choose_tuning(p, &p->tuning);
+  if (p->tuning.path != kPathGlobal) {
+    const size_t bytes = (size_t)glcm::kXcdSlots * (size_t)p->K * p->N * p->N * 4u;
+    if (bytes <= (256u << 20)) {
+      GLCM_TRY(hipMalloc((void**)&p->xbuf, bytes));
+      GLCM_TRY(hipMemset(p->xbuf, 0, bytes));
+    } else {
+      p->tuning.merge = 1;  // band partials only
+    }
+  }
 
   GLCM_TRY(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
   return GLCM_OK;
@@ -276,8 +291,13 @@ void plan_release(glcm_plan_t p) {
   }
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   if (p->partials) (void)hipFree(p->partials);
+  if (p->xbuf) (void)hipFree(p->xbuf);
 
   if (p->done) (void)hipEventDestroy(p->done);
+  for (auto& ev : p->timing) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
 }
 
 // Makes sure the plan's workspace can hold `bytes` of partials.  Waits for the
@@ -308,8 +328,10 @@ int record_done(glcm_plan_t p, hipStream_t s) {
 
 // Queues the counting of first-pixel rows [y_begin, y_end) of a device image
 // whose rows [0, H) are all resident, writing (or adding into) out.
+// finish = false leaves the counts in the per-XCD accumulators (host tiles);
+// the last call then finishes with accumulate = false.
 int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, int y_begin, int y_end,
-                 uint32_t lo, uint32_t hi, uint32_t* out, bool accumulate, hipStream_t stream) {
+                 uint32_t lo, uint32_t hi, uint32_t* out, bool accumulate, bool finish, hipStream_t stream) {
   const glcm_tuning_t& t = p->tuning;
   const int b = dtype_bytes(p->dtype);
   const uint32_t NN = (uint32_t)p->N * (uint32_t)p->N;
@@ -348,9 +370,11 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     const bool aligned = ((uintptr_t)img % 16 == 0) && (((uint64_t)stride * b) % 16 == 0);
     if (!aligned) path = (words <= (uint32_t)p->lds_budget_words) ? kPathGeneric : kPathPartitioned;
   }
+  const bool xcd = t.merge == 0 && p->xbuf != nullptr && path != kPathGlobal;
   if (y_end <= y_begin) {
     // nothing to count: clear (or keep) the output
-    if (!accumulate) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
+    if (xcd && finish) GLCM_TRY(glcm::launch_finish(p->xbuf, out, words, accumulate, stream));
+    else if (!accumulate && !xcd) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
     return GLCM_OK;
   }
 
@@ -394,11 +418,17 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     }
   }
 
-  // Row bands: about one workgroup per CU per partition (LDS allows one).
+  // Row bands: as many workgroups per partition as the CUs hold at once
+  // (limited by LDS and by 32 wavefronts per CU).
   const int rows = y_end - y_begin;
   const int wg = t.wg_size;
   const int nwaves = wg / 64;
-  int target_groups = std::max(1, p->num_cus / a.P);
+  size_t lds_need = ((size_t)a.part_words << log2R) * 4u;
+  if (path == kPathRows)
+    lds_need = (size_t)(a.part_words / NN) * row_glcm_dwords(p->N, R, t.counter_bits == 16 ? 16 : 32) * 4u;
+  lds_need = std::max(lds_need, (size_t)wg * 4u);
+  const int per_cu = std::max(1, std::min((int)(((size_t)p->lds_budget_words * 4u + 1024u) / lds_need), 32 / nwaves));
+  int target_groups = std::max(1, p->num_cus * per_cu / a.P);
   int nregions = std::min(rows, target_groups);
   // keep partials within 256 MiB
   while (nregions > 1 && (uint64_t)nregions * words * 4ull > (256ull << 20)) nregions = (nregions + 1) / 2;
@@ -409,9 +439,13 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   (void)nwaves;
   a.rows_per_wave = rpw;
 
-  int rc = ensure_partials(p, (size_t)a.nregions * words * 4u);
-  if (rc != GLCM_OK) return rc;
-  a.partials = p->partials;
+  if (xcd) {
+    a.xbuf = p->xbuf;
+  } else {
+    int rc = ensure_partials(p, (size_t)a.nregions * words * 4u);
+    if (rc != GLCM_OK) return rc;
+    a.partials = p->partials;
+  }
 
   // LDS: the copies (at least one word per thread)
   size_t lds_bytes = ((size_t)a.part_words << log2R) * 4u;
@@ -433,14 +467,32 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   lds_bytes = std::max(lds_bytes, (size_t)wg * 4u);
 
   const int maxdy = c.maxdy <= 1 ? 1 : (c.maxdy <= 2 ? 2 : 4);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (p->flags & GLCM_FLAG_TIMING) {
+    // device-scope release: timing needs no flush of host-visible caches
+    GLCM_TRY(hipEventCreateWithFlags(&ev0, hipEventReleaseToDevice));
+    GLCM_TRY(hipEventCreateWithFlags(&ev1, hipEventReleaseToDevice));
+    p->timing.emplace_back(ev0, ev1);
+    GLCM_TRY(hipEventRecord(ev0, stream));
+  }
   hipError_t e;
   if (path == kPathRows) {
     e = glcm::launch_vote_rows(a, b, maxdy, rpw, wg, lds_bytes, stream);
   } else {
     e = glcm::launch_vote_generic(a, b, wg, lds_bytes, stream);
   }
-  if (e == hipSuccess) e = glcm::launch_reduce(a.partials, out, words, a.nregions, accumulate, stream);
-  if (e != hipSuccess) return hip_status(e);
+  if (e == hipSuccess && ev1) e = hipEventRecord(ev1, stream);
+  if (e == hipSuccess) {
+    if (!xcd)
+      e = glcm::launch_reduce(a.partials, out, words, a.nregions, accumulate, stream);
+    else if (finish)
+      e = glcm::launch_finish(p->xbuf, out, words, accumulate, stream);
+  }
+  if (e != hipSuccess) {
+    // leave the accumulators clean for the next call
+    if (xcd) (void)hipMemsetAsync(p->xbuf, 0, (size_t)glcm::kXcdSlots * words * 4u, stream);
+    return hip_status(e);
+  }
   return GLCM_OK;
 }
 
@@ -512,8 +564,10 @@ int count_host(glcm_plan_t p, const void* img, bool pinned, int W, int H, int64_
     GLCM_TRY(hipEventRecord(p->uploaded[s], cs));
     p->pin_pending[s] = !pinned;
     if (!serial) GLCM_TRY(hipStreamWaitEvent(stream, p->uploaded[s], 0));
-    int rc = count_device(p, dev, W, rows, (int64_t)(pitch_bytes / b), r0 - ra, r1 - ra, lo, hi, out, tile > 0,
-                          stream);
+    const bool last = r1 >= H;
+    const bool xcd = p->tuning.merge == 0 && p->xbuf != nullptr;
+    int rc = count_device(p, dev, W, rows, (int64_t)(pitch_bytes / b), r0 - ra, r1 - ra, lo, hi, out,
+                          xcd ? false : tile > 0, xcd ? last : true, stream);
     if (rc != GLCM_OK) return rc;
     GLCM_TRY(hipEventRecord(p->consumed[s], stream));
     slot_used[s] = true;
@@ -615,6 +669,9 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
       if (t.partitions > 1) t.path = kPathPartitioned;
     }
     t.counter_bits = bits;
+    if (n.merge != 0 && n.merge != 1) return GLCM_EINVAL;
+    if (n.merge == 0 && !plan->xbuf && t.path != kPathGlobal) return GLCM_EINVAL;
+    t.merge = n.merge;
     t.replicas = n.replicas;
     t.wg_size = n.wg_size;
     if (t.path == kPathRows && n.rows_per_wave != 0) t.rows_per_wave = n.rows_per_wave;
@@ -623,6 +680,119 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
   }
   *tuning = plan->tuning;
   return GLCM_OK;
+}
+
+GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H, int64_t stride, uint32_t lo,
+                                uint32_t hi, int repeats, void* stream_, glcm_tuning_t* chosen) {
+  if (!plan || !img || W < 1 || H < 1 || stride < W || W > plan->max_W || H > plan->max_H) return GLCM_EINVAL;
+  if (repeats < 1 || repeats > 1000) return GLCM_EINVAL;
+  if (lo > hi || hi > (plan->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
+  if (((uintptr_t)img) % (uintptr_t)dtype_bytes(plan->dtype)) return GLCM_EINVAL;
+  int dev = -1;
+  if (pointer_kind(img, &dev) != 2) return GLCM_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  const glcm_tuning_t start = plan->tuning;
+  if (start.path == kPathGlobal) {
+    if (chosen) *chosen = start;
+    return GLCM_OK;
+  }
+  // candidates: copies x counter width x workgroup size, within 4x the
+  // minimal number of partitions
+  std::vector<glcm_tuning_t> cand;
+  if (start.path == kPathRows) {
+    const int Pmin = row_partitions(plan, 1, 32);
+    for (int bits : {32, 16})
+      for (int R = bits == 16 ? 2 : 1; R <= 64; R *= 2) {
+        const int P = row_partitions(plan, R, bits);
+        if (P == 0 || P > 4 * Pmin) continue;
+        for (int wg : {512, 1024}) {
+          glcm_tuning_t t = start;
+          t.replicas = R;
+          t.counter_bits = bits;
+          t.partitions = P;
+          t.wg_size = wg;
+          cand.push_back(t);
+        }
+      }
+  } else {
+    const uint64_t words = (uint64_t)plan->K * plan->N * plan->N, budget = (uint64_t)plan->lds_budget_words;
+    for (int R = 1; R <= 16; R *= 2) {
+      const uint64_t P = (words * R + budget - 1) / budget;
+      if (P > 16) continue;
+      for (int wg : {256, 512, 1024}) {
+        glcm_tuning_t t = start;
+        t.replicas = R;
+        t.partitions = (int)P;
+        t.path = P > 1 ? kPathPartitioned : kPathGeneric;
+        t.wg_size = wg;
+        cand.push_back(t);
+      }
+    }
+  }
+  const size_t words = (size_t)plan->K * plan->N * plan->N;
+  uint32_t* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GLCM_TRY(hipMalloc((void**)&out, words * 4u));
+  int rc = GLCM_OK;
+  float best = 0.f;
+  glcm_tuning_t best_t = start;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) rc = hip_status(he);
+  if (rc == GLCM_OK) rc = order_after_previous(plan, stream);
+  for (size_t c = 0; c < cand.size() && rc == GLCM_OK; ++c) {
+    plan->tuning = cand[c];
+    for (int i = 0; i < 2 && rc == GLCM_OK; ++i)
+      rc = count_device(plan, img, W, H, stride, 0, H, lo, hi, out, false, true, stream);
+    if (rc != GLCM_OK) break;
+    if ((he = hipEventRecord(e0, stream)) != hipSuccess) { rc = hip_status(he); break; }
+    for (int i = 0; i < repeats && rc == GLCM_OK; ++i)
+      rc = count_device(plan, img, W, H, stride, 0, H, lo, hi, out, false, true, stream);
+    if (rc != GLCM_OK) break;
+    if ((he = hipEventRecord(e1, stream)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess) {
+      rc = hip_status(he);
+      break;
+    }
+    float ms = 0.f;
+    if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = hip_status(he); break; }
+    // a later candidate must win by 3% to replace the kept one, so near ties
+    // resolve the same way from run to run
+    if (c == 0 || ms < 0.97f * best) {
+      best = ms;
+      best_t = cand[c];
+    }
+  }
+  if (rc == GLCM_OK) rc = record_done(plan, stream);
+  (void)hipStreamSynchronize(stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  plan->tuning = rc == GLCM_OK ? best_t : start;
+  if (rc == GLCM_OK) plan->user_tuned = true;
+  if (chosen) *chosen = plan->tuning;
+  return rc;
+}
+
+GLCM_API int glcm_plan_kernel_time(glcm_plan_t plan, double* ms_total, int* launches) {
+  if (!plan || !ms_total || !launches) return GLCM_EINVAL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  double sum = 0.0;
+  int n = 0, rc = GLCM_OK;
+  for (auto& ev : plan->timing) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(ev.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
+    if (e != hipSuccess && rc == GLCM_OK) rc = hip_status(e);
+    sum += ms;
+    ++n;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  plan->timing.clear();
+  *ms_total = sum;
+  *launches = n;
+  return rc;
 }
 
 GLCM_API int glcm_plan_destroy(glcm_plan_t plan) {
@@ -673,7 +843,7 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void* img, int W, int H, int64
   rc = order_after_previous(plan, stream);
   if (rc != GLCM_OK) return rc;
   if (kind == 2) {
-    rc = count_device(plan, img, W, H, stride, 0, H, lo, hi, out, false, stream);
+    rc = count_device(plan, img, W, H, stride, 0, H, lo, hi, out, false, true, stream);
   } else {
     rc = count_host(plan, img, kind == 1, W, H, stride, lo, hi, out, stream);
   }

@@ -7,6 +7,9 @@
 namespace glcm {
 
 constexpr int kMaxK = 64;
+// Accumulation slices for the per-XCD merge (an MI355X has 8 XCDs; the slice
+// is XCC_ID mod kXcdSlots, which stays one slice per XCD up to 16 XCDs).
+constexpr uint32_t kXcdSlots = 16;
 
 // Gray-level reduction q(v): 0 below lo, N-1 above hi, otherwise
 // floor(x / D) with x = (v - lo) * N and D = hi - lo + 1, evaluated as
@@ -39,7 +42,8 @@ struct VoteArgs {
   uint32_t pitch;             // row kernel: LDS row pitch of a GLCM, >= N + 1 (row/column N: sentinel)
   Quant div_n, div_nn;        // magic/shift for dividing by N and by N*N (only those fields used)
   int c16;                    // row kernel: 16-bit counters, two copies per dword
-  uint32_t* partials;         // [nregions][words_total] per-band counts
+  uint32_t* partials;         // [nregions][words_total] per-band counts (band-partial merge)
+  uint32_t* xbuf;             // [kXcdSlots][words_total] per-XCD accumulators, or null
   uint32_t* out;              // global-atomic kernel: [words_total] counts, zeroed beforehand
 };
 
@@ -50,6 +54,8 @@ hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int r
 // out[w] = (accumulate ? out[w] : 0) + sum_b partials[b * M + w] for w < M.
 hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, int nbands, bool accumulate,
                          hipStream_t stream);
+// out[w] = (accumulate ? out[w] : 0) + sum_x xbuf[x * M + w]; zeroes xbuf.
+hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, bool accumulate, hipStream_t stream);
 hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream);
 hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream);
 

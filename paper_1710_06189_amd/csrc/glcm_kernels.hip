@@ -38,12 +38,21 @@ __device__ __forceinline__ uint32_t quantize(uint32_t v, const Quant& q) {
 }
 
 // ---------------------------------------------------------------------------
-// Merge of the LDS copies into this workgroup's band partial.  Called by every
-// thread once its votes are done.  The LDS matrices may be padded: word
-// (k, i, j) of the partition (k counted from the partition's first GLCM) sits
-// at copy-block k * nn1 + i * n1 + j, each block holding R consecutive copies.
-// The cross-workgroup sum runs in k_reduce after this kernel: the kernel
-// boundary makes the partials visible without any in-kernel synchronisation.
+// Merge of the LDS copies (the final sum of Section II.A), in two steps that
+// need no synchronisation between workgroups inside a kernel:
+//
+//  * merge = per-XCD accumulation: every workgroup adds its non-zero counts to
+//    the accumulation slice of the XCD it runs on (hardware register XCC_ID),
+//    with workgroup-scope atomics, which execute in that XCD's L2 (all CUs of
+//    an XCD share it, and no other XCD touches the slice).  The kernel
+//    boundary writes the L2s back; k_finish sums the slices into `out` and
+//    clears them for the next launch.
+//  * merge = band partials: every workgroup stores its counts to its own row
+//    of a partial buffer and k_reduce sums the rows.
+//
+// The LDS matrices may be padded: word (k, i, j) of the partition (k counted
+// from the partition's first GLCM) sits at copy-block k * nn1 + i * n1 + j,
+// each block holding R copies (R / 2 dwords with 16-bit counters).
 // ---------------------------------------------------------------------------
 __device__ void store_partial(const VoteArgs& a, const uint32_t* lds, uint32_t pbase, uint32_t pwords, int region,
                               uint32_t n1, uint32_t nn1, bool c16) {
@@ -73,8 +82,33 @@ __device__ void store_partial(const VoteArgs& a, const uint32_t* lds, uint32_t p
     } else {
       for (uint32_t d = 0; d < D; ++d) s += c[d];
     }
-    dst[w] = s;
+    if (a.xbuf) {
+      if (s) {
+        uint32_t xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+        __hip_atomic_fetch_add(a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total + pbase + w, s,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    } else {
+      dst[w] = s;
+    }
   }
+}
+
+// out[w] = (accumulate ? out[w] : 0) + sum of the XCD slices; clears them.
+__global__ __launch_bounds__(256) void k_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, int accumulate) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= M) return;
+  uint32_t v[kXcdSlots];
+#pragma unroll
+  for (uint32_t x = 0; x < kXcdSlots; ++x) v[x] = xbuf[(size_t)x * M + w];
+  uint32_t s = accumulate ? out[w] : 0u;
+#pragma unroll
+  for (uint32_t x = 0; x < kXcdSlots; ++x) {
+    s += v[x];
+    xbuf[(size_t)x * M + w] = 0u;
+  }
+  out[w] = s;
 }
 
 // out[w] (+)= sum over bands of partials[band][w].  Each workgroup owns
@@ -373,10 +407,15 @@ __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const uint32_t r = threadIdx.x & (R - 1u);                // this thread's copy
-  const uint32_t B = dwords_per_bin * 4u;                   // bytes per bin (all copies)
-  const uint32_t Cr = a.c16 ? (r >> 1) * 4u : r * 4u;
-  const uint32_t inc = a.c16 ? (1u << ((r & 1u) * 16u)) : 1u;
+  // This thread's dword of a bin is lane mod D (D = dwords per bin): lanes
+  // sharing a dword are D chunks (16 D pixels) apart, so on smooth images they
+  // rarely vote the same bin; with 16-bit counters the half is bit log2(D).
+  const uint32_t D = dwords_per_bin;
+  const uint32_t g = threadIdx.x & (D - 1u);
+  const uint32_t h = (threadIdx.x / D) & 1u;
+  const uint32_t B = D * 4u;  // bytes per bin (all copies)
+  const uint32_t Cr = g * 4u;
+  const uint32_t inc = a.c16 ? (1u << (h * 16u)) : 1u;
   const uint32_t sent4 = N * 0x01010101u;
   const int y0 = a.y_begin + region * a.region_rows;
   const int y1 = min(a.y_end, y0 + a.region_rows);
@@ -535,6 +574,11 @@ hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int r
   if (rpw != 4) return hipErrorInvalidValue;
   return dtype_bytes == 1 ? launch_rows_t<uint8_t>(a, maxdy, wg, lds_bytes, stream)
                           : launch_rows_t<uint16_t>(a, maxdy, wg, lds_bytes, stream);
+}
+
+hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, bool accumulate, hipStream_t stream) {
+  hipLaunchKernelGGL(k_finish, dim3((M + 255) / 256), dim3(256), 0, stream, xbuf, out, M, accumulate ? 1 : 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, int nbands, bool accumulate,

@@ -94,12 +94,15 @@ def test_offsets_any(offs):
     (G.FLAG_FORCE_GLOBAL, "global"), (0, "auto"),
 ])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
-def test_forced_paths(flags, name, dtype):
+@pytest.mark.parametrize("merge", [0, 1])
+def test_forced_paths(flags, name, dtype, merge):
     img = synth.smooth(517, 731, 5.0, 11, dtype)
     offs = synth.offsets_for([1, 2, 4])
     top = int(np.iinfo(dtype).max)
     plan = G.glcm_plan_create(dtype, 32, offs, 731, 517, flags)
     try:
+        if plan.tuning.path != 3:
+            plan.set_tuning(merge=merge)
         check(img, 32, 0, top, offs, plan=plan, label=f"path {name} {plan.tuning.as_dict()}")
         check(img, 32, 0, top, offs, plan=plan, label=f"path {name} again")
     finally:
@@ -280,7 +283,8 @@ def test_features_large_and_empty():
 @pytest.mark.parametrize("tile_rows", [1, 7, 64, 1024])
 @pytest.mark.parametrize("pinned", [False, True])
 @pytest.mark.parametrize("serial", [False, True])
-def test_host_image_tiles(tile_rows, pinned, serial):
+@pytest.mark.parametrize("merge", [0, 1])
+def test_host_image_tiles(tile_rows, pinned, serial, merge):
     """Host images go up in row tiles with halo rows; each tile owns the pairs
     whose first pixel lies in its rows, so the sum over tiles is exact."""
     img = synth.smooth(301, 517, 3.0, 31, np.uint16, noise_frac=0.05)
@@ -288,7 +292,7 @@ def test_host_image_tiles(tile_rows, pinned, serial):
     flags = G.FLAG_SERIAL_UPLOAD if serial else 0
     plan = G.glcm_plan_create(np.uint16, 64, offs, 517, 301, flags)
     try:
-        plan.set_tuning(tile_rows=tile_rows)
+        plan.set_tuning(tile_rows=tile_rows, merge=merge)
         src = torch.from_numpy(img.view(np.int16)).view(torch.uint16)
         if pinned:
             src = src.pin_memory()
@@ -311,3 +315,48 @@ def test_host_multispectral_band_streamed():
     offs = synth.offsets_for([1, 2, 4])
     src = torch.from_numpy(img.view(np.int16)).view(torch.uint16).pin_memory()
     check(img, 64, 0, 65535, offs, t=src, label=f"multispectral 2048^2 streamed sigma={sigma:.1f}")
+
+
+@pytest.mark.parametrize("merge", [0, 1])
+def test_alternating_images_one_plan(merge):
+    """Consecutive calls on one plan with different images: nothing carries over."""
+    imgs = [synth.smooth(256, 1100, 2.0 + i, 50 + i) for i in range(3)] + [synth.constant(256, 1100, 200)]
+    offs = synth.offsets_for([1, 2])
+    wants = [oracle.glcm(im, 16, 0, 255, offs) for im in imgs]
+    ts = [to_device(im) for im in imgs]
+    plan = G.glcm_plan_create(np.uint8, 16, offs, 1100, 256)
+    try:
+        plan.set_tuning(merge=merge)
+        outs = [G.glcm_compute(ts[i % 4], 16, 0, 255, offs, plan=plan) for i in range(24)]
+        for i, o in enumerate(outs):
+            assert np.array_equal(to_host(o), wants[i % 4]), i
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("flags", [0, G.FLAG_FORCE_GENERIC])
+def test_autotune_keeps_results(flags):
+    img = synth.smooth(700, 1500, 6.0, 60)
+    offs = synth.offsets_for([1, 2])
+    plan = G.glcm_plan_create(np.uint8, 32, offs, 1500, 700, flags)
+    try:
+        t = plan.autotune(to_device(img), repeats=2)
+        assert t.replicas >= 1 and t.wg_size in (256, 512, 1024)
+        check(img, 32, 0, 255, offs, plan=plan, label=f"after autotune {t.as_dict()}")
+    finally:
+        plan.close()
+
+
+def test_kernel_timing_flag():
+    img = synth.uniform(512, 2048, 61)
+    offs = synth.offsets_for([1])
+    plan = G.glcm_plan_create(np.uint8, 16, offs, 2048, 512, G.FLAG_TIMING)
+    try:
+        t = to_device(img)
+        for _ in range(3):
+            check(img, 16, 0, 255, offs, plan=plan, t=t, label="timing")
+        ms, n = plan.kernel_time()
+        assert n == 3 and ms > 0
+        assert plan.kernel_time() == (0.0, 0)
+    finally:
+        plan.close()
