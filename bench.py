@@ -80,6 +80,11 @@ def main():
                     help="keep the plan's default layout instead of timing the candidates first")
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
+    ap.add_argument("--workload", default="square", choices=["square", "multispectral"],
+                    help="square: the 4096^2 device-resident image (the default line); multispectral: "
+                         "the 8-band 8192^2 uint16 stack streamed from pinned host memory")
+    ap.add_argument("--bands", type=int, default=8)
+    ap.add_argument("--size", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
@@ -95,6 +100,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.workload == "multispectral":
+        bench_multispectral(args, G, torch, np, oracle, synth, dev)
+        return
     oracle_cache, image_cache = {}, {}
     fixed = None
     if args.layout:
@@ -186,6 +194,10 @@ def main():
              "tuning": main_res["tuning"], "copies_rotated": args.copies,
              "rotated_bytes": args.copies * 4096 * 4096,
              "lds_vote_rate_tvotes_s": main_res["pairs"] / (main_res["vote_ms"] * 1e-3) / 1e12}
+    # per-call latency (events around each call, inputs rotating in HBM) and
+    # the features kernel on the same output
+    lat = call_latencies(G, torch, np, synth, dev, args)
+    extra.update(lat)
     if args.others:
         for kind in ("uniform", "constant", "smooth"):
             if kind == args.kind:
@@ -220,6 +232,124 @@ def main():
         "extra": extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def call_latencies(G, torch, np, synth, dev, args, calls=200):
+    """p50 / p99 of single glcm_compute calls (and of glcm_features) measured
+    with events around each call on the stream, inputs rotating in HBM."""
+    w = synth.square_4096(args.kind)
+    img, N, lo, hi, offs = w["images"][0], w["N"], w["lo"], w["hi"], w["offsets"]
+    base = torch.from_numpy(img).to(dev)
+    copies = [base.clone() for _ in range(args.copies)]
+    out = torch.empty((len(offs), N, N), dtype=torch.uint32, device=dev)
+    plan = G.glcm_plan_create(np.uint8, N, offs, img.shape[1], img.shape[0])
+    if args.layout:
+        R, bits, wg = (int(v) for v in args.layout.split(","))
+        plan.set_tuning(replicas=R, counter_bits=bits, wg_size=wg)
+    elif args.autotune:
+        plan.autotune(copies[0], lo, hi, repeats=10)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    fev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for i in range(20):
+        G.glcm_compute(copies[i % len(copies)], N, lo, hi, offs, out=out, plan=plan, stream=stream)
+        G.glcm_features(out, stream=stream)
+    torch.cuda.synchronize()
+    for i in range(calls):
+        ev[i][0].record(stream)
+        G.glcm_compute(copies[i % len(copies)], N, lo, hi, offs, out=out, plan=plan, stream=stream)
+        ev[i][1].record(stream)
+        fev[i][0].record(stream)
+        G.glcm_features(out, stream=stream)
+        fev[i][1].record(stream)
+    torch.cuda.synchronize()
+    plan.close()
+    t = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    f = np.array([a.elapsed_time(b) * 1e3 for a, b in fev])
+    return {"call_us_p50": float(np.percentile(t, 50)), "call_us_p99": float(np.percentile(t, 99)),
+            "features_us_p50": float(np.percentile(f, 50)), "features_us_p99": float(np.percentile(f, 99)),
+            "latency_calls": calls}
+
+
+def bench_multispectral(args, G, torch, np, oracle, synth, dev):
+    """8 bands of 8192^2 uint16 (N = 64 over [0, 65535], d in {1, 2, 4} x four
+    angles): device-resident counting, the host-to-device copy alone, and the
+    whole job from pinned host memory streamed in row tiles (upload of tile
+    t+1 overlapping the count of tile t) versus uploaded and counted
+    serially.  Band 0 is checked against the oracle bin for bin, every band by
+    its per-offset totals."""
+    offs = synth.offsets_for([1, 2, 4])
+    N, size, bands = 64, args.size, args.bands
+    hosts, imgs = [], []
+    for b in range(bands):
+        img, sigma = synth.multispectral_band(b, size)
+        imgs.append(img)
+        hosts.append(torch.from_numpy(img.view(np.int16)).pin_memory().view(torch.uint16))
+        print(f"[multispectral] band {b} generated (sigma {sigma:.1f})", file=sys.stderr, flush=True)
+    pairs_band = pairs_of(size, size, offs)
+    pairs = pairs_band * bands
+    stream = torch.cuda.current_stream()
+    outs = [torch.empty((len(offs), N, N), dtype=torch.uint32, device=dev) for _ in range(bands)]
+
+    def run(plan, srcs):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for b in range(bands):
+            G.glcm_compute(srcs[b], N, 0, 65535, offs, out=outs[b], plan=plan, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3
+
+    def verify(label):
+        want_tot = [max(0, size - abs(dx)) * max(0, size - abs(dy)) for dx, dy in offs]
+        for b in range(bands):
+            got = outs[b].view(torch.int32).cpu().numpy().view(np.uint32)
+            if [int(got[k].sum(dtype=np.uint64)) for k in range(len(offs))] != want_tot:
+                raise SystemExit(f"bench: multispectral band {b} totals wrong ({label})")
+        got0 = outs[0].view(torch.int32).cpu().numpy().view(np.uint32)
+        if not np.array_equal(got0, want0):
+            raise SystemExit(f"bench: multispectral band 0 differs from the oracle ({label})")
+
+    want0 = oracle.glcm(imgs[0], N, 0, 65535, offs)
+    print("[multispectral] oracle for band 0 done", file=sys.stderr, flush=True)
+    plan = G.glcm_plan_create(np.uint16, N, offs, size, size)
+    plan_serial = G.glcm_plan_create(np.uint16, N, offs, size, size, G.FLAG_SERIAL_UPLOAD)
+    devs = [h.to(dev) for h in hosts]
+    run(plan, devs)  # warm-up (workspace, code objects)
+    _, t_dev = run(plan, devs)
+    verify("device")
+    # the copy alone: every band pinned -> device on the stream
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for b in range(bands):
+        devs[b].copy_(hosts[b], non_blocking=True)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    t_copy = c0.elapsed_time(c1) * 1e-3
+    del devs
+    run(plan, hosts)
+    wall_stream, _ = run(plan, hosts)
+    verify("streamed")
+    run(plan_serial, hosts)
+    wall_serial, _ = run(plan_serial, hosts)
+    verify("serial")
+    tiles = plan.tuning.tile_rows
+    tuning = plan.tuning.as_dict()
+    plan.close()
+    plan_serial.close()
+    nbytes = bands * size * size * 2
+    print(json.dumps({
+        "workload": f"{bands}x{size}x{size}-u16-multispectral-N64-K12", "pairs": pairs, "bytes": nbytes,
+        "device_resident_gpairs_s": pairs / t_dev / 1e9, "device_resident_ms": t_dev * 1e3,
+        "h2d_only_ms": t_copy * 1e3, "h2d_gbs": nbytes / t_copy / 1e9,
+        "streamed_ms": wall_stream * 1e3, "streamed_gpairs_s": pairs / wall_stream / 1e9,
+        "serial_ms": wall_serial * 1e3, "serial_gpairs_s": pairs / wall_serial / 1e9,
+        "streamed_over_serial": wall_serial / wall_stream,
+        "h2d_share_of_serial": t_copy / wall_serial, "tile_rows": tiles, "tuning": tuning,
+        "resident": "pinned host", "check": "band 0 bit-exact vs oracle; all bands per-offset totals"}), flush=True)
 
 
 if __name__ == "__main__":

@@ -81,21 +81,26 @@ enum glcm_status {
 #define GLCM_FLAG_SERIAL_UPLOAD     (1u << 3) /* host images: copy, then count (no overlap) */
 #define GLCM_FLAG_TIMING            (1u << 4) /* record HIP events around each counting-kernel
                                                  launch; read with glcm_plan_kernel_time() */
+#define GLCM_FLAG_FORCE_SLABS       (1u << 5) /* row-slab kernel even where the strip kernel
+                                                 applies */
 
 typedef struct glcm_plan_s *glcm_plan_t;
 
 /* Launch parameters of a plan, readable and (for tuning) overridable. */
 typedef struct glcm_tuning {
     int replicas;       /* R: LDS copies of each GLCM per workgroup (power of two) */
-    int wg_size;        /* threads per workgroup: 256, 512 or 1024 */
-    int rows_per_wave;  /* row kernel: first-pixel rows per wavefront slab (4) */
+    int wg_size;        /* threads per workgroup: 256, 512 or 1024 (the strip kernel on
+                           uint16 images with offsets reaching 2 pixels runs at most 512) */
+    int rows_per_wave;  /* slab kernel: first-pixel rows per wavefront slab (4); 0 elsewhere */
     int tile_rows;      /* host-image upload tile height (rows) */
-    int counter_bits;   /* row kernel LDS counters: 16 (two copies per dword, used only
-                           when no count can overflow) or 32; 0 keeps the current value */
+    int counter_bits;   /* strip / slab kernel LDS counters: 16 (two copies per dword, used
+                           only when no count can overflow) or 32; 0 keeps the current value.
+                           The strip kernel takes replicas / dwords per bin of 4, 8 or 16 */
     int merge;          /* 0: workgroups add their counts into per-XCD accumulators in L2,
                            a small kernel sums the 8 slices; 1: per-band partial counts,
                            summed by a reduce kernel */
-    int path;           /* read-only: 0 generic, 1 row kernel, 2 partitioned, 3 global */
+    int path;           /* read-only: 0 generic, 1 slab kernel, 2 partitioned, 3 global,
+                           4 strip kernel */
     int partitions;     /* read-only: bin partitions per pass */
 } glcm_tuning_t;
 

@@ -34,9 +34,10 @@ int hip_status(hipError_t e) {
   } while (0)
 
 constexpr uint32_t kKnownFlags = GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED |
-                                 GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD | GLCM_FLAG_TIMING;
+                                 GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD | GLCM_FLAG_TIMING |
+                                 GLCM_FLAG_FORCE_SLABS;
 
-enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3 };
+enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3, kPathStrips = 4 };
 
 
 
@@ -202,6 +203,29 @@ int row_partitions(const glcm_plan_s* p, int R, int bits) {
   return (int)(((uint64_t)p->K + per - 1) / per);
 }
 
+// Strip kernel: dwords per bin of a layout with R copies of `bits`-bit
+// counters (4, 8 or 16), or 0 when the kernel has no such variant.
+int strip_dwords(int R, int bits) {
+  const int D = bits == 16 ? R / 2 : R;
+  return (D == 4 || D == 8 || D == 16) ? D : 0;
+}
+
+// Strip kernel: GLCMs per partition for D dwords per bin ((N+1)^2 bins each),
+// at most kStripMaxKp; 0 if one GLCM does not fit.
+int strip_kp(const glcm_plan_s* p, int D) {
+  const uint64_t n1 = (uint64_t)p->N + 1u;
+  const uint64_t per = (uint64_t)p->lds_budget_words / (n1 * n1 * (uint64_t)D);
+  return (int)std::min<uint64_t>(per, (uint64_t)glcm::kStripMaxKp);
+}
+
+int strip_partitions(const glcm_plan_s* p, int R, int bits) {
+  const int D = strip_dwords(R, bits);
+  if (D == 0) return 0;
+  const int kp = strip_kp(p, D);
+  if (kp == 0) return 0;
+  return (p->K + kp - 1) / kp;
+}
+
 int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   // Path and LDS layout for this plan's (dtype, N, K, offsets, flags).
   const uint32_t NN = (uint32_t)p->N * (uint32_t)p->N;
@@ -219,9 +243,25 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
     d.replicas = 1;
     d.partitions = 1;
   } else {
-    const bool rows_ok = !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) &&
-                         p->N <= 255 && c.maxadx <= 4 && c.maxdy <= 4 && row_partitions(p, 1, 32) > 0;
-    if (rows_ok) {
+    const bool any_rows = !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) && p->N <= 255;
+    const bool strips_ok = any_rows && !(p->flags & GLCM_FLAG_FORCE_SLABS) && c.maxadx <= 2 && c.maxdy <= 2 &&
+                           strip_partitions(p, 4, 32) > 0;
+    const bool rows_ok = any_rows && c.maxadx <= 4 && c.maxdy <= 4 && row_partitions(p, 1, 32) > 0;
+    if (strips_ok) {
+      d.path = kPathStrips;
+      // 16 dwords per bin keep the 16 lanes of an LDS pass on distinct dwords;
+      // take them unless that needs more than max(2, minimum) image passes
+      const int Pmin = strip_partitions(p, 4, 32);
+      for (int R = 16; R >= 4; R /= 2) {
+        const int P = strip_partitions(p, R, 32);
+        if (P > 0 && P <= std::max(2, Pmin)) {
+          d.replicas = R;
+          d.counter_bits = 32;
+          d.partitions = P;
+          break;
+        }
+      }
+    } else if (rows_ok) {
       d.path = kPathRows;
       d.rows_per_wave = 4;
       // The most dwords per bin (copies spread same-bin votes over more
@@ -366,7 +406,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
 
   int path = t.path;
   const Canon c = canonicalize(p->offsets, p->K);
-  if (path == kPathRows) {
+  if (path == kPathRows || path == kPathStrips) {
     const bool aligned = ((uintptr_t)img % 16 == 0) && (((uint64_t)stride * b) % 16 == 0);
     if (!aligned) path = (words <= (uint32_t)p->lds_budget_words) ? kPathGeneric : kPathPartitioned;
   }
@@ -389,7 +429,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   }
 
   int R = t.replicas, P = t.partitions;  // R may drop below if 16-bit counters cannot be used
-  if (path != kPathRows && t.path == kPathRows) {
+  if (path != t.path && (t.path == kPathRows || t.path == kPathStrips)) {
     // fell back from the row kernel: size the generic partitions
     const uint64_t budget = (uint64_t)p->lds_budget_words;
     P = (int)((words + budget - 1) / budget);
@@ -400,7 +440,24 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   while ((1 << log2R) < R) ++log2R;
   a.log2R = log2R;
   const int rpw = 4;
-  if (path == kPathRows) {
+  // strip kernel: dwords per bin, template reach (1 or 2) and GLCMs per partition
+  int sD = 0, smd = 1, skp = 0;
+  if (path == kPathStrips) {
+    sD = strip_dwords(R, t.counter_bits == 16 ? 16 : 32);
+    smd = std::max(c.maxdy, c.maxadx) <= 1 ? 1 : 2;
+    skp = sD ? strip_kp(p, sD) : 0;
+    if (skp == 0) return GLCM_EINVAL;  // tunings are validated when set
+    a.kp = skp;
+    a.part_words = (uint32_t)skp * NN;
+    a.P = (p->K + skp - 1) / skp;
+    a.pitch = (uint32_t)p->N + 1u;
+    for (int k = 0; k < p->K; ++k) {
+      a.dx[k] = c.dx[k];
+      a.dy[k] = c.dy[k];
+      a.vcode[k] = c.dy[k] * (2 * smd + 1) + c.dx[k] + smd;
+    }
+    a.tmask = c.tmask;
+  } else if (path == kPathRows) {
     const uint32_t per = (uint32_t)p->K / (uint32_t)P + ((uint32_t)p->K % (uint32_t)P ? 1u : 0u);
     a.part_words = per * NN;
     a.P = (int)((p->K + per - 1) / per);
@@ -421,23 +478,31 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   // Row bands: as many workgroups per partition as the CUs hold at once
   // (limited by LDS and by 32 wavefronts per CU).
   const int rows = y_end - y_begin;
-  const int wg = t.wg_size;
+  const int wg = path == kPathStrips ? std::min(t.wg_size, glcm::strip_max_threads(b, smd)) : t.wg_size;
   const int nwaves = wg / 64;
   size_t lds_need = ((size_t)a.part_words << log2R) * 4u;
   if (path == kPathRows)
     lds_need = (size_t)(a.part_words / NN) * row_glcm_dwords(p->N, R, t.counter_bits == 16 ? 16 : 32) * 4u;
+  const int spans = (((W + 15) / 16) + 63) / 64;
+  if (path == kPathStrips)
+    lds_need = (size_t)(p->N + 1) * (size_t)(p->N + 1) * (size_t)skp * (size_t)sD * 4u;
   lds_need = std::max(lds_need, (size_t)wg * 4u);
   const int per_cu = std::max(1, std::min((int)(((size_t)p->lds_budget_words * 4u + 1024u) / lds_need), 32 / nwaves));
   int target_groups = std::max(1, p->num_cus * per_cu / a.P);
   int nregions = std::min(rows, target_groups);
+  // strip kernel: bands tall enough for strips of >= 4 rows on every wavefront
+  if (path == kPathStrips) nregions = std::max(1, std::min(nregions, rows * spans / (4 * nwaves)));
   // keep partials within 256 MiB
   while (nregions > 1 && (uint64_t)nregions * words * 4ull > (256ull << 20)) nregions = (nregions + 1) / 2;
   const int region_rows = (rows + nregions - 1) / nregions;
   nregions = (rows + region_rows - 1) / region_rows;
   a.nregions = nregions;
   a.region_rows = region_rows;
-  (void)nwaves;
   a.rows_per_wave = rpw;
+  if (path == kPathStrips) {
+    const int strips_per_span = std::max(1, nwaves / spans);
+    a.strip_rows = std::max(1, (region_rows + strips_per_span - 1) / strips_per_span);
+  }
 
   if (xcd) {
     a.xbuf = p->xbuf;
@@ -464,6 +529,16 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     a.pitch = row_pitch(p->N);
     lds_bytes = (size_t)(a.part_words / NN) * row_glcm_dwords(p->N, R, bits) * 4u;
   }
+  if (path == kPathStrips) {
+    // 16-bit counters only when no count can reach 2^16: a counter is shared
+    // by wg / (2D) lanes, each voting at most 16 pixels per row it walks
+    int bits = t.counter_bits == 16 ? 16 : 32;
+    const int nstrips = spans * ((region_rows + a.strip_rows - 1) / a.strip_rows);
+    const uint64_t rows_per_lane = (uint64_t)((nstrips + nwaves - 1) / nwaves) * (uint64_t)a.strip_rows;
+    if (bits == 16 && (uint64_t)wg / (2u * sD) * 16u * rows_per_lane > 65535u) bits = 32;  // same layout, one copy per dword
+    a.c16 = bits == 16 ? 1 : 0;
+    lds_bytes = lds_need;
+  }
   lds_bytes = std::max(lds_bytes, (size_t)wg * 4u);
 
   const int maxdy = c.maxdy <= 1 ? 1 : (c.maxdy <= 2 ? 2 : 4);
@@ -476,7 +551,9 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     GLCM_TRY(hipEventRecord(ev0, stream));
   }
   hipError_t e;
-  if (path == kPathRows) {
+  if (path == kPathStrips) {
+    e = glcm::launch_vote_strips(a, b, smd, sD, wg, lds_bytes, stream);
+  } else if (path == kPathRows) {
     e = glcm::launch_vote_rows(a, b, maxdy, rpw, wg, lds_bytes, stream);
   } else {
     e = glcm::launch_vote_generic(a, b, wg, lds_bytes, stream);
@@ -653,7 +730,12 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
     glcm_tuning_t& t = plan->tuning;
     if (n.counter_bits != 0 && n.counter_bits != 16 && n.counter_bits != 32) return GLCM_EINVAL;
     int bits = n.counter_bits == 0 ? t.counter_bits : n.counter_bits;
-    if (t.path == kPathRows) {
+    if (t.path == kPathStrips) {
+      if (n.rows_per_wave != 0) return GLCM_EINVAL;  // strips have no slab height
+      const int P = strip_partitions(plan, n.replicas, bits);
+      if (P == 0) return GLCM_EINVAL;
+      t.partitions = P;
+    } else if (t.path == kPathRows) {
       // partitions are groups of whole GLCMs; the copies must fit one
       if (bits == 16 && n.replicas < 2) return GLCM_EINVAL;
       if (n.rows_per_wave != 0 && n.rows_per_wave != 4) return GLCM_EINVAL;
@@ -700,7 +782,22 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
   // candidates: copies x counter width x workgroup size, within 4x the
   // minimal number of partitions
   std::vector<glcm_tuning_t> cand;
-  if (start.path == kPathRows) {
+  if (start.path == kPathStrips) {
+    const int Pmin = strip_partitions(plan, 4, 32);
+    for (int bits : {32, 16})
+      for (int R = 4; R <= 32; R *= 2) {
+        const int P = strip_partitions(plan, R, bits);
+        if (P == 0 || P > 4 * Pmin) continue;
+        for (int wg : {512, 1024}) {
+          glcm_tuning_t t = start;
+          t.replicas = R;
+          t.counter_bits = bits;
+          t.partitions = P;
+          t.wg_size = wg;
+          cand.push_back(t);
+        }
+      }
+  } else if (start.path == kPathRows) {
     const int Pmin = row_partitions(plan, 1, 32);
     for (int bits : {32, 16})
       for (int R = bits == 16 ? 2 : 1; R <= 64; R *= 2) {

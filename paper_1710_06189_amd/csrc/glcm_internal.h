@@ -10,6 +10,10 @@ constexpr int kMaxK = 64;
 // Accumulation slices for the per-XCD merge (an MI355X has 8 XCDs; the slice
 // is XCC_ID mod kXcdSlots, which stays one slice per XCD up to 16 XCDs).
 constexpr uint32_t kXcdSlots = 16;
+// GLCMs per partition of the strip kernel (its vote loop is unrolled over them).
+constexpr int kStripMaxKp = 4;
+// Threads per workgroup the strip kernel accepts for a pixel size and reach.
+constexpr int strip_max_threads(int pixel_bytes, int maxdy) { return pixel_bytes == 2 && maxdy == 2 ? 512 : 1024; }
 
 // Gray-level reduction q(v): 0 below lo, N-1 above hi, otherwise
 // floor(x / D) with x = (v - lo) * N and D = hi - lo + 1, evaluated as
@@ -42,6 +46,10 @@ struct VoteArgs {
   uint32_t pitch;             // row kernel: LDS row pitch of a GLCM, >= N + 1 (row/column N: sentinel)
   Quant div_n, div_nn;        // magic/shift for dividing by N and by N*N (only those fields used)
   int c16;                    // row kernel: 16-bit counters, two copies per dword
+  int kp;                     // strip kernel: GLCMs per partition (LDS layout stride, <= 4)
+  int strip_rows;             // strip kernel: first-pixel rows per wavefront strip
+  int32_t vcode[kMaxK];       // strip kernel: dy * (2 MAXDY + 1) + dx + MAXDY of each canonical offset
+                              // (dwords: the kernel reads them with scalar loads)
   uint32_t* partials;         // [nregions][words_total] per-band counts (band-partial merge)
   uint32_t* xbuf;             // [kXcdSlots][words_total] per-XCD accumulators, or null
   uint32_t* out;              // global-atomic kernel: [words_total] counts, zeroed beforehand
@@ -51,6 +59,9 @@ struct VoteArgs {
 hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream);
 hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
                             hipStream_t stream);
+// D = dwords per bin (4, 8 or 16), maxdy = 1 or 2.
+hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
+                              hipStream_t stream);
 // out[w] = (accumulate ? out[w] : 0) + sum_b partials[b * M + w] for w < M.
 hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, int nbands, bool accumulate,
                          hipStream_t stream);

@@ -456,6 +456,269 @@ __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Strip kernel: the fast path for aligned images, N <= 255 and offsets with
+// 0 <= dy <= MAXDY and |dx| <= MAXDY (MAXDY <= 2) after canonicalisation.
+//
+// A wavefront owns a strip: 64 lanes x 16-pixel chunks (1024 columns) and a
+// run of consecutive first-pixel rows.  It walks down the strip keeping the
+// MAXDY + 1 rows that pairs starting on the current row can reach, each pixel
+// already turned into its share of an LDS address, and prefetches the rows
+// below while it votes, so each pixel is read from memory once per strip.
+//
+// LDS layout of a partition (kp GLCMs): dword ((bin * kp + k) * D + g) holds
+// the copy g (lane mod D) of bin = a * n1 + b of the partition's k-th GLCM,
+// n1 = N + 1 (row and column N catch pixels outside the image).  Its byte
+// address splits as
+//     base(a) + term(b) + 4 D k,   term(v) = v * 4 D kp,   base(a) = 4 g + term(a) * n1,
+// so a vote costs one VALU add of a first-pixel base and a second-pixel term,
+// and 4 D k rides in the offset field of the LDS atomic.  The 16 lanes of a
+// quarter-wave (one LDS pass) use 16 distinct dwords of any bin when D >= 16.
+// ---------------------------------------------------------------------------
+template <int NX>
+struct TermRow {
+  uint32_t s[16 + 2 * NX];  // [NX left halo | 16 chunk pixels | NX right halo]
+};
+
+// Loads of one row of a strip lane: its 16-pixel chunk and 4-pixel halo
+// blocks on both sides.  Every lane issues the same loads with addresses
+// clamped into the image (the row below the last, a chunk past the right
+// edge or a halo before column 0 read some other pixels of the image, which
+// to_terms replaces by the sentinel), so the number of loads in flight is the
+// same on every path and the prefetch needs no full wait.
+template <typename Pix>
+__device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0) {
+  const Pix* row = (const Pix*)a.img + (int64_t)min(y, a.H - 1) * a.stride;
+  const int xc = min(x0, (a.W - 1) & ~15);           // a chunk that starts inside the row
+  const int xl = x0 >= 16 ? x0 - 4 : 0;
+  const int xr = x0 + 16 < a.W ? x0 + 16 : xc;
+  rc.v[0] = *(const uint4*)(row + xc);
+  if (sizeof(Pix) == 1) {
+    rc.lh[0] = *(const uint32_t*)(row + xl);
+    rc.rh[0] = *(const uint32_t*)(row + xr);
+  } else {
+    // the second 8 pixels only when they start inside the row (the pitch is
+    // a multiple of 8 pixels, not necessarily of 16)
+    rc.v[sizeof(Pix) - 1] = *(const uint4*)(row + (xc + 8 < a.W ? xc + 8 : xc));
+    const uint2 l = *(const uint2*)(row + xl), r = *(const uint2*)(row + xr);
+    rc.lh[0] = l.x; rc.lh[sizeof(Pix) - 1] = l.y;
+    rc.rh[0] = r.x; rc.rh[sizeof(Pix) - 1] = r.y;
+  }
+}
+
+// Raw row -> per-pixel address terms (level * mb), sentinel level N outside
+// the image.  Halo pixels come from the neighbouring lanes; the wave-boundary
+// lanes use the halo dwords they loaded themselves.
+template <typename Pix, int NX>
+__device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0,
+                                         int lane, uint32_t sent4, uint32_t mb) {
+  uint32_t c[4], lh, rh;
+  if (sizeof(Pix) == 1) {
+    c[0] = quant4_u8(rc.v[0].x, a); c[1] = quant4_u8(rc.v[0].y, a);
+    c[2] = quant4_u8(rc.v[0].z, a); c[3] = quant4_u8(rc.v[0].w, a);
+    lh = quant4_u8(rc.lh[0], a);
+    rh = quant4_u8(rc.rh[0], a);
+  } else {
+    c[0] = quant4_u16(rc.v[0].x, rc.v[0].y, a); c[1] = quant4_u16(rc.v[0].z, rc.v[0].w, a);
+    c[2] = quant4_u16(rc.v[sizeof(Pix) - 1].x, rc.v[sizeof(Pix) - 1].y, a);
+    c[3] = quant4_u16(rc.v[sizeof(Pix) - 1].z, rc.v[sizeof(Pix) - 1].w, a);
+    lh = quant4_u16(rc.lh[0], rc.lh[sizeof(Pix) - 1], a);
+    rh = quant4_u16(rc.rh[0], rc.rh[sizeof(Pix) - 1], a);
+  }
+  if (y >= a.H) {
+    c[0] = c[1] = c[2] = c[3] = lh = rh = sent4;
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) c[m] = clip_dword(c[m], x0 + 4 * m, a.W, sent4);
+    lh = x0 >= 16 ? clip_dword(lh, x0 - 4, a.W, sent4) : sent4;
+    rh = clip_dword(rh, x0 + 16, a.W, sent4);
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) r.s[NX + t] = __umul24((c[t >> 2] >> ((t & 3) * 8)) & 0xffu, mb);
+#pragma unroll
+  for (int e = 0; e < NX; ++e) {
+    // pixel x0 - 1 - e is pixel 15 - e of the lane on the left; x0 + 16 + e is
+    // pixel e of the lane on the right (lanes 0 and 63 keep their own value)
+    const uint32_t own_l = __umul24((lh >> ((3 - e) * 8)) & 0xffu, mb);
+    const uint32_t own_r = __umul24((rh >> (e * 8)) & 0xffu, mb);
+    r.s[NX - 1 - e] = (uint32_t)__builtin_amdgcn_update_dpp((int)own_l, (int)r.s[NX + 15 - e], kDppWaveShr1, 0xf, 0xf, false);
+    r.s[NX + 16 + e] = (uint32_t)__builtin_amdgcn_update_dpp((int)own_r, (int)r.s[NX + e], kDppWaveShl1, 0xf, 0xf, false);
+  }
+  (void)lane;
+}
+
+// The 16 votes of one first-pixel row for offset (DX, dy): second pixel of
+// chunk pixel t is ring pixel NX + t + DX.
+// (fa[t] holds the LDS byte address of the first pixel's bin row, LDS base
+// included, so the vote is one add; KOFF lands in the instruction's offset.)
+typedef __attribute__((address_space(3))) uint32_t lds_word_t;
+
+__device__ __forceinline__ uint32_t lds_address(const uint32_t* p) {
+  return (uint32_t)(size_t)(const lds_word_t*)p;
+}
+
+template <int NX, int DX, uint32_t KOFF>
+__device__ __forceinline__ void vote_row(const uint32_t (&fa)[16], const TermRow<NX>& second, uint32_t inc) {
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const uint32_t addr = fa[t] + second.s[NX + t + DX];
+    __hip_atomic_fetch_add((lds_word_t*)(size_t)(addr + KOFF), inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Votes of the partition's GLCM number KI (compile time, so its LDS offset is
+// an immediate) for first-pixel row `cur` of the ring.
+template <int MAXDY, int D, int KI, int CUR>
+__device__ __forceinline__ void vote_glcm(const uint32_t (&fa)[16],
+                                          const TermRow<MAXDY> (&ring)[MAXDY + 1], int code, uint32_t inc) {
+  constexpr int NR = MAXDY + 1, NXS = 2 * MAXDY + 1;
+  constexpr uint32_t KOFF = 4u * D * KI;
+  // code = dy * (2 MAXDY + 1) + dx + MAXDY
+  // (the asm marker keeps the compiler from merging the cases into one body
+  // that would index the ring through memory)
+#define GLCM_STRIP_CASE(DY, DX)                                                                   \
+  case (DY) * NXS + (DX) + MAXDY:                                                                 \
+    vote_row<MAXDY, (DX), KOFF>(fa, ring[(CUR + (DY)) % NR], inc);                               \
+    asm volatile("; strip offset dy=" #DY " dx=" #DX);                                            \
+    break;
+  switch (code) {
+    GLCM_STRIP_CASE(0, 0) GLCM_STRIP_CASE(0, 1) GLCM_STRIP_CASE(1, -1) GLCM_STRIP_CASE(1, 0) GLCM_STRIP_CASE(1, 1)
+    default:
+      if constexpr (MAXDY >= 2) {
+        switch (code) {
+          GLCM_STRIP_CASE(0, 2) GLCM_STRIP_CASE(1, -2) GLCM_STRIP_CASE(1, 2)
+          GLCM_STRIP_CASE(2, -2) GLCM_STRIP_CASE(2, -1) GLCM_STRIP_CASE(2, 0) GLCM_STRIP_CASE(2, 1) GLCM_STRIP_CASE(2, 2)
+          default: break;  // the host launches only canonical offsets within reach
+        }
+      }
+      break;
+  }
+#undef GLCM_STRIP_CASE
+}
+
+// One first-pixel row of a strip: bases, votes of every GLCM of the
+// partition, then the ring slot of this row takes the row NR below (from the
+// prefetched raw row) and the raw slot starts loading the row 2 NR below.
+template <typename Pix, int MAXDY, int D, int CUR>
+__device__ __forceinline__ void strip_step(const VoteArgs& a, TermRow<MAXDY> (&ring)[MAXDY + 1],
+                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, int lane, uint32_t C,
+                                           uint32_t n1, uint32_t mb, uint32_t inc, uint32_t sent4,
+                                           const int (&code)[4], int kp) {
+  constexpr int NR = MAXDY + 1;
+  uint32_t fa[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) fa[t] = __umul24(ring[CUR].s[MAXDY + t], n1) + C;
+  vote_glcm<MAXDY, D, 0, CUR>(fa, ring, code[0], inc);
+  if (kp > 1) vote_glcm<MAXDY, D, 1, CUR>(fa, ring, code[1], inc);
+  if (kp > 2) vote_glcm<MAXDY, D, 2, CUR>(fa, ring, code[2], inc);
+  if (kp > 3) vote_glcm<MAXDY, D, 3, CUR>(fa, ring, code[3], inc);
+  to_terms<Pix, MAXDY>(ring[CUR], raw[CUR], a, y + NR, x0, lane, sent4, mb);
+  load_row<Pix>(raw[CUR], a, y + 2 * NR, x0);
+}
+
+// Merge of the strip layout: lanes read consecutive 16-byte units (D / 4
+// lanes per GLCM bin), add them up across those lanes, and the first lane of
+// each bin adds the sum to the per-XCD accumulator (or stores it to the band
+// partial), transposed for offsets that were negated.
+template <int D>
+__device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int region, int kp0, int kp,
+                                     uint32_t n1) {
+  constexpr uint32_t QPB = D / 4;  // 16-byte units per bin
+  __syncthreads();
+  const uint32_t N = a.q.nlev, NN = N * N;
+  const uint32_t units = n1 * n1 * (uint32_t)a.kp * QPB;
+  uint32_t* dst = a.partials + (size_t)region * a.words_total;
+  uint32_t xcc = 0;
+  if (a.xbuf) asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+  uint32_t* xs = a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total;
+  for (uint32_t u = threadIdx.x; u < units; u += blockDim.x) {
+    const uint4 v = ((const uint4*)lds)[u];
+    uint32_t s = a.c16 ? (v.x & 0xffffu) + (v.x >> 16) + (v.y & 0xffffu) + (v.y >> 16) + (v.z & 0xffffu) +
+                             (v.z >> 16) + (v.w & 0xffffu) + (v.w >> 16)
+                       : (v.x + v.y) + (v.z + v.w);
+    if (QPB >= 2) s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0xb1, 0xf, 0xf, false);  // quad [1,0,3,2]
+    if (QPB >= 4) s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x4e, 0xf, 0xf, false);  // quad [2,3,0,1]
+    if (u % QPB != 0) continue;
+    const uint32_t blk = u / QPB, k = blk % (uint32_t)a.kp, bin = blk / (uint32_t)a.kp;
+    const uint32_t i = bin / n1, j = bin % n1;
+    if ((int)k >= kp || i >= N || j >= N) continue;
+    const uint32_t kg = (uint32_t)kp0 + k;
+    const bool tr = (a.tmask >> kg) & 1ull;
+    const uint32_t w = kg * NN + (tr ? j * N + i : i * N + j);
+    if (a.xbuf) {
+      if (s) __hip_atomic_fetch_add(xs + w, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      dst[w] = s;
+    }
+  }
+}
+
+// (uint16 pixels with a reach of 2 need more than the 128 registers a
+// 1024-thread workgroup leaves a lane: that variant takes at most 512 threads,
+// as strip_max_threads tells the host)
+template <typename Pix, int MAXDY, int D>
+__global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k_vote_strips(VoteArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  constexpr int NR = MAXDY + 1;
+  const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
+  const int kp0 = part * a.kp, kp = min(a.kp, a.K - kp0);
+  const uint32_t N = a.q.nlev, n1 = a.pitch;
+  const uint32_t mb = 4u * D * (uint32_t)a.kp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t g = threadIdx.x & (D - 1u);
+  const uint32_t C = lds_address(lds) + 4u * g;
+  const uint32_t inc = a.c16 ? (1u << (16u * ((threadIdx.x / D) & 1u))) : 1u;
+  const uint32_t sent4 = N * 0x01010101u;
+  const int y0 = a.y_begin + region * a.region_rows;
+  const int y1 = min(a.y_end, y0 + a.region_rows);
+  const int chunks = (a.W + 15) >> 4;
+  const int spans = (chunks + 63) >> 6;
+  const int rows = max(0, y1 - y0);
+  const int per_span = (rows + a.strip_rows - 1) / a.strip_rows;
+  const int nstrips = spans * per_span;
+  // offset codes of this partition, read once (scalar loads)
+  int code[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) code[q] = q < kp ? __builtin_amdgcn_readfirstlane(a.vcode[kp0 + q]) : -1;
+
+  TermRow<MAXDY> ring[NR];
+  RawChunk<Pix> raw[NR];
+  // the first strip's loads go out before the LDS is cleared
+  int strip = wave;
+  if (strip < nstrips) {
+    const int x0 = (((strip % spans) << 6) + lane) << 4, ya = y0 + (strip / spans) * a.strip_rows;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], a, ya + r, x0);
+  }
+  zero_lds(lds, n1 * n1 * (uint32_t)a.kp * D);
+  __syncthreads();
+
+  for (; strip < nstrips; strip += nwaves) {
+    const int x0 = (((strip % spans) << 6) + lane) << 4;
+    const int ya = y0 + (strip / spans) * a.strip_rows;
+    const int yb = min(y1, ya + a.strip_rows);
+    if (strip != wave) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], a, ya + r, x0);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      to_terms<Pix, MAXDY>(ring[r], raw[r], a, ya + r, x0, lane, sent4, mb);
+      load_row<Pix>(raw[r], a, ya + NR + r, x0);
+    }
+    for (int y = ya; y < yb; y += NR) {
+      strip_step<Pix, MAXDY, D, 0>(a, ring, raw, y, x0, lane, C, n1, mb, inc, sent4, code, kp);
+      if (y + 1 >= yb) break;
+      strip_step<Pix, MAXDY, D, 1>(a, ring, raw, y + 1, x0, lane, C, n1, mb, inc, sent4, code, kp);
+      if constexpr (NR > 2) {
+        if (y + 2 >= yb) break;
+        strip_step<Pix, MAXDY, D, 2>(a, ring, raw, y + 2, x0, lane, C, n1, mb, inc, sent4, code, kp);
+      }
+    }
+  }
+  store_partial_strips<D>(a, lds, region, kp0, kp, n1);
+}
+
+// ---------------------------------------------------------------------------
 // Haralick statistics: one workgroup per GLCM.  Exact integer sums for the
 // contrast numerator and the correlation moments; fp32 for energy, entropy and
 // homogeneity; fp64 (from exact 128-bit integers) for the correlation.
@@ -574,6 +837,28 @@ hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int r
   if (rpw != 4) return hipErrorInvalidValue;
   return dtype_bytes == 1 ? launch_rows_t<uint8_t>(a, maxdy, wg, lds_bytes, stream)
                           : launch_rows_t<uint16_t>(a, maxdy, wg, lds_bytes, stream);
+}
+
+template <typename Pix, int MAXDY>
+static hipError_t launch_strips_t(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream) {
+  const dim3 grid(a.nregions * a.P), block(wg);
+  switch (D) {
+    case 4: return launch(k_vote_strips<Pix, MAXDY, 4>, a, grid, block, lds_bytes, stream);
+    case 8: return launch(k_vote_strips<Pix, MAXDY, 8>, a, grid, block, lds_bytes, stream);
+    case 16: return launch(k_vote_strips<Pix, MAXDY, 16>, a, grid, block, lds_bytes, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
+                              hipStream_t stream) {
+  if (maxdy == 1)
+    return dtype_bytes == 1 ? launch_strips_t<uint8_t, 1>(a, D, wg, lds_bytes, stream)
+                            : launch_strips_t<uint16_t, 1>(a, D, wg, lds_bytes, stream);
+  if (maxdy == 2)
+    return dtype_bytes == 1 ? launch_strips_t<uint8_t, 2>(a, D, wg, lds_bytes, stream)
+                            : launch_strips_t<uint16_t, 2>(a, D, wg, lds_bytes, stream);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, bool accumulate, hipStream_t stream) {

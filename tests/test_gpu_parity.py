@@ -91,7 +91,7 @@ def test_offsets_any(offs):
 
 @pytest.mark.parametrize("flags,name", [
     (G.FLAG_FORCE_GENERIC, "generic"), (G.FLAG_FORCE_PARTITIONED, "partitioned"),
-    (G.FLAG_FORCE_GLOBAL, "global"), (0, "auto"),
+    (G.FLAG_FORCE_GLOBAL, "global"), (G.FLAG_FORCE_SLABS, "slabs"), (0, "auto"),
 ])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 @pytest.mark.parametrize("merge", [0, 1])
@@ -109,28 +109,43 @@ def test_forced_paths(flags, name, dtype, merge):
         plan.close()
 
 
-@pytest.mark.parametrize("R,bits", [(1, 32), (2, 32), (4, 32), (8, 32), (16, 32), (2, 16), (4, 16), (8, 16),
-                                    (16, 16), (32, 16)])
+SLAB_LAYOUTS = [(1, 32), (2, 32), (4, 32), (8, 32), (16, 32), (2, 16), (4, 16), (8, 16), (16, 16), (32, 16)]
+STRIP_LAYOUTS = [(4, 32), (8, 32), (16, 32), (8, 16), (16, 16), (32, 16)]
+
+
+@pytest.mark.parametrize("kernel,R,bits", [("slabs", R, b) for R, b in SLAB_LAYOUTS] +
+                         [("strips", R, b) for R, b in STRIP_LAYOUTS])
 @pytest.mark.parametrize("wg", [256, 1024])
-def test_replica_counter_and_workgroup_sweep(R, bits, wg):
+def test_replica_counter_and_workgroup_sweep(kernel, R, bits, wg):
     img = synth.smooth(300, 2100, 8.0, 12)
     offs = synth.offsets_for([1])
-    plan = G.glcm_plan_create(np.uint8, 32, offs, 2100, 300)
+    plan = G.glcm_plan_create(np.uint8, 32, offs, 2100, 300, G.FLAG_FORCE_SLABS if kernel == "slabs" else 0)
     try:
+        assert G.PATH_NAMES[plan.tuning.path] == kernel
         t = plan.set_tuning(replicas=R, wg_size=wg, counter_bits=bits)
         assert t.replicas == R and t.wg_size == wg and t.counter_bits == bits
-        check(img, 32, 0, 255, offs, plan=plan, label=f"R={R} bits={bits} wg={wg} P={t.partitions}")
+        check(img, 32, 0, 255, offs, plan=plan, label=f"{kernel} R={R} bits={bits} wg={wg} P={t.partitions}")
+    finally:
+        plan.close()
+
+
+def test_strip_layout_rejects_unsupported_copies():
+    plan = G.glcm_plan_create(np.uint8, 32, [(1, 0)], 256, 256)
+    try:
+        for R, bits in [(1, 32), (2, 32), (32, 32), (4, 16), (64, 16)]:
+            with pytest.raises(G.GlcmError):
+                plan.set_tuning(replicas=R, counter_bits=bits)
     finally:
         plan.close()
 
 
 def test_sixteen_bit_counters_near_the_bound():
     """A constant image puts every vote of a copy into one bin: the largest
-    band the 16-bit counters accept, and one just beyond (falls back to 32)."""
+    band the 16-bit slab counters accept, and one just beyond (falls back to 32)."""
     for H in (4096, 8192):  # 16 and 32 slabs of 2048 same-bin votes per copy: 32768, then 65536
         img = synth.constant(H, 4096, 77)
         offs = synth.offsets_for([1])
-        plan = G.glcm_plan_create(np.uint8, 16, offs, 4096, H)
+        plan = G.glcm_plan_create(np.uint8, 16, offs, 4096, H, G.FLAG_FORCE_SLABS)
         try:
             plan.set_tuning(replicas=2, counter_bits=16)
             check(img, 16, 0, 255, offs, plan=plan, label=f"c16 bound H={H}")
@@ -138,25 +153,69 @@ def test_sixteen_bit_counters_near_the_bound():
             plan.close()
 
 
+@pytest.mark.parametrize("W,H", [(4096, 4096), (16, 8192), (1024, 65535)])
+def test_sixteen_bit_strip_counters_constant_image(W, H):
+    """Every vote of a 16-bit strip counter in one bin, on the tallest bands."""
+    img = synth.constant(H, W, 200)
+    offs = synth.offsets_for([1])
+    plan = G.glcm_plan_create(np.uint8, 16, offs, W, H)
+    try:
+        plan.set_tuning(replicas=8, counter_bits=16)
+        check(img, 16, 0, 255, offs, plan=plan, label=f"strips c16 constant {W}x{H}")
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("kernel,dists", [("slabs", [1, 2, 4]), ("strips", [1, 2]), ("strips", [1])])
 @pytest.mark.parametrize("H", [1, 2, 3, 4, 5, 7, 9, 255, 257, 1029])
-def test_band_heights(H):
-    """Heights that leave partial 4-row slabs and partial bands in the row kernel."""
+def test_band_heights(kernel, dists, H):
+    """Heights that leave partial slabs, strips and bands in the row kernels."""
     img = synth.uniform(H, 1500, 13 + H)
-    offs = synth.offsets_for([1, 2, 4])
+    offs = synth.offsets_for(dists)
     plan = G.glcm_plan_create(np.uint8, 8, offs, 1500, H)
     try:
-        assert G.PATH_NAMES[plan.tuning.path] == "rows"
-        check(img, 8, 0, 255, offs, plan=plan, label=f"H={H}")
+        assert G.PATH_NAMES[plan.tuning.path] == kernel
+        check(img, 8, 0, 255, offs, plan=plan, label=f"{kernel} d={dists} H={H}")
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("W", [1, 15, 16, 17, 1023, 1024, 1025, 2047, 3000])
+@pytest.mark.parametrize("dists", [[1], [2], [1, 2]])
+def test_strip_widths(W, dists):
+    """Widths around the 16-pixel chunk and 1024-pixel strip boundaries."""
+    img = synth.smooth(70, W, 3.0, 40 + W) if W > 2 else synth.uniform(70, W, 41)
+    offs = synth.offsets_for(dists) + [(0, 0), (-dists[-1], 0), (dists[-1], -dists[-1])]
+    check(img, 32, 0, 255, offs, label=f"strip widths W={W} d={dists}")
+
+
+@pytest.mark.parametrize("W", [8, 24, 40, 1032, 2056])
+def test_strip_u16_pitch_of_8_pixels(W):
+    """uint16 rows whose pitch is a multiple of 8 but not 16 pixels: aligned
+    for the strip kernel, with the last chunk ending inside the last row."""
+    img = synth.smooth(37, W, 2.5, 60 + W, np.uint16)
+    offs = synth.offsets_for([1, 2])
+    plan = G.glcm_plan_create(np.uint16, 64, offs, W, 37)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == "strips"
+        check(img, 64, 0, 65535, offs, plan=plan, label=f"u16 pitch W={W}")
     finally:
         plan.close()
 
 
 def test_rows_per_wave_knob():
-    plan = G.glcm_plan_create(np.uint8, 8, [(1, 0)], 64, 64)
+    plan = G.glcm_plan_create(np.uint8, 8, [(1, 0)], 64, 64, G.FLAG_FORCE_SLABS)
     try:
         assert plan.set_tuning(rows_per_wave=4).rows_per_wave == 4
         with pytest.raises(G.GlcmError):
             plan.set_tuning(rows_per_wave=3)
+    finally:
+        plan.close()
+    plan = G.glcm_plan_create(np.uint8, 8, [(1, 0)], 64, 64)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == "strips" and plan.tuning.rows_per_wave == 0
+        with pytest.raises(G.GlcmError):
+            plan.set_tuning(rows_per_wave=4)
     finally:
         plan.close()
 
