@@ -80,10 +80,11 @@ def main():
                     help="keep the plan's default layout instead of timing the candidates first")
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
-    ap.add_argument("--workload", default="square", choices=["square", "multispectral"],
+    ap.add_argument("--workload", default="square", choices=["square", "multispectral", "batch"],
                     help="square: the 4096^2 device-resident image (the default line); multispectral: "
                          "the 8-band 8192^2 uint16 stack streamed from pinned host memory")
     ap.add_argument("--bands", type=int, default=8)
+    ap.add_argument("--tiles", type=int, default=4096)
     ap.add_argument("--size", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -102,6 +103,9 @@ def main():
     dev = torch.device("cuda", 0)
     if args.workload == "multispectral":
         bench_multispectral(args, G, torch, np, oracle, synth, dev)
+        return
+    if args.workload == "batch":
+        bench_batch(args, G, torch, np, oracle, synth, dev)
         return
     oracle_cache, image_cache = {}, {}
     fixed = None
@@ -271,6 +275,71 @@ def call_latencies(G, torch, np, synth, dev, args, calls=200):
             "latency_calls": calls}
 
 
+def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
+    """4096 uint8 tiles (sides log-uniform in [32, 512], half noise, half
+    smooth), N = 16, d = 1 at four angles, counts plus the five statistics:
+    one fused launch for the whole batch against one glcm_compute +
+    glcm_features pair per tile on one stream.  The two must agree bit for
+    bit; 64 tiles are also checked against the oracle."""
+    w = synth.batch_tiles(args.tiles)
+    imgs, N, offs = w["images"], w["N"], w["offsets"]
+    T, K = len(imgs), len(offs)
+    print(f"[batch] {T} tiles generated", file=sys.stderr, flush=True)
+    tens = [torch.from_numpy(im).to(dev) for im in imgs]
+    pairs = sum(pairs_of(im.shape[1], im.shape[0], offs) for im in imgs)
+    px = sum(im.size for im in imgs)
+    plan = G.glcm_plan_create(np.uint8, N, offs, 512, 512)
+    out = torch.empty((T, K, N, N), dtype=torch.uint32, device=dev)
+    feats = torch.empty((T, K, 5), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        G.glcm_batch_compute(tens, plan, out=out, features=feats, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        G.glcm_batch_compute(tens, plan, out=out, features=feats, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_wall = (time.perf_counter() - t0) / reps
+    batch_dev = e0.elapsed_time(e1) * 1e-3 / reps
+    # one launch pair per tile
+    out1 = torch.empty_like(out)
+    feats1 = torch.empty_like(feats)
+    for t in range(min(T, 64)):
+        G.glcm_compute(tens[t], N, 0, 255, offs, out=out1[t], plan=plan, stream=stream)
+        G.glcm_features(out1[t], out=feats1[t], stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for t in range(T):
+        G.glcm_compute(tens[t], N, 0, 255, offs, out=out1[t], plan=plan, stream=stream)
+        G.glcm_features(out1[t], out=feats1[t], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per_wall = time.perf_counter() - t0
+    per_dev = e0.elapsed_time(e1) * 1e-3
+    plan.close()
+    a, b = out.view(torch.int32).cpu().numpy(), out1.view(torch.int32).cpu().numpy()
+    if not np.array_equal(a, b):
+        raise SystemExit("bench: batched counts differ from the per-image calls")
+    if not np.array_equal(feats.cpu().numpy(), feats1.cpu().numpy()):
+        raise SystemExit("bench: batched statistics differ from the per-image calls")
+    got = a.view(np.uint32)
+    for t in range(0, T, max(1, T // 64)):
+        if not np.array_equal(got[t], oracle.glcm(imgs[t], N, 0, 255, offs)):
+            raise SystemExit(f"bench: tile {t} differs from the oracle")
+    print(json.dumps({
+        "workload": w["name"], "tiles": T, "pixels": px, "pairs": pairs,
+        "batched_gpairs_s": pairs / batch_wall / 1e9, "batched_ms": batch_wall * 1e3,
+        "batched_device_ms": batch_dev * 1e3,
+        "per_image_gpairs_s": pairs / per_wall / 1e9, "per_image_ms": per_wall * 1e3,
+        "per_image_device_ms": per_dev * 1e3, "batched_over_per_image": per_wall / batch_wall,
+        "features": True, "check": "batched == per-image calls (counts and statistics); 64 tiles vs oracle"}),
+        flush=True)
+
+
 def bench_multispectral(args, G, torch, np, oracle, synth, dev):
     """8 bands of 8192^2 uint16 (N = 64 over [0, 65535], d in {1, 2, 4} x four
     angles): device-resident counting, the host-to-device copy alone, and the
@@ -324,8 +393,8 @@ def bench_multispectral(args, G, torch, np, oracle, synth, dev):
     torch.cuda.synchronize()
     c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     c0.record(stream)
-    for b in range(bands):
-        devs[b].copy_(hosts[b], non_blocking=True)
+    for b in range(bands):  # byte views: a plain DMA copy whatever the element type
+        devs[b].view(torch.uint8).copy_(hosts[b].view(torch.uint8), non_blocking=True)
     c1.record(stream)
     torch.cuda.synchronize()
     t_copy = c0.elapsed_time(c1) * 1e-3

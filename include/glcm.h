@@ -218,6 +218,44 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void *img, int W, int H, int64
  */
 GLCM_API int glcm_features(const uint32_t *glcm, int K, int N, float *out, void *stream);
 
+/* One device-resident image of a batch. */
+typedef struct glcm_tile {
+    const void *img;  /* device memory, row y at img + y*stride elements, aligned to the pixel size */
+    int64_t stride;   /* row pitch in elements, >= W */
+    int32_t W, H;     /* 1 <= W <= plan max_W, 1 <= H <= plan max_H */
+} glcm_tile_t;
+
+/*
+ * Computes the co-occurrence matrices of Eq. (1), and optionally their Haralick
+ * statistics, for T independent images in one launch: one workgroup per image
+ * fuses quantization, the pair visit, the LDS votes, the merge and the
+ * statistics (the per-image steps of Section II.A, applied to many small
+ * images at once).  Images are processed largest first; results land in the
+ * caller's order.
+ *
+ *   plan      a plan (its dtype, N, K and offsets apply to every image).  The
+ *             batch path needs K <= 4, offsets with |dx| <= 2 and |dy| <= 2, and
+ *             4 copies of the K (N+1) x (N+1) matrices in one workgroup's LDS
+ *             ((N+1)^2 * K * 16 bytes + 4 K N^2 + 3 KiB <= 159 KiB, e.g. N <= 43
+ *             for K = 4), else GLCM_EUNSUPPORTED; images need not be 16-byte
+ *             aligned (those that are not are counted per pixel).
+ *   tiles     host array of T image descriptors (read before returning).
+ *   T         number of images, 1 .. 2^20.
+ *   lo, hi    quantization range, as in glcm_compute.
+ *   out       device memory, T*K*N*N uint32: out[t][k][i][j], overwritten.
+ *   features  device memory, T*K*5 float (as glcm_features), or NULL.
+ *   stream    hipStream_t (as void*).
+ *
+ * Returns once the work is queued.  The plan's descriptor staging is reused
+ * by the next batch call after this one's upload has completed.  Errors:
+ * GLCM_EINVAL (nothing queued) for NULL pointers, T out of range, a tile with
+ * W or H < 1, W > max_W, H > max_H, stride < W, W*H > 2^32-1 or a misaligned
+ * img, lo > hi or hi above the dtype maximum; GLCM_EUNSUPPORTED as above;
+ * GLCM_EHIP / GLCM_ENOMEM on HIP failures while queueing.
+ */
+GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t *tiles, int T, uint32_t lo, uint32_t hi,
+                                uint32_t *out, float *features, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

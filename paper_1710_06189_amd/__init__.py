@@ -31,7 +31,7 @@ __all__ = [
     "glcm_offset_polar", "glcm_plan_create", "glcm_plan_destroy", "glcm_plan_tuning", "glcm_plan_autotune",
     "glcm_compute",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
-    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "PATH_NAMES", "glcm_plan_kernel_time",
+    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "glcm_batch_compute", "Tile", "PATH_NAMES", "glcm_plan_kernel_time",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -61,6 +61,10 @@ class GlcmError(RuntimeError):
 
 class Offset(ctypes.Structure):
     _fields_ = [("dx", ctypes.c_int32), ("dy", ctypes.c_int32)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("stride", ctypes.c_int64), ("W", ctypes.c_int32), ("H", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -107,6 +111,8 @@ def _lib():
         lib.glcm_compute.argtypes = [vp, vp, i32, i32, i64, i32, i32, u32, u32, ctypes.POINTER(Offset), i32, vp, vp]
         lib.glcm_features.restype = i32
         lib.glcm_features.argtypes = [vp, i32, i32, vp, vp]
+        lib.glcm_batch_compute.restype = i32
+        lib.glcm_batch_compute.argtypes = [vp, ctypes.POINTER(Tile), i32, u32, u32, vp, vp, vp]
         _L = lib
     return _L
 
@@ -294,3 +300,44 @@ def glcm_features(P, out=None, stream=None):
     _check(_lib().glcm_features(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()), s),
            "glcm_features")
     return out
+
+
+def glcm_batch_compute(images, plan, lo=0, hi=None, out=None, features=True, stream=None):
+    """Counts (and statistics) of many device images in one launch.
+
+    `images`: sequence of 2-D CUDA tensors (uint8 or uint16, the plan's dtype),
+    any sizes up to the plan's max_W x max_H.  Returns (out [T, K, N, N]
+    uint32, feats [T, K, 5] float32 or None)."""
+    T = len(images)
+    if T < 1:
+        raise ValueError("images must not be empty")
+    tiles = (Tile * T)()
+    keep = []
+    dev = None
+    for i, img in enumerate(images):
+        if not (isinstance(img, torch.Tensor) and img.is_cuda):
+            raise ValueError("batch images must be CUDA tensors")
+        ptr, W, H, stride, dt, k = _image_args(img)
+        if dt != plan.dtype:
+            raise ValueError("image dtype differs from the plan's")
+        tiles[i] = Tile(ptr, stride, W, H)
+        keep.append(k)
+        dev = img.device
+    if hi is None:
+        hi = 255 if plan.dtype == U8 else 65535
+    K, N = len(plan.offsets), plan.N
+    if out is None:
+        out = torch.empty((T, K, N, N), dtype=torch.uint32, device=dev)
+    elif not (out.is_cuda and out.is_contiguous() and out.numel() == T * K * N * N and out.element_size() == 4):
+        raise ValueError("out must be a contiguous CUDA tensor of T*K*N*N 32-bit elements")
+    feats = None
+    if features is True:
+        feats = torch.empty((T, K, 5), dtype=torch.float32, device=dev)
+    elif isinstance(features, torch.Tensor):
+        feats = features
+    s = _stream_handle(stream)
+    _check(_lib().glcm_batch_compute(plan.handle, tiles, T, int(lo), int(hi), ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(feats.data_ptr()) if feats is not None else None, s),
+           "glcm_batch_compute")
+    del keep
+    return out, feats

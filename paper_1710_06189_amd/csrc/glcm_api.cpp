@@ -33,6 +33,12 @@ int hip_status(hipError_t e) {
     if (e_ != hipSuccess) return hip_status(e_); \
   } while (0)
 
+#define GLCM_TRY_RC(expr)          \
+  do {                             \
+    const int rc_ = (expr);        \
+    if (rc_ != GLCM_OK) return rc_; \
+  } while (0)
+
 constexpr uint32_t kKnownFlags = GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED |
                                  GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD | GLCM_FLAG_TIMING |
                                  GLCM_FLAG_FORCE_SLABS;
@@ -87,6 +93,22 @@ glcm::Quant make_quant(int N, uint32_t lo, uint32_t hi) {
   q.magic = (uint32_t)(m - (1ull << 32));
   q.shift = s;
   return q;
+}
+
+// The shift form of q(): lo = 0, hi = dtype max and N a power of two give
+// level = pixel >> (bits - log2 N), applied to 4 packed u8 / 2 packed u16.
+void fast_quant(int b, int N, uint32_t lo, uint32_t hi, int* on, uint32_t* shift, uint32_t* mask) {
+  const uint32_t top = b == 1 ? 255u : 65535u, bits = b == 1 ? 8u : 16u;
+  uint32_t n = 0;
+  while ((1u << n) < (uint32_t)N) ++n;
+  *on = 0;
+  *shift = 0;
+  *mask = 0;
+  if (lo == 0 && hi == top && (1u << n) == (uint32_t)N && n <= bits) {
+    *on = 1;
+    *shift = bits - n;
+    *mask = b == 1 ? (0xffu >> *shift) * 0x01010101u : (0xffffu >> *shift) * 0x00010001u;
+  }
 }
 
 // Offsets as the row kernel wants them: dy >= 0 (and dx >= 0 when dy == 0);
@@ -170,6 +192,13 @@ struct glcm_plan_s {
   hipEvent_t uploaded[kSlots] = {nullptr, nullptr};
   bool pin_pending[kSlots] = {false, false};  // a staging slot's upload may still be running
   hipEvent_t consumed[kSlots] = {nullptr, nullptr};
+
+  // batch descriptors: pinned staging and its device copy
+  void* batch_pin = nullptr;
+  void* batch_dev = nullptr;
+  size_t batch_cap = 0;
+  hipEvent_t batch_uploaded = nullptr;
+  bool batch_pending = false;
 
   // GLCM_FLAG_TIMING: events around every counting-kernel launch
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
@@ -332,6 +361,10 @@ void plan_release(glcm_plan_t p) {
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   if (p->partials) (void)hipFree(p->partials);
   if (p->xbuf) (void)hipFree(p->xbuf);
+  if (p->batch_pending) (void)hipEventSynchronize(p->batch_uploaded);
+  if (p->batch_pin) (void)hipHostFree(p->batch_pin);
+  if (p->batch_dev) (void)hipFree(p->batch_dev);
+  if (p->batch_uploaded) (void)hipEventDestroy(p->batch_uploaded);
 
   if (p->done) (void)hipEventDestroy(p->done);
   for (auto& ev : p->timing) {
@@ -390,16 +423,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   // D = d and the same division constants
   a.div_n = make_quant(1, 0, (uint32_t)p->N - 1);
   a.div_nn = make_quant(1, 0, NN - 1);
-  {
-    const uint32_t top = b == 1 ? 255u : 65535u, bits = b == 1 ? 8u : 16u;
-    uint32_t n = 0;
-    while ((1u << n) < (uint32_t)p->N) ++n;
-    if (lo == 0 && hi == top && (1u << n) == (uint32_t)p->N && n <= bits) {
-      a.qfast = 1;
-      a.qfast_shift = bits - n;
-      a.qfast_mask = b == 1 ? (0xffu >> a.qfast_shift) * 0x01010101u : (0xffffu >> a.qfast_shift) * 0x00010001u;
-    }
-  }
+  fast_quant(b, p->N, lo, hi, &a.qfast, &a.qfast_shift, &a.qfast_mask);
   a.K = p->K;
   a.words_total = words;
   a.out = out;
@@ -945,6 +969,88 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void* img, int W, int H, int64
     rc = count_host(plan, img, kind == 1, W, H, stride, lo, hi, out, stream);
   }
   if (rc != GLCM_OK) return rc;
+  return record_done(plan, stream);
+}
+
+GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
+                                uint32_t* out, float* features, void* stream_) {
+  if (!plan || !tiles || !out || T < 1 || T > (1 << 20)) return GLCM_EINVAL;
+  const int b = dtype_bytes(plan->dtype);
+  if (lo > hi || hi > (b == 1 ? 255u : 65535u)) return GLCM_EINVAL;
+  for (int t = 0; t < T; ++t) {
+    const glcm_tile_t& e = tiles[t];
+    if (!e.img || e.W < 1 || e.H < 1 || e.W > plan->max_W || e.H > plan->max_H || e.stride < e.W) return GLCM_EINVAL;
+    if ((uint64_t)e.W * (uint64_t)e.H > 0xffffffffull || ((uintptr_t)e.img % (uintptr_t)b)) return GLCM_EINVAL;
+  }
+  int dev = -1;
+  if (pointer_kind(out, &dev) != 2) return GLCM_EINVAL;
+  if (features && pointer_kind(features, &dev) != 2) return GLCM_EINVAL;
+  const Canon c = canonicalize(plan->offsets, plan->K);
+  if (plan->N > 255 || plan->K > glcm::kStripMaxKp || c.maxdy > 2 || c.maxadx > 2) return GLCM_EUNSUPPORTED;
+  hipStream_t stream = (hipStream_t)stream_;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  // LDS layout: the most dwords per bin that leave room for three workgroups
+  // per CU (their loads and merges then overlap other workgroups' votes)
+  const size_t lds_cu = (size_t)plan->lds_budget_words * 4u + 1024u;
+  int D = 16;
+  while (D > 4 && glcm::batch_lds_bytes(plan->N, plan->K, D) * 3u > lds_cu) D /= 2;
+  const size_t lds_bytes = glcm::batch_lds_bytes(plan->N, plan->K, D);
+  if (lds_bytes > lds_cu - 1024u) return GLCM_EUNSUPPORTED;
+  GLCM_TRY_RC(order_after_previous(plan, stream));
+  // descriptors, largest image first
+  const size_t need = (size_t)T * sizeof(glcm::BatchTile);
+  if (plan->batch_pending) GLCM_TRY(hipEventSynchronize(plan->batch_uploaded));
+  plan->batch_pending = false;
+  if (need > plan->batch_cap) {
+    if (plan->batch_pin) GLCM_TRY(hipHostFree(plan->batch_pin));
+    if (plan->batch_dev) {
+      if (plan->has_done) GLCM_TRY(hipEventSynchronize(plan->done));  // the last batch may still read it
+      GLCM_TRY(hipFree(plan->batch_dev));
+    }
+    plan->batch_pin = plan->batch_dev = nullptr;
+    plan->batch_cap = 0;
+    GLCM_TRY(hipHostMalloc(&plan->batch_pin, need, hipHostMallocDefault));
+    GLCM_TRY(hipMalloc(&plan->batch_dev, need));
+    plan->batch_cap = need;
+  }
+  if (!plan->batch_uploaded) GLCM_TRY(hipEventCreateWithFlags(&plan->batch_uploaded, hipEventDisableTiming));
+  std::vector<int> order((size_t)T);
+  for (int t = 0; t < T; ++t) order[(size_t)t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (uint64_t)tiles[x].W * (uint64_t)tiles[x].H > (uint64_t)tiles[y].W * (uint64_t)tiles[y].H;
+  });
+  glcm::BatchTile* d = (glcm::BatchTile*)plan->batch_pin;
+  for (int i = 0; i < T; ++i) {
+    const glcm_tile_t& e = tiles[order[(size_t)i]];
+    d[i].img = e.img;
+    d[i].stride = e.stride;
+    d[i].W = e.W;
+    d[i].H = e.H;
+    d[i].index = order[(size_t)i];
+    d[i].aligned = ((uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0) ? 1 : 0;
+  }
+  GLCM_TRY(hipMemcpyAsync(plan->batch_dev, plan->batch_pin, need, hipMemcpyHostToDevice, stream));
+  GLCM_TRY(hipEventRecord(plan->batch_uploaded, stream));
+  plan->batch_pending = true;
+
+  glcm::BatchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.q = make_quant(plan->N, lo, hi);
+  fast_quant(b, plan->N, lo, hi, &a.qfast, &a.qfast_shift, &a.qfast_mask);
+  a.K = plan->K;
+  const int smd = std::max(c.maxdy, c.maxadx) <= 1 ? 1 : 2;
+  for (int k = 0; k < plan->K; ++k) {
+    a.dx[k] = plan->offsets[k].dx;
+    a.dy[k] = plan->offsets[k].dy;
+    a.vcode[k] = c.dy[k] * (2 * smd + 1) + c.dx[k] + smd;
+  }
+  a.tmask = c.tmask;
+  a.pitch = (uint32_t)plan->N + 1u;
+  a.min_rows = 8;
+  a.tiles = (const glcm::BatchTile*)plan->batch_dev;
+  a.out = out;
+  a.feat = features;
+  GLCM_TRY(glcm::launch_batch(a, T, b, smd, D, lds_bytes, stream));
   return record_done(plan, stream);
 }
 

@@ -55,6 +55,32 @@ struct VoteArgs {
   uint32_t* out;              // global-atomic kernel: [words_total] counts, zeroed beforehand
 };
 
+// One image of a batch as the batch kernel reads it (device memory, 32 bytes).
+struct BatchTile {
+  const void* img;  // device pixels, row y at img + y * stride elements
+  int64_t stride;   // elements
+  int32_t W, H;
+  int32_t index;    // slot of this image in the caller's order (output position)
+  int32_t aligned;  // 1: 16-byte aligned base and row pitch (strip loads), 0: per-pixel loads
+};
+
+// Arguments of the fused batch kernel (quantize, vote, merge, features per
+// image).  The quantizer fields match VoteArgs so the row helpers take either.
+struct BatchArgs {
+  Quant q;
+  int qfast;
+  uint32_t qfast_shift, qfast_mask;
+  int K;                               // offsets, <= kStripMaxKp
+  int32_t dx[kStripMaxKp], dy[kStripMaxKp];  // offsets as given (per-pixel path)
+  int32_t vcode[kStripMaxKp];          // canonical codes (strip path), as in VoteArgs
+  unsigned long long tmask;            // bit k: offset k counted as its opposite, stored transposed
+  uint32_t pitch;                      // N + 1
+  int min_rows;                        // shortest row segment a lane walks
+  const BatchTile* tiles;              // [T], largest first
+  uint32_t* out;                       // [T][K][N][N]
+  float* feat;                         // [T][K][5] or null
+};
+
 // Launchers (all asynchronous on `stream`; return the launch error).
 hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream);
 hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
@@ -69,5 +95,15 @@ hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, in
 hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, bool accumulate, hipStream_t stream);
 hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream);
 hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream);
+// One workgroup per image of the batch (T images); D = dwords per bin (4, 8
+// or 16), maxdy = 1 or 2.  lds_bytes from batch_lds_bytes().
+hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, size_t lds_bytes,
+                        hipStream_t stream);
+constexpr int kBatchThreads = 256;
+inline size_t batch_lds_bytes(int N, int K, int D) {
+  const size_t n1 = (size_t)N + 1u;
+  // vote copies, merged counts, 8-byte alignment pad, u64 + f32 reduction scratch
+  return (n1 * n1 * (size_t)K * (size_t)D + (size_t)K * N * N) * 4u + 8u + (size_t)kBatchThreads * 12u;
+}
 
 }  // namespace glcm

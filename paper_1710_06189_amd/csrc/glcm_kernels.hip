@@ -257,15 +257,18 @@ __device__ __forceinline__ uint32_t pack4(uint32_t l0, uint32_t l1, uint32_t l2,
   return l0 | (l1 << 8) | (l2 << 16) | (l3 << 24);
 }
 
-// Four packed 8-bit pixels -> four packed levels.
-__device__ __forceinline__ uint32_t quant4_u8(uint32_t raw, const VoteArgs& a) {
+// Four packed 8-bit pixels -> four packed levels (QA: any argument struct with
+// the quantizer fields q, qfast, qfast_shift, qfast_mask).
+template <class QA>
+__device__ __forceinline__ uint32_t quant4_u8(uint32_t raw, const QA& a) {
   if (a.qfast) return (raw >> a.qfast_shift) & a.qfast_mask;
   return pack4(quantize(raw & 0xffu, a.q), quantize((raw >> 8) & 0xffu, a.q), quantize((raw >> 16) & 0xffu, a.q),
                quantize(raw >> 24, a.q));
 }
 
 // Four 16-bit pixels (two dwords) -> four packed levels.
-__device__ __forceinline__ uint32_t quant4_u16(uint32_t lo2, uint32_t hi2, const VoteArgs& a) {
+template <class QA>
+__device__ __forceinline__ uint32_t quant4_u16(uint32_t lo2, uint32_t hi2, const QA& a) {
   if (a.qfast) {
     const uint32_t l = (lo2 >> a.qfast_shift) & a.qfast_mask;  // levels in bits 0..7 and 16..23
     const uint32_t h = (hi2 >> a.qfast_shift) & a.qfast_mask;
@@ -485,8 +488,14 @@ struct TermRow {
 // edge or a halo before column 0 read some other pixels of the image, which
 // to_terms replaces by the sentinel), so the number of loads in flight is the
 // same on every path and the prefetch needs no full wait.
+struct Geom {
+  const void* img;  // 16-byte aligned, row pitch a multiple of 16 bytes
+  int64_t stride;   // elements
+  int W, H;
+};
+
 template <typename Pix>
-__device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0) {
+__device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y, int x0) {
   const Pix* row = (const Pix*)a.img + (int64_t)min(y, a.H - 1) * a.stride;
   const int xc = min(x0, (a.W - 1) & ~15);           // a chunk that starts inside the row
   const int xl = x0 >= 16 ? x0 - 4 : 0;
@@ -507,10 +516,12 @@ __device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const VoteArgs& a, i
 
 // Raw row -> per-pixel address terms (level * mb), sentinel level N outside
 // the image.  Halo pixels come from the neighbouring lanes; the wave-boundary
-// lanes use the halo dwords they loaded themselves.
-template <typename Pix, int NX>
-__device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0,
-                                         int lane, uint32_t sent4, uint32_t mb) {
+// lanes use the halo dwords they loaded themselves.  SEG: a wavefront holds
+// several row segments side by side, so a halo pixel outside [0, W) takes the
+// sentinel whatever the neighbouring lane holds.
+template <typename Pix, int NX, bool SEG = false, class QA>
+__device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc, const QA& a, const Geom& g, int y,
+                                         int x0, uint32_t sent4, uint32_t mb) {
   uint32_t c[4], lh, rh;
   if (sizeof(Pix) == 1) {
     c[0] = quant4_u8(rc.v[0].x, a); c[1] = quant4_u8(rc.v[0].y, a);
@@ -524,13 +535,13 @@ __device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc
     lh = quant4_u16(rc.lh[0], rc.lh[sizeof(Pix) - 1], a);
     rh = quant4_u16(rc.rh[0], rc.rh[sizeof(Pix) - 1], a);
   }
-  if (y >= a.H) {
+  if (y >= g.H) {
     c[0] = c[1] = c[2] = c[3] = lh = rh = sent4;
   } else {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) c[m] = clip_dword(c[m], x0 + 4 * m, a.W, sent4);
-    lh = x0 >= 16 ? clip_dword(lh, x0 - 4, a.W, sent4) : sent4;
-    rh = clip_dword(rh, x0 + 16, a.W, sent4);
+    for (int m = 0; m < 4; ++m) c[m] = clip_dword(c[m], x0 + 4 * m, g.W, sent4);
+    lh = x0 >= 16 ? clip_dword(lh, x0 - 4, g.W, sent4) : sent4;
+    rh = clip_dword(rh, x0 + 16, g.W, sent4);
   }
 #pragma unroll
   for (int t = 0; t < 16; ++t) r.s[NX + t] = __umul24((c[t >> 2] >> ((t & 3) * 8)) & 0xffu, mb);
@@ -540,10 +551,16 @@ __device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc
     // pixel e of the lane on the right (lanes 0 and 63 keep their own value)
     const uint32_t own_l = __umul24((lh >> ((3 - e) * 8)) & 0xffu, mb);
     const uint32_t own_r = __umul24((rh >> (e * 8)) & 0xffu, mb);
-    r.s[NX - 1 - e] = (uint32_t)__builtin_amdgcn_update_dpp((int)own_l, (int)r.s[NX + 15 - e], kDppWaveShr1, 0xf, 0xf, false);
-    r.s[NX + 16 + e] = (uint32_t)__builtin_amdgcn_update_dpp((int)own_r, (int)r.s[NX + e], kDppWaveShl1, 0xf, 0xf, false);
+    uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp((int)own_l, (int)r.s[NX + 15 - e], kDppWaveShr1, 0xf, 0xf, false);
+    uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp((int)own_r, (int)r.s[NX + e], kDppWaveShl1, 0xf, 0xf, false);
+    if (SEG) {
+      const uint32_t sent = __umul24(sent4 & 0xffu, mb);
+      if (x0 - 1 - e < 0) left = sent;
+      if (x0 + 16 + e >= g.W) right = sent;
+    }
+    r.s[NX - 1 - e] = left;
+    r.s[NX + 16 + e] = right;
   }
-  (void)lane;
 }
 
 // The 16 votes of one first-pixel row for offset (DX, dy): second pixel of
@@ -599,8 +616,8 @@ __device__ __forceinline__ void vote_glcm(const uint32_t (&fa)[16],
 // partition, then the ring slot of this row takes the row NR below (from the
 // prefetched raw row) and the raw slot starts loading the row 2 NR below.
 template <typename Pix, int MAXDY, int D, int CUR>
-__device__ __forceinline__ void strip_step(const VoteArgs& a, TermRow<MAXDY> (&ring)[MAXDY + 1],
-                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, int lane, uint32_t C,
+__device__ __forceinline__ void strip_step(const VoteArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
+                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, uint32_t C,
                                            uint32_t n1, uint32_t mb, uint32_t inc, uint32_t sent4,
                                            const int (&code)[4], int kp) {
   constexpr int NR = MAXDY + 1;
@@ -611,8 +628,8 @@ __device__ __forceinline__ void strip_step(const VoteArgs& a, TermRow<MAXDY> (&r
   if (kp > 1) vote_glcm<MAXDY, D, 1, CUR>(fa, ring, code[1], inc);
   if (kp > 2) vote_glcm<MAXDY, D, 2, CUR>(fa, ring, code[2], inc);
   if (kp > 3) vote_glcm<MAXDY, D, 3, CUR>(fa, ring, code[3], inc);
-  to_terms<Pix, MAXDY>(ring[CUR], raw[CUR], a, y + NR, x0, lane, sent4, mb);
-  load_row<Pix>(raw[CUR], a, y + 2 * NR, x0);
+  to_terms<Pix, MAXDY>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb);
+  load_row<Pix>(raw[CUR], geo, y + 2 * NR, x0);
 }
 
 // Merge of the strip layout: lanes read consecutive 16-byte units (D / 4
@@ -679,6 +696,7 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
   int code[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) code[q] = q < kp ? __builtin_amdgcn_readfirstlane(a.vcode[kp0 + q]) : -1;
+  const Geom geo{a.img, a.stride, a.W, a.H};
 
   TermRow<MAXDY> ring[NR];
   RawChunk<Pix> raw[NR];
@@ -687,7 +705,7 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
   if (strip < nstrips) {
     const int x0 = (((strip % spans) << 6) + lane) << 4, ya = y0 + (strip / spans) * a.strip_rows;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], a, ya + r, x0);
+    for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, x0);
   }
   zero_lds(lds, n1 * n1 * (uint32_t)a.kp * D);
   __syncthreads();
@@ -698,20 +716,20 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
     const int yb = min(y1, ya + a.strip_rows);
     if (strip != wave) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], a, ya + r, x0);
+      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, x0);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      to_terms<Pix, MAXDY>(ring[r], raw[r], a, ya + r, x0, lane, sent4, mb);
-      load_row<Pix>(raw[r], a, ya + NR + r, x0);
+      to_terms<Pix, MAXDY>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb);
+      load_row<Pix>(raw[r], geo, ya + NR + r, x0);
     }
     for (int y = ya; y < yb; y += NR) {
-      strip_step<Pix, MAXDY, D, 0>(a, ring, raw, y, x0, lane, C, n1, mb, inc, sent4, code, kp);
+      strip_step<Pix, MAXDY, D, 0>(a, geo, ring, raw, y, x0, C, n1, mb, inc, sent4, code, kp);
       if (y + 1 >= yb) break;
-      strip_step<Pix, MAXDY, D, 1>(a, ring, raw, y + 1, x0, lane, C, n1, mb, inc, sent4, code, kp);
+      strip_step<Pix, MAXDY, D, 1>(a, geo, ring, raw, y + 1, x0, C, n1, mb, inc, sent4, code, kp);
       if constexpr (NR > 2) {
         if (y + 2 >= yb) break;
-        strip_step<Pix, MAXDY, D, 2>(a, ring, raw, y + 2, x0, lane, C, n1, mb, inc, sent4, code, kp);
+        strip_step<Pix, MAXDY, D, 2>(a, geo, ring, raw, y + 2, x0, C, n1, mb, inc, sent4, code, kp);
       }
     }
   }
@@ -719,34 +737,33 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
 }
 
 // ---------------------------------------------------------------------------
-// Haralick statistics: one workgroup per GLCM.  Exact integer sums for the
-// contrast numerator and the correlation moments; fp32 for energy, entropy and
-// homogeneity; fp64 (from exact 128-bit integers) for the correlation.
+// Haralick statistics of one GLCM computed by a whole workgroup (blockDim a
+// power of two >= 64).  Exact integer sums for the contrast numerator and the
+// correlation moments; fp32 for energy, entropy and homogeneity; fp64 (from
+// exact 128-bit integers) for the correlation.  redu / redf: blockDim words of
+// workgroup scratch each.  Every thread of the workgroup must call it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, float* out) {
-  const int k = blockIdx.x;
-  const uint32_t NN = (uint32_t)N * (uint32_t)N;
-  const uint32_t* P = glcm + (size_t)k * NN;
+template <typename T>
+__device__ __forceinline__ T wg_sum(T v, T* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (uint32_t h = blockDim.x / 2u; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const T r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ void glcm_features_wg(const uint32_t* P, uint32_t N, float* o, unsigned long long* redu, float* redf) {
+  const uint32_t NN = N * N;
   // pass 1: total (needed for p)
   unsigned long long T = 0;
   for (uint32_t t = threadIdx.x; t < NN; t += blockDim.x) T += P[t];
-  __shared__ unsigned long long redu[256];
-  __shared__ float redf[256];
-  redu[threadIdx.x] = T;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) redu[threadIdx.x] += redu[threadIdx.x + s];
-    __syncthreads();
-  }
-  T = redu[0];
-  __syncthreads();
-  float* o = out + (size_t)k * 5;
-  if (T == 0) {
-    if (threadIdx.x < 5) o[threadIdx.x] = 0.0f;
-    return;
-  }
-  if (T > 0xffffffffull) {
-    if (threadIdx.x < 5) o[threadIdx.x] = __builtin_nanf("");
+  T = wg_sum(T, redu);
+  if (T == 0 || T > 0xffffffffull) {
+    if (threadIdx.x < 5) o[threadIdx.x] = T == 0 ? 0.0f : __builtin_nanf("");
     return;
   }
   const float invT = 1.0f / (float)T;
@@ -755,7 +772,7 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, f
   for (uint32_t t = threadIdx.x; t < NN; t += blockDim.x) {
     const uint32_t c = P[t];
     if (c == 0) continue;
-    const unsigned long long i = t / (uint32_t)N, j = t % (uint32_t)N;
+    const unsigned long long i = t / N, j = t % N;
     const unsigned long long d = i > j ? i - j : j - i;
     sc += d * d * c;
     si += i * c; sj += j * c;
@@ -767,44 +784,175 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, f
     ent -= p * lp;
     homog += p / (1.0f + (float)(d * d));
   }
-  unsigned long long vals[6] = {sc, si, sj, sii, sjj, sij};
-  unsigned long long tot[6];
-  for (int v = 0; v < 6; ++v) {
-    redu[threadIdx.x] = vals[v];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) redu[threadIdx.x] += redu[threadIdx.x + s];
-      __syncthreads();
-    }
-    tot[v] = redu[0];
-    __syncthreads();
-  }
-  float fv[3] = {energy, ent, homog};
-  float ftot[3];
-  for (int v = 0; v < 3; ++v) {
-    redf[threadIdx.x] = fv[v];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) redf[threadIdx.x] += redf[threadIdx.x + s];
-      __syncthreads();
-    }
-    ftot[v] = redf[0];
-    __syncthreads();
-  }
+  sc = wg_sum(sc, redu);
+  si = wg_sum(si, redu);
+  sj = wg_sum(sj, redu);
+  sii = wg_sum(sii, redu);
+  sjj = wg_sum(sjj, redu);
+  sij = wg_sum(sij, redu);
+  energy = wg_sum(energy, redf);
+  ent = wg_sum(ent, redf);
+  homog = wg_sum(homog, redf);
   if (threadIdx.x == 0) {
     using i128 = __int128;
     const i128 tT = (i128)T;
-    const i128 vi = (i128)tot[3] * tT - (i128)tot[1] * (i128)tot[1];  // T^2 var_i
-    const i128 vj = (i128)tot[4] * tT - (i128)tot[2] * (i128)tot[2];  // T^2 var_j
-    const i128 cv = (i128)tot[5] * tT - (i128)tot[1] * (i128)tot[2];  // T^2 cov
+    const i128 vi = (i128)sii * tT - (i128)si * (i128)si;  // T^2 var_i
+    const i128 vj = (i128)sjj * tT - (i128)sj * (i128)sj;  // T^2 var_j
+    const i128 cv = (i128)sij * tT - (i128)si * (i128)sj;  // T^2 cov
     double corr = 1.0;
     if (vi != 0 && vj != 0) corr = (double)cv / sqrt((double)vi * (double)vj);
-    o[0] = (float)((double)tot[0] / (double)T);
-    o[1] = ftot[0];
-    o[2] = ftot[1];
-    o[3] = ftot[2];
+    o[0] = (float)((double)sc / (double)T);
+    o[1] = energy;
+    o[2] = ent;
+    o[3] = homog;
     o[4] = (float)corr;
   }
+}
+
+// One workgroup (256 threads) per GLCM.
+__global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, float* out) {
+  __shared__ unsigned long long redu[256];
+  __shared__ float redf[256];
+  glcm_features_wg(glcm + (size_t)blockIdx.x * (uint32_t)N * (uint32_t)N, (uint32_t)N, out + (size_t)blockIdx.x * 5,
+                   redu, redf);
+}
+
+// ---------------------------------------------------------------------------
+// Batch kernel: one workgroup per image of a batch, fusing quantize, vote,
+// merge and the Haralick statistics; results are stored directly (the
+// workgroup owns the whole image, so no atomics and no second kernel).
+// Images arrive largest first, so the hardware dispatcher balances the
+// workgroups over the CUs.
+//
+// Aligned images use the strip machinery with the wavefront split into row
+// segments when the image is narrower than 1024 columns: lane l handles chunk
+// l mod cw of segment l / cw (cw = chunks per row), each segment walking its
+// own run of rows; halo pixels outside [0, W) take the sentinel.  Images that
+// are not 16-byte aligned are counted per pixel.  Both write the strip LDS
+// layout (kp = K GLCMs, D dwords per bin).
+// ---------------------------------------------------------------------------
+template <int MAXDY, int D, int KI, int CUR>
+__device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermRow<MAXDY> (&ring)[MAXDY + 1],
+                                           const int (&code)[4], int K, uint32_t inc) {
+  vote_glcm<MAXDY, D, KI, CUR>(fa, ring, code[KI], inc);
+  if constexpr (KI + 1 < kStripMaxKp) {
+    if (K > KI + 1) batch_vote<MAXDY, D, KI + 1, CUR>(fa, ring, code, K, inc);
+  }
+}
+
+template <typename Pix, int MAXDY, int D, int CUR>
+__device__ __forceinline__ void batch_step(const BatchArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
+                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, uint32_t C, uint32_t n1,
+                                           uint32_t mb, uint32_t sent4, const int (&code)[4]) {
+  constexpr int NR = MAXDY + 1;
+  uint32_t fa[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) fa[t] = __umul24(ring[CUR].s[MAXDY + t], n1) + C;
+  batch_vote<MAXDY, D, 0, CUR>(fa, ring, code, a.K, 1u);
+  to_terms<Pix, MAXDY, true>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb);
+  load_row<Pix>(raw[CUR], geo, y + 2 * NR, x0);
+}
+
+template <typename Pix, int MAXDY, int D>
+__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  constexpr int NR = MAXDY + 1;
+  const BatchTile t = a.tiles[blockIdx.x];
+  const Geom geo{t.img, t.stride, t.W, t.H};
+  const int K = a.K;
+  const uint32_t N = a.q.nlev, n1 = a.pitch, NN = N * N;
+  const uint32_t mb = 4u * D * (uint32_t)K;
+  const uint32_t vote_words = n1 * n1 * (uint32_t)K * D;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t g = threadIdx.x & (D - 1u);
+  const uint32_t C = lds_address(lds) + 4u * g;
+  const uint32_t sent4 = N * 0x01010101u;
+  zero_lds(lds, vote_words);
+  __syncthreads();
+
+  if (t.aligned) {
+    int code[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) code[q] = q < K ? a.vcode[q] : -1;
+    // lane -> (segment, chunk)
+    const int chunks = (t.W + 15) >> 4;
+    const int cw = min(chunks, 64), segs = 64 / cw, spans = (chunks + 63) >> 6;
+    const int seg = lane / cw, c = lane - seg * cw;
+    const bool live = seg < segs;
+    const int slots = nwaves * segs;  // row segments walked at once by the workgroup
+    const int h = max(a.min_rows, (t.H * spans + slots - 1) / slots);
+    const int blocks = (t.H + segs * h - 1) / (segs * h);
+    for (int u = wave; u < spans * blocks; u += nwaves) {
+      const int span = u % spans, blk = u / spans;
+      const int x0 = live ? ((span << 6) + c) << 4 : spans << 10;  // idle lanes: past the right edge
+      const int ya = (blk * segs + (live ? seg : 0)) * h;
+      TermRow<MAXDY> ring[NR];
+      RawChunk<Pix> raw[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, x0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        to_terms<Pix, MAXDY, true>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb);
+        load_row<Pix>(raw[r], geo, ya + NR + r, x0);
+      }
+      // every lane takes h steps; rows past the image or the lane's segment
+      // end carry the sentinel or belong to this segment's own run
+      for (int j = 0; j < h; j += NR) {
+        batch_step<Pix, MAXDY, D, 0>(a, geo, ring, raw, ya + j, x0, C, n1, mb, sent4, code);
+        if (j + 1 >= h) break;
+        batch_step<Pix, MAXDY, D, 1>(a, geo, ring, raw, ya + j + 1, x0, C, n1, mb, sent4, code);
+        if constexpr (NR > 2) {
+          if (j + 2 >= h) break;
+          batch_step<Pix, MAXDY, D, 2>(a, geo, ring, raw, ya + j + 2, x0, C, n1, mb, sent4, code);
+        }
+      }
+    }
+  } else {
+    // per pixel: one thread per first pixel, votes in the strip layout (a
+    // negated offset is stored transposed, as the strip path counts it)
+    const Pix* img = (const Pix*)t.img;
+    const uint32_t n = (uint32_t)t.W * (uint32_t)t.H;
+    for (uint32_t idx = threadIdx.x; idx < n; idx += blockDim.x) {
+      const int y = (int)(idx / (uint32_t)t.W), x = (int)(idx % (uint32_t)t.W);
+      const uint32_t av = quantize(img[(int64_t)y * t.stride + x], a.q);
+      for (int k = 0; k < K; ++k) {
+        const int x2 = x + a.dx[k], y2 = y + a.dy[k];
+        if ((unsigned)x2 >= (unsigned)t.W || (unsigned)y2 >= (unsigned)t.H) continue;
+        const uint32_t bv = quantize(img[(int64_t)y2 * t.stride + x2], a.q);
+        const bool tr = (a.tmask >> k) & 1ull;
+        const uint32_t bin = tr ? bv * n1 + av : av * n1 + bv;
+        __hip_atomic_fetch_add((lds_word_t*)(size_t)(C + bin * mb + 4u * D * (uint32_t)k), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+
+  // merge: consecutive 16-byte units, D / 4 lanes per bin, into out and into
+  // an LDS copy for the statistics
+  __syncthreads();
+  constexpr uint32_t QPB = D / 4;
+  uint32_t* merged = lds + vote_words;
+  uint32_t* dst = a.out + (size_t)t.index * K * NN;
+  for (uint32_t u = threadIdx.x; u < vote_words / 4u; u += blockDim.x) {
+    const uint4 v = ((const uint4*)lds)[u];
+    uint32_t sum = (v.x + v.y) + (v.z + v.w);
+    if (QPB >= 2) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0xb1, 0xf, 0xf, false);
+    if (QPB >= 4) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0x4e, 0xf, 0xf, false);
+    if (u % QPB != 0) continue;
+    const uint32_t blk = u / QPB, k = blk % (uint32_t)K, bin = blk / (uint32_t)K;
+    const uint32_t i = bin / n1, j = bin % n1;
+    if (i >= N || j >= N) continue;
+    const bool tr = (a.tmask >> k) & 1ull;
+    const uint32_t w = k * NN + (tr ? j * N + i : i * N + j);
+    dst[w] = sum;
+    merged[w] = sum;
+  }
+  if (!a.feat) return;
+  __syncthreads();
+  unsigned long long* redu = (unsigned long long*)(merged + K * NN + ((K * NN) & 1u));
+  float* redf = (float*)(redu + blockDim.x);
+  for (int k = 0; k < K; ++k)
+    glcm_features_wg(merged + k * NN, N, a.feat + ((size_t)t.index * K + k) * 5, redu, redf);
 }
 
 }  // namespace
@@ -858,6 +1006,29 @@ hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int
   if (maxdy == 2)
     return dtype_bytes == 1 ? launch_strips_t<uint8_t, 2>(a, D, wg, lds_bytes, stream)
                             : launch_strips_t<uint16_t, 2>(a, D, wg, lds_bytes, stream);
+  return hipErrorInvalidValue;
+}
+
+template <typename Pix, int MAXDY>
+static hipError_t launch_batch_t(const BatchArgs& a, int T, int D, size_t lds_bytes, hipStream_t stream) {
+  const dim3 grid(T), block(kBatchThreads);
+  switch (D) {
+    case 4: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 4>), grid, block, lds_bytes, stream, a); break;
+    case 8: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 8>), grid, block, lds_bytes, stream, a); break;
+    case 16: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 16>), grid, block, lds_bytes, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, size_t lds_bytes,
+                        hipStream_t stream) {
+  if (maxdy == 1)
+    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 1>(a, T, D, lds_bytes, stream)
+                            : launch_batch_t<uint16_t, 1>(a, T, D, lds_bytes, stream);
+  if (maxdy == 2)
+    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 2>(a, T, D, lds_bytes, stream)
+                            : launch_batch_t<uint16_t, 2>(a, T, D, lds_bytes, stream);
   return hipErrorInvalidValue;
 }
 

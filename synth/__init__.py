@@ -145,3 +145,22 @@ def multispectral(size: int = 8192, bands: int = 8):
     imgs = [multispectral_band(b, size)[0] for b in range(bands)]
     return dict(name=f"{bands}x{size}x{size}-u16-multispectral-N64-K12", images=imgs,
                 N=64, lo=0, hi=65535, offsets=offsets_for([1, 2, 4]))
+
+
+def batch_tiles(count: int = 4096, seed_offset: int = 3):
+    """The batched workload: ``count`` uint8 tiles whose width and height are
+    drawn independently as floor(exp(uniform(ln 32, ln 513))) (log-uniform in
+    [32, 512]); the first half i.i.d. uniform, the second half smooth
+    (sigma = 4 px); then the order is shuffled.  N = 16, d = 1 at the four
+    angles."""
+    g = rng(BASE_SEED + seed_offset)
+    sides = np.floor(np.exp(g.uniform(np.log(32.0), np.log(513.0), size=(count, 2)))).astype(int)
+    tiles = []
+    for i in range(count):
+        h, w = int(sides[i, 0]), int(sides[i, 1])
+        s = BASE_SEED + seed_offset + 10 + i
+        tiles.append(uniform(h, w, s) if i < count // 2 else smooth(h, w, 4.0, s))
+    order = g.permutation(count)
+    tiles = [tiles[i] for i in order]
+    return dict(name=f"{count}-tiles-u8-32to512-N16-K4", images=tiles, N=16, lo=0, hi=255,
+                offsets=offsets_for([1]))

@@ -122,3 +122,11 @@ def test_plan_tuning_rejects_null(lib):
     t = glcm.Tuning()
     assert lib.glcm_plan_tuning(None, ctypes.byref(t), 0) == -1
     assert lib.glcm_plan_destroy(None) == 0
+
+
+def test_batch_rejects_bad_arguments(lib):
+    one = (glcm.Tile * 1)(glcm.Tile(0x10000, 8, 8, 8))
+    assert lib.glcm_batch_compute(None, one, 1, 0, 255, ctypes.c_void_p(0x20000), None, None) == -1
+    assert lib.glcm_batch_compute(ctypes.c_void_p(0x1000), None, 1, 0, 255, ctypes.c_void_p(0x20000), None, None) == -1
+    assert lib.glcm_batch_compute(ctypes.c_void_p(0x1000), one, 0, 0, 255, ctypes.c_void_p(0x20000), None, None) == -1
+    assert lib.glcm_batch_compute(ctypes.c_void_p(0x1000), one, 1, 0, 255, None, None, None) == -1

@@ -1,0 +1,156 @@
+"""GPU parity of the batched engine (glcm_batch_compute, through the C ABI):
+every image of a batch against the CPU oracle, bit-exact counts and features
+within 1e-5 relative of the fp64 oracle; aligned and misaligned images, u8 and
+u16, narrow and wide images, offsets counted transposed, plan reuse."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_1710_06189_amd")
+
+
+def to_device(img: np.ndarray) -> torch.Tensor:
+    if img.dtype == np.uint16:
+        return torch.from_numpy(np.ascontiguousarray(img).view(np.int16)).cuda().view(torch.uint16)
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    torch.cuda.synchronize()
+    if t.dtype == torch.float32:
+        return t.cpu().numpy()
+    return t.view(torch.int32).cpu().numpy().view(np.uint32)
+
+
+def check_features(got, want, label):
+    got = got.astype(np.float64)
+    zero = want == 0
+    assert np.all(got[zero] == 0), f"{label}: exact zeros not kept"
+    rel = np.abs(got[~zero] - want[~zero]) / np.abs(want[~zero])
+    assert np.all(rel <= 1e-5), f"{label}: features off by {rel.max():.3g}"
+
+
+def run_batch(imgs, N, lo, hi, offs, views=None, features=True, plan=None):
+    dt = imgs[0].dtype
+    tens = views if views is not None else [to_device(im) for im in imgs]
+    own = plan is None
+    if own:
+        plan = G.glcm_plan_create(dt, N, offs, max(im.shape[1] for im in imgs), max(im.shape[0] for im in imgs))
+    try:
+        print(f"[batch] T={len(imgs)} dtype={dt} N={N} K={len(offs)} offsets={offs}", flush=True)
+        out, feats = G.glcm_batch_compute(tens, plan, lo, hi, features=features)
+        got = host(out)
+        fgot = host(feats) if feats is not None else None
+    finally:
+        if own:
+            plan.close()
+    for t, im in enumerate(imgs):
+        want = oracle.glcm(im, N, lo, hi, offs)
+        if not np.array_equal(got[t], want):
+            bad = np.argwhere(got[t] != want)
+            raise AssertionError(f"image {t} {im.shape}: {len(bad)} bins differ, first {tuple(bad[0])}")
+        if fgot is not None:
+            check_features(fgot[t], oracle.features(want), f"image {t} {im.shape}")
+    return got, fgot
+
+
+def test_batch_tiles_workload_sample():
+    w = synth.batch_tiles(96)
+    run_batch(w["images"], w["N"], w["lo"], w["hi"], w["offsets"])
+
+
+@pytest.mark.parametrize("shapes", [
+    [(1, 1), (1, 40), (40, 1), (2, 2), (17, 3)],
+    [(32, 32), (512, 512), (33, 511), (511, 33), (100, 1000), (7, 2100)],
+    [(64, 64)] * 7 + [(300, 1100)],
+])
+def test_batch_shapes(shapes):
+    imgs = [synth.smooth(h, w, 2.0, 500 + i, np.uint8) if min(h, w) > 2 else synth.uniform(h, w, 500 + i)
+            for i, (h, w) in enumerate(shapes)]
+    run_batch(imgs, 16, 0, 255, synth.offsets_for([1]))
+
+
+@pytest.mark.parametrize("offs", [
+    [(1, 0)], [(0, 1), (1, 0), (-1, -1)], [(2, 0), (-2, 2), (0, 2), (2, 2)],
+    [(0, 0), (-1, 0), (1, -1), (0, -2)],
+])
+def test_batch_offsets(offs):
+    imgs = [synth.smooth(90 + 7 * i, 130 + 11 * i, 3.0, 600 + i) for i in range(6)]
+    run_batch(imgs, 32, 0, 255, offs)
+
+
+@pytest.mark.parametrize("N,lo,hi", [(8, 0, 255), (24, 10, 240), (43, 0, 255), (1, 0, 255)])
+def test_batch_levels_u8(N, lo, hi):
+    imgs = [synth.uniform(50, 70, 700), synth.smooth(120, 64, 4.0, 701)]
+    run_batch(imgs, N, lo, hi, synth.offsets_for([1]))
+
+
+@pytest.mark.parametrize("N,lo,hi", [(64, 0, 65535), (100, 1000, 60000)])
+def test_batch_u16(N, lo, hi):
+    imgs = [synth.smooth(80 + 13 * i, 48 + 40 * i, 3.0, 800 + i, np.uint16, noise_frac=0.05) for i in range(5)]
+    run_batch(imgs, N, lo, hi, synth.offsets_for([2]))
+
+
+def test_batch_misaligned_and_strided_views():
+    base = synth.smooth(300, 700, 4.0, 900)
+    tb = to_device(base)
+    cuts = [(0, 300, 0, 640), (3, 297, 1, 699), (10, 200, 16, 656), (0, 299, 5, 6), (7, 100, 33, 300)]
+    imgs = [base[y0:y1, x0:x1] for y0, y1, x0, x1 in cuts]
+    views = [tb[y0:y1, x0:x1] for y0, y1, x0, x1 in cuts]
+    run_batch(imgs, 16, 0, 255, synth.offsets_for([1]), views=views)
+
+
+def test_batch_without_features_and_plan_reuse():
+    offs = synth.offsets_for([1])
+    plan = G.glcm_plan_create(np.uint8, 16, offs, 512, 512)
+    try:
+        for T, seed in [(5, 1000), (40, 1100), (3, 1200)]:  # grows and reuses the descriptor staging
+            imgs = [synth.uniform(20 + 9 * i, 30 + 5 * i, seed + i) for i in range(T)]
+            got, f = run_batch(imgs, 16, 0, 255, offs, features=False, plan=plan)
+            assert f is None
+    finally:
+        plan.close()
+
+
+def test_batch_matches_per_image_calls():
+    w = synth.batch_tiles(32)
+    N, offs = w["N"], w["offsets"]
+    plan = G.glcm_plan_create(np.uint8, N, offs, 512, 512)
+    try:
+        tens = [to_device(im) for im in w["images"]]
+        out, feats = G.glcm_batch_compute(tens, plan)
+        for t, x in enumerate(tens):
+            P = G.glcm_compute(x, N, 0, 255, offs, plan=plan)
+            F = G.glcm_features(P)
+            assert np.array_equal(host(out[t].contiguous()), host(P))
+            assert np.array_equal(host(feats[t].contiguous()), host(F))
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("N,offs", [(16, [(1, 0)] * 5), (16, [(4, 0)]), (16, [(0, 3)]), (255, [(1, 0)] * 4)])
+def test_batch_unsupported(N, offs):
+    """More than 4 offsets, a reach beyond 2, or LDS copies that do not fit."""
+    plan = G.glcm_plan_create(np.uint8, N, offs, 64, 64)
+    try:
+        with pytest.raises(G.GlcmError) as e:
+            G.glcm_batch_compute([to_device(synth.uniform(8, 8, 1))], plan)
+        assert e.value.status == -3
+    finally:
+        plan.close()
+
+
+def test_batch_rejects_oversize_images():
+    plan = G.glcm_plan_create(np.uint8, 16, [(1, 0)], 64, 64)
+    try:
+        with pytest.raises(G.GlcmError) as e:
+            G.glcm_batch_compute([to_device(synth.uniform(65, 8, 1))], plan)
+        assert e.value.status == -1
+    finally:
+        plan.close()

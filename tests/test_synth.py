@@ -35,3 +35,14 @@ def test_offsets_for_eq2_directions():
 def test_checkerboard_pattern():
     c = synth.checkerboard(3, 4, 1, 9)
     assert c.tolist() == [[1, 9, 1, 9], [9, 1, 9, 1], [1, 9, 1, 9]]
+
+
+def test_batch_tiles_recipe():
+    w = synth.batch_tiles(64)
+    imgs = w["images"]
+    assert len(imgs) == 64 and w["N"] == 16 and len(w["offsets"]) == 4
+    for im in imgs:
+        assert im.dtype == np.uint8 and 32 <= im.shape[0] <= 512 and 32 <= im.shape[1] <= 512
+    # deterministic
+    again = synth.batch_tiles(64)["images"]
+    assert all(np.array_equal(a, b) for a, b in zip(imgs, again))
