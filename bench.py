@@ -171,18 +171,19 @@ def main():
                     offs=offs)
 
     if args.sweep:
-        grid = [(R, bits, wg) for R, bits in ((2, 32), (4, 32), (8, 32), (16, 32), (32, 32), (16, 16), (32, 16))
-                for wg in (256, 512, 1024)]
+        grid = [(R, bits, wg) for R, bits in ((8, 32), (16, 32), (32, 32), (8, 16), (16, 16), (32, 16))
+                for wg in (512, 1024)]
         for kind in ("smooth", "uniform", "constant"):
             for R, bits, wg in grid:
                 cfg = {"replicas": R, "counter_bits": bits, "wg_size": wg}
                 try:
-                    r = measure(kind, cfg)
+                    r = measure(kind, cfg, vote_timing=True)
                 except Exception as e:  # a layout the LDS cannot hold
                     print(json.dumps({"sweep": kind, **cfg, "error": str(e)}), flush=True)
                     continue
                 print(json.dumps({"sweep": kind, **cfg, "partitions": r["tuning"]["partitions"],
                                   "us_per_step": round(r["step_ms"] * 1e3, 2),
+                                  "vote_us": round(r["vote_ms"] * 1e3, 2) if r["vote_ms"] else None,
                                   "gpairs_s": round(r["pairs"] / (r["step_ms"] * 1e-3) / 1e9, 1)}), flush=True)
         return
 
@@ -292,14 +293,16 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
     out = torch.empty((T, K, N, N), dtype=torch.uint32, device=dev)
     feats = torch.empty((T, K, 5), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
+    tiles = G.prepare_tiles(tens, plan)  # the descriptor array a C caller would hold
+    aligned = sum(1 for x in tens if (x.data_ptr() % 16 == 0 and x.stride(0) % 16 == 0))
     for _ in range(3):
-        G.glcm_batch_compute(tens, plan, out=out, features=feats, stream=stream)
+        G.glcm_batch_compute(tiles, plan, out=out, features=feats, stream=stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(reps):
-        G.glcm_batch_compute(tens, plan, out=out, features=feats, stream=stream)
+        G.glcm_batch_compute(tiles, plan, out=out, features=feats, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     batch_wall = (time.perf_counter() - t0) / reps
@@ -331,7 +334,7 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
         if not np.array_equal(got[t], oracle.glcm(imgs[t], N, 0, 255, offs)):
             raise SystemExit(f"bench: tile {t} differs from the oracle")
     print(json.dumps({
-        "workload": w["name"], "tiles": T, "pixels": px, "pairs": pairs,
+        "workload": w["name"], "tiles": T, "pixels": px, "pairs": pairs, "aligned_tiles": aligned,
         "batched_gpairs_s": pairs / batch_wall / 1e9, "batched_ms": batch_wall * 1e3,
         "batched_device_ms": batch_dev * 1e3,
         "per_image_gpairs_s": pairs / per_wall / 1e9, "per_image_ms": per_wall * 1e3,

@@ -31,7 +31,7 @@ __all__ = [
     "glcm_offset_polar", "glcm_plan_create", "glcm_plan_destroy", "glcm_plan_tuning", "glcm_plan_autotune",
     "glcm_compute",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
-    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "glcm_batch_compute", "Tile", "PATH_NAMES", "glcm_plan_kernel_time",
+    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -302,27 +302,40 @@ def glcm_features(P, out=None, stream=None):
     return out
 
 
+class TileSet:
+    """Descriptors of a batch of device images, built once and reusable."""
+
+    def __init__(self, images, dtype):
+        T = len(images)
+        if T < 1:
+            raise ValueError("images must not be empty")
+        self.tiles = (Tile * T)()
+        self.keep = []
+        for i, img in enumerate(images):
+            if not (isinstance(img, torch.Tensor) and img.is_cuda):
+                raise ValueError("batch images must be CUDA tensors")
+            ptr, W, H, stride, dt, k = _image_args(img)
+            if dt != dtype:
+                raise ValueError("image dtype differs from the plan's")
+            self.tiles[i] = Tile(ptr, stride, W, H)
+            self.keep.append(k)
+        self.T = T
+        self.device = images[0].device
+
+
+def prepare_tiles(images, plan) -> TileSet:
+    return TileSet(images, plan.dtype)
+
+
 def glcm_batch_compute(images, plan, lo=0, hi=None, out=None, features=True, stream=None):
     """Counts (and statistics) of many device images in one launch.
 
     `images`: sequence of 2-D CUDA tensors (uint8 or uint16, the plan's dtype),
-    any sizes up to the plan's max_W x max_H.  Returns (out [T, K, N, N]
-    uint32, feats [T, K, 5] float32 or None)."""
-    T = len(images)
-    if T < 1:
-        raise ValueError("images must not be empty")
-    tiles = (Tile * T)()
-    keep = []
-    dev = None
-    for i, img in enumerate(images):
-        if not (isinstance(img, torch.Tensor) and img.is_cuda):
-            raise ValueError("batch images must be CUDA tensors")
-        ptr, W, H, stride, dt, k = _image_args(img)
-        if dt != plan.dtype:
-            raise ValueError("image dtype differs from the plan's")
-        tiles[i] = Tile(ptr, stride, W, H)
-        keep.append(k)
-        dev = img.device
+    any sizes up to the plan's max_W x max_H, or a TileSet from
+    prepare_tiles().  Returns (out [T, K, N, N] uint32, feats [T, K, 5]
+    float32 or None)."""
+    ts = images if isinstance(images, TileSet) else TileSet(images, plan.dtype)
+    T, tiles, dev = ts.T, ts.tiles, ts.device
     if hi is None:
         hi = 255 if plan.dtype == U8 else 65535
     K, N = len(plan.offsets), plan.N
@@ -339,5 +352,4 @@ def glcm_batch_compute(images, plan, lo=0, hi=None, out=None, features=True, str
     _check(_lib().glcm_batch_compute(plan.handle, tiles, T, int(lo), int(hi), ctypes.c_void_p(out.data_ptr()),
                                      ctypes.c_void_p(feats.data_ptr()) if feats is not None else None, s),
            "glcm_batch_compute")
-    del keep
     return out, feats

@@ -232,27 +232,70 @@ int row_partitions(const glcm_plan_s* p, int R, int bits) {
   return (int)(((uint64_t)p->K + per - 1) / per);
 }
 
-// Strip kernel: dwords per bin of a layout with R copies of `bits`-bit
-// counters (4, 8 or 16), or 0 when the kernel has no such variant.
-int strip_dwords(int R, int bits) {
-  const int D = bits == 16 ? R / 2 : R;
-  return (D == 4 || D == 8 || D == 16) ? D : 0;
-}
+// Strip kernel: dwords per bin for R copies (4, 8, 16 or 32), or 0 when the
+// kernel has no such variant.  With 16-bit counters the copies stay R and each
+// dword holds two GLCMs.
+int strip_dwords(int R) { return (R == 4 || R == 8 || R == 16 || R == 32) ? R : 0; }
 
 // Strip kernel: GLCMs per partition for D dwords per bin ((N+1)^2 bins each),
-// at most kStripMaxKp; 0 if one GLCM does not fit.
-int strip_kp(const glcm_plan_s* p, int D) {
+// two per dword group with 16-bit pairs, at most kStripMaxKp; 0 if none fits.
+int strip_kp(const glcm_plan_s* p, int D, bool pair) {
   const uint64_t n1 = (uint64_t)p->N + 1u;
-  const uint64_t per = (uint64_t)p->lds_budget_words / (n1 * n1 * (uint64_t)D);
-  return (int)std::min<uint64_t>(per, (uint64_t)glcm::kStripMaxKp);
+  const uint64_t groups = (uint64_t)p->lds_budget_words / (n1 * n1 * (uint64_t)D);
+  return (int)std::min<uint64_t>(groups * (pair ? 2u : 1u), (uint64_t)glcm::kStripMaxKp);
 }
 
 int strip_partitions(const glcm_plan_s* p, int R, int bits) {
-  const int D = strip_dwords(R, bits);
+  const int D = strip_dwords(R);
   if (D == 0) return 0;
-  const int kp = strip_kp(p, D);
+  const int kp = strip_kp(p, D, bits == 16);
   if (kp == 0) return 0;
   return (p->K + kp - 1) / kp;
+}
+
+// Strip kernel layout for `rows` first-pixel rows of width W: D dwords per
+// bin, kp GLCMs per partition in kg dword groups, row bands and strips.  The
+// 16-bit pair layout only when no counter can reach 2^16: a counter (bin,
+// copy, GLCM) is shared by wg / D lanes, each voting at most 16 pixels per row
+// it walks; otherwise 32-bit counters (fewer GLCMs per partition).
+struct StripLayout {
+  int D = 0, kp = 0, kg = 0, P = 0, pair = 0, nregions = 0, region_rows = 0, strip_rows = 0;
+  size_t lds = 0;
+};
+
+bool strip_layout(const glcm_plan_s* p, int W, int rows, int R, bool want_pair, int wg, StripLayout* L) {
+  const int spans = (((W + 15) / 16) + 63) / 64, nwaves = wg / 64;
+  const uint64_t n1 = (uint64_t)p->N + 1u, words = (uint64_t)p->K * p->N * p->N;
+  const int D = strip_dwords(R);
+  if (D == 0 || rows < 1) return false;
+  for (int pair = want_pair ? 1 : 0; pair >= 0; --pair) {
+    const int kp = strip_kp(p, D, pair != 0);
+    if (kp == 0) continue;
+    const int kg = pair ? (kp + 1) / 2 : kp;
+    const int P = (p->K + kp - 1) / kp;
+    const size_t lds = (size_t)(n1 * n1) * (size_t)kg * (size_t)D * 4u;
+    // as many bands per partition as the CUs hold at once, each tall enough
+    // for strips of >= 4 rows on every wavefront
+    const int per_cu =
+        std::max(1, std::min((int)(((size_t)p->lds_budget_words * 4u + 1024u) / std::max(lds, (size_t)wg * 4u)),
+                             32 / nwaves));
+    int nregions = std::min(rows, std::max(1, p->num_cus * per_cu / P));
+    nregions = std::max(1, std::min(nregions, rows * spans / (4 * nwaves)));
+    while (nregions > 1 && (uint64_t)nregions * words * 4ull > (256ull << 20)) nregions = (nregions + 1) / 2;
+    const int region_rows = (rows + nregions - 1) / nregions;
+    nregions = (rows + region_rows - 1) / region_rows;
+    const int strips_per_span = std::max(1, nwaves / spans);
+    const int strip_rows = std::max(1, (region_rows + strips_per_span - 1) / strips_per_span);
+    if (pair) {
+      const int nstrips = spans * ((region_rows + strip_rows - 1) / strip_rows);
+      const uint64_t rows_per_lane = (uint64_t)((nstrips + nwaves - 1) / nwaves) * (uint64_t)strip_rows;
+      if ((uint64_t)wg / (uint64_t)D * 16u * rows_per_lane > 65535u) continue;
+    }
+    L->D = D; L->kp = kp; L->kg = kg; L->P = P; L->pair = pair; L->lds = lds;
+    L->nregions = nregions; L->region_rows = region_rows; L->strip_rows = strip_rows;
+    return true;
+  }
+  return false;
 }
 
 int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
@@ -274,18 +317,23 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   } else {
     const bool any_rows = !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) && p->N <= 255;
     const bool strips_ok = any_rows && !(p->flags & GLCM_FLAG_FORCE_SLABS) && c.maxadx <= 2 && c.maxdy <= 2 &&
-                           strip_partitions(p, 4, 32) > 0;
+                           strip_partitions(p, 4, 16) > 0;
     const bool rows_ok = any_rows && c.maxadx <= 4 && c.maxdy <= 4 && row_partitions(p, 1, 32) > 0;
     if (strips_ok) {
       d.path = kPathStrips;
-      // 16 dwords per bin keep the 16 lanes of an LDS pass on distinct dwords;
-      // take them unless that needs more than max(2, minimum) image passes
-      const int Pmin = strip_partitions(p, 4, 32);
-      for (int R = 16; R >= 4; R /= 2) {
-        const int P = strip_partitions(p, R, 32);
+      // The most dwords per bin (32 put every lane of a 32-lane LDS pass on
+      // its own bank) that costs at most max(2, minimum) image passes, with
+      // two GLCMs per dword (16-bit counters) unless 32-bit counters fit in as
+      // few passes (measured on MI355X, 4096^2 at N = 32: 32 copies in pairs
+      // over two passes is the fastest layout on smooth and constant images)
+      const int Pmin = strip_partitions(p, 4, 16);
+      for (int R = 32; R >= 4; R /= 2) {
+        const int P32 = strip_partitions(p, R, 32), P16 = strip_partitions(p, R, 16);
+        const int bits = (P16 > 0 && (P32 == 0 || P16 < P32)) ? 16 : 32;
+        const int P = bits == 16 ? P16 : P32;
         if (P > 0 && P <= std::max(2, Pmin)) {
           d.replicas = R;
-          d.counter_bits = 32;
+          d.counter_bits = bits;
           d.partitions = P;
           break;
         }
@@ -464,16 +512,18 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   while ((1 << log2R) < R) ++log2R;
   a.log2R = log2R;
   const int rpw = 4;
-  // strip kernel: dwords per bin, template reach (1 or 2) and GLCMs per partition
-  int sD = 0, smd = 1, skp = 0;
+  // strip kernel: layout, template reach (1 or 2) and workgroup size
+  StripLayout sl;
+  const int smd = std::max(c.maxdy, c.maxadx) <= 1 ? 1 : 2;
   if (path == kPathStrips) {
-    sD = strip_dwords(R, t.counter_bits == 16 ? 16 : 32);
-    smd = std::max(c.maxdy, c.maxadx) <= 1 ? 1 : 2;
-    skp = sD ? strip_kp(p, sD) : 0;
-    if (skp == 0) return GLCM_EINVAL;  // tunings are validated when set
-    a.kp = skp;
-    a.part_words = (uint32_t)skp * NN;
-    a.P = (p->K + skp - 1) / skp;
+    const int swg = std::min(t.wg_size, glcm::strip_max_threads(b, smd));
+    if (!strip_layout(p, W, y_end - y_begin, R, t.counter_bits == 16, swg, &sl))
+      return GLCM_EINVAL;  // tunings are validated when set
+    a.kp = sl.kp;
+    a.kg = sl.kg;
+    a.c16 = sl.pair;
+    a.part_words = (uint32_t)sl.kp * NN;
+    a.P = sl.P;
     a.pitch = (uint32_t)p->N + 1u;
     for (int k = 0; k < p->K; ++k) {
       a.dx[k] = c.dx[k];
@@ -507,26 +557,22 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   size_t lds_need = ((size_t)a.part_words << log2R) * 4u;
   if (path == kPathRows)
     lds_need = (size_t)(a.part_words / NN) * row_glcm_dwords(p->N, R, t.counter_bits == 16 ? 16 : 32) * 4u;
-  const int spans = (((W + 15) / 16) + 63) / 64;
-  if (path == kPathStrips)
-    lds_need = (size_t)(p->N + 1) * (size_t)(p->N + 1) * (size_t)skp * (size_t)sD * 4u;
   lds_need = std::max(lds_need, (size_t)wg * 4u);
   const int per_cu = std::max(1, std::min((int)(((size_t)p->lds_budget_words * 4u + 1024u) / lds_need), 32 / nwaves));
   int target_groups = std::max(1, p->num_cus * per_cu / a.P);
   int nregions = std::min(rows, target_groups);
-  // strip kernel: bands tall enough for strips of >= 4 rows on every wavefront
-  if (path == kPathStrips) nregions = std::max(1, std::min(nregions, rows * spans / (4 * nwaves)));
   // keep partials within 256 MiB
   while (nregions > 1 && (uint64_t)nregions * words * 4ull > (256ull << 20)) nregions = (nregions + 1) / 2;
-  const int region_rows = (rows + nregions - 1) / nregions;
+  int region_rows = (rows + nregions - 1) / nregions;
   nregions = (rows + region_rows - 1) / region_rows;
+  if (path == kPathStrips) {
+    nregions = sl.nregions;
+    region_rows = sl.region_rows;
+    a.strip_rows = sl.strip_rows;
+  }
   a.nregions = nregions;
   a.region_rows = region_rows;
   a.rows_per_wave = rpw;
-  if (path == kPathStrips) {
-    const int strips_per_span = std::max(1, nwaves / spans);
-    a.strip_rows = std::max(1, (region_rows + strips_per_span - 1) / strips_per_span);
-  }
 
   if (xcd) {
     a.xbuf = p->xbuf;
@@ -553,16 +599,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     a.pitch = row_pitch(p->N);
     lds_bytes = (size_t)(a.part_words / NN) * row_glcm_dwords(p->N, R, bits) * 4u;
   }
-  if (path == kPathStrips) {
-    // 16-bit counters only when no count can reach 2^16: a counter is shared
-    // by wg / (2D) lanes, each voting at most 16 pixels per row it walks
-    int bits = t.counter_bits == 16 ? 16 : 32;
-    const int nstrips = spans * ((region_rows + a.strip_rows - 1) / a.strip_rows);
-    const uint64_t rows_per_lane = (uint64_t)((nstrips + nwaves - 1) / nwaves) * (uint64_t)a.strip_rows;
-    if (bits == 16 && (uint64_t)wg / (2u * sD) * 16u * rows_per_lane > 65535u) bits = 32;  // same layout, one copy per dword
-    a.c16 = bits == 16 ? 1 : 0;
-    lds_bytes = lds_need;
-  }
+  if (path == kPathStrips) lds_bytes = sl.lds;
   lds_bytes = std::max(lds_bytes, (size_t)wg * 4u);
 
   const int maxdy = c.maxdy <= 1 ? 1 : (c.maxdy <= 2 ? 2 : 4);
@@ -576,7 +613,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   }
   hipError_t e;
   if (path == kPathStrips) {
-    e = glcm::launch_vote_strips(a, b, smd, sD, wg, lds_bytes, stream);
+    e = glcm::launch_vote_strips(a, b, smd, sl.D, wg, lds_bytes, stream);
   } else if (path == kPathRows) {
     e = glcm::launch_vote_rows(a, b, maxdy, rpw, wg, lds_bytes, stream);
   } else {
@@ -807,7 +844,7 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
   // minimal number of partitions
   std::vector<glcm_tuning_t> cand;
   if (start.path == kPathStrips) {
-    const int Pmin = strip_partitions(plan, 4, 32);
+    const int Pmin = strip_partitions(plan, 4, 16);
     for (int bits : {32, 16})
       for (int R = 4; R <= 32; R *= 2) {
         const int P = strip_partitions(plan, R, bits);

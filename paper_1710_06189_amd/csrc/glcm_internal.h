@@ -45,8 +45,10 @@ struct VoteArgs {
   int rows_per_wave;          // row kernel: first-pixel rows per wavefront slab (4)
   uint32_t pitch;             // row kernel: LDS row pitch of a GLCM, >= N + 1 (row/column N: sentinel)
   Quant div_n, div_nn;        // magic/shift for dividing by N and by N*N (only those fields used)
-  int c16;                    // row kernel: 16-bit counters, two copies per dword
-  int kp;                     // strip kernel: GLCMs per partition (LDS layout stride, <= 4)
+  int c16;                    // slab kernel: 16-bit counters, two copies per dword; strip kernel:
+                              // 16-bit counters, two GLCMs per dword
+  int kp;                     // strip kernel: GLCMs per partition (<= 4)
+  int kg;                     // strip kernel: dword groups per bin (kp, or kp / 2 rounded up with c16)
   int strip_rows;             // strip kernel: first-pixel rows per wavefront strip
   int32_t vcode[kMaxK];       // strip kernel: dy * (2 MAXDY + 1) + dx + MAXDY of each canonical offset
                               // (dwords: the kernel reads them with scalar loads)
@@ -85,7 +87,7 @@ struct BatchArgs {
 hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream);
 hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
                             hipStream_t stream);
-// D = dwords per bin (4, 8 or 16), maxdy = 1 or 2.
+// D = dwords per bin (4, 8, 16 or 32), maxdy = 1 or 2.
 hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
                               hipStream_t stream);
 // out[w] = (accumulate ? out[w] : 0) + sum_b partials[b * M + w] for w < M.

@@ -468,14 +468,19 @@ __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
 // already turned into its share of an LDS address, and prefetches the rows
 // below while it votes, so each pixel is read from memory once per strip.
 //
-// LDS layout of a partition (kp GLCMs): dword ((bin * kp + k) * D + g) holds
-// the copy g (lane mod D) of bin = a * n1 + b of the partition's k-th GLCM,
-// n1 = N + 1 (row and column N catch pixels outside the image).  Its byte
-// address splits as
-//     base(a) + term(b) + 4 D k,   term(v) = v * 4 D kp,   base(a) = 4 g + term(a) * n1,
-// so a vote costs one VALU add of a first-pixel base and a second-pixel term,
-// and 4 D k rides in the offset field of the LDS atomic.  The 16 lanes of a
-// quarter-wave (one LDS pass) use 16 distinct dwords of any bin when D >= 16.
+// LDS layout of a partition (kp GLCMs in kg dword groups): dword
+// ((bin * kg + q) * D + g) holds copy g (lane mod D) of bin = a * n1 + b,
+// n1 = N + 1 (row and column N catch pixels outside the image), for GLCM q of
+// the partition (kg = kp, 32-bit counters) or for GLCMs 2q and 2q+1 in its
+// low and high halves (PAIR: kg = kp / 2 rounded up, 16-bit counters, used
+// when the host has bounded every count below 2^16).  The byte address splits
+// as
+//     base(a) + term(b) + 4 D q,   term(v) = v * 4 D kg,   base(a) = 4 g + term(a) * n1,
+// so a vote costs one VALU add of a first-pixel base and a second-pixel term;
+// 4 D q rides in the offset field of the LDS atomic and the half in the
+// added value.  gfx950's LDS serves 32 lanes per pass over 32 banks: with
+// D = 32 every lane of a pass writes its own bank whatever the bins; with
+// D = 16 lanes l and l + 16 share one (a two-way conflict on every vote).
 // ---------------------------------------------------------------------------
 template <int NX>
 struct TermRow {
@@ -485,30 +490,48 @@ struct TermRow {
 // Loads of one row of a strip lane: its 16-pixel chunk and 4-pixel halo
 // blocks on both sides.  Every lane issues the same loads with addresses
 // clamped into the image (the row below the last, a chunk past the right
-// edge or a halo before column 0 read some other pixels of the image, which
+// edge or a halo outside [0, W) read some other pixels of the image, which
 // to_terms replaces by the sentinel), so the number of loads in flight is the
-// same on every path and the prefetch needs no full wait.
+// same on every path and the prefetch needs no full wait.  Every access lies
+// in a 16-byte block that holds a pixel of the row it addresses.
 struct Geom {
   const void* img;  // 16-byte aligned, row pitch a multiple of 16 bytes
   int64_t stride;   // elements
   int W, H;
 };
 
+// Byte offsets, within a row, of what a lane loads: its chunk (a chunk that
+// starts inside the row), the chunk's second half for 16-bit pixels (only
+// when it starts inside the row: the pitch is a multiple of 8 pixels, not
+// necessarily of 16) and the halo blocks (only where they start inside the
+// row: a lane past the right edge must not read x0 - 4, which on the last
+// row is past the image).  Fixed for a lane's whole strip.
+struct LaneCols {
+  uint32_t c, c2, l, r;
+};
+
 template <typename Pix>
-__device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y, int x0) {
-  const Pix* row = (const Pix*)a.img + (int64_t)min(y, a.H - 1) * a.stride;
-  const int xc = min(x0, (a.W - 1) & ~15);           // a chunk that starts inside the row
-  const int xl = x0 >= 16 ? x0 - 4 : 0;
+__device__ __forceinline__ LaneCols lane_cols(const Geom& a, int x0) {
+  const int xc = min(x0, (a.W - 1) & ~15);
+  const int xl = (x0 >= 16 && x0 - 4 < a.W) ? x0 - 4 : xc;
   const int xr = x0 + 16 < a.W ? x0 + 16 : xc;
-  rc.v[0] = *(const uint4*)(row + xc);
+  const int xc2 = xc + 8 < a.W ? xc + 8 : xc;
+  constexpr uint32_t b = sizeof(Pix);
+  return {(uint32_t)xc * b, (uint32_t)xc2 * b, (uint32_t)xl * b, (uint32_t)xr * b};
+}
+
+// (In the strip kernel y is the same on every lane, so the row address stays
+// in scalar registers and each load is a scalar base plus the lane's offset.)
+template <typename Pix>
+__device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y, const LaneCols& o) {
+  const char* row = (const char*)a.img + (int64_t)min(y, a.H - 1) * a.stride * (int64_t)sizeof(Pix);
+  rc.v[0] = *(const uint4*)(row + o.c);
   if (sizeof(Pix) == 1) {
-    rc.lh[0] = *(const uint32_t*)(row + xl);
-    rc.rh[0] = *(const uint32_t*)(row + xr);
+    rc.lh[0] = *(const uint32_t*)(row + o.l);
+    rc.rh[0] = *(const uint32_t*)(row + o.r);
   } else {
-    // the second 8 pixels only when they start inside the row (the pitch is
-    // a multiple of 8 pixels, not necessarily of 16)
-    rc.v[sizeof(Pix) - 1] = *(const uint4*)(row + (xc + 8 < a.W ? xc + 8 : xc));
-    const uint2 l = *(const uint2*)(row + xl), r = *(const uint2*)(row + xr);
+    rc.v[sizeof(Pix) - 1] = *(const uint4*)(row + o.c2);
+    const uint2 l = *(const uint2*)(row + o.l), r = *(const uint2*)(row + o.r);
     rc.lh[0] = l.x; rc.lh[sizeof(Pix) - 1] = l.y;
     rc.rh[0] = r.x; rc.rh[sizeof(Pix) - 1] = r.y;
   }
@@ -518,10 +541,12 @@ __device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y
 // the image.  Halo pixels come from the neighbouring lanes; the wave-boundary
 // lanes use the halo dwords they loaded themselves.  SEG: a wavefront holds
 // several row segments side by side, so a halo pixel outside [0, W) takes the
-// sentinel whatever the neighbouring lane holds.
+// sentinel whatever the neighbouring lane holds.  edge (the same on every
+// lane): some pixel of the wavefront's chunks or halos lies at or past W;
+// otherwise the per-byte clipping is skipped.
 template <typename Pix, int NX, bool SEG = false, class QA>
 __device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc, const QA& a, const Geom& g, int y,
-                                         int x0, uint32_t sent4, uint32_t mb) {
+                                         int x0, uint32_t sent4, uint32_t mb, bool edge) {
   uint32_t c[4], lh, rh;
   if (sizeof(Pix) == 1) {
     c[0] = quant4_u8(rc.v[0].x, a); c[1] = quant4_u8(rc.v[0].y, a);
@@ -537,11 +562,13 @@ __device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc
   }
   if (y >= g.H) {
     c[0] = c[1] = c[2] = c[3] = lh = rh = sent4;
-  } else {
+  } else if (edge) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) c[m] = clip_dword(c[m], x0 + 4 * m, g.W, sent4);
     lh = x0 >= 16 ? clip_dword(lh, x0 - 4, g.W, sent4) : sent4;
     rh = clip_dword(rh, x0 + 16, g.W, sent4);
+  } else {
+    lh = x0 >= 16 ? lh : sent4;
   }
 #pragma unroll
   for (int t = 0; t < 16; ++t) r.s[NX + t] = __umul24((c[t >> 2] >> ((t & 3) * 8)) & 0xffu, mb);
@@ -584,11 +611,12 @@ __device__ __forceinline__ void vote_row(const uint32_t (&fa)[16], const TermRow
 
 // Votes of the partition's GLCM number KI (compile time, so its LDS offset is
 // an immediate) for first-pixel row `cur` of the ring.
-template <int MAXDY, int D, int KI, int CUR>
+template <int MAXDY, int D, int KI, int CUR, bool PAIR = false>
 __device__ __forceinline__ void vote_glcm(const uint32_t (&fa)[16],
-                                          const TermRow<MAXDY> (&ring)[MAXDY + 1], int code, uint32_t inc) {
+                                          const TermRow<MAXDY> (&ring)[MAXDY + 1], int code, uint32_t one) {
   constexpr int NR = MAXDY + 1, NXS = 2 * MAXDY + 1;
-  constexpr uint32_t KOFF = 4u * D * KI;
+  constexpr uint32_t KOFF = 4u * D * (PAIR ? KI / 2 : KI);
+  const uint32_t inc = PAIR && (KI & 1) ? one << 16 : one;
   // code = dy * (2 MAXDY + 1) + dx + MAXDY
   // (the asm marker keeps the compiler from merging the cases into one body
   // that would index the ring through memory)
@@ -615,56 +643,74 @@ __device__ __forceinline__ void vote_glcm(const uint32_t (&fa)[16],
 // One first-pixel row of a strip: bases, votes of every GLCM of the
 // partition, then the ring slot of this row takes the row NR below (from the
 // prefetched raw row) and the raw slot starts loading the row 2 NR below.
-template <typename Pix, int MAXDY, int D, int CUR>
+template <typename Pix, int MAXDY, int D, bool PAIR, int CUR>
 __device__ __forceinline__ void strip_step(const VoteArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
-                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, uint32_t C,
-                                           uint32_t n1, uint32_t mb, uint32_t inc, uint32_t sent4,
+                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, const LaneCols& cols,
+                                           bool edge, uint32_t C,
+                                           uint32_t n1, uint32_t mb, uint32_t sent4,
                                            const int (&code)[4], int kp) {
   constexpr int NR = MAXDY + 1;
   uint32_t fa[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) fa[t] = __umul24(ring[CUR].s[MAXDY + t], n1) + C;
-  vote_glcm<MAXDY, D, 0, CUR>(fa, ring, code[0], inc);
-  if (kp > 1) vote_glcm<MAXDY, D, 1, CUR>(fa, ring, code[1], inc);
-  if (kp > 2) vote_glcm<MAXDY, D, 2, CUR>(fa, ring, code[2], inc);
-  if (kp > 3) vote_glcm<MAXDY, D, 3, CUR>(fa, ring, code[3], inc);
-  to_terms<Pix, MAXDY>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb);
-  load_row<Pix>(raw[CUR], geo, y + 2 * NR, x0);
+  vote_glcm<MAXDY, D, 0, CUR, PAIR>(fa, ring, code[0], 1u);
+  if (kp > 1) vote_glcm<MAXDY, D, 1, CUR, PAIR>(fa, ring, code[1], 1u);
+  if (kp > 2) vote_glcm<MAXDY, D, 2, CUR, PAIR>(fa, ring, code[2], 1u);
+  if (kp > 3) vote_glcm<MAXDY, D, 3, CUR, PAIR>(fa, ring, code[3], 1u);
+  to_terms<Pix, MAXDY>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, edge);
+  load_row<Pix>(raw[CUR], geo, y + 2 * NR, cols);
 }
 
 // Merge of the strip layout: lanes read consecutive 16-byte units (D / 4
 // lanes per GLCM bin), add them up across those lanes, and the first lane of
 // each bin adds the sum to the per-XCD accumulator (or stores it to the band
 // partial), transposed for offsets that were negated.
-template <int D>
+template <int D, bool PAIR>
 __device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int region, int kp0, int kp,
                                      uint32_t n1) {
   constexpr uint32_t QPB = D / 4;  // 16-byte units per bin
   __syncthreads();
-  const uint32_t N = a.q.nlev, NN = N * N;
-  const uint32_t units = n1 * n1 * (uint32_t)a.kp * QPB;
+  const uint32_t N = a.q.nlev, NN = N * N, kg = (uint32_t)a.kg;
+  const uint32_t units = n1 * n1 * kg * QPB;
   uint32_t* dst = a.partials + (size_t)region * a.words_total;
   uint32_t xcc = 0;
   if (a.xbuf) asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
   uint32_t* xs = a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total;
   for (uint32_t u = threadIdx.x; u < units; u += blockDim.x) {
     const uint4 v = ((const uint4*)lds)[u];
-    uint32_t s = a.c16 ? (v.x & 0xffffu) + (v.x >> 16) + (v.y & 0xffffu) + (v.y >> 16) + (v.z & 0xffffu) +
-                             (v.z >> 16) + (v.w & 0xffffu) + (v.w >> 16)
+    // PAIR: lo = GLCM 2q (low halves), hi = GLCM 2q + 1 (high halves)
+    uint32_t lo = PAIR ? (v.x & 0xffffu) + (v.y & 0xffffu) + (v.z & 0xffffu) + (v.w & 0xffffu)
                        : (v.x + v.y) + (v.z + v.w);
-    if (QPB >= 2) s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0xb1, 0xf, 0xf, false);  // quad [1,0,3,2]
-    if (QPB >= 4) s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x4e, 0xf, 0xf, false);  // quad [2,3,0,1]
+    uint32_t hi = PAIR ? (v.x >> 16) + (v.y >> 16) + (v.z >> 16) + (v.w >> 16) : 0u;
+    if (QPB >= 2) {  // quad [1,0,3,2]
+      lo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xb1, 0xf, 0xf, false);
+      if (PAIR) hi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0xb1, 0xf, 0xf, false);
+    }
+    if (QPB >= 4) {  // quad [2,3,0,1]
+      lo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4e, 0xf, 0xf, false);
+      if (PAIR) hi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x4e, 0xf, 0xf, false);
+    }
+    if (QPB >= 8) {  // row_half_mirror: lane i of 8 meets lane 7 - i (the other quad)
+      lo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x141, 0xf, 0xf, false);
+      if (PAIR) hi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x141, 0xf, 0xf, false);
+    }
     if (u % QPB != 0) continue;
-    const uint32_t blk = u / QPB, k = blk % (uint32_t)a.kp, bin = blk / (uint32_t)a.kp;
+    const uint32_t blk = u / QPB, q = blk % kg, bin = blk / kg;
     const uint32_t i = bin / n1, j = bin % n1;
-    if ((int)k >= kp || i >= N || j >= N) continue;
-    const uint32_t kg = (uint32_t)kp0 + k;
-    const bool tr = (a.tmask >> kg) & 1ull;
-    const uint32_t w = kg * NN + (tr ? j * N + i : i * N + j);
-    if (a.xbuf) {
-      if (s) __hip_atomic_fetch_add(xs + w, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else {
-      dst[w] = s;
+    if (i >= N || j >= N) continue;
+#pragma unroll
+    for (uint32_t h = 0; h < (PAIR ? 2u : 1u); ++h) {
+      const uint32_t k = PAIR ? 2u * q + h : q;
+      if ((int)k >= kp) break;
+      const uint32_t s = h ? hi : lo;
+      const uint32_t kgl = (uint32_t)kp0 + k;
+      const bool tr = (a.tmask >> kgl) & 1ull;
+      const uint32_t w = kgl * NN + (tr ? j * N + i : i * N + j);
+      if (a.xbuf) {
+        if (s) __hip_atomic_fetch_add(xs + w, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        dst[w] = s;
+      }
     }
   }
 }
@@ -672,18 +718,20 @@ __device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int
 // (uint16 pixels with a reach of 2 need more than the 128 registers a
 // 1024-thread workgroup leaves a lane: that variant takes at most 512 threads,
 // as strip_max_threads tells the host)
-template <typename Pix, int MAXDY, int D>
+template <typename Pix, int MAXDY, int D, bool PAIR>
 __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k_vote_strips(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   constexpr int NR = MAXDY + 1;
   const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
   const int kp0 = part * a.kp, kp = min(a.kp, a.K - kp0);
   const uint32_t N = a.q.nlev, n1 = a.pitch;
-  const uint32_t mb = 4u * D * (uint32_t)a.kp;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t mb = 4u * D * (uint32_t)a.kg;
+  // (readfirstlane tells the compiler the wavefront index is uniform, so
+  // strip and row indices, and the row addresses, live in scalar registers)
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nwaves = blockDim.x >> 6;
   const uint32_t g = threadIdx.x & (D - 1u);
   const uint32_t C = lds_address(lds) + 4u * g;
-  const uint32_t inc = a.c16 ? (1u << (16u * ((threadIdx.x / D) & 1u))) : 1u;
   const uint32_t sent4 = N * 0x01010101u;
   const int y0 = a.y_begin + region * a.region_rows;
   const int y1 = min(a.y_end, y0 + a.region_rows);
@@ -704,36 +752,40 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
   int strip = wave;
   if (strip < nstrips) {
     const int x0 = (((strip % spans) << 6) + lane) << 4, ya = y0 + (strip / spans) * a.strip_rows;
+    const LaneCols cols = lane_cols<Pix>(geo, x0);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, x0);
+    for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
   }
-  zero_lds(lds, n1 * n1 * (uint32_t)a.kp * D);
+  zero_lds(lds, n1 * n1 * (uint32_t)a.kg * D);
   __syncthreads();
 
   for (; strip < nstrips; strip += nwaves) {
-    const int x0 = (((strip % spans) << 6) + lane) << 4;
+    const int span = strip % spans;
+    const int x0 = ((span << 6) + lane) << 4;
     const int ya = y0 + (strip / spans) * a.strip_rows;
     const int yb = min(y1, ya + a.strip_rows);
+    const LaneCols cols = lane_cols<Pix>(geo, x0);
+    const bool edge = ((span + 1) << 10) + 4 > a.W;  // chunks or right halos reach column W
     if (strip != wave) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, x0);
+      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      to_terms<Pix, MAXDY>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb);
-      load_row<Pix>(raw[r], geo, ya + NR + r, x0);
+      to_terms<Pix, MAXDY>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb, edge);
+      load_row<Pix>(raw[r], geo, ya + NR + r, cols);
     }
     for (int y = ya; y < yb; y += NR) {
-      strip_step<Pix, MAXDY, D, 0>(a, geo, ring, raw, y, x0, C, n1, mb, inc, sent4, code, kp);
+      strip_step<Pix, MAXDY, D, PAIR, 0>(a, geo, ring, raw, y, x0, cols, edge, C, n1, mb, sent4, code, kp);
       if (y + 1 >= yb) break;
-      strip_step<Pix, MAXDY, D, 1>(a, geo, ring, raw, y + 1, x0, C, n1, mb, inc, sent4, code, kp);
+      strip_step<Pix, MAXDY, D, PAIR, 1>(a, geo, ring, raw, y + 1, x0, cols, edge, C, n1, mb, sent4, code, kp);
       if constexpr (NR > 2) {
         if (y + 2 >= yb) break;
-        strip_step<Pix, MAXDY, D, 2>(a, geo, ring, raw, y + 2, x0, C, n1, mb, inc, sent4, code, kp);
+        strip_step<Pix, MAXDY, D, PAIR, 2>(a, geo, ring, raw, y + 2, x0, cols, edge, C, n1, mb, sent4, code, kp);
       }
     }
   }
-  store_partial_strips<D>(a, lds, region, kp0, kp, n1);
+  store_partial_strips<D, PAIR>(a, lds, region, kp0, kp, n1);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,7 +886,7 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, f
 template <int MAXDY, int D, int KI, int CUR>
 __device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermRow<MAXDY> (&ring)[MAXDY + 1],
                                            const int (&code)[4], int K, uint32_t inc) {
-  vote_glcm<MAXDY, D, KI, CUR>(fa, ring, code[KI], inc);
+  vote_glcm<MAXDY, D, KI, CUR>(fa, ring, code[KI], inc);  // 32-bit counters
   if constexpr (KI + 1 < kStripMaxKp) {
     if (K > KI + 1) batch_vote<MAXDY, D, KI + 1, CUR>(fa, ring, code, K, inc);
   }
@@ -842,15 +894,16 @@ __device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermR
 
 template <typename Pix, int MAXDY, int D, int CUR>
 __device__ __forceinline__ void batch_step(const BatchArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
-                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, uint32_t C, uint32_t n1,
+                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, const LaneCols& cols,
+                                           uint32_t C, uint32_t n1,
                                            uint32_t mb, uint32_t sent4, const int (&code)[4]) {
   constexpr int NR = MAXDY + 1;
   uint32_t fa[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) fa[t] = __umul24(ring[CUR].s[MAXDY + t], n1) + C;
   batch_vote<MAXDY, D, 0, CUR>(fa, ring, code, a.K, 1u);
-  to_terms<Pix, MAXDY, true>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb);
-  load_row<Pix>(raw[CUR], geo, y + 2 * NR, x0);
+  to_terms<Pix, MAXDY, true>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, true);
+  load_row<Pix>(raw[CUR], geo, y + 2 * NR, cols);
 }
 
 template <typename Pix, int MAXDY, int D>
@@ -888,22 +941,23 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
       const int ya = (blk * segs + (live ? seg : 0)) * h;
       TermRow<MAXDY> ring[NR];
       RawChunk<Pix> raw[NR];
+      const LaneCols cols = lane_cols<Pix>(geo, x0);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, x0);
+      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        to_terms<Pix, MAXDY, true>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb);
-        load_row<Pix>(raw[r], geo, ya + NR + r, x0);
+        to_terms<Pix, MAXDY, true>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb, true);
+        load_row<Pix>(raw[r], geo, ya + NR + r, cols);
       }
       // every lane takes h steps; rows past the image or the lane's segment
       // end carry the sentinel or belong to this segment's own run
       for (int j = 0; j < h; j += NR) {
-        batch_step<Pix, MAXDY, D, 0>(a, geo, ring, raw, ya + j, x0, C, n1, mb, sent4, code);
+        batch_step<Pix, MAXDY, D, 0>(a, geo, ring, raw, ya + j, x0, cols, C, n1, mb, sent4, code);
         if (j + 1 >= h) break;
-        batch_step<Pix, MAXDY, D, 1>(a, geo, ring, raw, ya + j + 1, x0, C, n1, mb, sent4, code);
+        batch_step<Pix, MAXDY, D, 1>(a, geo, ring, raw, ya + j + 1, x0, cols, C, n1, mb, sent4, code);
         if constexpr (NR > 2) {
           if (j + 2 >= h) break;
-          batch_step<Pix, MAXDY, D, 2>(a, geo, ring, raw, ya + j + 2, x0, C, n1, mb, sent4, code);
+          batch_step<Pix, MAXDY, D, 2>(a, geo, ring, raw, ya + j + 2, x0, cols, C, n1, mb, sent4, code);
         }
       }
     }
@@ -987,15 +1041,22 @@ hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int r
                           : launch_rows_t<uint16_t>(a, maxdy, wg, lds_bytes, stream);
 }
 
-template <typename Pix, int MAXDY>
-static hipError_t launch_strips_t(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream) {
+template <typename Pix, int MAXDY, bool PAIR>
+static hipError_t launch_strips_p(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream) {
   const dim3 grid(a.nregions * a.P), block(wg);
   switch (D) {
-    case 4: return launch(k_vote_strips<Pix, MAXDY, 4>, a, grid, block, lds_bytes, stream);
-    case 8: return launch(k_vote_strips<Pix, MAXDY, 8>, a, grid, block, lds_bytes, stream);
-    case 16: return launch(k_vote_strips<Pix, MAXDY, 16>, a, grid, block, lds_bytes, stream);
+    case 4: return launch(k_vote_strips<Pix, MAXDY, 4, PAIR>, a, grid, block, lds_bytes, stream);
+    case 8: return launch(k_vote_strips<Pix, MAXDY, 8, PAIR>, a, grid, block, lds_bytes, stream);
+    case 16: return launch(k_vote_strips<Pix, MAXDY, 16, PAIR>, a, grid, block, lds_bytes, stream);
+    case 32: return launch(k_vote_strips<Pix, MAXDY, 32, PAIR>, a, grid, block, lds_bytes, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename Pix, int MAXDY>
+static hipError_t launch_strips_t(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream) {
+  return a.c16 ? launch_strips_p<Pix, MAXDY, true>(a, D, wg, lds_bytes, stream)
+               : launch_strips_p<Pix, MAXDY, false>(a, D, wg, lds_bytes, stream);
 }
 
 hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,

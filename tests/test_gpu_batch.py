@@ -91,7 +91,7 @@ def test_batch_levels_u8(N, lo, hi):
     run_batch(imgs, N, lo, hi, synth.offsets_for([1]))
 
 
-@pytest.mark.parametrize("N,lo,hi", [(64, 0, 65535), (100, 1000, 60000)])
+@pytest.mark.parametrize("N,lo,hi", [(32, 0, 65535), (40, 1000, 60000)])
 def test_batch_u16(N, lo, hi):
     imgs = [synth.smooth(80 + 13 * i, 48 + 40 * i, 3.0, 800 + i, np.uint16, noise_frac=0.05) for i in range(5)]
     run_batch(imgs, N, lo, hi, synth.offsets_for([2]))

@@ -110,7 +110,7 @@ def test_forced_paths(flags, name, dtype, merge):
 
 
 SLAB_LAYOUTS = [(1, 32), (2, 32), (4, 32), (8, 32), (16, 32), (2, 16), (4, 16), (8, 16), (16, 16), (32, 16)]
-STRIP_LAYOUTS = [(4, 32), (8, 32), (16, 32), (8, 16), (16, 16), (32, 16)]
+STRIP_LAYOUTS = [(4, 32), (8, 32), (16, 32), (32, 32), (4, 16), (8, 16), (16, 16), (32, 16)]
 
 
 @pytest.mark.parametrize("kernel,R,bits", [("slabs", R, b) for R, b in SLAB_LAYOUTS] +
@@ -129,10 +129,27 @@ def test_replica_counter_and_workgroup_sweep(kernel, R, bits, wg):
         plan.close()
 
 
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 7])
+@pytest.mark.parametrize("R", [4, 16, 32])
+def test_strip_pairs_any_offset_count(K, R):
+    """16-bit pair layout with an odd number of GLCMs per partition and with
+    several partitions; offsets include negated ones (stored transposed)."""
+    pool = [(1, 0), (-1, -1), (0, 1), (1, 1), (-1, 1), (0, -1), (-1, 0)]
+    offs = pool[:K]
+    img = synth.smooth(203, 1100, 3.0, 70 + K)
+    plan = G.glcm_plan_create(np.uint8, 32, offs, 1100, 203)
+    try:
+        t = plan.set_tuning(replicas=R, counter_bits=16)
+        assert G.PATH_NAMES[t.path] == "strips"
+        check(img, 32, 0, 255, offs, plan=plan, label=f"pairs K={K} R={R} P={t.partitions}")
+    finally:
+        plan.close()
+
+
 def test_strip_layout_rejects_unsupported_copies():
     plan = G.glcm_plan_create(np.uint8, 32, [(1, 0)], 256, 256)
     try:
-        for R, bits in [(1, 32), (2, 32), (32, 32), (4, 16), (64, 16)]:
+        for R, bits in [(1, 32), (2, 32), (64, 32), (2, 16), (64, 16)]:
             with pytest.raises(G.GlcmError):
                 plan.set_tuning(replicas=R, counter_bits=bits)
     finally:
@@ -155,7 +172,8 @@ def test_sixteen_bit_counters_near_the_bound():
 
 @pytest.mark.parametrize("W,H", [(4096, 4096), (16, 8192), (1024, 65535)])
 def test_sixteen_bit_strip_counters_constant_image(W, H):
-    """Every vote of a 16-bit strip counter in one bin, on the tallest bands."""
+    """Every vote of a 16-bit strip counter in one bin, on the tallest bands
+    (two GLCMs share each dword, so a wrap would also corrupt the other)."""
     img = synth.constant(H, W, 200)
     offs = synth.offsets_for([1])
     plan = G.glcm_plan_create(np.uint8, 16, offs, W, H)
