@@ -167,6 +167,23 @@ __global__ __launch_bounds__(kReduceQuads * kReduceGroups) void k_reduce(const u
   }
 }
 
+// Workgroup -> (band, partition).  Workgroups go to the XCDs round-robin
+// (workgroup b runs on XCD b mod 8), and every partition of a band reads the
+// band's rows: keeping the partitions of one band on one XCD lets its L2
+// serve the second read instead of HBM.  Workgroup b = 8 s + x takes
+// partition s mod P of band 8 (s / P) + x for the first 8 floor(nregions / 8)
+// bands; the remaining bands take the plain order (a bijection either way).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int2 band_of_block(int b, int P, int nregions) {
+  const int full = nregions / kXcds * kXcds;
+  if (P > 1 && b < full * P) {
+    const int x = b % kXcds, s = b / kXcds;
+    return make_int2(s / P * kXcds + x, s % P);
+  }
+  const int r = b - full * P;
+  return make_int2(full + r / P, r % P);
+}
+
 // ---------------------------------------------------------------------------
 // Generic counting kernel: any alignment, stride and offsets.  One thread per
 // first pixel, loads through the cache, votes into the LDS copies of the
@@ -175,7 +192,8 @@ __global__ __launch_bounds__(kReduceQuads * kReduceGroups) void k_reduce(const u
 template <typename Pix>
 __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-  const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
+  const int2 rp = band_of_block(blockIdx.x, a.P, a.nregions);
+  const int region = rp.x, part = rp.y;
   const uint32_t pbase = (uint32_t)part * a.part_words;
   const uint32_t pwords = min(a.part_words, a.words_total - pbase);
   zero_lds(lds, pwords << a.log2R);
@@ -395,7 +413,8 @@ __device__ __forceinline__ void vote_offset(uint32_t* lds, const Ring (&rows)[NR
 template <typename Pix, int MAXDY, int RPW>
 __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-  const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
+  const int2 rp = band_of_block(blockIdx.x, a.P, a.nregions);
+  const int region = rp.x, part = rp.y;
   const uint32_t N = a.q.nlev, N1 = a.pitch, NN = N * N, NN1 = N1 * N1;
   // Partitions of the row kernel are groups of whole GLCMs (offsets).
   const uint32_t pbase = (uint32_t)part * a.part_words;
@@ -600,6 +619,15 @@ __device__ __forceinline__ uint32_t lds_address(const uint32_t* p) {
   return (uint32_t)(size_t)(const lds_word_t*)p;
 }
 
+// a * b + c on the 24-bit multiplier.  Callers pass a and b below 2^24 (a term
+// level * mb and the row pitch); written out because the compiler cannot
+// always see that bound and would mask a first.
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
 template <int NX, int DX, uint32_t KOFF>
 __device__ __forceinline__ void vote_row(const uint32_t (&fa)[16], const TermRow<NX>& second, uint32_t inc) {
 #pragma unroll
@@ -652,11 +680,12 @@ __device__ __forceinline__ void strip_step(const VoteArgs& a, const Geom& geo, T
   constexpr int NR = MAXDY + 1;
   uint32_t fa[16];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) fa[t] = __umul24(ring[CUR].s[MAXDY + t], n1) + C;
+  for (int t = 0; t < 16; ++t) fa[t] = mad_u24(ring[CUR].s[MAXDY + t], n1, C);
+  // (the code of a GLCM slot beyond kp is -1, which no case matches)
   vote_glcm<MAXDY, D, 0, CUR, PAIR>(fa, ring, code[0], 1u);
-  if (kp > 1) vote_glcm<MAXDY, D, 1, CUR, PAIR>(fa, ring, code[1], 1u);
-  if (kp > 2) vote_glcm<MAXDY, D, 2, CUR, PAIR>(fa, ring, code[2], 1u);
-  if (kp > 3) vote_glcm<MAXDY, D, 3, CUR, PAIR>(fa, ring, code[3], 1u);
+  vote_glcm<MAXDY, D, 1, CUR, PAIR>(fa, ring, code[1], 1u);
+  vote_glcm<MAXDY, D, 2, CUR, PAIR>(fa, ring, code[2], 1u);
+  vote_glcm<MAXDY, D, 3, CUR, PAIR>(fa, ring, code[3], 1u);
   to_terms<Pix, MAXDY>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, edge);
   load_row<Pix>(raw[CUR], geo, y + 2 * NR, cols);
 }
@@ -676,6 +705,14 @@ __device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int
   uint32_t xcc = 0;
   if (a.xbuf) asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
   uint32_t* xs = a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total;
+  // unit u = ((i * n1 + j) * kg + q) * QPB + r: r stays fixed for a thread
+  // (blockDim is a multiple of QPB) and (i, j, q) advance by the mixed-radix
+  // digits of blockDim / QPB each pass, so the loop divides nothing
+  const uint32_t S = blockDim.x / QPB;
+  const uint32_t sq = S % kg, sj = S / kg % n1, si = S / kg / n1;
+  const uint32_t blk0 = threadIdx.x / QPB;
+  uint32_t q = blk0 % kg, j = blk0 / kg % n1, i = blk0 / kg / n1;
+  const bool lead = threadIdx.x % QPB == 0;
   for (uint32_t u = threadIdx.x; u < units; u += blockDim.x) {
     const uint4 v = ((const uint4*)lds)[u];
     // PAIR: lo = GLCM 2q (low halves), hi = GLCM 2q + 1 (high halves)
@@ -694,24 +731,29 @@ __device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int
       lo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x141, 0xf, 0xf, false);
       if (PAIR) hi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x141, 0xf, 0xf, false);
     }
-    if (u % QPB != 0) continue;
-    const uint32_t blk = u / QPB, q = blk % kg, bin = blk / kg;
-    const uint32_t i = bin / n1, j = bin % n1;
-    if (i >= N || j >= N) continue;
+    if (lead && i < N && j < N) {
 #pragma unroll
-    for (uint32_t h = 0; h < (PAIR ? 2u : 1u); ++h) {
-      const uint32_t k = PAIR ? 2u * q + h : q;
-      if ((int)k >= kp) break;
-      const uint32_t s = h ? hi : lo;
-      const uint32_t kgl = (uint32_t)kp0 + k;
-      const bool tr = (a.tmask >> kgl) & 1ull;
-      const uint32_t w = kgl * NN + (tr ? j * N + i : i * N + j);
-      if (a.xbuf) {
-        if (s) __hip_atomic_fetch_add(xs + w, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      } else {
-        dst[w] = s;
+      for (uint32_t h = 0; h < (PAIR ? 2u : 1u); ++h) {
+        const uint32_t k = PAIR ? 2u * q + h : q;
+        if ((int)k >= kp) break;
+        const uint32_t s = h ? hi : lo;
+        const uint32_t kgl = (uint32_t)kp0 + k;
+        const bool tr = (a.tmask >> kgl) & 1ull;
+        const uint32_t w = kgl * NN + (tr ? j * N + i : i * N + j);
+        if (a.xbuf) {
+          if (s) __hip_atomic_fetch_add(xs + w, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+          dst[w] = s;
+        }
       }
     }
+    q += sq;
+    const uint32_t cq = q >= kg;
+    q -= cq ? kg : 0u;
+    j += sj + cq;  // < 2 n1
+    const uint32_t cj = j >= n1;
+    j -= cj ? n1 : 0u;
+    i += si + cj;
   }
 }
 
@@ -722,7 +764,8 @@ template <typename Pix, int MAXDY, int D, bool PAIR>
 __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k_vote_strips(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   constexpr int NR = MAXDY + 1;
-  const int region = blockIdx.x / a.P, part = blockIdx.x % a.P;
+  const int2 rp = band_of_block(blockIdx.x, a.P, a.nregions);
+  const int region = rp.x, part = rp.y;
   const int kp0 = part * a.kp, kp = min(a.kp, a.K - kp0);
   const uint32_t N = a.q.nlev, n1 = a.pitch;
   const uint32_t mb = 4u * D * (uint32_t)a.kg;
@@ -757,6 +800,10 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
     for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
   }
   zero_lds(lds, n1 * n1 * (uint32_t)a.kg * D);
+  // the quantizer's scalars are waited for here, once: a first use inside
+  // the loop would wait on the counter the LDS votes share, every row
+  asm volatile("" ::"s"(a.qfast), "s"(a.qfast_shift), "s"(a.qfast_mask), "s"(a.q.lo), "s"(a.q.hi), "s"(a.q.nlev),
+               "s"(a.q.magic), "s"(a.q.shift));
   __syncthreads();
 
   for (; strip < nstrips; strip += nwaves) {
