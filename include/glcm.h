@@ -79,8 +79,9 @@ enum glcm_status {
 #define GLCM_FLAG_FORCE_PARTITIONED (1u << 1) /* split bins into LDS-sized partitions */
 #define GLCM_FLAG_FORCE_GLOBAL      (1u << 2) /* one global atomic per pair, no LDS */
 #define GLCM_FLAG_SERIAL_UPLOAD     (1u << 3) /* host images: copy, then count (no overlap) */
-#define GLCM_FLAG_TIMING            (1u << 4) /* record HIP events around each counting-kernel
-                                                 launch; read with glcm_plan_kernel_time() */
+#define GLCM_FLAG_TIMING            (1u << 4) /* time each counting-kernel launch with HIP events
+                                                 its dispatch stamps; read with
+                                                 glcm_plan_kernel_time() */
 #define GLCM_FLAG_FORCE_SLABS       (1u << 5) /* row-slab kernel even where the strip kernel
                                                  applies */
 
@@ -160,7 +161,9 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void *img, int W, int H,
  * For plans created with GLCM_FLAG_TIMING: waits for the recorded launches and
  * returns the summed duration (ms) of the counting kernel (the vote kernel,
  * without the merge step) over the launches since the previous call, as
- * measured by HIP events on each launch's stream; then forgets them.
+ * measured by HIP events that the kernel's dispatch packet stamps with the
+ * kernel's start and end (hipExtLaunchKernel), so launch latency is not
+ * included; then forgets them.
  * Errors: GLCM_EINVAL for NULL arguments; GLCM_EHIP.
  */
 GLCM_API int glcm_plan_kernel_time(glcm_plan_t plan, double *ms_total, int *launches);

@@ -176,6 +176,7 @@ struct glcm_plan_s {
   uint32_t* partials = nullptr;
   size_t partials_bytes = 0;
   uint32_t* xbuf = nullptr;  // [kXcdSlots][K*N*N] per-XCD accumulators, kept zero between calls
+  uint32_t xslots = glcm::kXcdSlots;  // slices the device's XCC_IDs reach (the rest stay zero)
 
 
   // ordering across streams
@@ -207,6 +208,33 @@ struct glcm_plan_s {
 };
 
 namespace {
+
+// Accumulation slices the per-XCD merge uses on a device: one more than the
+// largest XCC_ID (mod kXcdSlots) its workgroups report.  Workgroups go to the
+// XCDs round-robin, so 1024 probe workgroups visit every XCD.  Probed once
+// per device; on any failure all kXcdSlots slices are kept.
+uint32_t xcc_slots(int device) {
+  static std::mutex m;
+  static std::map<int, uint32_t> cache;
+  std::lock_guard<std::mutex> g(m);
+  auto it = cache.find(device);
+  if (it != cache.end()) return it->second;
+  constexpr int kBlocks = 1024;
+  uint32_t slots = glcm::kXcdSlots;
+  uint32_t* d = nullptr;
+  if (hipMalloc((void**)&d, kBlocks * sizeof(uint32_t)) == hipSuccess) {
+    std::vector<uint32_t> h(kBlocks, glcm::kXcdSlots - 1u);
+    if (glcm::launch_xcc_probe(d, kBlocks, nullptr) == hipSuccess &&
+        hipMemcpy(h.data(), d, kBlocks * sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess) {
+      uint32_t mx = 0;
+      for (uint32_t v : h) mx = std::max(mx, v & (glcm::kXcdSlots - 1u));
+      slots = mx + 1u;
+    }
+    (void)hipFree(d);
+  }
+  cache[device] = slots;
+  return slots;
+}
 
 // Row pitch of the LDS copy of a GLCM in the row kernel: at least N + 1 (row
 // and column N take the votes of pixels outside the image) and 2 mod 4, so
@@ -388,6 +416,7 @@ int plan_init(glcm_plan_t p) {
     if (bytes <= (256u << 20)) {
       GLCM_TRY(hipMalloc((void**)&p->xbuf, bytes));
       GLCM_TRY(hipMemset(p->xbuf, 0, bytes));
+      p->xslots = xcc_slots(p->device);
     } else {
       p->tuning.merge = 1;  // band partials only
     }
@@ -485,7 +514,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   const bool xcd = t.merge == 0 && p->xbuf != nullptr && path != kPathGlobal;
   if (y_end <= y_begin) {
     // nothing to count: clear (or keep) the output
-    if (xcd && finish) GLCM_TRY(glcm::launch_finish(p->xbuf, out, words, accumulate, stream));
+    if (xcd && finish) GLCM_TRY(glcm::launch_finish(p->xbuf, out, words, p->xslots, accumulate, stream));
     else if (!accumulate && !xcd) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
     return GLCM_OK;
   }
@@ -603,32 +632,30 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   lds_bytes = std::max(lds_bytes, (size_t)wg * 4u);
 
   const int maxdy = c.maxdy <= 1 ? 1 : (c.maxdy <= 2 ? 2 : 4);
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  glcm::LaunchTiming tm;
   if (p->flags & GLCM_FLAG_TIMING) {
-    // device-scope release: timing needs no flush of host-visible caches
-    GLCM_TRY(hipEventCreateWithFlags(&ev0, hipEventReleaseToDevice));
-    GLCM_TRY(hipEventCreateWithFlags(&ev1, hipEventReleaseToDevice));
-    p->timing.emplace_back(ev0, ev1);
-    GLCM_TRY(hipEventRecord(ev0, stream));
+    // the dispatch stamps the events with the kernel's own start and end
+    GLCM_TRY(hipEventCreate(&tm.start));
+    GLCM_TRY(hipEventCreate(&tm.stop));
+    p->timing.emplace_back(tm.start, tm.stop);
   }
   hipError_t e;
   if (path == kPathStrips) {
-    e = glcm::launch_vote_strips(a, b, smd, sl.D, wg, lds_bytes, stream);
+    e = glcm::launch_vote_strips(a, b, smd, sl.D, wg, lds_bytes, stream, tm);
   } else if (path == kPathRows) {
-    e = glcm::launch_vote_rows(a, b, maxdy, rpw, wg, lds_bytes, stream);
+    e = glcm::launch_vote_rows(a, b, maxdy, rpw, wg, lds_bytes, stream, tm);
   } else {
-    e = glcm::launch_vote_generic(a, b, wg, lds_bytes, stream);
+    e = glcm::launch_vote_generic(a, b, wg, lds_bytes, stream, tm);
   }
-  if (e == hipSuccess && ev1) e = hipEventRecord(ev1, stream);
   if (e == hipSuccess) {
     if (!xcd)
       e = glcm::launch_reduce(a.partials, out, words, a.nregions, accumulate, stream);
     else if (finish)
-      e = glcm::launch_finish(p->xbuf, out, words, accumulate, stream);
+      e = glcm::launch_finish(p->xbuf, out, words, p->xslots, accumulate, stream);
   }
   if (e != hipSuccess) {
     // leave the accumulators clean for the next call
-    if (xcd) (void)hipMemsetAsync(p->xbuf, 0, (size_t)glcm::kXcdSlots * words * 4u, stream);
+    if (xcd) (void)hipMemsetAsync(p->xbuf, 0, (size_t)p->xslots * words * 4u, stream);
     return hip_status(e);
   }
   return GLCM_OK;

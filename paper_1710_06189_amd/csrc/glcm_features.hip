@@ -1,0 +1,27 @@
+// Haralick statistics kernel: one workgroup per GLCM (Section I; the five
+// statistics and their precision are described in glcm_features.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "glcm_features.h"
+#include "glcm_internal.h"
+
+namespace glcm {
+namespace {
+
+__global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, float* out) {
+  __shared__ unsigned long long redu[256];
+  __shared__ float redf[256];
+  glcm_features_wg(glcm + (size_t)blockIdx.x * (uint32_t)N * (uint32_t)N, (uint32_t)N, out + (size_t)blockIdx.x * 5,
+                   redu, redf);
+}
+
+}  // namespace
+
+hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_features, dim3(K), dim3(256), 0, stream, glcm, N, out);
+  return hipGetLastError();
+}
+
+}  // namespace glcm

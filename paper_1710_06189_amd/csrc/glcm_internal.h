@@ -83,18 +83,28 @@ struct BatchArgs {
   float* feat;                         // [T][K][5] or null
 };
 
+// Optional events the counting kernel's dispatch stamps with its own start
+// and end time (both null: plain launch).
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Launchers (all asynchronous on `stream`; return the launch error).
-hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream,
+                               const LaunchTiming& tm = {});
 hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
-                            hipStream_t stream);
+                            hipStream_t stream, const LaunchTiming& tm = {});
 // D = dwords per bin (4, 8, 16 or 32), maxdy = 1 or 2.
 hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
-                              hipStream_t stream);
+                              hipStream_t stream, const LaunchTiming& tm = {});
 // out[w] = (accumulate ? out[w] : 0) + sum_b partials[b * M + w] for w < M.
 hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, int nbands, bool accumulate,
                          hipStream_t stream);
-// out[w] = (accumulate ? out[w] : 0) + sum_x xbuf[x * M + w]; zeroes xbuf.
-hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, bool accumulate, hipStream_t stream);
+// out[w] = (accumulate ? out[w] : 0) + sum_{x < nslots} xbuf[x * M + w]; zeroes those slices.
+hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, uint32_t nslots, bool accumulate,
+                         hipStream_t stream);
+// ids[b] = XCC_ID of the XCD that ran workgroup b (b < blocks).
+hipError_t launch_xcc_probe(uint32_t* ids, int blocks, hipStream_t stream);
 hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream);
 hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream);
 // One workgroup per image of the batch (T images); D = dwords per bin (4, 8

@@ -9,33 +9,16 @@
 // different banks.  The merge of all copies into one result (the final sum in
 // Section II.A) takes two steps: every workgroup writes its band's counts to
 // a partial buffer, and a second kernel sums the partials into `out`.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
+#include "glcm_device.h"
 #include "glcm_internal.h"
 
 namespace glcm {
 namespace {
-
-// floor(x / d) for x < 2^32 with (magic, shift) from the host (see Quant).
-__device__ __forceinline__ uint32_t divide(uint32_t x, uint32_t magic, uint32_t shift) {
-  return (uint32_t)(((uint64_t)x + __umulhi(x, magic)) >> shift);
-}
-
-// Zeroes n dwords of LDS starting at a 16-byte aligned address.
-__device__ __forceinline__ void zero_lds(uint32_t* lds, uint32_t n) {
-  uint4* v = (uint4*)lds;
-  const uint32_t n4 = n / 4u;
-  for (uint32_t i = threadIdx.x; i < n4; i += blockDim.x) v[i] = make_uint4(0u, 0u, 0u, 0u);
-  for (uint32_t i = n4 * 4u + threadIdx.x; i < n; i += blockDim.x) lds[i] = 0u;
-}
-
-__device__ __forceinline__ uint32_t quantize(uint32_t v, const Quant& q) {
-  const uint32_t x = (v - q.lo) * q.nlev;
-  const uint32_t lv = (x + __umulhi(x, q.magic)) >> q.shift;
-  return v < q.lo ? 0u : (v > q.hi ? q.nlev - 1u : lv);
-}
 
 // ---------------------------------------------------------------------------
 // Merge of the LDS copies (the final sum of Section II.A), in two steps that
@@ -95,20 +78,29 @@ __device__ void store_partial(const VoteArgs& a, const uint32_t* lds, uint32_t p
   }
 }
 
-// out[w] = (accumulate ? out[w] : 0) + sum of the XCD slices; clears them.
-__global__ __launch_bounds__(256) void k_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, int accumulate) {
+// out[w] = (accumulate ? out[w] : 0) + sum of the first nslots XCD slices
+// (the slices of XCC_IDs the device has; the others stay zero); clears them.
+__global__ __launch_bounds__(256) void k_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, uint32_t nslots,
+                                                int accumulate) {
   const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= M) return;
   uint32_t v[kXcdSlots];
 #pragma unroll
-  for (uint32_t x = 0; x < kXcdSlots; ++x) v[x] = xbuf[(size_t)x * M + w];
+  for (uint32_t x = 0; x < kXcdSlots; ++x) v[x] = x < nslots ? xbuf[(size_t)x * M + w] : 0u;
   uint32_t s = accumulate ? out[w] : 0u;
 #pragma unroll
   for (uint32_t x = 0; x < kXcdSlots; ++x) {
     s += v[x];
-    xbuf[(size_t)x * M + w] = 0u;
+    if (x < nslots) xbuf[(size_t)x * M + w] = 0u;
   }
   out[w] = s;
+}
+
+// Each workgroup records the XCC_ID of the XCD it runs on.
+__global__ __launch_bounds__(64) void k_xcc_probe(uint32_t* ids) {
+  uint32_t xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+  if (threadIdx.x == 0) ids[blockIdx.x] = xcc;
 }
 
 // out[w] (+)= sum over bands of partials[band][w].  Each workgroup owns
@@ -264,53 +256,8 @@ __global__ __launch_bounds__(256) void k_vote_global(VoteArgs a) {
 // sentinel land in row or column N and are dropped by the merge, so the vote
 // loop carries no bounds checks at all.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kDppWaveShr1 = 0x138;  // lane l receives lane l-1
-constexpr uint32_t kDppWaveShl1 = 0x130;  // lane l receives lane l+1
-
 struct Ring {
   uint32_t w[6];  // [left halo (4 px) | 16 px chunk | right halo (4 px)], one level per byte
-};
-
-__device__ __forceinline__ uint32_t pack4(uint32_t l0, uint32_t l1, uint32_t l2, uint32_t l3) {
-  return l0 | (l1 << 8) | (l2 << 16) | (l3 << 24);
-}
-
-// Four packed 8-bit pixels -> four packed levels (QA: any argument struct with
-// the quantizer fields q, qfast, qfast_shift, qfast_mask).
-template <class QA>
-__device__ __forceinline__ uint32_t quant4_u8(uint32_t raw, const QA& a) {
-  if (a.qfast) return (raw >> a.qfast_shift) & a.qfast_mask;
-  return pack4(quantize(raw & 0xffu, a.q), quantize((raw >> 8) & 0xffu, a.q), quantize((raw >> 16) & 0xffu, a.q),
-               quantize(raw >> 24, a.q));
-}
-
-// Four 16-bit pixels (two dwords) -> four packed levels.
-template <class QA>
-__device__ __forceinline__ uint32_t quant4_u16(uint32_t lo2, uint32_t hi2, const QA& a) {
-  if (a.qfast) {
-    const uint32_t l = (lo2 >> a.qfast_shift) & a.qfast_mask;  // levels in bits 0..7 and 16..23
-    const uint32_t h = (hi2 >> a.qfast_shift) & a.qfast_mask;
-    return __builtin_amdgcn_perm(h, l, 0x06040200u);            // bytes l0, l2, h0, h2
-  }
-  return pack4(quantize(lo2 & 0xffffu, a.q), quantize(lo2 >> 16, a.q), quantize(hi2 & 0xffffu, a.q),
-               quantize(hi2 >> 16, a.q));
-}
-
-// Byte mask keeping the first n (0..4) bytes of a dword.
-__device__ __forceinline__ uint32_t keep_bytes(int n) {
-  return n <= 0 ? 0u : (n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u));
-}
-
-// Replaces the levels of pixels at or beyond W by the sentinel.
-__device__ __forceinline__ uint32_t clip_dword(uint32_t lv, int x, int W, uint32_t sent4) {
-  const uint32_t m = keep_bytes(W - x);
-  return (lv & m) | (sent4 & ~m);
-}
-
-template <typename Pix>
-struct RawChunk {
-  uint4 v[sizeof(Pix)];  // 16 pixels
-  uint32_t lh[sizeof(Pix)], rh[sizeof(Pix)];  // 4-pixel halos of the wave-boundary lanes
 };
 
 template <typename Pix>
@@ -475,197 +422,6 @@ __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
     }
   }
   store_partial(a, lds, pbase, pwords, region, N1, NN1, a.c16 != 0);
-}
-
-// ---------------------------------------------------------------------------
-// Strip kernel: the fast path for aligned images, N <= 255 and offsets with
-// 0 <= dy <= MAXDY and |dx| <= MAXDY (MAXDY <= 2) after canonicalisation.
-//
-// A wavefront owns a strip: 64 lanes x 16-pixel chunks (1024 columns) and a
-// run of consecutive first-pixel rows.  It walks down the strip keeping the
-// MAXDY + 1 rows that pairs starting on the current row can reach, each pixel
-// already turned into its share of an LDS address, and prefetches the rows
-// below while it votes, so each pixel is read from memory once per strip.
-//
-// LDS layout of a partition (kp GLCMs in kg dword groups): dword
-// ((bin * kg + q) * D + g) holds copy g (lane mod D) of bin = a * n1 + b,
-// n1 = N + 1 (row and column N catch pixels outside the image), for GLCM q of
-// the partition (kg = kp, 32-bit counters) or for GLCMs 2q and 2q+1 in its
-// low and high halves (PAIR: kg = kp / 2 rounded up, 16-bit counters, used
-// when the host has bounded every count below 2^16).  The byte address splits
-// as
-//     base(a) + term(b) + 4 D q,   term(v) = v * 4 D kg,   base(a) = 4 g + term(a) * n1,
-// so a vote costs one VALU add of a first-pixel base and a second-pixel term;
-// 4 D q rides in the offset field of the LDS atomic and the half in the
-// added value.  gfx950's LDS serves 32 lanes per pass over 32 banks: with
-// D = 32 every lane of a pass writes its own bank whatever the bins; with
-// D = 16 lanes l and l + 16 share one (a two-way conflict on every vote).
-// ---------------------------------------------------------------------------
-template <int NX>
-struct TermRow {
-  uint32_t s[16 + 2 * NX];  // [NX left halo | 16 chunk pixels | NX right halo]
-};
-
-// Loads of one row of a strip lane: its 16-pixel chunk and 4-pixel halo
-// blocks on both sides.  Every lane issues the same loads with addresses
-// clamped into the image (the row below the last, a chunk past the right
-// edge or a halo outside [0, W) read some other pixels of the image, which
-// to_terms replaces by the sentinel), so the number of loads in flight is the
-// same on every path and the prefetch needs no full wait.  Every access lies
-// in a 16-byte block that holds a pixel of the row it addresses.
-struct Geom {
-  const void* img;  // 16-byte aligned, row pitch a multiple of 16 bytes
-  int64_t stride;   // elements
-  int W, H;
-};
-
-// Byte offsets, within a row, of what a lane loads: its chunk (a chunk that
-// starts inside the row), the chunk's second half for 16-bit pixels (only
-// when it starts inside the row: the pitch is a multiple of 8 pixels, not
-// necessarily of 16) and the halo blocks (only where they start inside the
-// row: a lane past the right edge must not read x0 - 4, which on the last
-// row is past the image).  Fixed for a lane's whole strip.
-struct LaneCols {
-  uint32_t c, c2, l, r;
-};
-
-template <typename Pix>
-__device__ __forceinline__ LaneCols lane_cols(const Geom& a, int x0) {
-  const int xc = min(x0, (a.W - 1) & ~15);
-  const int xl = (x0 >= 16 && x0 - 4 < a.W) ? x0 - 4 : xc;
-  const int xr = x0 + 16 < a.W ? x0 + 16 : xc;
-  const int xc2 = xc + 8 < a.W ? xc + 8 : xc;
-  constexpr uint32_t b = sizeof(Pix);
-  return {(uint32_t)xc * b, (uint32_t)xc2 * b, (uint32_t)xl * b, (uint32_t)xr * b};
-}
-
-// (In the strip kernel y is the same on every lane, so the row address stays
-// in scalar registers and each load is a scalar base plus the lane's offset.)
-template <typename Pix>
-__device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y, const LaneCols& o) {
-  const char* row = (const char*)a.img + (int64_t)min(y, a.H - 1) * a.stride * (int64_t)sizeof(Pix);
-  rc.v[0] = *(const uint4*)(row + o.c);
-  if (sizeof(Pix) == 1) {
-    rc.lh[0] = *(const uint32_t*)(row + o.l);
-    rc.rh[0] = *(const uint32_t*)(row + o.r);
-  } else {
-    rc.v[sizeof(Pix) - 1] = *(const uint4*)(row + o.c2);
-    const uint2 l = *(const uint2*)(row + o.l), r = *(const uint2*)(row + o.r);
-    rc.lh[0] = l.x; rc.lh[sizeof(Pix) - 1] = l.y;
-    rc.rh[0] = r.x; rc.rh[sizeof(Pix) - 1] = r.y;
-  }
-}
-
-// Raw row -> per-pixel address terms (level * mb), sentinel level N outside
-// the image.  Halo pixels come from the neighbouring lanes; the wave-boundary
-// lanes use the halo dwords they loaded themselves.  SEG: a wavefront holds
-// several row segments side by side, so a halo pixel outside [0, W) takes the
-// sentinel whatever the neighbouring lane holds.  edge (the same on every
-// lane): some pixel of the wavefront's chunks or halos lies at or past W;
-// otherwise the per-byte clipping is skipped.
-template <typename Pix, int NX, bool SEG = false, class QA>
-__device__ __forceinline__ void to_terms(TermRow<NX>& r, const RawChunk<Pix>& rc, const QA& a, const Geom& g, int y,
-                                         int x0, uint32_t sent4, uint32_t mb, bool edge) {
-  uint32_t c[4], lh, rh;
-  if (sizeof(Pix) == 1) {
-    c[0] = quant4_u8(rc.v[0].x, a); c[1] = quant4_u8(rc.v[0].y, a);
-    c[2] = quant4_u8(rc.v[0].z, a); c[3] = quant4_u8(rc.v[0].w, a);
-    lh = quant4_u8(rc.lh[0], a);
-    rh = quant4_u8(rc.rh[0], a);
-  } else {
-    c[0] = quant4_u16(rc.v[0].x, rc.v[0].y, a); c[1] = quant4_u16(rc.v[0].z, rc.v[0].w, a);
-    c[2] = quant4_u16(rc.v[sizeof(Pix) - 1].x, rc.v[sizeof(Pix) - 1].y, a);
-    c[3] = quant4_u16(rc.v[sizeof(Pix) - 1].z, rc.v[sizeof(Pix) - 1].w, a);
-    lh = quant4_u16(rc.lh[0], rc.lh[sizeof(Pix) - 1], a);
-    rh = quant4_u16(rc.rh[0], rc.rh[sizeof(Pix) - 1], a);
-  }
-  if (y >= g.H) {
-    c[0] = c[1] = c[2] = c[3] = lh = rh = sent4;
-  } else if (edge) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) c[m] = clip_dword(c[m], x0 + 4 * m, g.W, sent4);
-    lh = x0 >= 16 ? clip_dword(lh, x0 - 4, g.W, sent4) : sent4;
-    rh = clip_dword(rh, x0 + 16, g.W, sent4);
-  } else {
-    lh = x0 >= 16 ? lh : sent4;
-  }
-#pragma unroll
-  for (int t = 0; t < 16; ++t) r.s[NX + t] = __umul24((c[t >> 2] >> ((t & 3) * 8)) & 0xffu, mb);
-#pragma unroll
-  for (int e = 0; e < NX; ++e) {
-    // pixel x0 - 1 - e is pixel 15 - e of the lane on the left; x0 + 16 + e is
-    // pixel e of the lane on the right (lanes 0 and 63 keep their own value)
-    const uint32_t own_l = __umul24((lh >> ((3 - e) * 8)) & 0xffu, mb);
-    const uint32_t own_r = __umul24((rh >> (e * 8)) & 0xffu, mb);
-    uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp((int)own_l, (int)r.s[NX + 15 - e], kDppWaveShr1, 0xf, 0xf, false);
-    uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp((int)own_r, (int)r.s[NX + e], kDppWaveShl1, 0xf, 0xf, false);
-    if (SEG) {
-      const uint32_t sent = __umul24(sent4 & 0xffu, mb);
-      if (x0 - 1 - e < 0) left = sent;
-      if (x0 + 16 + e >= g.W) right = sent;
-    }
-    r.s[NX - 1 - e] = left;
-    r.s[NX + 16 + e] = right;
-  }
-}
-
-// The 16 votes of one first-pixel row for offset (DX, dy): second pixel of
-// chunk pixel t is ring pixel NX + t + DX.
-// (fa[t] holds the LDS byte address of the first pixel's bin row, LDS base
-// included, so the vote is one add; KOFF lands in the instruction's offset.)
-typedef __attribute__((address_space(3))) uint32_t lds_word_t;
-
-__device__ __forceinline__ uint32_t lds_address(const uint32_t* p) {
-  return (uint32_t)(size_t)(const lds_word_t*)p;
-}
-
-// a * b + c on the 24-bit multiplier.  Callers pass a and b below 2^24 (a term
-// level * mb and the row pitch); written out because the compiler cannot
-// always see that bound and would mask a first.
-__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
-  return r;
-}
-
-template <int NX, int DX, uint32_t KOFF>
-__device__ __forceinline__ void vote_row(const uint32_t (&fa)[16], const TermRow<NX>& second, uint32_t inc) {
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const uint32_t addr = fa[t] + second.s[NX + t + DX];
-    __hip_atomic_fetch_add((lds_word_t*)(size_t)(addr + KOFF), inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
-}
-
-// Votes of the partition's GLCM number KI (compile time, so its LDS offset is
-// an immediate) for first-pixel row `cur` of the ring.
-template <int MAXDY, int D, int KI, int CUR, bool PAIR = false>
-__device__ __forceinline__ void vote_glcm(const uint32_t (&fa)[16],
-                                          const TermRow<MAXDY> (&ring)[MAXDY + 1], int code, uint32_t one) {
-  constexpr int NR = MAXDY + 1, NXS = 2 * MAXDY + 1;
-  constexpr uint32_t KOFF = 4u * D * (PAIR ? KI / 2 : KI);
-  const uint32_t inc = PAIR && (KI & 1) ? one << 16 : one;
-  // code = dy * (2 MAXDY + 1) + dx + MAXDY
-  // (the asm marker keeps the compiler from merging the cases into one body
-  // that would index the ring through memory)
-#define GLCM_STRIP_CASE(DY, DX)                                                                   \
-  case (DY) * NXS + (DX) + MAXDY:                                                                 \
-    vote_row<MAXDY, (DX), KOFF>(fa, ring[(CUR + (DY)) % NR], inc);                               \
-    asm volatile("; strip offset dy=" #DY " dx=" #DX);                                            \
-    break;
-  switch (code) {
-    GLCM_STRIP_CASE(0, 0) GLCM_STRIP_CASE(0, 1) GLCM_STRIP_CASE(1, -1) GLCM_STRIP_CASE(1, 0) GLCM_STRIP_CASE(1, 1)
-    default:
-      if constexpr (MAXDY >= 2) {
-        switch (code) {
-          GLCM_STRIP_CASE(0, 2) GLCM_STRIP_CASE(1, -2) GLCM_STRIP_CASE(1, 2)
-          GLCM_STRIP_CASE(2, -2) GLCM_STRIP_CASE(2, -1) GLCM_STRIP_CASE(2, 0) GLCM_STRIP_CASE(2, 1) GLCM_STRIP_CASE(2, 2)
-          default: break;  // the host launches only canonical offsets within reach
-        }
-      }
-      break;
-  }
-#undef GLCM_STRIP_CASE
 }
 
 // One first-pixel row of a strip: bases, votes of every GLCM of the
@@ -835,313 +591,81 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
   store_partial_strips<D, PAIR>(a, lds, region, kp0, kp, n1);
 }
 
-// ---------------------------------------------------------------------------
-// Haralick statistics of one GLCM computed by a whole workgroup (blockDim a
-// power of two >= 64).  Exact integer sums for the contrast numerator and the
-// correlation moments; fp32 for energy, entropy and homogeneity; fp64 (from
-// exact 128-bit integers) for the correlation.  redu / redf: blockDim words of
-// workgroup scratch each.  Every thread of the workgroup must call it.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wg_sum(T v, T* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (uint32_t h = blockDim.x / 2u; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const T r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__device__ void glcm_features_wg(const uint32_t* P, uint32_t N, float* o, unsigned long long* redu, float* redf) {
-  const uint32_t NN = N * N;
-  // pass 1: total (needed for p)
-  unsigned long long T = 0;
-  for (uint32_t t = threadIdx.x; t < NN; t += blockDim.x) T += P[t];
-  T = wg_sum(T, redu);
-  if (T == 0 || T > 0xffffffffull) {
-    if (threadIdx.x < 5) o[threadIdx.x] = T == 0 ? 0.0f : __builtin_nanf("");
-    return;
-  }
-  const float invT = 1.0f / (float)T;
-  unsigned long long sc = 0, si = 0, sj = 0, sii = 0, sjj = 0, sij = 0;
-  float energy = 0.f, ent = 0.f, homog = 0.f;
-  for (uint32_t t = threadIdx.x; t < NN; t += blockDim.x) {
-    const uint32_t c = P[t];
-    if (c == 0) continue;
-    const unsigned long long i = t / N, j = t % N;
-    const unsigned long long d = i > j ? i - j : j - i;
-    sc += d * d * c;
-    si += i * c; sj += j * c;
-    sii += i * i * c; sjj += j * j * c; sij += i * j * c;
-    const float p = (float)c * invT;
-    energy += p * p;
-    // -p ln p; for p > 1/2 use log1p of the exact complement to keep accuracy
-    const float lp = (2ull * c > T) ? log1pf(-(float)(T - c) * invT) : logf(p);
-    ent -= p * lp;
-    homog += p / (1.0f + (float)(d * d));
-  }
-  sc = wg_sum(sc, redu);
-  si = wg_sum(si, redu);
-  sj = wg_sum(sj, redu);
-  sii = wg_sum(sii, redu);
-  sjj = wg_sum(sjj, redu);
-  sij = wg_sum(sij, redu);
-  energy = wg_sum(energy, redf);
-  ent = wg_sum(ent, redf);
-  homog = wg_sum(homog, redf);
-  if (threadIdx.x == 0) {
-    using i128 = __int128;
-    const i128 tT = (i128)T;
-    const i128 vi = (i128)sii * tT - (i128)si * (i128)si;  // T^2 var_i
-    const i128 vj = (i128)sjj * tT - (i128)sj * (i128)sj;  // T^2 var_j
-    const i128 cv = (i128)sij * tT - (i128)si * (i128)sj;  // T^2 cov
-    double corr = 1.0;
-    if (vi != 0 && vj != 0) corr = (double)cv / sqrt((double)vi * (double)vj);
-    o[0] = (float)((double)sc / (double)T);
-    o[1] = energy;
-    o[2] = ent;
-    o[3] = homog;
-    o[4] = (float)corr;
-  }
-}
-
-// One workgroup (256 threads) per GLCM.
-__global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, float* out) {
-  __shared__ unsigned long long redu[256];
-  __shared__ float redf[256];
-  glcm_features_wg(glcm + (size_t)blockIdx.x * (uint32_t)N * (uint32_t)N, (uint32_t)N, out + (size_t)blockIdx.x * 5,
-                   redu, redf);
-}
-
-// ---------------------------------------------------------------------------
-// Batch kernel: one workgroup per image of a batch, fusing quantize, vote,
-// merge and the Haralick statistics; results are stored directly (the
-// workgroup owns the whole image, so no atomics and no second kernel).
-// Images arrive largest first, so the hardware dispatcher balances the
-// workgroups over the CUs.
-//
-// Aligned images use the strip machinery with the wavefront split into row
-// segments when the image is narrower than 1024 columns: lane l handles chunk
-// l mod cw of segment l / cw (cw = chunks per row), each segment walking its
-// own run of rows; halo pixels outside [0, W) take the sentinel.  Images that
-// are not 16-byte aligned are counted per pixel.  Both write the strip LDS
-// layout (kp = K GLCMs, D dwords per bin).
-// ---------------------------------------------------------------------------
-template <int MAXDY, int D, int KI, int CUR>
-__device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermRow<MAXDY> (&ring)[MAXDY + 1],
-                                           const int (&code)[4], int K, uint32_t inc) {
-  vote_glcm<MAXDY, D, KI, CUR>(fa, ring, code[KI], inc);  // 32-bit counters
-  if constexpr (KI + 1 < kStripMaxKp) {
-    if (K > KI + 1) batch_vote<MAXDY, D, KI + 1, CUR>(fa, ring, code, K, inc);
-  }
-}
-
-template <typename Pix, int MAXDY, int D, int CUR>
-__device__ __forceinline__ void batch_step(const BatchArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
-                                           RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, const LaneCols& cols,
-                                           uint32_t C, uint32_t n1,
-                                           uint32_t mb, uint32_t sent4, const int (&code)[4]) {
-  constexpr int NR = MAXDY + 1;
-  uint32_t fa[16];
-#pragma unroll
-  for (int t = 0; t < 16; ++t) fa[t] = __umul24(ring[CUR].s[MAXDY + t], n1) + C;
-  batch_vote<MAXDY, D, 0, CUR>(fa, ring, code, a.K, 1u);
-  to_terms<Pix, MAXDY, true>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, true);
-  load_row<Pix>(raw[CUR], geo, y + 2 * NR, cols);
-}
-
-template <typename Pix, int MAXDY, int D>
-__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
-  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-  constexpr int NR = MAXDY + 1;
-  const BatchTile t = a.tiles[blockIdx.x];
-  const Geom geo{t.img, t.stride, t.W, t.H};
-  const int K = a.K;
-  const uint32_t N = a.q.nlev, n1 = a.pitch, NN = N * N;
-  const uint32_t mb = 4u * D * (uint32_t)K;
-  const uint32_t vote_words = n1 * n1 * (uint32_t)K * D;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const uint32_t g = threadIdx.x & (D - 1u);
-  const uint32_t C = lds_address(lds) + 4u * g;
-  const uint32_t sent4 = N * 0x01010101u;
-  zero_lds(lds, vote_words);
-  __syncthreads();
-
-  if (t.aligned) {
-    int code[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) code[q] = q < K ? a.vcode[q] : -1;
-    // lane -> (segment, chunk)
-    const int chunks = (t.W + 15) >> 4;
-    const int cw = min(chunks, 64), segs = 64 / cw, spans = (chunks + 63) >> 6;
-    const int seg = lane / cw, c = lane - seg * cw;
-    const bool live = seg < segs;
-    const int slots = nwaves * segs;  // row segments walked at once by the workgroup
-    const int h = max(a.min_rows, (t.H * spans + slots - 1) / slots);
-    const int blocks = (t.H + segs * h - 1) / (segs * h);
-    for (int u = wave; u < spans * blocks; u += nwaves) {
-      const int span = u % spans, blk = u / spans;
-      const int x0 = live ? ((span << 6) + c) << 4 : spans << 10;  // idle lanes: past the right edge
-      const int ya = (blk * segs + (live ? seg : 0)) * h;
-      TermRow<MAXDY> ring[NR];
-      RawChunk<Pix> raw[NR];
-      const LaneCols cols = lane_cols<Pix>(geo, x0);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        to_terms<Pix, MAXDY, true>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb, true);
-        load_row<Pix>(raw[r], geo, ya + NR + r, cols);
-      }
-      // every lane takes h steps; rows past the image or the lane's segment
-      // end carry the sentinel or belong to this segment's own run
-      for (int j = 0; j < h; j += NR) {
-        batch_step<Pix, MAXDY, D, 0>(a, geo, ring, raw, ya + j, x0, cols, C, n1, mb, sent4, code);
-        if (j + 1 >= h) break;
-        batch_step<Pix, MAXDY, D, 1>(a, geo, ring, raw, ya + j + 1, x0, cols, C, n1, mb, sent4, code);
-        if constexpr (NR > 2) {
-          if (j + 2 >= h) break;
-          batch_step<Pix, MAXDY, D, 2>(a, geo, ring, raw, ya + j + 2, x0, cols, C, n1, mb, sent4, code);
-        }
-      }
-    }
-  } else {
-    // per pixel: one thread per first pixel, votes in the strip layout (a
-    // negated offset is stored transposed, as the strip path counts it)
-    const Pix* img = (const Pix*)t.img;
-    const uint32_t n = (uint32_t)t.W * (uint32_t)t.H;
-    for (uint32_t idx = threadIdx.x; idx < n; idx += blockDim.x) {
-      const int y = (int)(idx / (uint32_t)t.W), x = (int)(idx % (uint32_t)t.W);
-      const uint32_t av = quantize(img[(int64_t)y * t.stride + x], a.q);
-      for (int k = 0; k < K; ++k) {
-        const int x2 = x + a.dx[k], y2 = y + a.dy[k];
-        if ((unsigned)x2 >= (unsigned)t.W || (unsigned)y2 >= (unsigned)t.H) continue;
-        const uint32_t bv = quantize(img[(int64_t)y2 * t.stride + x2], a.q);
-        const bool tr = (a.tmask >> k) & 1ull;
-        const uint32_t bin = tr ? bv * n1 + av : av * n1 + bv;
-        __hip_atomic_fetch_add((lds_word_t*)(size_t)(C + bin * mb + 4u * D * (uint32_t)k), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    }
-  }
-
-  // merge: consecutive 16-byte units, D / 4 lanes per bin, into out and into
-  // an LDS copy for the statistics
-  __syncthreads();
-  constexpr uint32_t QPB = D / 4;
-  uint32_t* merged = lds + vote_words;
-  uint32_t* dst = a.out + (size_t)t.index * K * NN;
-  for (uint32_t u = threadIdx.x; u < vote_words / 4u; u += blockDim.x) {
-    const uint4 v = ((const uint4*)lds)[u];
-    uint32_t sum = (v.x + v.y) + (v.z + v.w);
-    if (QPB >= 2) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0xb1, 0xf, 0xf, false);
-    if (QPB >= 4) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0x4e, 0xf, 0xf, false);
-    if (u % QPB != 0) continue;
-    const uint32_t blk = u / QPB, k = blk % (uint32_t)K, bin = blk / (uint32_t)K;
-    const uint32_t i = bin / n1, j = bin % n1;
-    if (i >= N || j >= N) continue;
-    const bool tr = (a.tmask >> k) & 1ull;
-    const uint32_t w = k * NN + (tr ? j * N + i : i * N + j);
-    dst[w] = sum;
-    merged[w] = sum;
-  }
-  if (!a.feat) return;
-  __syncthreads();
-  unsigned long long* redu = (unsigned long long*)(merged + K * NN + ((K * NN) & 1u));
-  float* redf = (float*)(redu + blockDim.x);
-  for (int k = 0; k < K; ++k)
-    glcm_features_wg(merged + k * NN, N, a.feat + ((size_t)t.index * K + k) * 5, redu, redf);
-}
-
 }  // namespace
 
 template <typename K>
-static hipError_t launch(K kernel, const VoteArgs& a, dim3 grid, dim3 block, size_t lds_bytes, hipStream_t stream) {
-  hipLaunchKernelGGL(kernel, grid, block, lds_bytes, stream, a);
+static hipError_t launch(K kernel, const VoteArgs& a, dim3 grid, dim3 block, size_t lds_bytes, hipStream_t stream,
+                         const LaunchTiming& tm) {
+  // with events, the dispatch itself stamps the kernel's start and end
+  hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds_bytes, stream, tm.start, tm.stop, 0u, a);
   return hipGetLastError();
 }
 
-hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream) {
+hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_t lds_bytes, hipStream_t stream,
+                               const LaunchTiming& tm) {
   const dim3 grid(a.nregions * a.P), block(wg);
-  if (dtype_bytes == 1) return launch(k_vote_generic<uint8_t>, a, grid, block, lds_bytes, stream);
-  return launch(k_vote_generic<uint16_t>, a, grid, block, lds_bytes, stream);
+  if (dtype_bytes == 1) return launch(k_vote_generic<uint8_t>, a, grid, block, lds_bytes, stream, tm);
+  return launch(k_vote_generic<uint16_t>, a, grid, block, lds_bytes, stream, tm);
 }
 
 template <typename Pix>
-static hipError_t launch_rows_t(const VoteArgs& a, int maxdy, int wg, size_t lds_bytes, hipStream_t stream) {
+static hipError_t launch_rows_t(const VoteArgs& a, int maxdy, int wg, size_t lds_bytes, hipStream_t stream,
+                               const LaunchTiming& tm) {
   const dim3 grid(a.nregions * a.P), block(wg);
   switch (maxdy) {
-    case 1: return launch(k_vote_rows<Pix, 1, 4>, a, grid, block, lds_bytes, stream);
-    case 2: return launch(k_vote_rows<Pix, 2, 4>, a, grid, block, lds_bytes, stream);
-    case 4: return launch(k_vote_rows<Pix, 4, 4>, a, grid, block, lds_bytes, stream);
+    case 1: return launch(k_vote_rows<Pix, 1, 4>, a, grid, block, lds_bytes, stream, tm);
+    case 2: return launch(k_vote_rows<Pix, 2, 4>, a, grid, block, lds_bytes, stream, tm);
+    case 4: return launch(k_vote_rows<Pix, 4, 4>, a, grid, block, lds_bytes, stream, tm);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
-                            hipStream_t stream) {
+                            hipStream_t stream, const LaunchTiming& tm) {
   if (rpw != 4) return hipErrorInvalidValue;
-  return dtype_bytes == 1 ? launch_rows_t<uint8_t>(a, maxdy, wg, lds_bytes, stream)
-                          : launch_rows_t<uint16_t>(a, maxdy, wg, lds_bytes, stream);
+  return dtype_bytes == 1 ? launch_rows_t<uint8_t>(a, maxdy, wg, lds_bytes, stream, tm)
+                          : launch_rows_t<uint16_t>(a, maxdy, wg, lds_bytes, stream, tm);
 }
 
 template <typename Pix, int MAXDY, bool PAIR>
-static hipError_t launch_strips_p(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream) {
+static hipError_t launch_strips_p(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream,
+                                 const LaunchTiming& tm) {
   const dim3 grid(a.nregions * a.P), block(wg);
   switch (D) {
-    case 4: return launch(k_vote_strips<Pix, MAXDY, 4, PAIR>, a, grid, block, lds_bytes, stream);
-    case 8: return launch(k_vote_strips<Pix, MAXDY, 8, PAIR>, a, grid, block, lds_bytes, stream);
-    case 16: return launch(k_vote_strips<Pix, MAXDY, 16, PAIR>, a, grid, block, lds_bytes, stream);
-    case 32: return launch(k_vote_strips<Pix, MAXDY, 32, PAIR>, a, grid, block, lds_bytes, stream);
+    case 4: return launch(k_vote_strips<Pix, MAXDY, 4, PAIR>, a, grid, block, lds_bytes, stream, tm);
+    case 8: return launch(k_vote_strips<Pix, MAXDY, 8, PAIR>, a, grid, block, lds_bytes, stream, tm);
+    case 16: return launch(k_vote_strips<Pix, MAXDY, 16, PAIR>, a, grid, block, lds_bytes, stream, tm);
+    case 32: return launch(k_vote_strips<Pix, MAXDY, 32, PAIR>, a, grid, block, lds_bytes, stream, tm);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename Pix, int MAXDY>
-static hipError_t launch_strips_t(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream) {
-  return a.c16 ? launch_strips_p<Pix, MAXDY, true>(a, D, wg, lds_bytes, stream)
-               : launch_strips_p<Pix, MAXDY, false>(a, D, wg, lds_bytes, stream);
+static hipError_t launch_strips_t(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream,
+                                 const LaunchTiming& tm) {
+  return a.c16 ? launch_strips_p<Pix, MAXDY, true>(a, D, wg, lds_bytes, stream, tm)
+               : launch_strips_p<Pix, MAXDY, false>(a, D, wg, lds_bytes, stream, tm);
 }
 
 hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
-                              hipStream_t stream) {
+                              hipStream_t stream, const LaunchTiming& tm) {
   if (maxdy == 1)
-    return dtype_bytes == 1 ? launch_strips_t<uint8_t, 1>(a, D, wg, lds_bytes, stream)
-                            : launch_strips_t<uint16_t, 1>(a, D, wg, lds_bytes, stream);
+    return dtype_bytes == 1 ? launch_strips_t<uint8_t, 1>(a, D, wg, lds_bytes, stream, tm)
+                            : launch_strips_t<uint16_t, 1>(a, D, wg, lds_bytes, stream, tm);
   if (maxdy == 2)
-    return dtype_bytes == 1 ? launch_strips_t<uint8_t, 2>(a, D, wg, lds_bytes, stream)
-                            : launch_strips_t<uint16_t, 2>(a, D, wg, lds_bytes, stream);
+    return dtype_bytes == 1 ? launch_strips_t<uint8_t, 2>(a, D, wg, lds_bytes, stream, tm)
+                            : launch_strips_t<uint16_t, 2>(a, D, wg, lds_bytes, stream, tm);
   return hipErrorInvalidValue;
 }
 
-template <typename Pix, int MAXDY>
-static hipError_t launch_batch_t(const BatchArgs& a, int T, int D, size_t lds_bytes, hipStream_t stream) {
-  const dim3 grid(T), block(kBatchThreads);
-  switch (D) {
-    case 4: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 4>), grid, block, lds_bytes, stream, a); break;
-    case 8: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 8>), grid, block, lds_bytes, stream, a); break;
-    case 16: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 16>), grid, block, lds_bytes, stream, a); break;
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_xcc_probe(uint32_t* ids, int blocks, hipStream_t stream) {
+  hipLaunchKernelGGL(k_xcc_probe, dim3(blocks), dim3(64), 0, stream, ids);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, size_t lds_bytes,
-                        hipStream_t stream) {
-  if (maxdy == 1)
-    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 1>(a, T, D, lds_bytes, stream)
-                            : launch_batch_t<uint16_t, 1>(a, T, D, lds_bytes, stream);
-  if (maxdy == 2)
-    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 2>(a, T, D, lds_bytes, stream)
-                            : launch_batch_t<uint16_t, 2>(a, T, D, lds_bytes, stream);
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, bool accumulate, hipStream_t stream) {
-  hipLaunchKernelGGL(k_finish, dim3((M + 255) / 256), dim3(256), 0, stream, xbuf, out, M, accumulate ? 1 : 0);
+hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, uint32_t nslots, bool accumulate,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL(k_finish, dim3((M + 255) / 256), dim3(256), 0, stream, xbuf, out, M, nslots, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1161,11 +685,6 @@ hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t st
     hipLaunchKernelGGL(k_vote_global<uint8_t>, grid, block, 0, stream, a);
   else
     hipLaunchKernelGGL(k_vote_global<uint16_t>, grid, block, 0, stream, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_features, dim3(K), dim3(256), 0, stream, glcm, N, out);
   return hipGetLastError();
 }
 
