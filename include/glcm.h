@@ -65,7 +65,7 @@ enum glcm_status {
     GLCM_ENOMEM = -2,       /* device or pinned-host allocation failed */
     GLCM_EUNSUPPORTED = -3, /* valid request this build cannot serve */
     GLCM_EHIP = -4,         /* a HIP call failed; see glcm_last_hip_error() */
-    GLCM_EBUSY = -5         /* reserved */
+    GLCM_EBUSY = -5         /* the object is still in use (e.g. a request not done yet) */
 };
 
 /* Limits checked by every entry point. */
@@ -168,6 +168,23 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void *img, int W, int H,
  */
 GLCM_API int glcm_plan_kernel_time(glcm_plan_t plan, double *ms_total, int *launches);
 
+/*
+ * Re-targets a plan at another offset list (same dtype and N) of at most the K
+ * it was created with, keeping its device workspace: the per-XCD accumulators
+ * are zero between calls whatever K is, so only the host-side launch layout
+ * is recomputed (a tuning set with glcm_plan_tuning is discarded).  For
+ * callers whose offsets change from call to call, such as the request server
+ * below.  Work already queued keeps the offsets it was launched with.
+ * Errors: GLCM_EINVAL for a NULL plan, NULL offsets, K < 1 or above the
+ * plan's creation K, or a displacement beyond GLCM_MAX_DISPLACEMENT.
+ */
+GLCM_API int glcm_plan_rebind(glcm_plan_t plan, const glcm_offset_t *offsets, int K);
+
+/* Device bytes the plan holds right now (accumulators, band partials, tile
+ * and descriptor buffers; some are allocated on first use).  GLCM_EINVAL for
+ * NULL arguments. */
+GLCM_API int glcm_plan_workspace(glcm_plan_t plan, size_t *device_bytes);
+
 /* Releases a plan after waiting for its queued work.  NULL is accepted. */
 GLCM_API int glcm_plan_destroy(glcm_plan_t plan);
 
@@ -258,6 +275,99 @@ typedef struct glcm_tile {
  */
 GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t *tiles, int T, uint32_t lo, uint32_t hi,
                                 uint32_t *out, float *features, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Request server: continuous admission of GLCM jobs of mixed image size, N
+ * and offset lists.  A scheduler thread admits queued requests in arrival
+ * order as soon as a lane (a HIP stream with its own plans, one per dtype and
+ * N, re-targeted per request) is free and the request's device memory fits
+ * the HBM budget; requests on different lanes run concurrently on the GPU,
+ * and a lane is handed to the next request the moment its work completes
+ * (a host function queued behind it).  Images stay the caller's; counts and
+ * statistics go to caller buffers or to the server's device result pool,
+ * where they stay until fetched or released.
+ * ------------------------------------------------------------------------ */
+typedef struct glcm_server_s *glcm_server_t;
+
+typedef struct glcm_request {
+    const void *img;                /* DEVICE image, row y at img + y*stride elements */
+    int32_t W, H;                   /* 1 .. 65535 each, W*H <= 2^32 - 1 */
+    int64_t stride;                 /* elements, >= W */
+    int32_t dtype;                  /* GLCM_U8 or GLCM_U16 */
+    int32_t N;                      /* 1 .. GLCM_MAX_LEVELS */
+    uint32_t lo, hi;                /* quantization range, as in glcm_compute */
+    const glcm_offset_t *offsets;   /* host, K entries, copied at submit */
+    int32_t K;                      /* 1 .. GLCM_MAX_OFFSETS */
+    int32_t features;               /* non-zero: also the five statistics */
+    uint32_t *out;                  /* device K*N*N uint32, or NULL: a server-owned buffer */
+    float *feat;                    /* device K*5 float (features != 0), or NULL: server-owned */
+} glcm_request_t;
+
+typedef struct glcm_request_info {
+    int32_t done;                   /* 1 once the request's work has completed (or failed) */
+    int32_t status;                 /* GLCM_OK, or the error the request ended with */
+    int32_t lane;                   /* lane it ran on, -1 while queued */
+    int32_t reserved;
+    double submit_us, admit_us, done_us;  /* host steady clock, us since server creation */
+    const uint32_t *out;            /* device counts [K][N][N] (valid once done) */
+    const float *feat;              /* device statistics [K][5], or NULL */
+} glcm_request_info_t;
+
+typedef struct glcm_server_stats {
+    uint64_t submitted, completed, failed;
+    int32_t lanes, max_inflight;    /* lanes, most requests admitted at once */
+    uint64_t budget_bytes;          /* the HBM budget */
+    uint64_t bytes_in_use;          /* budgeted bytes held now (plans + results) */
+    uint64_t max_bytes_in_use;      /* most budgeted bytes held at once */
+} glcm_server_stats_t;
+
+/*
+ * Creates a server on the current device.
+ *   lanes              concurrent requests, 1 .. 16 (one HIP stream each).
+ *   hbm_budget         bytes the server may hold at once for plan workspaces
+ *                      and server-owned results; a request is admitted only
+ *                      when its results and any plan workspace it needs fit
+ *                      beside what is held (idle plans are evicted first).
+ *   result_pool_bytes  device pool for server-owned results (<= hbm_budget);
+ *                      0: every request must bring out (and feat).
+ * Errors: GLCM_EINVAL for a NULL pointer, lanes outside 1 .. 16, a zero
+ * budget, a pool larger than the budget, or flags other than 0;
+ * GLCM_ENOMEM / GLCM_EHIP.
+ */
+GLCM_API int glcm_server_create(glcm_server_t *srv, int lanes, uint64_t hbm_budget, uint64_t result_pool_bytes,
+                                uint32_t flags);
+
+/* Queues one request (validated here; nothing is queued on error) and returns
+ * its ticket.  Errors: GLCM_EINVAL for a bad descriptor (as glcm_compute, plus
+ * a host image, or a NULL out / feat without a result pool);
+ * GLCM_EUNSUPPORTED when the request alone needs more than the budget. */
+GLCM_API int glcm_server_submit(glcm_server_t srv, const glcm_request_t *req, uint64_t *ticket);
+
+/* State of a request (non-blocking).  GLCM_EINVAL for an unknown ticket. */
+GLCM_API int glcm_server_query(glcm_server_t srv, uint64_t ticket, glcm_request_info_t *info);
+
+/* Blocks until the request is done; info may be NULL.  Returns the request's
+ * status (GLCM_EINVAL for an unknown ticket). */
+GLCM_API int glcm_server_wait(glcm_server_t srv, uint64_t ticket, glcm_request_info_t *info);
+
+/* Copies a done request's counts (and statistics, if it has them and feat is
+ * not NULL) to caller device buffers on `stream`.  GLCM_EINVAL for an unknown
+ * or unfinished ticket or a NULL out; GLCM_EHIP. */
+GLCM_API int glcm_server_fetch(glcm_server_t srv, uint64_t ticket, uint32_t *out, float *feat, void *stream);
+
+/* Forgets a done request and returns its server-owned result memory to the
+ * pool.  GLCM_EINVAL for an unknown ticket, GLCM_EBUSY if it is not done. */
+GLCM_API int glcm_server_release(glcm_server_t srv, uint64_t ticket);
+
+/* Waits until every submitted request is done. */
+GLCM_API int glcm_server_drain(glcm_server_t srv);
+
+/* Counters since creation.  GLCM_EINVAL for NULL arguments. */
+GLCM_API int glcm_server_stats(glcm_server_t srv, glcm_server_stats_t *stats);
+
+/* Drains, stops the scheduler and releases streams, plans and the pool.
+ * NULL is accepted. */
+GLCM_API int glcm_server_destroy(glcm_server_t srv);
 
 #ifdef __cplusplus
 }

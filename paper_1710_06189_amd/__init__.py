@@ -9,6 +9,9 @@ memory and streams.  The functions keep the C names:
     glcm_features(P, out=None, stream=None) -> torch.Tensor [K, 5] float32
     glcm_offset_polar(d, theta_deg) -> (dx, dy)
     glcm_plan_create(dtype, N, offsets, max_W, max_H, flags=0) -> Plan
+    glcm_batch_compute(images_or_tileset, plan, ...) -> (counts [T, K, N, N], statistics [T, K, 5])
+    Server(lanes, hbm_budget, result_pool_bytes): the request server
+        (glcm_server_submit / wait / query / fetch / release / drain / stats)
 
 Conventions (Eq. (1) of the paper, made precise): out[k][i][j] counts pixels
 (x, y) with level i whose neighbour (x + dx_k, y + dy_k) lies inside the image
@@ -32,6 +35,7 @@ __all__ = [
     "glcm_compute",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
     "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
+    "glcm_plan_rebind", "glcm_plan_workspace", "Server", "RequestInfo", "ServerStats",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +69,25 @@ class Offset(ctypes.Structure):
 
 class Tile(ctypes.Structure):
     _fields_ = [("img", ctypes.c_void_p), ("stride", ctypes.c_int64), ("W", ctypes.c_int32), ("H", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("stride", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("N", ctypes.c_int32), ("lo", ctypes.c_uint32), ("hi", ctypes.c_uint32),
+                ("offsets", ctypes.c_void_p), ("K", ctypes.c_int32), ("features", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("feat", ctypes.c_void_p)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("lane", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("done_us", ctypes.c_double), ("out", ctypes.c_void_p), ("feat", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("lanes", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_uint64), ("max_bytes_in_use", ctypes.c_uint64)]
 
 
 class Tuning(ctypes.Structure):
@@ -113,6 +136,29 @@ def _lib():
         lib.glcm_features.argtypes = [vp, i32, i32, vp, vp]
         lib.glcm_batch_compute.restype = i32
         lib.glcm_batch_compute.argtypes = [vp, ctypes.POINTER(Tile), i32, u32, u32, vp, vp, vp]
+        lib.glcm_plan_rebind.restype = i32
+        lib.glcm_plan_rebind.argtypes = [vp, ctypes.POINTER(Offset), i32]
+        lib.glcm_plan_workspace.restype = i32
+        lib.glcm_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        u64 = ctypes.c_uint64
+        lib.glcm_server_create.restype = i32
+        lib.glcm_server_create.argtypes = [ctypes.POINTER(vp), i32, u64, u64, u32]
+        lib.glcm_server_submit.restype = i32
+        lib.glcm_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]
+        lib.glcm_server_query.restype = i32
+        lib.glcm_server_query.argtypes = [vp, u64, ctypes.POINTER(RequestInfo)]
+        lib.glcm_server_wait.restype = i32
+        lib.glcm_server_wait.argtypes = [vp, u64, ctypes.POINTER(RequestInfo)]
+        lib.glcm_server_fetch.restype = i32
+        lib.glcm_server_fetch.argtypes = [vp, u64, vp, vp, vp]
+        lib.glcm_server_release.restype = i32
+        lib.glcm_server_release.argtypes = [vp, u64]
+        lib.glcm_server_drain.restype = i32
+        lib.glcm_server_drain.argtypes = [vp]
+        lib.glcm_server_stats.restype = i32
+        lib.glcm_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        lib.glcm_server_destroy.restype = i32
+        lib.glcm_server_destroy.argtypes = [vp]
         _L = lib
     return _L
 
@@ -229,6 +275,20 @@ def glcm_plan_kernel_time(plan: Plan):
 
 def glcm_plan_destroy(plan: Plan):
     plan.close()
+
+
+def glcm_plan_rebind(plan: Plan, offsets):
+    """Re-targets `plan` at another offset list of at most its creation K."""
+    arr, K = _offsets(offsets)
+    _check(_lib().glcm_plan_rebind(plan.handle, arr, K), "glcm_plan_rebind")
+    plan.offsets = [tuple(o) for o in offsets]
+
+
+def glcm_plan_workspace(plan: Plan) -> int:
+    """Device bytes the plan holds now."""
+    b = ctypes.c_size_t()
+    _check(_lib().glcm_plan_workspace(plan.handle, ctypes.byref(b)), "glcm_plan_workspace")
+    return int(b.value)
 
 
 def _dtype_code(dtype) -> int:
@@ -353,3 +413,84 @@ def glcm_batch_compute(images, plan, lo=0, hi=None, out=None, features=True, str
                                      ctypes.c_void_p(feats.data_ptr()) if feats is not None else None, s),
            "glcm_batch_compute")
     return out, feats
+
+
+class Server:
+    """Owner of a glcm_server_t: requests of mixed size, N and offsets admitted
+    onto `lanes` HIP streams as lanes and the HBM budget allow.
+
+    submit() takes a 2-D device tensor (any row stride) and returns a ticket;
+    results go to the given `out` / `feat` tensors or, if omitted, to the
+    server's device pool (then read them with fetch() and free them with
+    release())."""
+
+    def __init__(self, lanes=4, hbm_budget=32 << 30, result_pool_bytes=256 << 20):
+        h = ctypes.c_void_p()
+        _check(_lib().glcm_server_create(ctypes.byref(h), int(lanes), int(hbm_budget), int(result_pool_bytes), 0),
+               "glcm_server_create")
+        self.handle = h
+        self._keep = {}  # ticket -> tensors the request reads or writes
+
+    def submit(self, img, N, lo=0, hi=None, offsets=((1, 0),), features=False, out=None, feat=None) -> int:
+        if not (isinstance(img, torch.Tensor) and img.is_cuda):
+            raise ValueError("the server takes device images (CUDA tensors)")
+        ptr, W, H, stride, dt, keep = _image_args(img)
+        if hi is None:
+            hi = 255 if dt == U8 else 65535
+        arr, K = _offsets(offsets)
+        for t, n in ((out, K * N * N), (feat, K * 5)):
+            if t is not None and not (t.is_cuda and t.is_contiguous() and t.numel() == n and t.element_size() == 4):
+                raise ValueError("out / feat must be contiguous CUDA tensors of K*N*N / K*5 32-bit elements")
+        r = Request(ctypes.c_void_p(ptr), W, H, stride, dt, int(N), int(lo), int(hi),
+                    ctypes.cast(arr, ctypes.c_void_p), K, 1 if features else 0,
+                    ctypes.c_void_p(out.data_ptr() if out is not None else 0),
+                    ctypes.c_void_p(feat.data_ptr() if feat is not None else 0))
+        ticket = ctypes.c_uint64()
+        _check(_lib().glcm_server_submit(self.handle, ctypes.byref(r), ctypes.byref(ticket)), "glcm_server_submit")
+        self._keep[ticket.value] = (keep, out, feat, K, int(N), bool(features))
+        return ticket.value
+
+    def query(self, ticket) -> RequestInfo:
+        info = RequestInfo()
+        _check(_lib().glcm_server_query(self.handle, int(ticket), ctypes.byref(info)), "glcm_server_query")
+        return info
+
+    def wait(self, ticket) -> RequestInfo:
+        info = RequestInfo()
+        _check(_lib().glcm_server_wait(self.handle, int(ticket), ctypes.byref(info)), "glcm_server_wait")
+        return info
+
+    def fetch(self, ticket, stream=None):
+        """Copies a done request's results into new tensors: (counts [K, N, N] uint32, statistics [K, 5] or None)."""
+        _, _, _, K, N, feats = self._keep[int(ticket)]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = torch.empty((K, N, N), dtype=torch.uint32, device=dev)
+        feat = torch.empty((K, 5), dtype=torch.float32, device=dev) if feats else None
+        _check(_lib().glcm_server_fetch(self.handle, int(ticket), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(feat.data_ptr() if feat is not None else 0),
+                                        _stream_handle(stream)), "glcm_server_fetch")
+        return out, feat
+
+    def release(self, ticket):
+        _check(_lib().glcm_server_release(self.handle, int(ticket)), "glcm_server_release")
+        self._keep.pop(int(ticket), None)
+
+    def drain(self):
+        _check(_lib().glcm_server_drain(self.handle), "glcm_server_drain")
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(_lib().glcm_server_stats(self.handle, ctypes.byref(st)), "glcm_server_stats")
+        return st
+
+    def close(self):
+        if self.handle:
+            _lib().glcm_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "glcm.h"
+#include "glcm_host.h"
 #include "glcm_internal.h"
 
 using glcm::VoteArgs;
@@ -62,16 +63,25 @@ int check_offsets(const glcm_offset_t* offsets, int K) {
   return GLCM_OK;
 }
 
-int check_compute_args(const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo,
-                       uint32_t hi, const glcm_offset_t* offsets, int K, const uint32_t* out) {
+int check_image_args(const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo, uint32_t hi,
+                     const glcm_offset_t* offsets, int K) {
   const int b = dtype_bytes(dtype);
-  if (!img || !out || b == 0) return GLCM_EINVAL;
+  if (!img || b == 0) return GLCM_EINVAL;
   if (W < 1 || H < 1 || stride < W) return GLCM_EINVAL;
   if ((uint64_t)W * (uint64_t)H > 0xffffffffull) return GLCM_EINVAL;
   if (N < 1 || N > GLCM_MAX_LEVELS) return GLCM_EINVAL;
   if (lo > hi || hi > (b == 1 ? 255u : 65535u)) return GLCM_EINVAL;
   if (((uintptr_t)img) % (uintptr_t)b) return GLCM_EINVAL;
   if (check_offsets(offsets, K) != GLCM_OK) return GLCM_EINVAL;
+  return GLCM_OK;
+}
+
+int check_compute_args(const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo,
+                       uint32_t hi, const glcm_offset_t* offsets, int K, const uint32_t* out) {
+  const int rc = check_image_args(img, W, H, stride, dtype, N, lo, hi, offsets, K);
+  if (rc != GLCM_OK) return rc;
+  if (!out) return GLCM_EINVAL;
+  const int b = dtype_bytes(dtype);
   // out must not overlap the image bytes
   const uintptr_t i0 = (uintptr_t)img;
   const uintptr_t i1 = i0 + (uintptr_t)(((uint64_t)(H - 1) * (uint64_t)stride + (uint64_t)W) * (uint64_t)b);
@@ -164,6 +174,7 @@ struct glcm_plan_s {
   int device = 0;
   int dtype = 0;
   int N = 0, K = 0;
+  int k_cap = 0;  // the K the workspace was sized for (glcm_plan_rebind may lower K)
   glcm_offset_t offsets[GLCM_MAX_OFFSETS];
   int max_W = 0, max_H = 0;
   uint32_t flags = 0;
@@ -792,6 +803,7 @@ GLCM_API int glcm_plan_create(glcm_plan_t* plan, int dtype, int N, int K, const 
   p->dtype = dtype;
   p->N = N;
   p->K = K;
+  p->k_cap = K;
   std::memcpy(p->offsets, offsets, sizeof(glcm_offset_t) * K);
   p->max_W = max_W;
   p->max_H = max_H;
@@ -980,6 +992,33 @@ GLCM_API int glcm_plan_kernel_time(glcm_plan_t plan, double* ms_total, int* laun
   return rc;
 }
 
+GLCM_API int glcm_plan_rebind(glcm_plan_t plan, const glcm_offset_t* offsets, int K) {
+  if (!plan || check_offsets(offsets, K) != GLCM_OK || K > plan->k_cap) return GLCM_EINVAL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  // queued launches took their offsets by value; the XCD slices are zero
+  // between calls whatever K, so only the host-side layout changes
+  plan->K = K;
+  std::memcpy(plan->offsets, offsets, sizeof(glcm_offset_t) * K);
+  plan->user_tuned = false;
+  glcm_tuning_t t{};
+  const int rc = choose_tuning(plan, &t);
+  if (rc != GLCM_OK) return rc;
+  if (t.path != kPathGlobal && !plan->xbuf) t.merge = 1;
+  plan->tuning = t;
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_plan_workspace(glcm_plan_t plan, size_t* device_bytes) {
+  if (!plan || !device_bytes) return GLCM_EINVAL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  size_t b = plan->partials_bytes + plan->batch_cap;
+  if (plan->xbuf) b += (size_t)glcm::kXcdSlots * (size_t)plan->k_cap * plan->N * plan->N * 4u;
+  for (int s = 0; s < glcm_plan_s::kSlots; ++s)
+    if (plan->dev_tile[s]) b += plan->tile_bytes;
+  *device_bytes = b;
+  return GLCM_OK;
+}
+
 GLCM_API int glcm_plan_destroy(glcm_plan_t plan) {
   if (!plan) return GLCM_OK;
   plan_release(plan);
@@ -1127,3 +1166,16 @@ GLCM_API int glcm_features(const uint32_t* glcm_u32, int K, int N, float* out, v
 }
 
 }  // extern "C"
+
+namespace glcm {
+
+int hip_error_status(hipError_t e) { return hip_status(e); }
+
+int check_request_args(const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo, uint32_t hi,
+                       const glcm_offset_t* offsets, int K) {
+  return check_image_args(img, W, H, stride, dtype, N, lo, hi, offsets, K);
+}
+
+int memory_kind(const void* p, int* device) { return pointer_kind(p, device); }
+
+}  // namespace glcm

@@ -1,0 +1,25 @@
+// Host-side helpers of glcm_api.cpp that the request server shares (not
+// exported from the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "glcm.h"
+
+namespace glcm {
+
+// Records a failed HIP call for glcm_last_hip_error() and maps it to
+// GLCM_ENOMEM / GLCM_EHIP (GLCM_OK for hipSuccess).
+int hip_error_status(hipError_t e);
+
+// The argument checks of glcm_compute that need no HIP call (out may be NULL
+// here: the server allocates it later).
+int check_request_args(const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo, uint32_t hi,
+                       const glcm_offset_t* offsets, int K);
+
+// 0 = pageable host, 1 = pinned host, 2 = device memory; *device = its device.
+int memory_kind(const void* p, int* device);
+
+}  // namespace glcm

@@ -130,3 +130,34 @@ def test_batch_rejects_bad_arguments(lib):
     assert lib.glcm_batch_compute(ctypes.c_void_p(0x1000), None, 1, 0, 255, ctypes.c_void_p(0x20000), None, None) == -1
     assert lib.glcm_batch_compute(ctypes.c_void_p(0x1000), one, 0, 0, 255, ctypes.c_void_p(0x20000), None, None) == -1
     assert lib.glcm_batch_compute(ctypes.c_void_p(0x1000), one, 1, 0, 255, None, None, None) == -1
+
+
+def test_rebind_and_workspace_reject_bad_arguments(lib):
+    offs = (glcm.Offset * 1)(glcm.Offset(1, 0))
+    assert lib.glcm_plan_rebind(None, offs, 1) == -1
+    assert lib.glcm_plan_workspace(None, ctypes.byref(ctypes.c_size_t())) == -1
+
+
+def test_server_create_rejects_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    assert lib.glcm_server_create(None, 4, 1 << 30, 0, 0) == -1
+    assert lib.glcm_server_create(ctypes.byref(h), 0, 1 << 30, 0, 0) == -1   # no lanes
+    assert lib.glcm_server_create(ctypes.byref(h), 17, 1 << 30, 0, 0) == -1  # more than 16
+    assert lib.glcm_server_create(ctypes.byref(h), 4, 0, 0, 0) == -1         # no budget
+    assert lib.glcm_server_create(ctypes.byref(h), 4, 1 << 20, 2 << 20, 0) == -1  # pool beyond budget
+    assert lib.glcm_server_create(ctypes.byref(h), 4, 1 << 30, 0, 1) == -1   # unknown flags
+    assert h.value is None
+
+
+def test_server_calls_reject_null_server(lib):
+    r = glcm.Request()
+    t = ctypes.c_uint64()
+    info = glcm.RequestInfo()
+    assert lib.glcm_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == -1
+    assert lib.glcm_server_query(None, 1, ctypes.byref(info)) == -1
+    assert lib.glcm_server_wait(None, 1, ctypes.byref(info)) == -1
+    assert lib.glcm_server_fetch(None, 1, ctypes.c_void_p(0x1000), None, None) == -1
+    assert lib.glcm_server_release(None, 1) == -1
+    assert lib.glcm_server_drain(None) == -1
+    assert lib.glcm_server_stats(None, ctypes.byref(glcm.ServerStats())) == -1
+    assert lib.glcm_server_destroy(None) == 0

@@ -1,0 +1,210 @@
+"""GPU tests of the request server (glcm_server_*, through the C ABI) and of
+plan re-targeting: every result of a mixed, concurrently served set of
+requests equals the same request computed alone (counts and statistics bit
+for bit), small ones also match the oracle; admission honours the HBM budget
+and the result pool; bad requests are rejected before anything is queued."""
+
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_1710_06189_amd")
+
+ALL12 = [(d * a, d * b) for d in (1, 2, 4) for a, b in ((1, 0), (-1, 1), (0, 1), (1, 1))]
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    torch.cuda.synchronize()
+    if t.dtype == torch.float32:
+        return t.cpu().numpy()
+    return t.view(torch.int32).cpu().numpy().view(np.uint32)
+
+
+@pytest.fixture(scope="module")
+def pool_images():
+    smooth = torch.from_numpy(synth.smooth(2048, 2048, 8.0, 9100)).cuda()
+    noise = torch.from_numpy(synth.uniform(2048, 2048, 9101)).cuda()
+    return smooth, noise
+
+
+def mixed_requests(n, seed, pool_images, max_side=1500):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        side_w, side_h = (int(v) for v in rng.integers(1, max_side + 1, size=2))
+        src = pool_images[int(rng.integers(0, 2))]
+        y0 = int(rng.integers(0, src.shape[0] - side_h + 1))
+        x0 = int(rng.integers(0, src.shape[1] - side_w + 1))
+        N = int(rng.choice([8, 16, 32, 64, 256]))
+        mask = int(rng.integers(1, 1 << 12))
+        offs = [ALL12[b] for b in range(12) if mask >> b & 1]
+        reqs.append(dict(img=src[y0:y0 + side_h, x0:x0 + side_w], N=N, offsets=offs,
+                         features=bool(rng.integers(0, 2)), box=(y0, x0, side_h, side_w), src=src))
+    return reqs
+
+
+def alone(r):
+    P = G.glcm_compute(r["img"], r["N"], 0, 255, r["offsets"])
+    F = G.glcm_features(P) if r["features"] else None
+    return host(P), (host(F) if F is not None else None)
+
+
+def test_mixed_requests_equal_alone(pool_images):
+    reqs = mixed_requests(40, 1, pool_images)
+    srv = G.Server(lanes=4, hbm_budget=8 << 30, result_pool_bytes=256 << 20)
+    try:
+        print(f"[server] submitting {len(reqs)} mixed requests", flush=True)
+        tickets = [srv.submit(r["img"], r["N"], 0, 255, r["offsets"], features=r["features"]) for r in reqs]
+        srv.drain()
+        st = srv.stats()
+        assert st.completed == len(reqs) and st.failed == 0
+        assert st.max_inflight > 1, "no two requests ever ran at once"
+        for t, r in zip(tickets, reqs):
+            info = srv.query(t)
+            assert info.done == 1 and info.status == 0 and 0 <= info.lane < 4
+            assert info.submit_us <= info.admit_us <= info.done_us
+            P, F = srv.fetch(t)
+            p_alone, f_alone = alone(r)
+            assert np.array_equal(host(P), p_alone), f"counts differ from the request alone: {r['box']} N={r['N']}"
+            if r["features"]:
+                assert np.array_equal(host(F), f_alone), "statistics differ from the request alone"
+            else:
+                assert F is None
+            srv.release(t)
+        assert srv.stats().bytes_in_use <= st.budget_bytes
+    finally:
+        srv.close()
+
+
+def test_small_requests_match_oracle(pool_images):
+    reqs = mixed_requests(12, 2, pool_images, max_side=200)
+    srv = G.Server(lanes=3, hbm_budget=4 << 30, result_pool_bytes=64 << 20)
+    try:
+        tickets = [srv.submit(r["img"], r["N"], 0, 255, r["offsets"], features=True) for r in reqs]
+        for t, r in zip(tickets, reqs):
+            assert srv.wait(t).status == 0
+            P, F = srv.fetch(t)
+            y0, x0, h, w = r["box"]
+            img = r["src"].cpu().numpy()[y0:y0 + h, x0:x0 + w]
+            want = oracle.glcm(img, r["N"], 0, 255, r["offsets"])
+            assert np.array_equal(host(P), want)
+            fw = oracle.features(want)
+            fg = host(F).astype(np.float64)
+            nz = fw != 0
+            assert np.all(fg[~nz] == 0)
+            assert np.all(np.abs(fg[nz] - fw[nz]) / np.abs(fw[nz]) <= 1e-5)
+            srv.release(t)
+    finally:
+        srv.close()
+
+
+def test_caller_owned_buffers(pool_images):
+    reqs = mixed_requests(6, 3, pool_images, max_side=700)
+    srv = G.Server(lanes=2, hbm_budget=2 << 30, result_pool_bytes=0)
+    try:
+        outs = []
+        for r in reqs:
+            K, N = len(r["offsets"]), r["N"]
+            out = torch.empty((K, N, N), dtype=torch.uint32, device="cuda")
+            feat = torch.empty((K, 5), dtype=torch.float32, device="cuda") if r["features"] else None
+            t = srv.submit(r["img"], N, 0, 255, r["offsets"], features=r["features"], out=out, feat=feat)
+            outs.append((t, out, feat))
+        srv.drain()
+        for (t, out, feat), r in zip(outs, reqs):
+            info = srv.query(t)
+            assert info.out == out.data_ptr()
+            p_alone, f_alone = alone(r)
+            assert np.array_equal(host(out), p_alone)
+            if feat is not None:
+                assert np.array_equal(host(feat), f_alone)
+            srv.release(t)
+        assert srv.stats().bytes_in_use > 0  # the lanes' plans stay cached
+    finally:
+        srv.close()
+
+
+def test_budget_admits_one_at_a_time(pool_images):
+    # a plan for N = 32 holds 16 * 12 * 32 * 32 * 4 = 786,432 bytes: a budget
+    # below two plans keeps a second lane from starting while the first runs
+    img = pool_images[0][:1024, :1024]
+    srv = G.Server(lanes=4, hbm_budget=1_200_000, result_pool_bytes=256 * 1024)
+    try:
+        tickets = [srv.submit(img, 32, 0, 255, ALL12[:k + 1], features=True) for k in range(8)]
+        srv.drain()
+        st = srv.stats()
+        assert st.completed == 8 and st.max_inflight == 1
+        assert st.max_bytes_in_use <= 1_200_000
+        ref = host(G.glcm_compute(img, 32, 0, 255, ALL12[:8]))
+        for k, t in enumerate(tickets):
+            P, _ = srv.fetch(t)
+            assert np.array_equal(host(P), ref[:k + 1])
+            srv.release(t)
+    finally:
+        srv.close()
+
+
+def test_result_pool_backpressure(pool_images):
+    img = pool_images[1][:256, :256]
+    K, N = 12, 64
+    per = K * N * N * 4  # 196,608 bytes of counts per request (256-byte multiple)
+    srv = G.Server(lanes=4, hbm_budget=1 << 30, result_pool_bytes=2 * per)
+    try:
+        t = [srv.submit(img, N, 0, 255, ALL12) for _ in range(3)]
+        assert srv.wait(t[0]).status == 0 and srv.wait(t[1]).status == 0
+        time.sleep(0.2)
+        info = srv.query(t[2])
+        assert info.done == 0 and info.lane == -1, "admitted without room in the result pool"
+        with pytest.raises(G.GlcmError) as e:
+            srv.release(t[2])
+        assert e.value.status == -5  # not done yet
+        srv.release(t[0])
+        assert srv.wait(t[2]).status == 0
+        P, _ = srv.fetch(t[2])
+        assert np.array_equal(host(P), host(G.glcm_compute(img, N, 0, 255, ALL12)))
+        srv.release(t[1])
+        srv.release(t[2])
+    finally:
+        srv.close()
+
+
+def test_server_rejects_bad_requests(pool_images):
+    srv = G.Server(lanes=1, hbm_budget=1 << 20, result_pool_bytes=1 << 20)
+    try:
+        with pytest.raises(ValueError):
+            srv.submit(torch.zeros((8, 8), dtype=torch.uint8), 8)  # host image
+        with pytest.raises(G.GlcmError) as e:  # N = 256 needs a 50 MB plan: beyond the budget
+            srv.submit(pool_images[0][:64, :64], 256, 0, 255, ALL12)
+        assert e.value.status == -3
+        with pytest.raises(G.GlcmError) as e:
+            srv.submit(pool_images[0][:64, :64], 8, 10, 5)  # lo > hi
+        assert e.value.status == -1
+        with pytest.raises(G.GlcmError) as e:
+            srv.query(12345)
+        assert e.value.status == -1
+        assert srv.stats().submitted == 0
+    finally:
+        srv.close()
+
+
+def test_plan_rebind_changes_offsets():
+    img = synth.smooth(300, 400, 3.0, 9200)
+    t = torch.from_numpy(img).cuda()
+    plan = G.glcm_plan_create(np.uint8, 16, ALL12[:4], 512, 512)
+    try:
+        ws = G.glcm_plan_workspace(plan)
+        assert ws >= 16 * 4 * 16 * 16 * 4
+        for offs in (ALL12[4:6], [(0, 0), (-3, 2), (5, -1)], ALL12[:4], [(-2, -2)]):
+            G.glcm_plan_rebind(plan, offs)
+            got = host(G.glcm_compute(t, 16, 0, 255, offs, plan=plan))
+            assert np.array_equal(got, oracle.glcm(img, 16, 0, 255, offs))
+        with pytest.raises(G.GlcmError):
+            G.glcm_plan_rebind(plan, ALL12[:5])  # more offsets than the plan was made for
+    finally:
+        plan.close()
