@@ -88,12 +88,15 @@ def main():
                     help="time the candidate layouts (glcm_plan_autotune) instead of keeping the default one")
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
-    ap.add_argument("--workload", default="square", choices=["square", "multispectral", "batch"],
+    ap.add_argument("--workload", default="square", choices=["square", "multispectral", "batch", "serving"],
                     help="square: the 4096^2 device-resident image (the default line); multispectral: "
                          "the 8-band 8192^2 uint16 stack streamed from pinned host memory")
     ap.add_argument("--bands", type=int, default=8)
     ap.add_argument("--tiles", type=int, default=4096)
     ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--requests", type=int, default=1000, help="serving: requests per measurement")
+    ap.add_argument("--lanes", type=int, default=4, help="serving: server lanes (streams)")
+    ap.add_argument("--budget-gib", type=int, default=32, help="serving: HBM budget of the server")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
@@ -114,6 +117,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args, G, torch, np, oracle, synth, dev)
+        return
+    if args.workload == "serving":
+        bench_serving(args, G, torch, np, oracle, synth, dev)
         return
     oracle_cache, image_cache = {}, {}
     fixed = None
@@ -433,6 +439,147 @@ def bench_multispectral(args, G, torch, np, oracle, synth, dev):
         "streamed_over_serial": wall_serial / wall_stream,
         "h2d_share_of_serial": t_copy / wall_serial, "tile_rows": tiles, "tuning": tuning,
         "resident": "pinned host", "check": "band 0 bit-exact vs oracle; all bands per-offset totals"}), flush=True)
+
+
+def bench_serving(args, G, torch, np, oracle, synth, dev):
+    """The serving workload: requests are square crops (side uniform in
+    [256, 8192]) of a smooth or a noise 8192^2 pool image, N from {8, 16, 32,
+    64, 256}, a random non-empty subset of the 12 offsets, statistics with
+    probability 1/2.  Measures (a) one request at a time on one stream,
+    waiting for each (a plain request loop), (b) all requests queued on one
+    stream, (c) the request server with every request submitted at once
+    (closed-loop capacity) and (d) Poisson arrivals at 0.5x and 0.9x that
+    capacity, with p50/p99 latency from arrival to completion.  Every served
+    result must equal the one-at-a-time result bit for bit; 16 small requests
+    are also checked against the oracle."""
+    all12 = synth.offsets_for([1, 2, 4])
+    pool = synth.serving_pool(args.size)
+    pool_dev = {k: torch.from_numpy(v).to(dev) for k, v in pool.items()}
+    reqs = synth.serving_requests(args.requests, args.size)
+    views = [pool_dev[r["kind"]][r["y0"]:r["y0"] + r["side"], r["x0"]:r["x0"] + r["side"]] for r in reqs]
+    pairs = [pairs_of(r["side"], r["side"], r["offsets"]) for r in reqs]
+    total_pairs = float(sum(pairs))
+    print(f"[serving] {len(reqs)} requests, {total_pairs:.3g} pairs", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    outs = [torch.empty((len(r["offsets"]), r["N"], r["N"]), dtype=torch.uint32, device=dev) for r in reqs]
+    feats = [torch.empty((len(r["offsets"]), 5), dtype=torch.float32, device=dev) if r["features"] else None
+             for r in reqs]
+    plans = {N: G.glcm_plan_create(np.uint8, N, all12, args.size, args.size) for N in sorted({r["N"] for r in reqs})}
+
+    def one_stream(sync):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r, v, o, f in zip(reqs, views, outs, feats):
+            p = plans[r["N"]]
+            G.glcm_plan_rebind(p, r["offsets"])
+            G.glcm_compute(v, r["N"], 0, 255, r["offsets"], out=o, plan=p, stream=stream)
+            if f is not None:
+                G.glcm_features(o, out=f, stream=stream)
+            if sync:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    one_stream(False)  # warm-up
+    t_sync = one_stream(True)
+    t_stream = one_stream(False)
+    print(f"[serving] one at a time {t_sync * 1e3:.1f} ms, one stream {t_stream * 1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+    # oracle on 16 small requests (bit-exact counts)
+    small = sorted(range(len(reqs)), key=lambda i: reqs[i]["side"])[:16]
+    for i in small:
+        r = reqs[i]
+        img = pool[r["kind"]][r["y0"]:r["y0"] + r["side"], r["x0"]:r["x0"] + r["side"]]
+        want = oracle.glcm(img, r["N"], 0, 255, r["offsets"])
+        if not np.array_equal(outs[i].view(torch.int32).cpu().numpy().view(np.uint32), want):
+            raise SystemExit(f"bench: request {i} differs from the oracle")
+
+    srv = G.Server(lanes=args.lanes, hbm_budget=args.budget_gib << 30, result_pool_bytes=min(4 << 30, args.budget_gib << 29))
+
+    def submit_all(arrivals=None):
+        tickets, lags = [], []
+        t0 = time.perf_counter()
+        for i, (r, v) in enumerate(zip(reqs, views)):
+            if arrivals is not None:
+                due = t0 + arrivals[i]
+                while True:
+                    now = time.perf_counter()
+                    if now >= due:
+                        break
+                    if due - now > 2e-3:
+                        time.sleep(due - now - 1e-3)
+                lags.append(max(0.0, time.perf_counter() - due))
+            tickets.append(srv.submit(v, r["N"], 0, 255, r["offsets"], features=r["features"]))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        infos = [srv.query(t) for t in tickets]
+        return tickets, infos, lags, wall
+
+    def explain(i, P):
+        """Which side of a mismatch agrees with the oracle, and by how much the other is off."""
+        r = reqs[i]
+        img = pool[r["kind"]][r["y0"]:r["y0"] + r["side"], r["x0"]:r["x0"] + r["side"]]
+        want = oracle.glcm(img, r["N"], 0, 255, r["offsets"]).astype(np.int64)
+        got = {"served": P.view(torch.int32).cpu().numpy().view(np.uint32).astype(np.int64),
+               "alone": outs[i].view(torch.int32).cpu().numpy().view(np.uint32).astype(np.int64)}
+        parts = []
+        for name, g in got.items():
+            d = g - want
+            per_k = [(tuple(r["offsets"][k]), int(np.count_nonzero(d[k])), int(d[k].sum())) for k in range(len(d))
+                     if d[k].any()]
+            parts.append(f"{name}: {'== oracle' if not d.any() else f'differs (offset, bins, count delta) {per_k}'}")
+        return (f"request {i} N={r['N']} side={r['side']} K={len(r['offsets'])} ptr%16={views[i].data_ptr() % 16}: "
+                + "; ".join(parts))
+
+    def check_and_release(tickets, infos):
+        bad = []
+        for i, (t, info) in enumerate(zip(tickets, infos)):
+            if info.status != 0:
+                raise SystemExit(f"bench: served request {i} failed with status {info.status}")
+            P, F = srv.fetch(t)
+            if not torch.equal(P.view(torch.int32), outs[i].view(torch.int32)):
+                bad.append(explain(i, P))
+                print(f"[serving] MISMATCH {bad[-1]}", file=sys.stderr, flush=True)
+            elif F is not None and not torch.equal(F, feats[i]):
+                bad.append(f"statistics of request {i}")
+            srv.release(t)
+        if bad:
+            raise SystemExit(f"bench: {len(bad)} served results differ from the same requests alone")
+
+    tk, inf, _, _ = submit_all()  # warm-up: every lane gets its plans
+    check_and_release(tk, inf)
+    tk, inf, _, t_closed = submit_all()
+    check_and_release(tk, inf)
+    capacity = len(reqs) / t_closed
+    print(f"[serving] closed loop {t_closed * 1e3:.1f} ms, capacity {capacity:.0f} req/s", file=sys.stderr, flush=True)
+    open_loop = []
+    g = np.random.default_rng(171006189 + 40)
+    for load in (0.5, 0.9):
+        qps = load * capacity
+        arrivals = np.cumsum(g.exponential(1.0 / qps, size=len(reqs)))
+        arrivals -= arrivals[0]
+        tk, inf, lags, wall = submit_all(arrivals)
+        lat_ms = np.array([(i.done_us - i.submit_us) / 1e3 + lag * 1e3 for i, lag in zip(inf, lags)])
+        check_and_release(tk, inf)
+        open_loop.append({"load": load, "offered_qps": qps, "achieved_qps": len(reqs) / wall,
+                          "gpairs_s": total_pairs / wall / 1e9, "p50_ms": float(np.percentile(lat_ms, 50)),
+                          "p99_ms": float(np.percentile(lat_ms, 99)), "max_submit_lag_ms": float(max(lags) * 1e3)})
+        print(f"[serving] load {load}: p50 {open_loop[-1]['p50_ms']:.3f} ms p99 {open_loop[-1]['p99_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+    st = srv.stats()
+    srv.close()
+    for p in plans.values():
+        p.close()
+    line = {"workload": f"serving-{len(reqs)}-requests-u8-256to{args.size}-N8to256-K1to12",
+            "requests": len(reqs), "pairs": total_pairs, "lanes": args.lanes, "hbm_budget_gib": args.budget_gib,
+            "one_at_a_time_gpairs_s": total_pairs / t_sync / 1e9, "one_stream_gpairs_s": total_pairs / t_stream / 1e9,
+            "served_closed_loop_gpairs_s": total_pairs / t_closed / 1e9, "capacity_req_s": capacity,
+            "served_over_one_at_a_time": t_sync / t_closed, "served_over_one_stream": t_stream / t_closed,
+            "open_loop": open_loop, "max_inflight": st.max_inflight,
+            "max_budgeted_gib": st.max_bytes_in_use / 2 ** 30,
+            "check": "every served result == the same request alone (counts and statistics, bit for bit); "
+                     "16 smallest requests == oracle"}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

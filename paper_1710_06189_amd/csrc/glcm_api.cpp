@@ -426,7 +426,10 @@ int plan_init(glcm_plan_t p) {
     const size_t bytes = (size_t)glcm::kXcdSlots * (size_t)p->K * p->N * p->N * 4u;
     if (bytes <= (256u << 20)) {
       GLCM_TRY(hipMalloc((void**)&p->xbuf, bytes));
-      GLCM_TRY(hipMemset(p->xbuf, 0, bytes));
+      // zeroed before the plan is returned: its first call may come on a
+      // non-blocking stream, which is not ordered after the null stream
+      GLCM_TRY(hipMemsetAsync(p->xbuf, 0, bytes, nullptr));
+      GLCM_TRY(hipStreamSynchronize(nullptr));
       p->xslots = xcc_slots(p->device);
     } else {
       p->tuning.merge = 1;  // band partials only

@@ -164,3 +164,31 @@ def batch_tiles(count: int = 4096, seed_offset: int = 3):
     tiles = [tiles[i] for i in order]
     return dict(name=f"{count}-tiles-u8-32to512-N16-K4", images=tiles, N=16, lo=0, hi=255,
                 offsets=offsets_for([1]))
+
+
+def serving_pool(size: int = 8192):
+    """The two pool images requests are cropped from: smooth (sigma = 8 px)
+    and i.i.d. uniform noise, both uint8 size x size."""
+    s = BASE_SEED + 4
+    return {"smooth": smooth(size, size, 8.0, s), "noise": uniform(size, size, s + 1)}
+
+
+def serving_requests(count: int = 1000, size: int = 8192, seed_offset: int = 5):
+    """The serving workload's requests: a square crop with side uniform in
+    [256, size] at a uniform position of the smooth or the noise pool image
+    (probability 1/2 each), N drawn from {8, 16, 32, 64, 256}, the offsets a
+    uniform non-empty subset (mask in [1, 4095]) of d in {1, 2, 4} at the four
+    angles, statistics requested with probability 1/2."""
+    g = rng(BASE_SEED + seed_offset)
+    all12 = offsets_for([1, 2, 4])
+    out = []
+    for _ in range(count):
+        side = int(g.integers(256, size + 1))
+        kind = "smooth" if g.integers(0, 2) == 0 else "noise"
+        y0 = int(g.integers(0, size - side + 1))
+        x0 = int(g.integers(0, size - side + 1))
+        N = int(g.choice([8, 16, 32, 64, 256]))
+        mask = int(g.integers(1, 4096))
+        offs = [all12[b] for b in range(12) if mask >> b & 1]
+        out.append(dict(kind=kind, side=side, y0=y0, x0=x0, N=N, offsets=offs, features=bool(g.integers(0, 2))))
+    return out

@@ -208,3 +208,23 @@ def test_plan_rebind_changes_offsets():
             G.glcm_plan_rebind(plan, ALL12[:5])  # more offsets than the plan was made for
     finally:
         plan.close()
+
+
+def test_new_plan_used_at_once_on_nonblocking_streams():
+    """A plan's accumulators are zero when glcm_plan_create returns, even while
+    the null stream is still busy and the first call comes on a non-blocking
+    stream (which the null stream does not order)."""
+    img = synth.smooth(700, 900, 4.0, 9300)
+    t = torch.from_numpy(img).cuda()
+    want = oracle.glcm(img, 32, 0, 255, ALL12[:4])
+    big = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    for rep in range(6):
+        big.fill_(rep)  # keeps the default stream busy while the plans are made
+        plans = [G.glcm_plan_create(np.uint8, 32, ALL12[:4], 1024, 1024) for _ in streams]
+        outs = [G.glcm_compute(t, 32, 0, 255, ALL12[:4], plan=p, stream=s) for p, s in zip(plans, streams)]
+        torch.cuda.synchronize()
+        for o in outs:
+            assert np.array_equal(host(o), want)
+        for p in plans:
+            p.close()
