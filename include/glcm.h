@@ -84,6 +84,9 @@ enum glcm_status {
                                                  glcm_plan_kernel_time() */
 #define GLCM_FLAG_FORCE_SLABS       (1u << 5) /* row-slab kernel even where the strip kernel
                                                  applies */
+#define GLCM_FLAG_FORCE_L2          (1u << 6) /* large-N path: pairs added straight into
+                                                 per-XCD accumulators in L2, no LDS copies
+                                                 (when those fit in 256 MiB) */
 
 typedef struct glcm_plan_s *glcm_plan_t;
 
@@ -101,7 +104,7 @@ typedef struct glcm_tuning {
                            a small kernel sums the 8 slices; 1: per-band partial counts,
                            summed by a reduce kernel */
     int path;           /* read-only: 0 generic, 1 slab kernel, 2 partitioned, 3 global,
-                           4 strip kernel */
+                           4 strip kernel, 5 L2 slices (large N) */
     int partitions;     /* read-only: bin partitions per pass */
 } glcm_tuning_t;
 

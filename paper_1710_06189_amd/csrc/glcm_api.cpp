@@ -42,9 +42,9 @@ int hip_status(hipError_t e) {
 
 constexpr uint32_t kKnownFlags = GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED |
                                  GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD | GLCM_FLAG_TIMING |
-                                 GLCM_FLAG_FORCE_SLABS;
+                                 GLCM_FLAG_FORCE_SLABS | GLCM_FLAG_FORCE_L2;
 
-enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3, kPathStrips = 4 };
+enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3, kPathStrips = 4, kPathL2 = 5 };
 
 
 
@@ -337,6 +337,12 @@ bool strip_layout(const glcm_plan_s* p, int W, int rows, int R, bool want_pair, 
   return false;
 }
 
+// The per-XCD accumulation slices of all K GLCMs stay within 256 MiB (then
+// the plan keeps them and the L2-slice path is possible).
+bool l2_slices_fit(const glcm_plan_s* p) {
+  return (uint64_t)glcm::kXcdSlots * (uint64_t)p->k_cap * (uint64_t)p->N * (uint64_t)p->N * 4ull <= (256ull << 20);
+}
+
 int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   // Path and LDS layout for this plan's (dtype, N, K, offsets, flags).
   const uint32_t NN = (uint32_t)p->N * (uint32_t)p->N;
@@ -351,6 +357,10 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   d.merge = 0;
   if (p->flags & GLCM_FLAG_FORCE_GLOBAL) {
     d.path = kPathGlobal;
+    d.replicas = 1;
+    d.partitions = 1;
+  } else if ((p->flags & GLCM_FLAG_FORCE_L2) && l2_slices_fit(p)) {
+    d.path = kPathL2;
     d.replicas = 1;
     d.partitions = 1;
   } else {
@@ -398,7 +408,10 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
       uint64_t P1 = (words + budget - 1) / budget;
       if (p->flags & GLCM_FLAG_FORCE_PARTITIONED) P1 = std::max<uint64_t>(P1, std::min<uint64_t>(words, 3));
       if (P1 > 16) {
-        d.path = kPathGlobal;
+        // more LDS passes than pay off: pairs straight into the per-XCD
+        // slices when they fit (never slower than device-wide atomics on
+        // MI355X, faster on smooth images), else device-wide atomics
+        d.path = l2_slices_fit(p) ? kPathL2 : kPathGlobal;
         d.replicas = 1;
         d.partitions = 1;
       } else {
@@ -533,13 +546,36 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     return GLCM_OK;
   }
 
-  if (path == kPathGlobal) {
+  if (path == kPathGlobal || (path == kPathL2 && !xcd)) {
     for (int k = 0; k < p->K; ++k) {
       a.dx[k] = p->offsets[k].dx;
       a.dy[k] = p->offsets[k].dy;
     }
     if (!accumulate) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
     GLCM_TRY(glcm::launch_vote_global(a, b, stream));
+    return GLCM_OK;
+  }
+  if (path == kPathL2) {
+    for (int k = 0; k < p->K; ++k) {
+      a.dx[k] = p->offsets[k].dx;
+      a.dy[k] = p->offsets[k].dy;
+    }
+    a.xbuf = p->xbuf;
+    a.region_rows = 16;
+    glcm::LaunchTiming tm;
+    if (p->flags & GLCM_FLAG_TIMING) {
+      GLCM_TRY(hipEventCreate(&tm.start));
+      GLCM_TRY(hipEventCreate(&tm.stop));
+      p->timing.emplace_back(tm.start, tm.stop);
+    }
+    const int cols = (W + 63) / 64, runs = (y_end - y_begin + 15) / 16;
+    const int groups = std::max(1, std::min((cols * runs + 3) / 4, p->num_cus * 8));
+    hipError_t e = glcm::launch_vote_l2(a, b, groups, stream, tm);
+    if (e == hipSuccess && finish) e = glcm::launch_finish(p->xbuf, out, words, p->xslots, accumulate, stream);
+    if (e != hipSuccess) {
+      (void)hipMemsetAsync(p->xbuf, 0, (size_t)p->xslots * words * 4u, stream);
+      return hip_status(e);
+    }
     return GLCM_OK;
   }
 
@@ -845,7 +881,7 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
       const int P = row_partitions(plan, n.replicas, bits);
       if (P == 0) return GLCM_EINVAL;
       t.partitions = P;
-    } else if (t.path != kPathGlobal) {
+    } else if (t.path != kPathGlobal && t.path != kPathL2) {
       bits = 32;
       const uint64_t words = (uint64_t)plan->K * NN;
       if ((uint64_t)n.replicas > (uint64_t)plan->lds_budget_words) return GLCM_EINVAL;
@@ -928,6 +964,14 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
         t.wg_size = wg;
         cand.push_back(t);
       }
+    }
+    if (plan->xbuf && l2_slices_fit(plan)) {  // no LDS copies: pairs straight into the XCD slices
+      glcm_tuning_t t = start;
+      t.path = kPathL2;
+      t.replicas = 1;
+      t.partitions = 1;
+      t.merge = 0;
+      cand.push_back(t);
     }
   }
   const size_t words = (size_t)plan->K * plan->N * plan->N;

@@ -106,6 +106,10 @@ hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, uint32_t nsl
 // ids[b] = XCC_ID of the XCD that ran workgroup b (b < blocks).
 hipError_t launch_xcc_probe(uint32_t* ids, int blocks, hipStream_t stream);
 hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream);
+// Large-N path: pairs added straight into the per-XCD slices (a.xbuf), rows
+// in runs of a.region_rows; `groups` workgroups of 256 threads.
+hipError_t launch_vote_l2(const VoteArgs& a, int dtype_bytes, int groups, hipStream_t stream,
+                          const LaunchTiming& tm = {});
 hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream);
 // One workgroup per image of the batch (T images); D = dwords per bin (4, 8
 // or 16), maxdy = 1 or 2.  lds_bytes from batch_lds_bytes().

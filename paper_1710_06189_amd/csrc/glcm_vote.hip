@@ -196,17 +196,23 @@ __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
   const uint32_t N = a.q.nlev, NN = N * N;
   const int y0 = a.y_begin + region * a.region_rows;
   const int y1 = min(a.y_end, y0 + a.region_rows);
+  // GLCMs [k0, k1) overlap this partition's words [pbase, pbase + pwords);
+  // within them, a first pixel of level i can only vote if its row of bins
+  // (k, i, *) overlaps the range too, checked before the second pixel is read
+  const int k0 = (int)(pbase / NN), k1 = min(a.K, (int)((pbase + pwords + NN - 1) / NN));
   if (y1 > y0) {
     const uint32_t n = (uint32_t)(y1 - y0) * (uint32_t)a.W;
     for (uint32_t idx = threadIdx.x; idx < n; idx += blockDim.x) {
       const int y = y0 + (int)(idx / (uint32_t)a.W);
       const int x = (int)(idx % (uint32_t)a.W);
       const uint32_t av = quantize(img[(int64_t)y * a.stride + x], a.q);
-      for (int k = 0; k < a.K; ++k) {
+      for (int k = k0; k < k1; ++k) {
+        const uint32_t row = (uint32_t)k * NN + av * N;  // first word of bins (k, av, *)
+        if (a.P > 1 && (row + N <= pbase || row >= pbase + pwords)) continue;
         const int x2 = x + a.dx[k], y2 = y + a.dy[k];
         if ((unsigned)x2 >= (unsigned)a.W || (unsigned)y2 >= (unsigned)a.H) continue;
         const uint32_t bv = quantize(img[(int64_t)y2 * a.stride + x2], a.q);
-        const uint32_t w = (uint32_t)k * NN + av * N + bv - pbase;
+        const uint32_t w = row + bv - pbase;
         if (w < pwords)
           __hip_atomic_fetch_add(&lds[(w << a.log2R) + r], 1u, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -237,6 +243,47 @@ __global__ __launch_bounds__(256) void k_vote_global(VoteArgs a) {
       const uint32_t bv = quantize(img[(int64_t)y2 * a.stride + x2], a.q);
       __hip_atomic_fetch_add(&a.out[(size_t)k * NN + av * N + bv], 1u, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L2-slice counting for large N, where LDS bin partitions would re-read the
+// image many times: no LDS copies.  Each pair is added, with a
+// workgroup-scope atomic, to the accumulation slice of the XCD the workgroup
+// runs on (the atomic executes in that XCD's L2, and no other XCD touches the
+// slice); k_finish then sums the slices into `out`.  A wavefront walks 64
+// consecutive columns down a run of region_rows rows, so first-pixel loads
+// are coalesced and second pixels mostly hit the caches.  Any alignment.
+// ---------------------------------------------------------------------------
+template <typename Pix>
+__global__ __launch_bounds__(256) void k_vote_l2(VoteArgs a) {
+  uint32_t xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+  uint32_t* xs = a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total;
+  const Pix* img = (const Pix*)a.img;
+  const uint32_t N = a.q.nlev, NN = N * N;
+  const int cols = (a.W + 63) >> 6;
+  const int runs = (a.y_end - a.y_begin + a.region_rows - 1) / a.region_rows;
+  const int lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const int tasks = cols * runs;
+  for (int task = __builtin_amdgcn_readfirstlane((int)blockIdx.x * nw + (int)(threadIdx.x >> 6)); task < tasks;
+       task += (int)gridDim.x * nw) {
+    const int x = (task % cols) * 64 + lane;
+    const int ya = a.y_begin + (task / cols) * a.region_rows;
+    const int yb = min(a.y_end, ya + a.region_rows);
+    if (x >= a.W) continue;
+    for (int y = ya; y < yb; ++y) {
+      const uint32_t v = img[(int64_t)y * a.stride + x];
+      const uint32_t base = (a.qfast ? v >> a.qfast_shift : quantize(v, a.q)) * N;
+      for (int k = 0; k < a.K; ++k) {
+        const int x2 = x + a.dx[k], y2 = y + a.dy[k];
+        if ((unsigned)x2 >= (unsigned)a.W || (unsigned)y2 >= (unsigned)a.H) continue;
+        const uint32_t v2 = img[(int64_t)y2 * a.stride + x2];
+        const uint32_t bv = a.qfast ? v2 >> a.qfast_shift : quantize(v2, a.q);
+        __hip_atomic_fetch_add(xs + (size_t)k * NN + base + bv, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
     }
   }
 }
@@ -675,6 +722,12 @@ hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, in
   hipLaunchKernelGGL(k_reduce, dim3((M + per - 1) / per), dim3(kReduceQuads * kReduceGroups), 0, stream, partials,
                      out, M, nbands, accumulate ? 1 : 0);
   return hipGetLastError();
+}
+
+hipError_t launch_vote_l2(const VoteArgs& a, int dtype_bytes, int groups, hipStream_t stream, const LaunchTiming& tm) {
+  const dim3 grid(groups), block(256);
+  if (dtype_bytes == 1) return launch(k_vote_l2<uint8_t>, a, grid, block, 0, stream, tm);
+  return launch(k_vote_l2<uint16_t>, a, grid, block, 0, stream, tm);
 }
 
 hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream) {

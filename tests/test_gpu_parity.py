@@ -91,7 +91,7 @@ def test_offsets_any(offs):
 
 @pytest.mark.parametrize("flags,name", [
     (G.FLAG_FORCE_GENERIC, "generic"), (G.FLAG_FORCE_PARTITIONED, "partitioned"),
-    (G.FLAG_FORCE_GLOBAL, "global"), (G.FLAG_FORCE_SLABS, "slabs"), (0, "auto"),
+    (G.FLAG_FORCE_GLOBAL, "global"), (G.FLAG_FORCE_SLABS, "slabs"), (G.FLAG_FORCE_L2, "l2"), (0, "auto"),
 ])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 @pytest.mark.parametrize("merge", [0, 1])
@@ -105,6 +105,31 @@ def test_forced_paths(flags, name, dtype, merge):
             plan.set_tuning(merge=merge)
         check(img, 32, 0, top, offs, plan=plan, label=f"path {name} {plan.tuning.as_dict()}")
         check(img, 32, 0, top, offs, plan=plan, label=f"path {name} again")
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("N,dtype,shape,offs", [
+    (256, np.uint8, (700, 900), synth.offsets_for([1, 2, 4])),
+    (256, np.uint8, (1, 1), [(1, 0)]),
+    (512, np.uint16, (333, 1001), [(1, 0), (0, -3), (-5, 5)]),
+    (1024, np.uint16, (257, 129), [(0, 0), (7, 7)]),
+    (128, np.uint8, (64, 2100), synth.offsets_for([1]) + [(-64, 0), (2100, 0)]),
+])
+def test_l2_slice_path(N, dtype, shape, offs):
+    """Pairs added straight into the per-XCD slices (large N), on aligned and
+    misaligned views, twice on one plan (the slices are clean again after each
+    call)."""
+    H, W = shape
+    top = int(np.iinfo(dtype).max)
+    img = synth.smooth(H + 3, W + 5, 4.0, 31 + N, dtype) if H > 2 and W > 2 else synth.uniform(H + 3, W + 5, 3, dtype)
+    plan = G.glcm_plan_create(dtype, N, offs, W + 5, H + 3, G.FLAG_FORCE_L2)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == "l2"
+        t = to_device(img)
+        for y0, x0 in ((0, 0), (3, 5), (1, 2)):
+            view, sub = t[y0:y0 + H, x0:x0 + W], img[y0:y0 + H, x0:x0 + W]
+            check(sub, N, 0, top, offs, plan=plan, t=view, label=f"l2 N={N} at ({y0},{x0})")
     finally:
         plan.close()
 
