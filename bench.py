@@ -480,7 +480,40 @@ def bench_serving(args, G, torch, np, oracle, synth, dev):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    def by_n():
+        """Device time and counting path of each request alone, summed per N."""
+        torch.cuda.synchronize()
+        evs = []
+        for r, v, o, f in zip(reqs, views, outs, feats):
+            p = plans[r["N"]]
+            G.glcm_plan_rebind(p, r["offsets"])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            G.glcm_compute(v, r["N"], 0, 255, r["offsets"], out=o, plan=p, stream=stream)
+            if f is not None:
+                G.glcm_features(o, out=f, stream=stream)
+            e1.record(stream)
+            aligned = v.data_ptr() % 16 == 0 and v.stride(0) % 16 == 0
+            path = G.PATH_NAMES.get(p.tuning.path, "?")
+            if not aligned and path in ("strips", "slabs"):
+                path = (f"{path} (staged copy)" if v.shape[0] * v.shape[1] >= 1 << 16
+                        else "generic (misaligned)")
+            evs.append((r["N"], path, e0, e1))
+        torch.cuda.synchronize()
+        agg = {}
+        for (N, path, e0, e1), pr in zip(evs, pairs):
+            a = agg.setdefault(str(N), {"requests": 0, "pairs": 0, "ms": 0.0, "paths": {}})
+            a["requests"] += 1
+            a["pairs"] += pr
+            a["ms"] += e0.elapsed_time(e1)
+            a["paths"][path] = a["paths"].get(path, 0) + 1
+        for a in agg.values():
+            a["gpairs_s"] = a["pairs"] / (a["ms"] * 1e-3) / 1e9
+        return agg
+
     one_stream(False)  # warm-up
+    per_n = by_n()
+    print(f"[serving] per N: {json.dumps(per_n)}", file=sys.stderr, flush=True)
     t_sync = one_stream(True)
     t_stream = one_stream(False)
     print(f"[serving] one at a time {t_sync * 1e3:.1f} ms, one stream {t_stream * 1e3:.1f} ms",
@@ -575,7 +608,7 @@ def bench_serving(args, G, torch, np, oracle, synth, dev):
             "one_at_a_time_gpairs_s": total_pairs / t_sync / 1e9, "one_stream_gpairs_s": total_pairs / t_stream / 1e9,
             "served_closed_loop_gpairs_s": total_pairs / t_closed / 1e9, "capacity_req_s": capacity,
             "served_over_one_at_a_time": t_sync / t_closed, "served_over_one_stream": t_stream / t_closed,
-            "open_loop": open_loop, "max_inflight": st.max_inflight,
+            "open_loop": open_loop, "max_inflight": st.max_inflight, "alone_by_N": per_n,
             "max_budgeted_gib": st.max_bytes_in_use / 2 ** 30,
             "check": "every served result == the same request alone (counts and statistics, bit for bit); "
                      "16 smallest requests == oracle"}

@@ -46,6 +46,13 @@ constexpr uint32_t kKnownFlags = GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTI
 
 enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3, kPathStrips = 4, kPathL2 = 5 };
 
+// Misaligned device images of at least this many pixels are copied into an
+// aligned staging buffer and counted by the strip / slab kernels (measured on
+// MI355X: the per-pixel kernel is 3-4x slower than the strip kernel, the copy
+// costs about two extra passes over the image at HBM speed); smaller ones
+// take the per-pixel kernel directly.
+constexpr uint64_t kStageMinPixels = 1u << 16;
+
 
 
 int dtype_bytes(int dtype) { return dtype == GLCM_U8 ? 1 : (dtype == GLCM_U16 ? 2 : 0); }
@@ -186,6 +193,8 @@ struct glcm_plan_s {
   // device workspace
   uint32_t* partials = nullptr;
   size_t partials_bytes = 0;
+  void* stage = nullptr;  // aligned copy of a misaligned device image (row pitch a multiple of 16 bytes)
+  size_t stage_bytes = 0;
   uint32_t* xbuf = nullptr;  // [kXcdSlots][K*N*N] per-XCD accumulators, kept zero between calls
   uint32_t xslots = glcm::kXcdSlots;  // slices the device's XCC_IDs reach (the rest stay zero)
 
@@ -464,6 +473,7 @@ void plan_release(glcm_plan_t p) {
   }
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   if (p->partials) (void)hipFree(p->partials);
+  if (p->stage) (void)hipFree(p->stage);
   if (p->xbuf) (void)hipFree(p->xbuf);
   if (p->batch_pending) (void)hipEventSynchronize(p->batch_uploaded);
   if (p->batch_pin) (void)hipHostFree(p->batch_pin);
@@ -487,6 +497,19 @@ int ensure_partials(glcm_plan_t p, size_t bytes) {
   p->partials_bytes = 0;
   GLCM_TRY(hipMalloc((void**)&p->partials, bytes));
   p->partials_bytes = bytes;
+  return GLCM_OK;
+}
+
+// Makes sure the plan's staging buffer holds `bytes`; waits for the plan's
+// queued work before replacing it.
+int ensure_stage(glcm_plan_t p, size_t bytes) {
+  if (bytes <= p->stage_bytes) return GLCM_OK;
+  if (p->has_done) GLCM_TRY(hipEventSynchronize(p->done));
+  if (p->stage) GLCM_TRY(hipFree(p->stage));
+  p->stage = nullptr;
+  p->stage_bytes = 0;
+  GLCM_TRY(hipMalloc(&p->stage, bytes));
+  p->stage_bytes = bytes;
   return GLCM_OK;
 }
 
@@ -536,7 +559,19 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   const Canon c = canonicalize(p->offsets, p->K);
   if (path == kPathRows || path == kPathStrips) {
     const bool aligned = ((uintptr_t)img % 16 == 0) && (((uint64_t)stride * b) % 16 == 0);
-    if (!aligned) path = (words <= (uint32_t)p->lds_budget_words) ? kPathGeneric : kPathPartitioned;
+    if (!aligned && (uint64_t)W * (uint64_t)H >= kStageMinPixels && y_begin == 0 && y_end == H) {
+      // one pitched copy into the plan's aligned buffer, then the fast kernels
+      const size_t pitch = ((size_t)W * b + 15) & ~(size_t)15;
+      GLCM_TRY_RC(ensure_stage(p, pitch * (size_t)H));
+      GLCM_TRY(hipMemcpy2DAsync(p->stage, pitch, img, (size_t)stride * b, (size_t)W * b, (size_t)H,
+                                hipMemcpyDeviceToDevice, stream));
+      img = p->stage;
+      stride = (int64_t)(pitch / b);
+      a.img = img;
+      a.stride = stride;
+    } else if (!aligned) {
+      path = (words <= (uint32_t)p->lds_budget_words) ? kPathGeneric : kPathPartitioned;
+    }
   }
   const bool xcd = t.merge == 0 && p->xbuf != nullptr && path != kPathGlobal;
   if (y_end <= y_begin) {
@@ -1058,7 +1093,7 @@ GLCM_API int glcm_plan_rebind(glcm_plan_t plan, const glcm_offset_t* offsets, in
 GLCM_API int glcm_plan_workspace(glcm_plan_t plan, size_t* device_bytes) {
   if (!plan || !device_bytes) return GLCM_EINVAL;
   std::lock_guard<std::mutex> lk(plan->mu);
-  size_t b = plan->partials_bytes + plan->batch_cap;
+  size_t b = plan->partials_bytes + plan->batch_cap + plan->stage_bytes;
   if (plan->xbuf) b += (size_t)glcm::kXcdSlots * (size_t)plan->k_cap * plan->N * plan->N * 4u;
   for (int s = 0; s < glcm_plan_s::kSlots; ++s)
     if (plan->dev_tile[s]) b += plan->tile_bytes;

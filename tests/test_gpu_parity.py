@@ -462,3 +462,24 @@ def test_kernel_timing_flag():
         assert plan.kernel_time() == (0.0, 0)
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("offs", [synth.offsets_for([1]), synth.offsets_for([1, 2, 4])])
+def test_misaligned_large_views_staged(dtype, offs):
+    """Misaligned views of at least 2^16 pixels are copied to an aligned
+    staging buffer and counted by the strip / slab kernels: bit-exact, and the
+    plan's workspace grows by the staging buffer."""
+    top = int(np.iinfo(dtype).max)
+    base = synth.smooth(520, 1100, 4.0, 41, dtype)
+    t = to_device(base)
+    plan = G.glcm_plan_create(dtype, 32, offs, 1100, 520)
+    try:
+        before = G.glcm_plan_workspace(plan)
+        for y0, x0, h, w in ((1, 3, 500, 1001), (0, 1, 257, 1099), (7, 13, 300, 700)):
+            sub = base[y0:y0 + h, x0:x0 + w]
+            check(sub, 32, 0, top, offs, plan=plan, t=t[y0:y0 + h, x0:x0 + w],
+                  label=f"staged view ({y0},{x0}) {h}x{w}")
+        assert G.glcm_plan_workspace(plan) >= before + 500 * ((1001 * base.itemsize + 15) // 16 * 16)
+    finally:
+        plan.close()
