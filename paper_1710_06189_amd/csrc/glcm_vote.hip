@@ -200,19 +200,23 @@ __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
   // within them, a first pixel of level i can only vote if its row of bins
   // (k, i, *) overlaps the range too, checked before the second pixel is read
   const int k0 = (int)(pbase / NN), k1 = min(a.K, (int)((pbase + pwords + NN - 1) / NN));
-  if (y1 > y0) {
-    const uint32_t n = (uint32_t)(y1 - y0) * (uint32_t)a.W;
-    for (uint32_t idx = threadIdx.x; idx < n; idx += blockDim.x) {
-      const int y = y0 + (int)(idx / (uint32_t)a.W);
-      const int x = (int)(idx % (uint32_t)a.W);
-      const uint32_t av = quantize(img[(int64_t)y * a.stride + x], a.q);
+  // threads as (rows at once) x (columns at once): tw columns, a power of
+  // two from 64 up to blockDim (also a power of two, so tw divides it), and
+  // blockDim / tw rows; no division inside the loops
+  int tw = 64;
+  while (tw < a.W && tw < (int)blockDim.x) tw *= 2;
+  const int tr = (int)blockDim.x / tw, tx = (int)threadIdx.x & (tw - 1), ty = (int)threadIdx.x / tw;
+  for (int y = y0 + ty; y < y1; y += tr) {
+    for (int x = tx; x < a.W; x += tw) {
+      const uint32_t v = img[(int64_t)y * a.stride + x];
+      const uint32_t av = a.qfast ? v >> a.qfast_shift : quantize(v, a.q);
       for (int k = k0; k < k1; ++k) {
         const uint32_t row = (uint32_t)k * NN + av * N;  // first word of bins (k, av, *)
         if (a.P > 1 && (row + N <= pbase || row >= pbase + pwords)) continue;
         const int x2 = x + a.dx[k], y2 = y + a.dy[k];
         if ((unsigned)x2 >= (unsigned)a.W || (unsigned)y2 >= (unsigned)a.H) continue;
-        const uint32_t bv = quantize(img[(int64_t)y2 * a.stride + x2], a.q);
-        const uint32_t w = row + bv - pbase;
+        const uint32_t v2 = img[(int64_t)y2 * a.stride + x2];
+        const uint32_t w = row + (a.qfast ? v2 >> a.qfast_shift : quantize(v2, a.q)) - pbase;
         if (w < pwords)
           __hip_atomic_fetch_add(&lds[(w << a.log2R) + r], 1u, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
