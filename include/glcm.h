@@ -97,9 +97,11 @@ typedef struct glcm_tuning {
                            uint16 images with offsets reaching 2 pixels runs at most 512) */
     int rows_per_wave;  /* slab kernel: first-pixel rows per wavefront slab (4); 0 elsewhere */
     int tile_rows;      /* host-image upload tile height (rows) */
-    int counter_bits;   /* strip / slab kernel LDS counters: 16 (two copies per dword, used
-                           only when no count can overflow) or 32; 0 keeps the current value.
-                           The strip kernel takes replicas / dwords per bin of 4, 8 or 16 */
+    int counter_bits;   /* LDS counters: 16 or 32; 0 keeps the current value.  Slab kernel:
+                           two copies per dword; strip kernel: two GLCMs per dword (dwords
+                           per bin 4, 8, 16 or 32); partitioned kernel: two bins per dword
+                           with one copy (replicas 1), bands then kept below 2^16 pixels.
+                           16-bit layouts are used only where no count can overflow */
     int merge;          /* 0: workgroups add their counts into per-XCD accumulators in L2,
                            a small kernel sums the 8 slices; 1: per-band partial counts,
                            summed by a reduce kernel */

@@ -429,6 +429,10 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
         d.path = P1 > 1 ? kPathPartitioned : kPathGeneric;
         d.replicas = R;
         d.partitions = (int)P1;
+        // several bin partitions with one copy: 16-bit counters, two bins per
+        // dword, half the passes (faster on smooth images; on noise the
+        // shorter bands' merge can cost more, which the autotuner weighs)
+        if (P1 > 1 && R == 1) d.counter_bits = 16;
       }
     }
   }
@@ -622,6 +626,18 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     R = 1;
     while (R < 16 && ((uint64_t)words * 2 * R + budget - 1) / budget <= (uint64_t)P) R *= 2;
   }
+  // generic kernel over two or more bin partitions with one copy: 16-bit
+  // counters, two words per dword, halve the partitions (each band is then
+  // kept below 2^16 first pixels, the most one counter can receive, which
+  // needs rows of at most 65535 pixels)
+  bool g16 = false;
+  if ((path == kPathGeneric || path == kPathPartitioned) && t.counter_bits == 16 && P >= 2 && R == 1 && xcd &&
+      W <= 65535) {
+    const uint64_t budget = (uint64_t)p->lds_budget_words;
+    const int P16 = (int)(((uint64_t)words + 2 * budget - 1) / (2 * budget));
+    P = (p->flags & GLCM_FLAG_FORCE_PARTITIONED) ? std::max(P16, P) : P16;  // forced: keep the passes
+    g16 = true;
+  }
   int log2R = 0;
   while ((1 << log2R) < R) ++log2R;
   a.log2R = log2R;
@@ -668,7 +684,8 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   const int rows = y_end - y_begin;
   const int wg = path == kPathStrips ? std::min(t.wg_size, glcm::strip_max_threads(b, smd)) : t.wg_size;
   const int nwaves = wg / 64;
-  size_t lds_need = ((size_t)a.part_words << log2R) * 4u;
+  if (g16) a.c16 = 1;
+  size_t lds_need = g16 ? (size_t)((a.part_words + 1u) / 2u) * 4u : ((size_t)a.part_words << log2R) * 4u;
   if (path == kPathRows)
     lds_need = (size_t)(a.part_words / NN) * row_glcm_dwords(p->N, R, t.counter_bits == 16 ? 16 : 32) * 4u;
   lds_need = std::max(lds_need, (size_t)wg * 4u);
@@ -684,6 +701,10 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     region_rows = sl.region_rows;
     a.strip_rows = sl.strip_rows;
   }
+  if (g16 && (uint64_t)region_rows * (uint64_t)W > 65535u) {
+    region_rows = std::max(1, 65535 / W);
+    nregions = (rows + region_rows - 1) / region_rows;
+  }
   a.nregions = nregions;
   a.region_rows = region_rows;
   a.rows_per_wave = rpw;
@@ -697,7 +718,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   }
 
   // LDS: the copies (at least one word per thread)
-  size_t lds_bytes = ((size_t)a.part_words << log2R) * 4u;
+  size_t lds_bytes = g16 ? (size_t)((a.part_words + 1u) / 2u) * 4u : ((size_t)a.part_words << log2R) * 4u;
   if (path == kPathRows) {
     // 16-bit counters only when no count can reach 2^16: each slab gives a
     // copy at most 64 lanes / R x 16 pixels x 4 rows votes into one bin.
@@ -917,7 +938,7 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
       if (P == 0) return GLCM_EINVAL;
       t.partitions = P;
     } else if (t.path != kPathGlobal && t.path != kPathL2) {
-      bits = 32;
+      if (bits == 16 && n.replicas != 1) return GLCM_EINVAL;  // 16-bit bins: one copy
       const uint64_t words = (uint64_t)plan->K * NN;
       if ((uint64_t)n.replicas > (uint64_t)plan->lds_budget_words) return GLCM_EINVAL;
       const uint64_t cap = (uint64_t)plan->lds_budget_words / n.replicas;
@@ -991,13 +1012,17 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
     for (int R = 1; R <= 16; R *= 2) {
       const uint64_t P = (words * R + budget - 1) / budget;
       if (P > 16) continue;
-      for (int wg : {256, 512, 1024}) {
-        glcm_tuning_t t = start;
-        t.replicas = R;
-        t.partitions = (int)P;
-        t.path = P > 1 ? kPathPartitioned : kPathGeneric;
-        t.wg_size = wg;
-        cand.push_back(t);
+      for (int bits : {32, 16}) {
+        if (bits == 16 && (R != 1 || P < 2)) continue;  // 16-bit bins: one copy, several passes
+        for (int wg : {256, 512, 1024}) {
+          glcm_tuning_t t = start;
+          t.replicas = R;
+          t.partitions = (int)P;
+          t.path = P > 1 ? kPathPartitioned : kPathGeneric;
+          t.counter_bits = bits;
+          t.wg_size = wg;
+          cand.push_back(t);
+        }
       }
     }
     if (plan->xbuf && l2_slices_fit(plan)) {  // no LDS copies: pairs straight into the XCD slices

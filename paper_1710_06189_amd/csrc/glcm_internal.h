@@ -46,7 +46,8 @@ struct VoteArgs {
   uint32_t pitch;             // row kernel: LDS row pitch of a GLCM, >= N + 1 (row/column N: sentinel)
   Quant div_n, div_nn;        // magic/shift for dividing by N and by N*N (only those fields used)
   int c16;                    // slab kernel: 16-bit counters, two copies per dword; strip kernel:
-                              // 16-bit counters, two GLCMs per dword
+                              // 16-bit counters, two GLCMs per dword; generic kernel: 16-bit
+                              // counters, two consecutive words per dword (one copy)
   int kp;                     // strip kernel: GLCMs per partition (<= 4)
   int kg;                     // strip kernel: dword groups per bin (kp, or kp / 2 rounded up with c16)
   int strip_rows;             // strip kernel: first-pixel rows per wavefront strip

@@ -78,6 +78,31 @@ __device__ void store_partial(const VoteArgs& a, const uint32_t* lds, uint32_t p
   }
 }
 
+// Merge of the generic kernel's 16-bit layout (word w in half w & 1 of dword
+// w >> 1, one copy): into the XCD slice or the band partial.
+__device__ void store_partial_bin_pairs(const VoteArgs& a, const uint32_t* lds, uint32_t pbase, uint32_t pwords,
+                                        int region) {
+  __syncthreads();
+  uint32_t* dst = a.partials + (size_t)region * a.words_total + pbase;
+  uint32_t xcc = 0;
+  if (a.xbuf) asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+  uint32_t* xs = a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total + pbase;
+  for (uint32_t m = threadIdx.x; 2u * m < pwords; m += blockDim.x) {
+    const uint32_t d = lds[m];
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+      const uint32_t w = 2u * m + h;
+      if (w >= pwords) break;
+      const uint32_t s = (d >> (16u * h)) & 0xffffu;
+      if (a.xbuf) {
+        if (s) __hip_atomic_fetch_add(xs + w, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        dst[w] = s;
+      }
+    }
+  }
+}
+
 // out[w] = (accumulate ? out[w] : 0) + sum of the first nslots XCD slices
 // (the slices of XCC_IDs the device has; the others stay zero); clears them.
 __global__ __launch_bounds__(256) void k_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, uint32_t nslots,
@@ -188,7 +213,9 @@ __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
   const int region = rp.x, part = rp.y;
   const uint32_t pbase = (uint32_t)part * a.part_words;
   const uint32_t pwords = min(a.part_words, a.words_total - pbase);
-  zero_lds(lds, pwords << a.log2R);
+  // c16: 16-bit counters, words 2m and 2m + 1 in the low and high halves of
+  // dword m (one copy); the host keeps every band below 2^16 first pixels
+  zero_lds(lds, a.c16 ? (pwords + 1u) >> 1 : pwords << a.log2R);
   __syncthreads();
 
   const Pix* img = (const Pix*)a.img;
@@ -217,13 +244,21 @@ __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
         if ((unsigned)x2 >= (unsigned)a.W || (unsigned)y2 >= (unsigned)a.H) continue;
         const uint32_t v2 = img[(int64_t)y2 * a.stride + x2];
         const uint32_t w = row + (a.qfast ? v2 >> a.qfast_shift : quantize(v2, a.q)) - pbase;
-        if (w < pwords)
-          __hip_atomic_fetch_add(&lds[(w << a.log2R) + r], 1u, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (w < pwords) {
+          if (a.c16)
+            __hip_atomic_fetch_add(&lds[w >> 1], 1u << ((w & 1u) << 4), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          else
+            __hip_atomic_fetch_add(&lds[(w << a.log2R) + r], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
       }
     }
   }
-  store_partial(a, lds, pbase, pwords, region, a.q.nlev, a.q.nlev * a.q.nlev, false);
+  if (a.c16)
+    store_partial_bin_pairs(a, lds, pbase, pwords, region);
+  else
+    store_partial(a, lds, pbase, pwords, region, a.q.nlev, a.q.nlev * a.q.nlev, false);
 }
 
 // ---------------------------------------------------------------------------

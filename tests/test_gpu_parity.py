@@ -483,3 +483,26 @@ def test_misaligned_large_views_staged(dtype, offs):
         assert G.glcm_plan_workspace(plan) >= before + 500 * ((1001 * base.itemsize + 15) // 16 * 16)
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("N,dtype,shape,offs", [
+    (256, np.uint8, (60, 8200), synth.offsets_for([1, 2, 4])[:6]),   # bands of 7 rows (W > 4369)
+    (256, np.uint8, (700, 300), synth.offsets_for([1, 2, 4])[:9]),
+    (400, np.uint16, (257, 1030), [(1, 0), (-2, 3), (0, -4)]),
+    (256, np.uint8, (1, 70000), [(1, 0), (3, 0)]),                      # one row wider than 2^16
+])
+def test_partitioned_sixteen_bit_bins(N, dtype, shape, offs):
+    """Bin partitions with 16-bit counters, two bins per dword: every band
+    stays below 2^16 first pixels, so a constant image (all pairs in one bin
+    per GLCM) must count exactly too."""
+    H, W = shape
+    top = int(np.iinfo(dtype).max)
+    img = synth.smooth(H, W, 3.0, 51 + N, dtype) if H > 2 else synth.uniform(H, W, 52, dtype)
+    plan = G.glcm_plan_create(dtype, N, offs, W, H)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == "partitioned"
+        check(img, N, 0, top, offs, plan=plan, label=f"16-bit bins N={N} {W}x{H}")
+        const = np.full((H, W), top // 3, dtype=dtype)
+        check(const, N, 0, top, offs, plan=plan, label=f"16-bit bins constant N={N} {W}x{H}")
+    finally:
+        plan.close()
