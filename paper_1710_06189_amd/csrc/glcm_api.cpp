@@ -1207,8 +1207,20 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
   const size_t lds_bytes = glcm::batch_lds_bytes(plan->N, plan->K, D);
   if (lds_bytes > lds_cu - 1024u) return GLCM_EUNSUPPORTED;
   GLCM_TRY_RC(order_after_previous(plan, stream));
-  // descriptors, largest image first
-  const size_t need = (size_t)T * sizeof(glcm::BatchTile);
+  // misaligned images are first copied into the plan's staging buffer with a
+  // 16-byte pitch (one realignment launch), so every image takes the strip
+  // path of the batch kernel
+  size_t n_mis = 0, stage_need = 0;
+  for (int t = 0; t < T; ++t) {
+    const glcm_tile_t& e = tiles[t];
+    if ((uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0) continue;
+    ++n_mis;
+    stage_need += (((size_t)e.W * b + 15) & ~(size_t)15) * (size_t)e.H;
+  }
+  if (n_mis) GLCM_TRY_RC(ensure_stage(plan, stage_need));
+  // descriptors, largest image first, then the copies
+  const size_t tiles_bytes = (size_t)T * sizeof(glcm::BatchTile);
+  const size_t need = tiles_bytes + n_mis * sizeof(glcm::RealignDesc);
   if (plan->batch_pending) GLCM_TRY(hipEventSynchronize(plan->batch_uploaded));
   plan->batch_pending = false;
   if (need > plan->batch_cap) {
@@ -1230,6 +1242,8 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
     return (uint64_t)tiles[x].W * (uint64_t)tiles[x].H > (uint64_t)tiles[y].W * (uint64_t)tiles[y].H;
   });
   glcm::BatchTile* d = (glcm::BatchTile*)plan->batch_pin;
+  glcm::RealignDesc* rd = (glcm::RealignDesc*)((char*)plan->batch_pin + tiles_bytes);
+  size_t off = 0, r = 0;
   for (int i = 0; i < T; ++i) {
     const glcm_tile_t& e = tiles[order[(size_t)i]];
     d[i].img = e.img;
@@ -1237,11 +1251,27 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
     d[i].W = e.W;
     d[i].H = e.H;
     d[i].index = order[(size_t)i];
-    d[i].aligned = ((uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0) ? 1 : 0;
+    d[i].reserved = 0;
+    if ((uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0) continue;
+    const size_t pitch = ((size_t)e.W * b + 15) & ~(size_t)15;
+    rd[r].src = e.img;
+    rd[r].sstride = e.stride;
+    rd[r].dst_off = off;
+    rd[r].dpitch = (int32_t)(pitch / b);
+    rd[r].W = e.W;
+    rd[r].H = e.H;
+    rd[r].pad = 0;
+    d[i].img = (const char*)plan->stage + off;
+    d[i].stride = (int64_t)(pitch / b);
+    off += pitch * (size_t)e.H;
+    ++r;
   }
   GLCM_TRY(hipMemcpyAsync(plan->batch_dev, plan->batch_pin, need, hipMemcpyHostToDevice, stream));
   GLCM_TRY(hipEventRecord(plan->batch_uploaded, stream));
   plan->batch_pending = true;
+  if (n_mis)
+    GLCM_TRY(glcm::launch_batch_realign((const glcm::RealignDesc*)((char*)plan->batch_dev + tiles_bytes), (int)n_mis,
+                                        (char*)plan->stage, b, stream));
 
   glcm::BatchArgs a;
   std::memset(&a, 0, sizeof(a));

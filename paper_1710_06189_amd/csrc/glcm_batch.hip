@@ -18,12 +18,12 @@ namespace {
 // Images arrive largest first, so the hardware dispatcher balances the
 // workgroups over the CUs.
 //
-// Aligned images use the strip machinery with the wavefront split into row
+// Images (16-byte aligned: misaligned ones are first copied by
+// k_batch_realign) use the strip machinery with the wavefront split into row
 // segments when the image is narrower than 1024 columns: lane l handles chunk
 // l mod cw of segment l / cw (cw = chunks per row), each segment walking its
-// own run of rows; halo pixels outside [0, W) take the sentinel.  Images that
-// are not 16-byte aligned are counted per pixel.  Both write the strip LDS
-// layout (kp = K GLCMs, D dwords per bin).
+// own run of rows; halo pixels outside [0, W) take the sentinel.  Votes go to
+// the strip LDS layout (kp = K GLCMs, D dwords per bin).
 // ---------------------------------------------------------------------------
 template <int MAXDY, int D, int KI, int CUR>
 __device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermRow<MAXDY> (&ring)[MAXDY + 1],
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
   zero_lds(lds, vote_words);
   __syncthreads();
 
-  if (t.aligned) {
+  {
     int code[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) code[q] = q < K ? a.vcode[q] : -1;
@@ -103,24 +103,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
         }
       }
     }
-  } else {
-    // per pixel: one thread per first pixel, votes in the strip layout (a
-    // negated offset is stored transposed, as the strip path counts it)
-    const Pix* img = (const Pix*)t.img;
-    const uint32_t n = (uint32_t)t.W * (uint32_t)t.H;
-    for (uint32_t idx = threadIdx.x; idx < n; idx += blockDim.x) {
-      const int y = (int)(idx / (uint32_t)t.W), x = (int)(idx % (uint32_t)t.W);
-      const uint32_t av = quantize(img[(int64_t)y * t.stride + x], a.q);
-      for (int k = 0; k < K; ++k) {
-        const int x2 = x + a.dx[k], y2 = y + a.dy[k];
-        if ((unsigned)x2 >= (unsigned)t.W || (unsigned)y2 >= (unsigned)t.H) continue;
-        const uint32_t bv = quantize(img[(int64_t)y2 * t.stride + x2], a.q);
-        const bool tr = (a.tmask >> k) & 1ull;
-        const uint32_t bin = tr ? bv * n1 + av : av * n1 + bv;
-        __hip_atomic_fetch_add((lds_word_t*)(size_t)(C + bin * mb + 4u * D * (uint32_t)k), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    }
   }
 
   // merge: consecutive 16-byte units, D / 4 lanes per bin, into out and into
@@ -129,19 +111,31 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
   constexpr uint32_t QPB = D / 4;
   uint32_t* merged = lds + vote_words;
   uint32_t* dst = a.out + (size_t)t.index * K * NN;
+  // unit u = ((i * n1 + j) * K + k) * QPB + r: (i, j, k) step by the
+  // mixed-radix digits of blockDim / QPB each pass, so nothing is divided
+  const uint32_t S = blockDim.x / QPB, uK = (uint32_t)K;
+  const uint32_t sk = S % uK, sj = S / uK % n1, si = S / uK / n1;
+  const uint32_t blk0 = threadIdx.x / QPB;
+  uint32_t mk = blk0 % uK, mj = blk0 / uK % n1, mi = blk0 / uK / n1;
+  const bool lead = threadIdx.x % QPB == 0;
   for (uint32_t u = threadIdx.x; u < vote_words / 4u; u += blockDim.x) {
     const uint4 v = ((const uint4*)lds)[u];
     uint32_t sum = (v.x + v.y) + (v.z + v.w);
     if (QPB >= 2) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0xb1, 0xf, 0xf, false);
     if (QPB >= 4) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0x4e, 0xf, 0xf, false);
-    if (u % QPB != 0) continue;
-    const uint32_t blk = u / QPB, k = blk % (uint32_t)K, bin = blk / (uint32_t)K;
-    const uint32_t i = bin / n1, j = bin % n1;
-    if (i >= N || j >= N) continue;
-    const bool tr = (a.tmask >> k) & 1ull;
-    const uint32_t w = k * NN + (tr ? j * N + i : i * N + j);
-    dst[w] = sum;
-    merged[w] = sum;
+    if (lead && mi < N && mj < N) {
+      const bool tr = (a.tmask >> mk) & 1ull;
+      const uint32_t w = mk * NN + (tr ? mj * N + mi : mi * N + mj);
+      dst[w] = sum;
+      merged[w] = sum;
+    }
+    mk += sk;
+    const uint32_t ck = mk >= uK;
+    mk -= ck ? uK : 0u;
+    mj += sj + ck;  // < 2 n1
+    const uint32_t cj = mj >= n1;
+    mj -= cj ? n1 : 0u;
+    mi += si + cj;
   }
   if (!a.feat) return;
   __syncthreads();
@@ -151,7 +145,41 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
     glcm_features_wg(merged + k * NN, N, a.feat + ((size_t)t.index * K + k) * 5, redu, redf);
 }
 
+// Copies each misaligned image of a batch into the staging buffer with a
+// 16-byte row pitch, so the batch kernel reads every image with 16-byte
+// loads.  One workgroup per image; source pixels are read one by one (any
+// alignment), destination dwords written whole (pixels past W as zero).
+template <typename Pix>
+__global__ __launch_bounds__(256) void k_batch_realign(const RealignDesc* d, char* stage) {
+  const RealignDesc e = d[blockIdx.x];
+  const Pix* src = (const Pix*)e.src;
+  uint32_t* dst = (uint32_t*)(stage + e.dst_off);
+  constexpr int PPD = 4 / (int)sizeof(Pix);          // pixels per dword
+  const uint32_t dw = (uint32_t)(e.W + PPD - 1) / PPD;  // dwords of a row that hold pixels
+  const uint32_t dpd = (uint32_t)e.dpitch / PPD;       // dwords per copy row
+  const uint32_t n = dw * (uint32_t)e.H;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t y = i / dw, q = i - y * dw;
+    const Pix* s = src + (int64_t)y * e.sstride;
+    uint32_t v = 0;
+#pragma unroll
+    for (int p = 0; p < PPD; ++p) {
+      const uint32_t x = q * PPD + (uint32_t)p;
+      if (x < (uint32_t)e.W) v |= (uint32_t)s[x] << (p * 8 * (int)sizeof(Pix));
+    }
+    dst[(size_t)y * dpd + q] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_batch_realign(const RealignDesc* d, int n, char* stage, int dtype_bytes, hipStream_t stream) {
+  if (dtype_bytes == 1)
+    hipLaunchKernelGGL(k_batch_realign<uint8_t>, dim3(n), dim3(256), 0, stream, d, stage);
+  else
+    hipLaunchKernelGGL(k_batch_realign<uint16_t>, dim3(n), dim3(256), 0, stream, d, stage);
+  return hipGetLastError();
+}
 
 template <typename Pix, int MAXDY>
 static hipError_t launch_batch_t(const BatchArgs& a, int T, int D, size_t lds_bytes, hipStream_t stream) {
