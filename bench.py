@@ -241,6 +241,7 @@ def main():
         cpu = {"value": reps * main_res["pairs"] / el / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
                "sample": f"{reps} full passes over the 4096x4096 {args.kind} image, 4 offsets, single-threaded C "
                          f"oracle, {el:.1f} s"}
+        extra["cpu_all_cores"] = cpu_all_cores(oracle, np, img, N, lo, hi, offs, main_res["pairs"], args.cpu_seconds)
 
     line = {
         "metric": METRIC, "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
@@ -254,6 +255,33 @@ def main():
         "extra": extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def cpu_all_cores(oracle, np, img, N, lo, hi, offs, pairs, seconds):
+    """The oracle run on row bands by one thread per host core (ctypes releases
+    the GIL), each band into its own GLCM, summed: the multi-core CPU figure.
+    Checked against the single-threaded oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    cores = min(16, len(os.sched_getaffinity(0)))  # the GPU box's CPU share
+    H = img.shape[0]
+    bands = [(H * b // cores, H * (b + 1) // cores) for b in range(cores)]
+
+    def once(ex):
+        return sum(ex.map(lambda r: oracle.glcm(img, N, lo, hi, offs, rows=r).astype(np.uint64), bands))
+
+    with ThreadPoolExecutor(cores) as ex:
+        if not np.array_equal(once(ex), oracle.glcm(img, N, lo, hi, offs)):
+            raise SystemExit("bench: the multi-core oracle run differs from the single-threaded one")
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            once(ex)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+    return {"value": reps * pairs / el / 1e9, "unit": "Gpairs/s", "cores": cores,
+            "kind": "oracle on row bands, one thread per core, private GLCMs summed",
+            "sample": f"{reps} full passes over the same image, {el:.1f} s"}
 
 
 def call_latencies(G, torch, np, synth, dev, args, calls=200):
