@@ -281,6 +281,33 @@ typedef struct glcm_tile {
 GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t *tiles, int T, uint32_t lo, uint32_t hi,
                                 uint32_t *out, float *features, void *stream);
 
+/*
+ * A batch prepared once and launched many times, e.g. from a HIP graph.
+ * glcm_batch_prepare uploads the T descriptors (sorted as in
+ * glcm_batch_compute) and reserves an aligned copy of every misaligned image
+ * into device memory owned by the returned handle; it takes the plan's dtype,
+ * N, offsets and limits at that moment and blocks until the upload is done.
+ * The images must stay at their addresses while the handle is used (their
+ * pixels may change between launches).  Errors as glcm_batch_compute;
+ * GLCM_ENOMEM / GLCM_EHIP.
+ */
+typedef struct glcm_batch_s *glcm_batch_t;
+GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t *tiles, int T, glcm_batch_t *batch);
+
+/*
+ * Queues the prepared batch on `stream`: the realignment copies (if any) and
+ * the fused kernel, nothing else (no copy from host memory, no allocation, no
+ * synchronisation, no memset), so the call can be captured into a HIP graph
+ * and replayed.  out / features as in glcm_batch_compute.  One handle must not
+ * run on two streams at once (its copies are shared).  GLCM_EINVAL for a NULL
+ * handle or out, lo > hi or hi above the dtype maximum; GLCM_EHIP.
+ */
+GLCM_API int glcm_batch_run(glcm_batch_t batch, uint32_t lo, uint32_t hi, uint32_t *out, float *features,
+                            void *stream);
+
+/* Waits for the device to go idle, then releases the handle.  NULL is accepted. */
+GLCM_API int glcm_batch_destroy(glcm_batch_t batch);
+
 /* ------------------------------------------------------------------------
  * Request server: continuous admission of GLCM jobs of mixed image size, N
  * and offset lists.  A scheduler thread admits queued requests in arrival

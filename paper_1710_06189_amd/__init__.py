@@ -35,7 +35,7 @@ __all__ = [
     "glcm_compute",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
     "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
-    "glcm_plan_rebind", "glcm_plan_workspace", "Server", "RequestInfo", "ServerStats",
+    "glcm_plan_rebind", "glcm_plan_workspace", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -137,6 +137,12 @@ def _lib():
         lib.glcm_features.argtypes = [vp, i32, i32, vp, vp]
         lib.glcm_batch_compute.restype = i32
         lib.glcm_batch_compute.argtypes = [vp, ctypes.POINTER(Tile), i32, u32, u32, vp, vp, vp]
+        lib.glcm_batch_prepare.restype = i32
+        lib.glcm_batch_prepare.argtypes = [vp, ctypes.POINTER(Tile), i32, ctypes.POINTER(vp)]
+        lib.glcm_batch_run.restype = i32
+        lib.glcm_batch_run.argtypes = [vp, u32, u32, vp, vp, vp]
+        lib.glcm_batch_destroy.restype = i32
+        lib.glcm_batch_destroy.argtypes = [vp]
         lib.glcm_plan_rebind.restype = i32
         lib.glcm_plan_rebind.argtypes = [vp, ctypes.POINTER(Offset), i32]
         lib.glcm_plan_workspace.restype = i32
@@ -414,6 +420,48 @@ def glcm_batch_compute(images, plan, lo=0, hi=None, out=None, features=True, str
                                      ctypes.c_void_p(feats.data_ptr()) if feats is not None else None, s),
            "glcm_batch_compute")
     return out, feats
+
+
+class PreparedBatch:
+    """A batch whose descriptors live on the device (glcm_batch_prepare):
+    run() only queues kernels, so it can be captured in a graph.  The images
+    (and the plan's dtype, N and offsets at preparation) are fixed; their
+    pixels may change between runs."""
+
+    def __init__(self, images, plan):
+        ts = images if isinstance(images, TileSet) else TileSet(images, plan.dtype)
+        h = ctypes.c_void_p()
+        _check(_lib().glcm_batch_prepare(plan.handle, ts.tiles, ts.T, ctypes.byref(h)), "glcm_batch_prepare")
+        self.handle, self.tileset = h, ts
+        self.T, self.K, self.N, self.dtype = ts.T, len(plan.offsets), plan.N, plan.dtype
+
+    def run(self, lo=0, hi=None, out=None, features=None, stream=None):
+        """Queues the batch; returns (out [T, K, N, N], features or None)."""
+        if hi is None:
+            hi = 255 if self.dtype == U8 else 65535
+        dev = self.tileset.device
+        if out is None:
+            out = torch.empty((self.T, self.K, self.N, self.N), dtype=torch.uint32, device=dev)
+        elif not (out.is_cuda and out.is_contiguous() and out.numel() == self.T * self.K * self.N * self.N
+                  and out.element_size() == 4):
+            raise ValueError("out must be a contiguous CUDA tensor of T*K*N*N 32-bit elements")
+        if features is True:
+            features = torch.empty((self.T, self.K, 5), dtype=torch.float32, device=dev)
+        _check(_lib().glcm_batch_run(self.handle, int(lo), int(hi), ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(features.data_ptr()) if isinstance(features, torch.Tensor)
+                                     else None, _stream_handle(stream)), "glcm_batch_run")
+        return out, (features if isinstance(features, torch.Tensor) else None)
+
+    def close(self):
+        if self.handle:
+            _lib().glcm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

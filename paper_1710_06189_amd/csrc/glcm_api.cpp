@@ -1182,23 +1182,26 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void* img, int W, int H, int64
   return record_done(plan, stream);
 }
 
-GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
-                                uint32_t* out, float* features, void* stream_) {
-  if (!plan || !tiles || !out || T < 1 || T > (1 << 20)) return GLCM_EINVAL;
+namespace {
+
+// What a batch launch needs besides lo, hi and the output pointers.
+struct BatchLayout {
+  int D = 0, smd = 1, b = 1;
+  size_t lds_bytes = 0;
+  glcm::BatchArgs args{};  // offsets, codes and layout; quantizer and outputs filled per launch
+};
+
+// Checks a batch request against the plan and picks its LDS layout.
+int batch_layout(glcm_plan_t plan, const glcm_tile_t* tiles, int T, BatchLayout* L) {
+  if (!plan || !tiles || T < 1 || T > (1 << 20)) return GLCM_EINVAL;
   const int b = dtype_bytes(plan->dtype);
-  if (lo > hi || hi > (b == 1 ? 255u : 65535u)) return GLCM_EINVAL;
   for (int t = 0; t < T; ++t) {
     const glcm_tile_t& e = tiles[t];
     if (!e.img || e.W < 1 || e.H < 1 || e.W > plan->max_W || e.H > plan->max_H || e.stride < e.W) return GLCM_EINVAL;
     if ((uint64_t)e.W * (uint64_t)e.H > 0xffffffffull || ((uintptr_t)e.img % (uintptr_t)b)) return GLCM_EINVAL;
   }
-  int dev = -1;
-  if (pointer_kind(out, &dev) != 2) return GLCM_EINVAL;
-  if (features && pointer_kind(features, &dev) != 2) return GLCM_EINVAL;
   const Canon c = canonicalize(plan->offsets, plan->K);
   if (plan->N > 255 || plan->K > glcm::kStripMaxKp || c.maxdy > 2 || c.maxadx > 2) return GLCM_EUNSUPPORTED;
-  hipStream_t stream = (hipStream_t)stream_;
-  std::lock_guard<std::mutex> lk(plan->mu);
   // LDS layout: the most dwords per bin that leave room for three workgroups
   // per CU (their loads and merges then overlap other workgroups' votes)
   const size_t lds_cu = (size_t)plan->lds_budget_words * 4u + 1024u;
@@ -1206,21 +1209,115 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
   while (D > 4 && glcm::batch_lds_bytes(plan->N, plan->K, D) * 3u > lds_cu) D /= 2;
   const size_t lds_bytes = glcm::batch_lds_bytes(plan->N, plan->K, D);
   if (lds_bytes > lds_cu - 1024u) return GLCM_EUNSUPPORTED;
+  L->D = D;
+  L->b = b;
+  L->lds_bytes = lds_bytes;
+  L->smd = std::max(c.maxdy, c.maxadx) <= 1 ? 1 : 2;
+  glcm::BatchArgs& a = L->args;
+  std::memset(&a, 0, sizeof(a));
+  a.K = plan->K;
+  for (int k = 0; k < plan->K; ++k) {
+    a.dx[k] = plan->offsets[k].dx;
+    a.dy[k] = plan->offsets[k].dy;
+    a.vcode[k] = c.dy[k] * (2 * L->smd + 1) + c.dx[k] + L->smd;
+  }
+  a.tmask = c.tmask;
+  a.pitch = (uint32_t)plan->N + 1u;
+  a.min_rows = 8;
+  return GLCM_OK;
+}
+
+bool tile_aligned(const glcm_tile_t& e, int b) {
+  return (uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0;
+}
+
+// Staging bytes the misaligned images of a batch need (16-byte row pitch).
+size_t batch_stage_bytes(const glcm_tile_t* tiles, int T, int b, size_t* n_mis) {
+  size_t need = 0, n = 0;
+  for (int t = 0; t < T; ++t) {
+    if (tile_aligned(tiles[t], b)) continue;
+    ++n;
+    need += (((size_t)tiles[t].W * b + 15) & ~(size_t)15) * (size_t)tiles[t].H;
+  }
+  *n_mis = n;
+  return need;
+}
+
+// Fills the descriptors (largest image first) and, after them, the copies of
+// the misaligned images into `stage` (device address); `host` holds
+// T * sizeof(BatchTile) + n_mis * sizeof(RealignDesc) bytes.
+void batch_descriptors(const glcm_tile_t* tiles, int T, int b, const void* stage, void* host) {
+  std::vector<int> order((size_t)T);
+  for (int t = 0; t < T; ++t) order[(size_t)t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (uint64_t)tiles[x].W * (uint64_t)tiles[x].H > (uint64_t)tiles[y].W * (uint64_t)tiles[y].H;
+  });
+  glcm::BatchTile* d = (glcm::BatchTile*)host;
+  glcm::RealignDesc* rd = (glcm::RealignDesc*)((char*)host + (size_t)T * sizeof(glcm::BatchTile));
+  size_t off = 0, r = 0;
+  for (int i = 0; i < T; ++i) {
+    const glcm_tile_t& e = tiles[order[(size_t)i]];
+    d[i].img = e.img;
+    d[i].stride = e.stride;
+    d[i].W = e.W;
+    d[i].H = e.H;
+    d[i].index = order[(size_t)i];
+    d[i].reserved = 0;
+    if (tile_aligned(e, b)) continue;
+    const size_t pitch = ((size_t)e.W * b + 15) & ~(size_t)15;
+    rd[r].src = e.img;
+    rd[r].sstride = e.stride;
+    rd[r].dst_off = off;
+    rd[r].dpitch = (int32_t)(pitch / b);
+    rd[r].W = e.W;
+    rd[r].H = e.H;
+    rd[r].pad = 0;
+    d[i].img = (const char*)stage + off;
+    d[i].stride = (int64_t)(pitch / b);
+    off += pitch * (size_t)e.H;
+    ++r;
+  }
+}
+
+// Queues the realignment copies (if any) and the fused batch kernel.
+int batch_launch(const BatchLayout& L, int T, const void* desc_dev, size_t n_mis, void* stage, uint32_t N,
+                 uint32_t lo, uint32_t hi, uint32_t* out, float* features, hipStream_t stream) {
+  glcm::BatchArgs a = L.args;
+  a.q = make_quant((int)N, lo, hi);
+  fast_quant(L.b, (int)N, lo, hi, &a.qfast, &a.qfast_shift, &a.qfast_mask);
+  a.tiles = (const glcm::BatchTile*)desc_dev;
+  a.out = out;
+  a.feat = features;
+  if (n_mis)
+    GLCM_TRY(glcm::launch_batch_realign(
+        (const glcm::RealignDesc*)((const char*)desc_dev + (size_t)T * sizeof(glcm::BatchTile)), (int)n_mis,
+        (char*)stage, L.b, stream));
+  GLCM_TRY(glcm::launch_batch(a, T, L.b, L.smd, L.D, L.lds_bytes, stream));
+  return GLCM_OK;
+}
+
+}  // namespace
+
+GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
+                                uint32_t* out, float* features, void* stream_) {
+  if (!plan || !tiles || !out || T < 1 || T > (1 << 20)) return GLCM_EINVAL;  // before touching the plan
+  if (lo > hi || hi > (plan->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
+  BatchLayout L;
+  int rc = batch_layout(plan, tiles, T, &L);
+  if (rc != GLCM_OK) return rc;
+  int dev = -1;
+  if (pointer_kind(out, &dev) != 2) return GLCM_EINVAL;
+  if (features && pointer_kind(features, &dev) != 2) return GLCM_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  std::lock_guard<std::mutex> lk(plan->mu);
   GLCM_TRY_RC(order_after_previous(plan, stream));
   // misaligned images are first copied into the plan's staging buffer with a
   // 16-byte pitch (one realignment launch), so every image takes the strip
   // path of the batch kernel
-  size_t n_mis = 0, stage_need = 0;
-  for (int t = 0; t < T; ++t) {
-    const glcm_tile_t& e = tiles[t];
-    if ((uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0) continue;
-    ++n_mis;
-    stage_need += (((size_t)e.W * b + 15) & ~(size_t)15) * (size_t)e.H;
-  }
+  size_t n_mis = 0;
+  const size_t stage_need = batch_stage_bytes(tiles, T, L.b, &n_mis);
   if (n_mis) GLCM_TRY_RC(ensure_stage(plan, stage_need));
-  // descriptors, largest image first, then the copies
-  const size_t tiles_bytes = (size_t)T * sizeof(glcm::BatchTile);
-  const size_t need = tiles_bytes + n_mis * sizeof(glcm::RealignDesc);
+  const size_t need = (size_t)T * sizeof(glcm::BatchTile) + n_mis * sizeof(glcm::RealignDesc);
   if (plan->batch_pending) GLCM_TRY(hipEventSynchronize(plan->batch_uploaded));
   plan->batch_pending = false;
   if (need > plan->batch_cap) {
@@ -1236,62 +1333,71 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
     plan->batch_cap = need;
   }
   if (!plan->batch_uploaded) GLCM_TRY(hipEventCreateWithFlags(&plan->batch_uploaded, hipEventDisableTiming));
-  std::vector<int> order((size_t)T);
-  for (int t = 0; t < T; ++t) order[(size_t)t] = t;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return (uint64_t)tiles[x].W * (uint64_t)tiles[x].H > (uint64_t)tiles[y].W * (uint64_t)tiles[y].H;
-  });
-  glcm::BatchTile* d = (glcm::BatchTile*)plan->batch_pin;
-  glcm::RealignDesc* rd = (glcm::RealignDesc*)((char*)plan->batch_pin + tiles_bytes);
-  size_t off = 0, r = 0;
-  for (int i = 0; i < T; ++i) {
-    const glcm_tile_t& e = tiles[order[(size_t)i]];
-    d[i].img = e.img;
-    d[i].stride = e.stride;
-    d[i].W = e.W;
-    d[i].H = e.H;
-    d[i].index = order[(size_t)i];
-    d[i].reserved = 0;
-    if ((uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0) continue;
-    const size_t pitch = ((size_t)e.W * b + 15) & ~(size_t)15;
-    rd[r].src = e.img;
-    rd[r].sstride = e.stride;
-    rd[r].dst_off = off;
-    rd[r].dpitch = (int32_t)(pitch / b);
-    rd[r].W = e.W;
-    rd[r].H = e.H;
-    rd[r].pad = 0;
-    d[i].img = (const char*)plan->stage + off;
-    d[i].stride = (int64_t)(pitch / b);
-    off += pitch * (size_t)e.H;
-    ++r;
-  }
+  batch_descriptors(tiles, T, L.b, plan->stage, plan->batch_pin);
   GLCM_TRY(hipMemcpyAsync(plan->batch_dev, plan->batch_pin, need, hipMemcpyHostToDevice, stream));
   GLCM_TRY(hipEventRecord(plan->batch_uploaded, stream));
   plan->batch_pending = true;
-  if (n_mis)
-    GLCM_TRY(glcm::launch_batch_realign((const glcm::RealignDesc*)((char*)plan->batch_dev + tiles_bytes), (int)n_mis,
-                                        (char*)plan->stage, b, stream));
-
-  glcm::BatchArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.q = make_quant(plan->N, lo, hi);
-  fast_quant(b, plan->N, lo, hi, &a.qfast, &a.qfast_shift, &a.qfast_mask);
-  a.K = plan->K;
-  const int smd = std::max(c.maxdy, c.maxadx) <= 1 ? 1 : 2;
-  for (int k = 0; k < plan->K; ++k) {
-    a.dx[k] = plan->offsets[k].dx;
-    a.dy[k] = plan->offsets[k].dy;
-    a.vcode[k] = c.dy[k] * (2 * smd + 1) + c.dx[k] + smd;
-  }
-  a.tmask = c.tmask;
-  a.pitch = (uint32_t)plan->N + 1u;
-  a.min_rows = 8;
-  a.tiles = (const glcm::BatchTile*)plan->batch_dev;
-  a.out = out;
-  a.feat = features;
-  GLCM_TRY(glcm::launch_batch(a, T, b, smd, D, lds_bytes, stream));
+  GLCM_TRY_RC(batch_launch(L, T, plan->batch_dev, n_mis, plan->stage, (uint32_t)plan->N, lo, hi, out, features,
+                           stream));
   return record_done(plan, stream);
+}
+
+struct glcm_batch_s {
+  BatchLayout layout;
+  int T = 0;
+  int dtype = 0;
+  uint32_t N = 0;
+  size_t n_mis = 0;
+  void* desc = nullptr;   // device: descriptors, then realignment copies
+  void* stage = nullptr;  // device: aligned copies of the misaligned images
+  size_t bytes = 0;
+};
+
+GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t* tiles, int T, glcm_batch_t* batch) {
+  if (!batch || !plan || !tiles || T < 1 || T > (1 << 20)) return GLCM_EINVAL;
+  *batch = nullptr;
+  std::unique_ptr<glcm_batch_s> h(new (std::nothrow) glcm_batch_s());
+  if (!h) return GLCM_ENOMEM;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  int rc = batch_layout(plan, tiles, T, &h->layout);
+  if (rc != GLCM_OK) return rc;
+  h->T = T;
+  h->dtype = plan->dtype;
+  h->N = (uint32_t)plan->N;
+  const size_t stage_need = batch_stage_bytes(tiles, T, h->layout.b, &h->n_mis);
+  const size_t need = (size_t)T * sizeof(glcm::BatchTile) + h->n_mis * sizeof(glcm::RealignDesc);
+  std::vector<char> host(need);
+  hipError_t e = hipMalloc(&h->desc, need);
+  if (e == hipSuccess && stage_need) e = hipMalloc(&h->stage, stage_need);
+  if (e == hipSuccess) {
+    batch_descriptors(tiles, T, h->layout.b, h->stage, host.data());
+    e = hipMemcpy(h->desc, host.data(), need, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    if (h->desc) (void)hipFree(h->desc);
+    if (h->stage) (void)hipFree(h->stage);
+    return hip_status(e);
+  }
+  h->bytes = need + stage_need;
+  *batch = h.release();
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_batch_run(glcm_batch_t batch, uint32_t lo, uint32_t hi, uint32_t* out, float* features,
+                            void* stream) {
+  if (!batch || !out) return GLCM_EINVAL;
+  if (lo > hi || hi > (batch->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
+  return batch_launch(batch->layout, batch->T, batch->desc, batch->n_mis, batch->stage, batch->N, lo, hi, out,
+                      features, (hipStream_t)stream);
+}
+
+GLCM_API int glcm_batch_destroy(glcm_batch_t batch) {
+  if (!batch) return GLCM_OK;
+  (void)hipDeviceSynchronize();  // a queued or captured launch may still read its buffers
+  if (batch->desc) (void)hipFree(batch->desc);
+  if (batch->stage) (void)hipFree(batch->stage);
+  delete batch;
+  return GLCM_OK;
 }
 
 GLCM_API int glcm_features(const uint32_t* glcm_u32, int K, int N, float* out, void* stream) {

@@ -161,3 +161,14 @@ def test_server_calls_reject_null_server(lib):
     assert lib.glcm_server_drain(None) == -1
     assert lib.glcm_server_stats(None, ctypes.byref(glcm.ServerStats())) == -1
     assert lib.glcm_server_destroy(None) == 0
+
+
+def test_prepared_batch_rejects_bad_arguments(lib):
+    one = (glcm.Tile * 1)(glcm.Tile(0x10000, 8, 8, 8))
+    h = ctypes.c_void_p()
+    assert lib.glcm_batch_prepare(None, one, 1, ctypes.byref(h)) == -1
+    assert lib.glcm_batch_prepare(ctypes.c_void_p(0x1000), None, 1, ctypes.byref(h)) == -1
+    assert lib.glcm_batch_prepare(ctypes.c_void_p(0x1000), one, 0, ctypes.byref(h)) == -1
+    assert lib.glcm_batch_prepare(ctypes.c_void_p(0x1000), one, 1, None) == -1
+    assert lib.glcm_batch_run(None, 0, 255, ctypes.c_void_p(0x20000), None, None) == -1
+    assert lib.glcm_batch_destroy(None) == 0

@@ -154,3 +154,48 @@ def test_batch_rejects_oversize_images():
         assert e.value.status == -1
     finally:
         plan.close()
+
+
+def test_prepared_batch_runs_and_graph_replays():
+    """A prepared batch equals glcm_batch_compute; captured in a graph it is
+    replayed several times, with eager work on the same images in between
+    (which changes their pixels), and every replay is checked against an
+    eager run of the same pixels."""
+    w = synth.batch_tiles(48)
+    imgs = w["images"]
+    N, offs = w["N"], w["offsets"]
+    tens = [to_device(im) for im in imgs]
+    plan = G.glcm_plan_create(np.uint8, N, offs, 512, 512)
+    pb = G.PreparedBatch(tens, plan)
+    try:
+        ref_out, ref_f = G.glcm_batch_compute(tens, plan)
+        out, f = pb.run(features=True)
+        assert np.array_equal(host(out), host(ref_out)) and np.array_equal(host(f), host(ref_f))
+        # capture one run into a graph on a side stream
+        g_out = torch.empty_like(out)
+        g_f = torch.empty_like(f)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            pb.run(out=g_out, features=g_f, stream=side)  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            pb.run(out=g_out, features=g_f, stream=side)
+        torch.cuda.synchronize()
+        for rep in range(4):
+            for t in tens:  # eager work in between: new pixels in place
+                t.copy_((t.to(torch.int32) * 7 + rep + 1).remainder(256).to(torch.uint8))
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            e_out, e_f = G.glcm_batch_compute(tens, plan)
+            assert np.array_equal(host(g_out), host(e_out)), f"replay {rep}: counts differ from the eager run"
+            assert np.array_equal(host(g_f), host(e_f)), f"replay {rep}: statistics differ from the eager run"
+        last = [t.cpu().numpy() for t in tens[:4]]
+        for i, im in enumerate(last):
+            assert np.array_equal(host(g_out)[i], oracle.glcm(im, N, 0, 255, offs))
+    finally:
+        pb.close()
+        plan.close()
