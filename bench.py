@@ -368,6 +368,28 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
     torch.cuda.synchronize()
     per_wall = time.perf_counter() - t0
     per_dev = e0.elapsed_time(e1) * 1e-3
+    # the same batch prepared once and captured in a HIP graph, replayed
+    pb = G.PreparedBatch(tiles, plan)
+    g_out, g_f = torch.empty_like(out), torch.empty_like(feats)
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        pb.run(out=g_out, features=g_f, stream=side)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        pb.run(out=g_out, features=g_f, stream=side)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_wall = (time.perf_counter() - t0) / reps
+    if not (torch.equal(g_out.view(torch.int32), out.view(torch.int32)) and torch.equal(g_f, feats)):
+        raise SystemExit("bench: graph-replayed batch differs from glcm_batch_compute")
+    del graph
+    pb.close()
     plan.close()
     a, b = out.view(torch.int32).cpu().numpy(), out1.view(torch.int32).cpu().numpy()
     if not np.array_equal(a, b):
@@ -384,7 +406,9 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
         "batched_device_ms": batch_dev * 1e3,
         "per_image_gpairs_s": pairs / per_wall / 1e9, "per_image_ms": per_wall * 1e3,
         "per_image_device_ms": per_dev * 1e3, "batched_over_per_image": per_wall / batch_wall,
-        "features": True, "check": "batched == per-image calls (counts and statistics); 64 tiles vs oracle"}),
+        "graph_replay_ms": graph_wall * 1e3, "graph_replay_gpairs_s": pairs / graph_wall / 1e9,
+        "features": True, "check": "batched == per-image calls == graph replay (counts and statistics); "
+                                   "64 tiles vs oracle"}),
         flush=True)
 
 
