@@ -46,6 +46,17 @@ def _load():
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         lib.oracle_features.restype = None
         lib.oracle_features.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_histogram.restype = ctypes.c_int
+        lib.oracle_histogram.argtypes = [
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+            ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        for name in ("oracle_symmetric", "oracle_normalize"):
+            getattr(lib, name).restype = None
+            getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_average.restype = None
+        lib.oracle_average.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_haralick.restype = ctypes.c_int
+        lib.oracle_haralick.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -93,4 +104,71 @@ def features(P: np.ndarray) -> np.ndarray:
     K, N, _ = P.shape
     out = np.zeros((K, 5), dtype=np.float64)
     _load().oracle_features(P.ctypes.data, K, N, out.ctypes.data)
+    return out[0] if squeeze else out
+
+
+def histogram(img: np.ndarray, N: int, lo: int, hi: int) -> np.ndarray:
+    """h[i] (uint32, N entries) = number of pixels of a 2-D uint8/uint16 image
+    (strided views allowed) whose quantized level is i."""
+    img = np.asarray(img)
+    if img.ndim != 2 or img.dtype not in (np.uint8, np.uint16):
+        raise ValueError("img must be a 2-D uint8 or uint16 array")
+    if img.strides[1] != img.itemsize:
+        img = np.ascontiguousarray(img)
+    H, W = img.shape
+    out = np.zeros(N, dtype=np.uint32)
+    rc = _load().oracle_histogram(img.ctypes.data, W, H, img.strides[0] // img.itemsize, img.itemsize,
+                                  N, lo, hi, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_histogram rejected its arguments")
+    return out
+
+
+def _stack(P: np.ndarray):
+    P = np.ascontiguousarray(P, dtype=np.uint32)
+    squeeze = P.ndim == 2
+    return (P[None] if squeeze else P), squeeze
+
+
+def symmetric(P: np.ndarray) -> np.ndarray:
+    """P + P^T per matrix (uint32, modulo 2^32); shape [K, N, N] or [N, N]."""
+    P, squeeze = _stack(P)
+    K, N, _ = P.shape
+    out = np.empty_like(P)
+    _load().oracle_symmetric(P.ctypes.data, K, N, out.ctypes.data)
+    return out[0] if squeeze else out
+
+
+def normalize(P: np.ndarray) -> np.ndarray:
+    """P / sum(P) per matrix in float64 (all zeros for an empty matrix)."""
+    P, squeeze = _stack(P)
+    K, N, _ = P.shape
+    out = np.empty(P.shape, dtype=np.float64)
+    _load().oracle_normalize(P.ctypes.data, K, N, out.ctypes.data)
+    return out[0] if squeeze else out
+
+
+def average(P: np.ndarray, m: int) -> np.ndarray:
+    """Mean of the normalised matrices over consecutive groups of m, float64
+    [K/m, N, N]."""
+    P, _ = _stack(P)
+    K, N, _ = P.shape
+    if m < 1 or K % m:
+        raise ValueError("K must be a positive multiple of m")
+    out = np.empty((K // m, N, N), dtype=np.float64)
+    _load().oracle_average(P.ctypes.data, K, N, m, out.ctypes.data)
+    return out
+
+
+HARALICK_NAMES = ("asm", "contrast", "correlation", "variance", "idm", "sum_average", "sum_variance",
+                  "sum_entropy", "entropy", "difference_variance", "difference_entropy", "imc1", "imc2")
+
+
+def haralick(P: np.ndarray) -> np.ndarray:
+    """Haralick's f1..f13 per matrix in float64, shape [K, 13] (or [13])."""
+    P, squeeze = _stack(P)
+    K, N, _ = P.shape
+    out = np.zeros((K, 13), dtype=np.float64)
+    if _load().oracle_haralick(P.ctypes.data, K, N, out.ctypes.data) != 0:
+        raise MemoryError("oracle_haralick could not allocate")
     return out[0] if squeeze else out
