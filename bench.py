@@ -88,7 +88,8 @@ def main():
                     help="time the candidate layouts (glcm_plan_autotune) instead of keeping the default one")
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
-    ap.add_argument("--workload", default="square", choices=["square", "multispectral", "batch", "serving"],
+    ap.add_argument("--workload", default="square",
+                    choices=["square", "multispectral", "batch", "serving", "histogram", "variants"],
                     help="square: the 4096^2 device-resident image (the default line); multispectral: "
                          "the 8-band 8192^2 uint16 stack streamed from pinned host memory")
     ap.add_argument("--bands", type=int, default=8)
@@ -120,6 +121,12 @@ def main():
         return
     if args.workload == "serving":
         bench_serving(args, G, torch, np, oracle, synth, dev)
+        return
+    if args.workload == "histogram":
+        bench_histogram(args, G, torch, np, oracle, synth, dev)
+        return
+    if args.workload == "variants":
+        bench_variants(args, G, torch, np, oracle, synth, dev)
         return
     oracle_cache, image_cache = {}, {}
     fixed = None
@@ -410,6 +417,144 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
         "features": True, "check": "batched == per-image calls == graph replay (counts and statistics); "
                                    "64 tiles vs oracle"}),
         flush=True)
+
+
+def time_oracle(fn, seconds):
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return reps, el
+
+
+def bench_histogram(args, G, torch, np, oracle, synth, dev):
+    """1-D histogram of the 4096x4096 uint8 smooth image (N = 32 levels, also
+    N = 256 in `extra`): copies rotated through HBM as for the GLCM line, every
+    copy's result checked bit-exact against the oracle.  The roofline prices
+    the histogram kernel (image once + N counts) over its kernel-stamped
+    average duration; the call also runs the partial reduction."""
+    w = synth.square_4096(args.kind)
+    img = w["images"][0]
+    H, W = img.shape
+    base = torch.from_numpy(img).to(dev)
+    copies = [base.clone() for _ in range(args.copies)]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for N in (32, 256):
+        want = oracle.histogram(img, N, 0, 255)
+        outs = [torch.empty(N, dtype=torch.uint32, device=dev) for _ in copies]
+        for flags in (0, G.FLAG_TIMING):
+            plan = G.glcm_plan_create(np.uint8, N, [(0, 0)], W, H, flags)
+            for i in range(args.warmup):
+                G.glcm_histogram(copies[i % len(copies)], N, 0, 255, out=outs[i % len(copies)], stream=stream,
+                                 plan=plan)
+            torch.cuda.synchronize()
+            if flags:
+                plan.kernel_time()
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                G.glcm_histogram(copies[i % len(copies)], N, 0, 255, out=outs[i % len(copies)], stream=stream,
+                                 plan=plan)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            if flags:
+                ms, n = plan.kernel_time()
+                res[N]["kernel_ms"] = ms / n
+            else:
+                res[N] = {"wall_ms": wall * 1e3}
+            plan.close()
+        for j in range(min(len(copies), args.steps)):
+            if not np.array_equal(outs[j].view(torch.int32).cpu().numpy().view(np.uint32), want):
+                raise SystemExit(f"bench: histogram of copy {j} differs from the oracle (N={N})")
+    px = W * H
+    r = res[32]
+    nbytes = px + 32 * 4
+    achieved = nbytes / (r["kernel_ms"] * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        reps, el = time_oracle(lambda: oracle.histogram(img, 32, 0, 255), args.cpu_seconds)
+        cpu = {"value": reps * px / el / 1e9, "unit": "Gpixels/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full passes over the 4096x4096 {args.kind} image, N=32, single-threaded C oracle, "
+                         f"{el:.1f} s"}
+    print(json.dumps({
+        "metric": "histogram Gpixels/s (bit-exact)", "value": px / (r["wall_ms"] * 1e-3) / 1e9, "unit": "Gpixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"histogram-4096x4096-u8-{args.kind}-N32", "resident": "device"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+        "extra": {"kernel_ms_n32": r["kernel_ms"], "wall_ms_n256": res[256]["wall_ms"],
+                  "kernel_ms_n256": res[256]["kernel_ms"],
+                  "gpixels_s_n256": px / (res[256]["wall_ms"] * 1e-3) / 1e9, "copies_rotated": len(copies)},
+    }), flush=True)
+
+
+def bench_variants(args, G, torch, np, oracle, synth, dev, reps=50):
+    """The post-processing kernels on 16384 GLCM-like matrices of N = 16 (the
+    output shape of the 4096-tile batch): symmetric, normalised and
+    direction-averaged (m = 4) matrices and the thirteen Haralick statistics.
+    Each kernel is timed with events around its own launch; every output is
+    checked against the oracle (bit for bit, statistics within 1e-5 rel +
+    1e-6 abs)."""
+    w = synth.glcm_like_counts()
+    P = w["counts"]
+    K, N = P.shape[0], P.shape[1]
+    t = torch.from_numpy(P.view(np.int32)).to(dev).view(torch.uint32)
+    stream = torch.cuda.current_stream()
+    sym = torch.empty_like(t)
+    nrm = torch.empty((K, N, N), dtype=torch.float32, device=dev)
+    avg = torch.empty((K // 4, N, N), dtype=torch.float32, device=dev)
+    har = torch.empty((K, 13), dtype=torch.float32, device=dev)
+    calls = {
+        "symmetrize": (lambda: G.glcm_symmetrize(t, out=sym, stream=stream), 2 * K * N * N * 4),
+        "normalize": (lambda: G.glcm_normalize(t, out=nrm, stream=stream), 2 * K * N * N * 4),
+        "average": (lambda: G.glcm_average(t, 4, out=avg, stream=stream), K * N * N * 4 + K // 4 * N * N * 4),
+        "haralick": (lambda: G.glcm_haralick(t, out=har, stream=stream), K * N * N * 4 + K * 13 * 4),
+    }
+    timing = {}
+    for name, (fn, nbytes) in calls.items():
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        timing[name] = {"ms": ms, "gb_s": nbytes / (ms * 1e-3) / 1e9, "matrices_per_s": K / (ms * 1e-3)}
+    host = lambda x: x.view(torch.int32).cpu().numpy().view(np.uint32) if x.dtype == torch.uint32 else x.cpu().numpy()
+    if not np.array_equal(host(sym), oracle.symmetric(P)):
+        raise SystemExit("bench: symmetric matrices differ from the oracle")
+    if not np.array_equal(host(nrm), oracle.normalize(P).astype(np.float32)):
+        raise SystemExit("bench: normalised matrices differ from the oracle")
+    if not np.array_equal(host(avg), oracle.average(P, 4).astype(np.float32)):
+        raise SystemExit("bench: averaged matrices differ from the oracle")
+    want = oracle.haralick(P)
+    if (np.abs(host(har).astype(np.float64) - want) > 1e-5 * np.abs(want) + 1e-6).any():
+        raise SystemExit("bench: Haralick statistics differ from the oracle")
+    cpu = None
+    if not args.no_cpu:
+        sample = P[:2048]
+        reps_c, el = time_oracle(lambda: oracle.haralick(sample), args.cpu_seconds)
+        cpu = {"value": reps_c * len(sample) / el, "unit": "matrices/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps_c} passes of the C oracle's f1..f13 over the first {len(sample)} matrices, "
+                         f"{el:.1f} s"}
+    h = timing["haralick"]
+    print(json.dumps({
+        "metric": "Haralick f1..f13 matrices/s (within 1e-5 of the fp64 oracle)", "value": h["matrices_per_s"],
+        "unit": "matrices/s", "n_gpus": 1, "steps": reps, "warmup": 5, "ms_per_step": h["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w["name"], "matrices": K, "levels": N, "resident": "device"},
+        "roofline": {"bound": "hbm", "achieved": h["gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": h["gb_s"] / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+        "extra": {"kernels": timing, "check": "symmetric, normalised, averaged bit-exact; statistics within tolerance"},
+    }), flush=True)
 
 
 def bench_multispectral(args, G, torch, np, oracle, synth, dev):

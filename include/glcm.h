@@ -243,6 +243,65 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void *img, int W, int H, int64
  */
 GLCM_API int glcm_features(const uint32_t *glcm, int K, int N, float *out, void *stream);
 
+/*
+ * 1-D gray-level histogram of a device image (the paper notes among its
+ * contributions that its analysis of colliding increments carries over to
+ * statistical histograms): out[i] = number of pixels (x, y) of the W x H
+ * image with q(img(x, y)) = i, for i < N, counted with the same replicated
+ * LDS votes as the co-occurrence matrices.
+ *
+ *   plan     NULL (an internal plan cached per device, dtype and N) or a plan
+ *            with the same dtype and N (its offsets and maximum image size do
+ *            not matter).  Its workspace holds the per-workgroup histograms and
+ *            the call is ordered after the plan's previous work.
+ *   img, W, H, stride, dtype, N, lo, hi   as for glcm_compute, except that img
+ *            must be device memory (GLCM_EUNSUPPORTED for host memory).
+ *   out      device memory, N uint32, overwritten; must not overlap img.
+ * Errors as for glcm_compute.
+ */
+GLCM_API int glcm_histogram(glcm_plan_t plan, const void *img, int W, int H, int64_t stride, int dtype,
+                            int N, uint32_t lo, uint32_t hi, uint32_t *out, void *stream);
+
+/*
+ * Variants of K co-occurrence matrices P[k]: device memory, K*N*N uint32 in
+ * the layout glcm_compute writes, K in [1, 2^20], N in [1, GLCM_MAX_LEVELS].
+ * Each call is one asynchronous kernel on `stream`, with a fixed order of
+ * operations (the same input always gives the same bits).
+ *
+ * glcm_symmetrize   out[k] = P[k] + P[k]^T modulo 2^32: the symmetric GLCM,
+ *                   a reading of Section I.B, where a pair increments both
+ *                   coordinates.  out: K*N*N uint32; may be the input itself
+ *                   (in place) but must not overlap it otherwise.
+ * glcm_normalize    out[k][i][j] = P[k][i][j] / T_k, T_k = sum of P[k]: the
+ *                   quotient correctly rounded in fp64, then rounded to fp32;
+ *                   T_k = 0 gives zeros.  out: K*N*N float, not overlapping P.
+ * glcm_average      the mean of the normalised matrices over consecutive
+ *                   groups of m (for example the four directions of one
+ *                   distance): out[g] = (sum over k in [g m, g m + m), in
+ *                   order, of P[k] / T_k) / m in fp64, rounded to fp32.  An
+ *                   empty matrix adds nothing but counts in m.  m in [1, 64],
+ *                   K a multiple of m.  out: (K/m)*N*N float, not overlapping P.
+ * glcm_haralick     Haralick's statistics f1..f13 (cited in the introduction;
+ *                   the fourteenth, the maximal correlation coefficient, needs
+ *                   an eigenvalue solver and is not provided).  out[k][0..12] =
+ *                   angular second moment, contrast, correlation, sum of
+ *                   squares (variance of the row marginal), inverse difference
+ *                   moment, sum average, sum variance (about the sum average),
+ *                   sum entropy, entropy, difference variance, difference
+ *                   entropy, information measures of correlation 1 and 2.
+ *                   Levels numbered from 0, natural logs, p = P/T.  T = 0
+ *                   gives zeros; a marginal on a single level gives
+ *                   correlation 1; both marginal entropies 0 give f12 = 0.
+ *                   Computed in fp64, stored as fp32.  N <= 1024
+ *                   (GLCM_EUNSUPPORTED above).  out: K*13 float.
+ * Errors: GLCM_EINVAL for NULL, host or other-device pointers, sizes out of
+ * range or overlapping buffers (nothing queued); GLCM_EHIP if the launch fails.
+ */
+GLCM_API int glcm_symmetrize(const uint32_t *glcm, int K, int N, uint32_t *out, void *stream);
+GLCM_API int glcm_normalize(const uint32_t *glcm, int K, int N, float *out, void *stream);
+GLCM_API int glcm_average(const uint32_t *glcm, int K, int N, int m, float *out, void *stream);
+GLCM_API int glcm_haralick(const uint32_t *glcm, int K, int N, float *out, void *stream);
+
 /* One device-resident image of a batch. */
 typedef struct glcm_tile {
     const void *img;  /* device memory, row y at img + y*stride elements, aligned to the pixel size */

@@ -7,6 +7,10 @@ memory and streams.  The functions keep the C names:
     glcm_compute(img, N, lo=0, hi=None, offsets=((1, 0),), out=None, stream=None, plan=None)
         -> torch.Tensor [K, N, N] uint32 on the current device
     glcm_features(P, out=None, stream=None) -> torch.Tensor [K, 5] float32
+    glcm_histogram(img, N, lo=0, hi=None, out=None, stream=None, plan=None) -> torch.Tensor [N] uint32
+    glcm_symmetrize(P, out=None) / glcm_normalize(P) / glcm_average(P, m) / glcm_haralick(P)
+        -> P + P^T [K, N, N] uint32 / P / sum P [K, N, N] float32 /
+           mean of normalised groups of m [K/m, N, N] float32 / statistics f1..f13 [K, 13] float32
     glcm_offset_polar(d, theta_deg) -> (dx, dy)
     glcm_plan_create(dtype, N, offsets, max_W, max_H, flags=0) -> Plan
     glcm_batch_compute(images_or_tileset, plan, ...) -> (counts [T, K, N, N], statistics [T, K, 5])
@@ -36,6 +40,7 @@ __all__ = [
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
     "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
     "glcm_plan_rebind", "glcm_plan_workspace", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
+    "glcm_histogram", "glcm_symmetrize", "glcm_normalize", "glcm_average", "glcm_haralick", "HARALICK_NAMES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -135,6 +140,13 @@ def _lib():
         lib.glcm_compute.argtypes = [vp, vp, i32, i32, i64, i32, i32, u32, u32, ctypes.POINTER(Offset), i32, vp, vp]
         lib.glcm_features.restype = i32
         lib.glcm_features.argtypes = [vp, i32, i32, vp, vp]
+        lib.glcm_histogram.restype = i32
+        lib.glcm_histogram.argtypes = [vp, vp, i32, i32, i64, i32, i32, u32, u32, vp, vp]
+        for name in ("glcm_symmetrize", "glcm_normalize", "glcm_haralick"):
+            getattr(lib, name).restype = i32
+            getattr(lib, name).argtypes = [vp, i32, i32, vp, vp]
+        lib.glcm_average.restype = i32
+        lib.glcm_average.argtypes = [vp, i32, i32, i32, vp, vp]
         lib.glcm_batch_compute.restype = i32
         lib.glcm_batch_compute.argtypes = [vp, ctypes.POINTER(Tile), i32, u32, u32, vp, vp, vp]
         lib.glcm_batch_prepare.restype = i32
@@ -366,6 +378,85 @@ def glcm_features(P, out=None, stream=None):
     s = _stream_handle(stream)
     _check(_lib().glcm_features(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()), s),
            "glcm_features")
+    return out
+
+
+def glcm_histogram(img, N, lo=0, hi=None, out=None, stream=None, plan=None):
+    """Histogram of the quantized levels of a device image, as an [N] uint32 tensor."""
+    if not (isinstance(img, torch.Tensor) and img.is_cuda):
+        raise ValueError("img must be a CUDA tensor")
+    ptr, W, H, stride, dt, keep = _image_args(img)
+    if hi is None:
+        hi = 255 if dt == U8 else 65535
+    if out is None:
+        out = torch.empty(N, dtype=torch.uint32, device=img.device)
+    elif not (out.is_cuda and out.is_contiguous() and out.numel() == N and out.element_size() == 4):
+        raise ValueError("out must be a contiguous CUDA tensor of N 32-bit elements")
+    _check(_lib().glcm_histogram(plan.handle if plan is not None else None, ctypes.c_void_p(ptr), W, H, stride, dt,
+                                 int(N), int(lo), int(hi), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+           "glcm_histogram")
+    del keep
+    return out
+
+
+def _matrices(P):
+    if not (isinstance(P, torch.Tensor) and P.is_cuda and P.element_size() == 4 and P.is_contiguous()):
+        raise ValueError("P must be a contiguous CUDA tensor of 32-bit counts")
+    if P.dim() == 2:
+        P = P.unsqueeze(0)
+    if P.dim() != 3 or P.shape[1] != P.shape[2]:
+        raise ValueError("P must be [K, N, N]")
+    return P, P.shape[0], P.shape[1]
+
+
+def _output(out, shape, dtype, device):
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    n = int(np.prod(shape))
+    if not (out.is_cuda and out.is_contiguous() and out.numel() == n and out.element_size() == 4):
+        raise ValueError(f"out must be a contiguous CUDA tensor of {n} 32-bit elements")
+    return out
+
+
+def glcm_symmetrize(P, out=None, stream=None):
+    """P + P^T per matrix (uint32, modulo 2^32); out may be P itself."""
+    P, K, N = _matrices(P)
+    out = _output(out, (K, N, N), torch.uint32, P.device)
+    _check(_lib().glcm_symmetrize(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()),
+                                  _stream_handle(stream)), "glcm_symmetrize")
+    return out
+
+
+def glcm_normalize(P, out=None, stream=None):
+    """P / sum(P) per matrix, float32 (zeros for an empty matrix)."""
+    P, K, N = _matrices(P)
+    out = _output(out, (K, N, N), torch.float32, P.device)
+    _check(_lib().glcm_normalize(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()),
+                                 _stream_handle(stream)), "glcm_normalize")
+    return out
+
+
+def glcm_average(P, m, out=None, stream=None):
+    """Mean of the normalised matrices over consecutive groups of m, float32 [K/m, N, N]."""
+    P, K, N = _matrices(P)
+    if m < 1 or K % m:
+        raise ValueError("K must be a positive multiple of m")
+    out = _output(out, (K // m, N, N), torch.float32, P.device)
+    _check(_lib().glcm_average(ctypes.c_void_p(P.data_ptr()), K, N, int(m), ctypes.c_void_p(out.data_ptr()),
+                               _stream_handle(stream)), "glcm_average")
+    return out
+
+
+HARALICK_NAMES = ("asm", "contrast", "correlation", "variance", "idm", "sum_average", "sum_variance",
+                  "sum_entropy", "entropy", "difference_variance", "difference_entropy", "imc1", "imc2")
+
+
+def glcm_haralick(P, out=None, stream=None):
+    """Haralick's statistics f1..f13 of each matrix (names in HARALICK_NAMES), float32 [K, 13]."""
+    P, K, N = _matrices(P)
+    out = _output(out, (K, 13), torch.float32, P.device)
+    _check(_lib().glcm_haralick(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()),
+                                _stream_handle(stream)), "glcm_haralick")
     return out
 
 

@@ -1400,6 +1400,69 @@ GLCM_API int glcm_batch_destroy(glcm_batch_t batch) {
   return GLCM_OK;
 }
 
+GLCM_API int glcm_histogram(glcm_plan_t plan, const void* img, int W, int H, int64_t stride, int dtype, int N,
+                            uint32_t lo, uint32_t hi, uint32_t* out, void* stream_) {
+  static const glcm_offset_t kZero{0, 0};
+  int rc = check_image_args(img, W, H, stride, dtype, N, lo, hi, &kZero, 1);
+  if (rc != GLCM_OK) return rc;
+  if (!out || (plan && (plan->dtype != dtype || plan->N != N))) return GLCM_EINVAL;
+  const int b = dtype_bytes(dtype);
+  const uintptr_t i0 = (uintptr_t)img;
+  const uintptr_t i1 = i0 + (uintptr_t)(((uint64_t)(H - 1) * (uint64_t)stride + (uint64_t)W) * (uint64_t)b);
+  const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (uintptr_t)N * 4u;
+  if (o0 < i1 && i0 < o1) return GLCM_EINVAL;
+  int out_dev = -1, img_dev = -1, cur = 0;
+  if (pointer_kind(out, &out_dev) != 2) return GLCM_EINVAL;
+  if (pointer_kind(img, &img_dev) != 2) return GLCM_EUNSUPPORTED;
+  GLCM_TRY(hipGetDevice(&cur));
+  if (out_dev != cur || img_dev != cur) return GLCM_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!plan) {
+    auto tk = std::make_tuple(cur, dtype, N, 1, std::vector<int32_t>{0, 0});
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(tk);
+    if (it == g_cache.end()) {
+      glcm_plan_t np = nullptr;
+      rc = glcm_plan_create(&np, dtype, N, 1, &kZero, 65535, 65535, 0);
+      if (rc != GLCM_OK) return rc;
+      it = g_cache.emplace(tk, np).first;
+    }
+    plan = it->second;
+  }
+  std::lock_guard<std::mutex> lk(plan->mu);
+  GLCM_TRY_RC(order_after_previous(plan, stream));
+  glcm::HistArgs a{};
+  a.img = img;
+  a.stride = stride;
+  a.W = W;
+  a.H = H;
+  a.q = make_quant(N, lo, hi);
+  fast_quant(b, N, lo, hi, &a.qfast, &a.qfast_shift, &a.qfast_mask);
+  a.vec = (i0 % 16u == 0) && ((uint64_t)stride * (uint64_t)b) % 16u == 0;
+  // 32 copies (every lane of an LDS pass its own bank) while 4 N D bytes stay
+  // within 64 KiB, so several workgroups share a CU
+  a.D = 32;
+  while (a.D > 1 && (uint64_t)N * a.D * 4u > 65536u) a.D >>= 1;
+  a.cpr = (uint32_t)((W + 15) / 16);
+  const uint64_t chunks = (uint64_t)H * a.cpr;
+  // at least two chunks per thread, at most one workgroup per CU
+  const uint64_t want = (chunks + 2u * glcm::kHistThreads - 1u) / (2u * glcm::kHistThreads);
+  int groups = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)plan->num_cus));
+  a.per_block = (chunks + groups - 1) / groups;
+  groups = (int)((chunks + a.per_block - 1) / a.per_block);
+  GLCM_TRY_RC(ensure_partials(plan, (size_t)groups * N * 4u));
+  a.partials = plan->partials;
+  glcm::LaunchTiming tm;
+  if (plan->flags & GLCM_FLAG_TIMING) {
+    GLCM_TRY(hipEventCreate(&tm.start));
+    GLCM_TRY(hipEventCreate(&tm.stop));
+    plan->timing.emplace_back(tm.start, tm.stop);
+  }
+  GLCM_TRY(glcm::launch_histogram(a, b, groups, (size_t)N * a.D * 4u, stream, tm));
+  GLCM_TRY(glcm::launch_reduce(a.partials, out, (uint32_t)N, groups, false, stream));
+  return record_done(plan, stream);
+}
+
 GLCM_API int glcm_features(const uint32_t* glcm_u32, int K, int N, float* out, void* stream) {
   if (!glcm_u32 || !out || K < 1 || K > (1 << 20) || N < 1 || N > GLCM_MAX_LEVELS) return GLCM_EINVAL;
   int d1 = -1, d2 = -1;

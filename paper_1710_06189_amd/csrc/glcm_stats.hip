@@ -1,0 +1,259 @@
+// Post-processing of K co-occurrence matrices (N x N uint32 counts, the layout
+// glcm_compute writes): the symmetric matrix P + P^T (a reading of the pair
+// increment of Section I.B), the normalised matrix P / sum P, the mean of the
+// normalised matrices over groups of directions, and Haralick's statistics
+// f1..f13 (cited in the introduction).  Everything is computed in fp64 and
+// stored as fp32, in a fixed order of operations: the same input always gives
+// the same bits.
+
+#include <hip/hip_runtime.h>
+
+#include "glcm_device.h"
+
+namespace glcm {
+namespace {
+
+constexpr int kStatsThreads = 256;
+constexpr int kStatsWaves = kStatsThreads / 64;
+
+// Sum over the workgroup, the same value returned to every thread.  The
+// butterfly and the wave order are fixed, so the result is deterministic.
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* part) {
+  for (int o = 32; o; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o);
+  __syncthreads();  // the previous call's readers are done with part
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t s = 0;
+  for (int w = 0; w < kStatsWaves; ++w) s += part[w];
+  return s;
+}
+
+template <int M>
+__device__ __forceinline__ void block_sum_f64(double (&v)[M], double* part) {
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    for (int o = 32; o; o >>= 1) v[m] += __shfl_xor(v[m], o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) part[(threadIdx.x >> 6) * M + m] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double s = 0.0;
+    for (int w = 0; w < kStatsWaves; ++w) s += part[w * M + m];
+    v[m] = s;
+  }
+}
+
+__device__ __forceinline__ uint64_t matrix_total(const uint32_t* P, uint32_t NN, uint64_t* part) {
+  uint64_t t = 0;
+  for (uint32_t r = threadIdx.x; r < NN; r += blockDim.x) t += P[r];
+  return block_sum_u64(t, part);
+}
+
+// S = P + P^T modulo 2^32.  The thread of bin (i, j) with i <= j reads both
+// bins before writing both, so in == out is safe.
+__global__ __launch_bounds__(kStatsThreads) void k_symmetrize(StatsArgs a) {
+  const uint32_t N = (uint32_t)a.N, NN = N * N;
+  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+    const uint32_t* P = a.in + (size_t)k * NN;
+    uint32_t* S = a.out_u + (size_t)k * NN;
+    for (uint32_t r = threadIdx.x; r < NN; r += blockDim.x) {
+      const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * N;
+      if (i > j) continue;
+      const uint32_t s = P[r] + P[j * N + i];
+      S[r] = s;
+      S[j * N + i] = s;
+    }
+  }
+}
+
+// p = P / T, the quotient correctly rounded in fp64 and then to fp32.
+__global__ __launch_bounds__(kStatsThreads) void k_normalize(StatsArgs a) {
+  __shared__ uint64_t part[kStatsWaves];
+  const uint32_t NN = (uint32_t)a.N * (uint32_t)a.N;
+  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+    const uint32_t* P = a.in + (size_t)k * NN;
+    const uint64_t T = matrix_total(P, NN, part);
+    const double dT = (double)T;
+    float* o = a.out_f + (size_t)k * NN;
+    for (uint32_t r = threadIdx.x; r < NN; r += blockDim.x) o[r] = T ? (float)((double)P[r] / dT) : 0.0f;
+  }
+}
+
+// out[g] = (sum over the m matrices of group g, in order, of P_k / T_k) / m;
+// an empty matrix adds nothing.
+__global__ __launch_bounds__(kStatsThreads) void k_average(StatsArgs a) {
+  __shared__ uint64_t part[kStatsWaves];
+  __shared__ uint64_t totals[kAverageMaxGroup];
+  const uint32_t NN = (uint32_t)a.N * (uint32_t)a.N;
+  const int G = a.K / a.m;
+  for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    const uint32_t* P0 = a.in + (size_t)g * a.m * NN;
+    for (int q = 0; q < a.m; ++q) {
+      const uint64_t T = matrix_total(P0 + (size_t)q * NN, NN, part);
+      if (threadIdx.x == 0) totals[q] = T;
+    }
+    __syncthreads();
+    float* o = a.out_f + (size_t)g * NN;
+    for (uint32_t r = threadIdx.x; r < NN; r += blockDim.x) {
+      double acc = 0.0;
+      for (int q = 0; q < a.m; ++q) {
+        const uint64_t T = totals[q];
+        if (T) acc += (double)P0[(size_t)q * NN + r] / (double)T;
+      }
+      o[r] = (float)(acc / (double)a.m);
+    }
+    __syncthreads();  // totals is rewritten for the next group
+  }
+}
+
+__device__ __forceinline__ double neg_plogp(double p) { return p > 0.0 ? -p * log(p) : 0.0; }
+
+// Haralick's f1..f13 of one matrix per workgroup (levels numbered from 0):
+// f1 angular second moment, f2 contrast, f3 correlation, f4 variance of the
+// row marginal, f5 inverse difference moment, f6 sum average, f7 sum
+// variance, f8 sum entropy, f9 entropy, f10 difference variance, f11
+// difference entropy, f12 and f13 the information measures of correlation.
+// The marginals and the distributions of i + j and |i - j| are exact integer
+// sums over rows, columns and (anti-)diagonals divided by T.
+__global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
+  extern __shared__ double sh[];  // px[N] py[N] ps[2N - 1] pd[N]
+  __shared__ uint64_t part[kStatsWaves];
+  __shared__ double dpart[kStatsWaves * 10];
+  const int N = a.N;
+  const uint32_t NN = (uint32_t)N * (uint32_t)N;
+  double* px = sh;
+  double* py = px + N;
+  double* ps = py + N;
+  double* pd = ps + (2 * N - 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+    const uint32_t* P = a.in + (size_t)k * NN;
+    float* f = a.out_f + (size_t)k * kHaralickStats;
+    const uint64_t T = matrix_total(P, NN, part);
+    if (T == 0) {
+      if (threadIdx.x < kHaralickStats) f[threadIdx.x] = 0.0f;
+      continue;
+    }
+    const double dT = (double)T;
+    // row marginal: a wavefront per row
+    for (int i = wave; i < N; i += kStatsWaves) {
+      uint64_t s = 0;
+      for (int j = lane; j < N; j += 64) s += P[(size_t)i * N + j];
+      for (int o = 32; o; o >>= 1) s += (uint64_t)__shfl_xor((unsigned long long)s, o);
+      if (lane == 0) px[i] = (double)s / dT;
+    }
+    // column marginal, sum and difference distributions: a thread per entry
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      uint64_t s = 0;
+      for (int i = 0; i < N; ++i) s += P[(size_t)i * N + j];
+      py[j] = (double)s / dT;
+    }
+    for (int t = threadIdx.x; t < 2 * N - 1; t += blockDim.x) {
+      uint64_t s = 0;
+      for (int i = max(0, t - N + 1); i <= min(t, N - 1); ++i) s += P[(size_t)i * N + (t - i)];
+      ps[t] = (double)s / dT;
+    }
+    for (int d = threadIdx.x; d < N; d += blockDim.x) {
+      uint64_t s = 0;
+      for (int i = 0; i + d < N; ++i) s += P[(size_t)i * N + i + d];
+      if (d)
+        for (int i = 0; i + d < N; ++i) s += P[(size_t)(i + d) * N + i];
+      pd[d] = (double)s / dT;
+    }
+    __syncthreads();
+    // first moments, entropies of the marginals and distributions, occupied rows/columns
+    double m1[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      m1[0] += i * px[i];
+      m1[1] += i * py[i];
+      m1[3] += i * pd[i];
+      m1[4] += neg_plogp(px[i]);
+      m1[5] += neg_plogp(py[i]);
+      m1[7] += neg_plogp(pd[i]);
+      m1[8] += px[i] > 0.0 ? 1.0 : 0.0;
+      m1[9] += py[i] > 0.0 ? 1.0 : 0.0;
+    }
+    for (int t = threadIdx.x; t < 2 * N - 1; t += blockDim.x) {
+      m1[2] += t * ps[t];
+      m1[6] += neg_plogp(ps[t]);
+    }
+    block_sum_f64<10>(m1, dpart);
+    const double mux = m1[0], muy = m1[1], sa = m1[2], da = m1[3];
+    // second moments about those means
+    double m2[4] = {0, 0, 0, 0};
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      m2[0] += (i - mux) * (i - mux) * px[i];
+      m2[1] += (i - muy) * (i - muy) * py[i];
+      m2[3] += (i - da) * (i - da) * pd[i];
+    }
+    for (int t = threadIdx.x; t < 2 * N - 1; t += blockDim.x) m2[2] += (t - sa) * (t - sa) * ps[t];
+    block_sum_f64<4>(m2, dpart);
+    // sums over the bins
+    double b[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t r = threadIdx.x; r < NN; r += blockDim.x) {
+      const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * (uint32_t)N;
+      const double p = (double)P[r] / dT, d = (double)i - (double)j;
+      const double q = px[i] * py[j];
+      b[0] += p * p;
+      b[1] += d * d * p;
+      b[2] += p / (1.0 + d * d);
+      b[4] += ((double)i - mux) * ((double)j - muy) * p;
+      if (p > 0.0) {
+        b[3] -= p * log(p);
+        b[5] -= p * log(q);
+      }
+      if (q > 0.0) b[6] -= q * log(q);
+    }
+    block_sum_f64<7>(b, dpart);
+    if (threadIdx.x == 0) {
+      const double varx = m2[0], vary = m2[1], ent = b[3], hx = m1[4], hy = m1[5];
+      const double hmax = hx > hy ? hx : hy;
+      const double x = 1.0 - exp(-2.0 * (b[6] - ent));
+      f[0] = (float)b[0];
+      f[1] = (float)b[1];
+      f[2] = (float)((m1[8] == 1.0 || m1[9] == 1.0) ? 1.0 : b[4] / sqrt(varx * vary));
+      f[3] = (float)varx;
+      f[4] = (float)b[2];
+      f[5] = (float)sa;
+      f[6] = (float)m2[2];
+      f[7] = (float)m1[6];
+      f[8] = (float)ent;
+      f[9] = (float)m2[3];
+      f[10] = (float)m1[7];
+      f[11] = (float)(hmax > 0.0 ? (ent - b[5]) / hmax : 0.0);
+      f[12] = (float)sqrt(x > 0.0 ? x : 0.0);
+    }
+    __syncthreads();  // the marginals are rewritten for the next matrix
+  }
+}
+
+unsigned grid_for(int units) { return (unsigned)(units < 8192 ? (units > 0 ? units : 1) : 8192); }
+
+}  // namespace
+
+hipError_t launch_symmetrize(const StatsArgs& a, hipStream_t stream) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(grid_for(a.K)), dim3(kStatsThreads), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const StatsArgs& a, hipStream_t stream) {
+  hipLaunchKernelGGL(k_normalize, dim3(grid_for(a.K)), dim3(kStatsThreads), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_average(const StatsArgs& a, hipStream_t stream) {
+  hipLaunchKernelGGL(k_average, dim3(grid_for(a.K / a.m)), dim3(kStatsThreads), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_haralick(const StatsArgs& a, hipStream_t stream) {
+  const size_t lds = (size_t)(5 * a.N - 1) * sizeof(double);
+  hipLaunchKernelGGL(k_haralick, dim3(grid_for(a.K)), dim3(kStatsThreads), (uint32_t)lds, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace glcm

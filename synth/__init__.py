@@ -192,3 +192,20 @@ def serving_requests(count: int = 1000, size: int = 8192, seed_offset: int = 5):
         offs = [all12[b] for b in range(12) if mask >> b & 1]
         out.append(dict(kind=kind, side=side, y0=y0, x0=x0, N=N, offsets=offs, features=bool(g.integers(0, 2))))
     return out
+
+
+def glcm_like_counts(count: int = 16384, N: int = 16, seed_offset: int = 6):
+    """Synthetic co-occurrence counts shaped like those of the batch tiles:
+    ``count`` matrices of N x N uint32, entry (i, j) Poisson with mean
+    T * exp(-(i - j)^2 / (2 s^2)) / Z, T (pairs of a tile) log-uniform in
+    [3000, 260000], s (neighbour spread in levels) uniform in [0.3, 6]; one
+    matrix in 64 is left empty."""
+    g = rng(BASE_SEED + seed_offset)
+    T = np.exp(g.uniform(np.log(3000.0), np.log(260000.0), size=count))
+    s = g.uniform(0.3, 6.0, size=count)
+    d = np.subtract.outer(np.arange(N), np.arange(N)).astype(np.float64)
+    shape = np.exp(-(d[None] ** 2) / (2.0 * s[:, None, None] ** 2))
+    lam = shape / shape.sum(axis=(1, 2), keepdims=True) * T[:, None, None]
+    P = g.poisson(lam).astype(np.uint32)
+    P[::64] = 0
+    return dict(name=f"{count}-glcm-like-N{N}", counts=P)

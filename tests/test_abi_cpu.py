@@ -118,6 +118,42 @@ def test_features_rejects_bad_arguments(lib):
     assert lib.glcm_features(ctypes.c_void_p(0x1000), 1, 5000, ctypes.c_void_p(0x2000), None) == -1
 
 
+def test_histogram_rejects_bad_arguments(lib):
+    img, out = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x200000)
+    ok = (None, img, 8, 8, 8, 0, 8, 0, 255, out, None)
+
+    def call(**kw):
+        names = ("plan", "img", "W", "H", "stride", "dtype", "N", "lo", "hi", "out", "stream")
+        args = dict(zip(names, ok))
+        args.update(kw)
+        return lib.glcm_histogram(*[args[n] for n in names])
+
+    assert call(img=None) == -1
+    assert call(W=0) == -1 and call(H=0) == -1 and call(stride=7) == -1
+    assert call(dtype=3) == -1 and call(N=0) == -1 and call(N=5000) == -1
+    assert call(lo=10, hi=9) == -1 and call(hi=256) == -1
+    assert call(out=None) == -1
+    assert call(out=ctypes.c_void_p(0x10010)) == -1  # overlaps the image
+    assert call(img=ctypes.c_void_p(0x10001), dtype=1, hi=65535) == -1  # misaligned u16 image
+
+
+def test_post_processing_rejects_bad_arguments(lib):
+    a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x800000)
+    for fn in (lib.glcm_symmetrize, lib.glcm_normalize, lib.glcm_haralick):
+        assert fn(None, 1, 8, b, None) == -1
+        assert fn(a, 1, 8, None, None) == -1
+        assert fn(a, 0, 8, b, None) == -1
+        assert fn(a, (1 << 20) + 1, 8, b, None) == -1
+        assert fn(a, 1, 0, b, None) == -1
+        assert fn(a, 1, 5000, b, None) == -1
+        assert fn(a, 1, 8, b, None) == -1  # not device memory
+    assert lib.glcm_average(a, 4, 8, 0, b, None) == -1
+    assert lib.glcm_average(a, 4, 8, 3, b, None) == -1  # K not a multiple of m
+    assert lib.glcm_average(a, 130, 8, 65, b, None) == -1
+    assert lib.glcm_average(None, 4, 8, 2, b, None) == -1
+    assert lib.glcm_average(a, 4, 8, 2, b, None) == -1  # not device memory
+
+
 def test_plan_tuning_rejects_null(lib):
     t = glcm.Tuning()
     assert lib.glcm_plan_tuning(None, ctypes.byref(t), 0) == -1

@@ -1,0 +1,202 @@
+"""GPU parity of the 1-D histogram and the GLCM variants against the oracle,
+through the C ABI: histograms and symmetric matrices bit for bit, normalised
+and averaged matrices equal to the oracle's fp64 value rounded to fp32, and
+Haralick's thirteen statistics (fp64 on the device, stored as fp32) within
+1e-5 relative plus 1e-6 absolute of the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_1710_06189_amd")
+
+RNG = np.random.default_rng(20171006)
+ALL12 = [(d * a, d * b) for d in (1, 2, 4) for a, b in ((1, 0), (-1, 1), (0, 1), (1, 1))]
+
+
+def host(t):
+    torch.cuda.synchronize()
+    if t.dtype == torch.float32:
+        return t.cpu().numpy()
+    return t.view(torch.int32).cpu().numpy().view(np.uint32)
+
+
+def dev(a):
+    if a.dtype == np.uint32:
+        return torch.from_numpy(a.view(np.int32)).cuda().view(torch.uint32)
+    return torch.from_numpy(a).cuda()
+
+
+# ---------------------------------------------------------------- histogram
+
+HIST_CASES = [
+    # (H, W, dtype, N, lo, hi)
+    (1, 1, np.uint8, 8, 0, 255),
+    (37, 53, np.uint8, 32, 0, 255),        # shift quantizer, ragged chunks
+    (29, 1000, np.uint8, 5, 17, 200),      # magic-number quantizer
+    (3, 4099, np.uint8, 256, 0, 255),
+    (1, 70001, np.uint8, 16, 0, 255),      # one long row
+    (2049, 3, np.uint8, 7, 0, 255),        # many short rows
+    (61, 77, np.uint16, 64, 0, 65535),
+    (40, 515, np.uint16, 1000, 0, 65535),  # levels beyond a byte
+    (33, 65, np.uint16, 4096, 1000, 60000),
+    (50, 50, np.uint8, 4096, 0, 255),      # more levels than values
+    (8, 8, np.uint8, 1, 0, 255),
+]
+
+
+@pytest.mark.parametrize("H,W,dt,N,lo,hi", HIST_CASES)
+def test_histogram_matches_oracle(H, W, dt, N, lo, hi):
+    top = 256 if dt == np.uint8 else 65536
+    img = RNG.integers(0, top, size=(H, W), dtype=dt)
+    print(f"[hist] {H}x{W} {np.dtype(dt).name} N={N}", flush=True)
+    got = host(G.glcm_histogram(dev(img), N, lo, hi))
+    assert np.array_equal(got, oracle.histogram(img, N, lo, hi))
+
+
+@pytest.mark.parametrize("dt", [np.uint8, np.uint16])
+@pytest.mark.parametrize("pitch", [301, 320])
+def test_histogram_views(dt, pitch):
+    """Views with odd pitches and offsets take the per-pixel loads; a 16-byte
+    pitch with a 16-byte aligned offset keeps the chunk loads."""
+    hi = 255 if dt == np.uint8 else 65535
+    base = RNG.integers(0, hi + 1, size=(90, pitch), dtype=dt)
+    t = dev(base)
+    for (y0, x0, h, w) in [(0, 1, 90, 299), (3, 5, 80, 17), (1, 0, 89, 300), (7, 13, 1, 250), (2, 16, 70, 280)]:
+        view = t[y0:y0 + h, x0:x0 + w]
+        got = host(G.glcm_histogram(view, 24, 0, hi))
+        assert np.array_equal(got, oracle.histogram(base[y0:y0 + h, x0:x0 + w], 24, 0, hi))
+
+
+@pytest.mark.parametrize("N", [32, 256])
+def test_histogram_full_size(N):
+    img = synth.smooth(4096, 4096, 8.0, 171006190)
+    print(f"[hist] 4096x4096 smooth N={N}", flush=True)
+    got = host(G.glcm_histogram(dev(img), N, 0, 255))
+    assert np.array_equal(got, oracle.histogram(img, N, 0, 255))
+    assert int(got.sum()) == 4096 * 4096
+
+
+def test_histogram_equals_glcm_marginals():
+    img = synth.smooth(500, 700, 4.0, 3)
+    t = dev(img)
+    P = host(G.glcm_compute(t, 32, 0, 255, [(1, 0), (0, 1)]))
+    assert np.array_equal(P[0].sum(axis=1), host(G.glcm_histogram(t[:, :-1].contiguous(), 32, 0, 255)))
+    assert np.array_equal(P[1].sum(axis=0), host(G.glcm_histogram(t[1:], 32, 0, 255)))
+
+
+def test_histogram_with_plan_and_errors():
+    img = RNG.integers(0, 256, size=(100, 130), dtype=np.uint8)
+    plan = G.glcm_plan_create(np.uint8, 16, [(1, 0)], 64, 64)
+    try:
+        got = host(G.glcm_histogram(dev(img), 16, 0, 255, plan=plan))  # the plan's size limits do not apply
+        assert np.array_equal(got, oracle.histogram(img, 16, 0, 255))
+        with pytest.raises(G.GlcmError):
+            G.glcm_histogram(dev(img), 8, 0, 255, plan=plan)  # N differs from the plan's
+    finally:
+        plan.close()
+    with pytest.raises(ValueError):
+        G.glcm_histogram(torch.from_numpy(img), 16)  # host tensor
+    lib = G._lib()
+    import ctypes
+    out = torch.empty(16, dtype=torch.uint32, device="cuda")
+    rc = lib.glcm_histogram(None, ctypes.c_void_p(img.ctypes.data), 130, 100, 130, 0, 16, 0, 255,
+                            ctypes.c_void_p(out.data_ptr()), None)
+    assert rc == -3  # host image: not served
+
+
+# ---------------------------------------------------------------- variants
+
+def image_glcms(N, K=4, size=(300, 400), seed=0, kind="smooth"):
+    img = synth.smooth(*size, 4.0, seed) if kind == "smooth" else synth.uniform(*size, seed)
+    return oracle.glcm(img, N, 0, 255, ALL12[:K])
+
+
+def random_counts(K, N, high, density=0.6):
+    P = RNG.integers(0, high, size=(K, N, N), dtype=np.uint64).astype(np.uint32)
+    P[RNG.random((K, N, N)) > density] = 0
+    return P
+
+
+VARIANT_INPUTS = [
+    ("image N=8", lambda: image_glcms(8)),
+    ("image N=33 noise", lambda: image_glcms(33, kind="uniform", seed=4)),
+    ("image N=256", lambda: image_glcms(256, K=2, size=(500, 500), seed=2)),
+    ("random N=7", lambda: random_counts(50, 7, 1000)),
+    ("random N=16 batch", lambda: random_counts(4096, 16, 2 ** 16)),
+    ("random large counts", lambda: random_counts(6, 9, 2 ** 32)),
+    ("single level", lambda: np.full((3, 1, 1), 5, dtype=np.uint32)),
+]
+
+
+@pytest.mark.parametrize("name,make", VARIANT_INPUTS, ids=[v[0] for v in VARIANT_INPUTS])
+def test_symmetrize_normalize(name, make):
+    P = make()
+    P[0] = 0  # an empty matrix
+    t = dev(P)
+    assert np.array_equal(host(G.glcm_symmetrize(t)), oracle.symmetric(P))
+    assert np.array_equal(host(G.glcm_normalize(t)), oracle.normalize(P).astype(np.float32))
+    inplace = t.clone()
+    G.glcm_symmetrize(inplace, out=inplace)
+    assert np.array_equal(host(inplace), oracle.symmetric(P))
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 12])
+def test_average(m):
+    P = np.concatenate([image_glcms(16, K=12, seed=5), random_counts(12, 16, 5000)])
+    P[3] = 0
+    got = host(G.glcm_average(dev(P), m))
+    assert np.array_equal(got, oracle.average(P, m).astype(np.float32))
+
+
+def assert_stats_close(got, want):
+    bad = np.abs(got.astype(np.float64) - want) > 1e-5 * np.abs(want) + 1e-6
+    assert not bad.any(), (np.argwhere(bad)[:5], got[bad][:5], want[bad][:5])
+
+
+@pytest.mark.parametrize("name,make", VARIANT_INPUTS, ids=[v[0] for v in VARIANT_INPUTS])
+def test_haralick(name, make):
+    P = make()
+    P[0] = 0
+    got = host(G.glcm_haralick(dev(P)))
+    assert got.shape == (P.shape[0], 13)
+    assert_stats_close(got, oracle.haralick(P))
+    assert not got[0].any()
+
+
+def test_haralick_special_matrices():
+    N = 24
+    mats = np.zeros((5, N, N), dtype=np.uint32)
+    mats[0, 3, 17] = 99                      # single bin off the diagonal
+    mats[1] = 7                              # uniform
+    mats[2][np.arange(N), np.arange(N)] = 3  # uniform diagonal
+    mats[3] = np.outer(RNG.integers(1, 40, N), RNG.integers(1, 40, N)).astype(np.uint32)  # independent
+    mats[4, :, 5] = RNG.integers(1, 100, N)  # column marginal on one level
+    got = host(G.glcm_haralick(dev(mats)))
+    assert_stats_close(got, oracle.haralick(mats))
+    assert got[4, 2] == 1.0
+
+
+def test_haralick_largest_levels_and_limit():
+    P = random_counts(2, 1024, 50, density=0.01)
+    assert_stats_close(host(G.glcm_haralick(dev(P))), oracle.haralick(P))
+    with pytest.raises(G.GlcmError) as e:
+        G.glcm_haralick(torch.zeros((1, 1025, 1025), dtype=torch.uint32, device="cuda"))
+    assert e.value.status == -3
+
+
+def test_variants_compose_with_compute():
+    """The direction-averaged, symmetric statistics of an image: counts from
+    glcm_compute, then the post-processing calls, all on the device."""
+    img = synth.smooth(600, 800, 6.0, 8)
+    t = dev(img)
+    P = G.glcm_compute(t, 32, 0, 255, ALL12)
+    Pc = oracle.glcm(img, 32, 0, 255, ALL12)
+    S = G.glcm_symmetrize(P)
+    assert np.array_equal(host(G.glcm_average(S, 4)), oracle.average(oracle.symmetric(Pc), 4).astype(np.float32))
+    assert_stats_close(host(G.glcm_haralick(S)), oracle.haralick(oracle.symmetric(Pc)))
