@@ -43,6 +43,10 @@ HBM_PEAK_GBS = 8000.0
 VOTE_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)
                 for f in ("glcm_vote.hip", "glcm_device.h", "glcm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vote_strips_4096x4096_u8_smooth_traffic.json")
+# the same for the histogram kernel
+HIST_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)
+                for f in ("glcm_hist.hip", "glcm_device.h", "glcm_stats.h", "glcm_internal.h")]
+HIST_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "histogram_4096x4096_u8_smooth_traffic.json")
 TUNING_KEYS = ("replicas", "wg_size", "counter_bits", "merge", "partitions")
 
 
@@ -50,9 +54,9 @@ def pairs_of(W, H, offsets):
     return sum(max(0, W - abs(dx)) * max(0, H - abs(dy)) for dx, dy in offsets)
 
 
-def kernel_source_sha256():
+def kernel_source_sha256(paths=None):
     h = hashlib.sha256()
-    for path in VOTE_SOURCES:
+    for path in paths or VOTE_SOURCES:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -69,6 +73,19 @@ def recorded_traffic(tuning):
     if rec.get("kernel_source_sha256") != kernel_source_sha256():
         return None
     if any(rec.get("tuning", {}).get(k) != tuning.get(k) for k in TUNING_KEYS):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def recorded_hist_traffic():
+    """HBM bytes per histogram-kernel launch (N = 32) from the committed counter
+    summary, or None when the kernel's sources differ from what was measured."""
+    try:
+        with open(HIST_TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_sha256(HIST_SOURCES):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -484,7 +501,7 @@ def bench_histogram(args, G, torch, np, oracle, synth, dev):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"histogram-4096x4096-u8-{args.kind}-N32", "resident": "device"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_hist_traffic()},
         "cpu_baseline": cpu,
         "extra": {"kernel_ms_n32": r["kernel_ms"], "wall_ms_n256": res[256]["wall_ms"],
                   "kernel_ms_n256": res[256]["kernel_ms"],

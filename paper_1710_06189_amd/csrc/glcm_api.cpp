@@ -15,6 +15,7 @@
 #include "glcm.h"
 #include "glcm_host.h"
 #include "glcm_internal.h"
+#include "glcm_stats.h"
 
 using glcm::VoteArgs;
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "glcm_device.h"
+#include "glcm_stats.h"
 
 namespace glcm {
 namespace {

@@ -8,6 +8,7 @@
 #include "glcm.h"
 #include "glcm_host.h"
 #include "glcm_internal.h"
+#include "glcm_stats.h"
 
 namespace {
 

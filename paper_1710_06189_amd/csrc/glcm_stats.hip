@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "glcm_device.h"
+#include "glcm_stats.h"
 
 namespace glcm {
 namespace {
@@ -120,7 +121,7 @@ __device__ __forceinline__ double neg_plogp(double p) { return p > 0.0 ? -p * lo
 // The marginals and the distributions of i + j and |i - j| are exact integer
 // sums over rows, columns and (anti-)diagonals divided by T.
 __global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
-  extern __shared__ double sh[];  // px[N] py[N] ps[2N - 1] pd[N]
+  extern __shared__ double sh[];  // px[N] py[N] ps[2N - 1] pd[N] lpx[N] lpy[N]
   __shared__ uint64_t part[kStatsWaves];
   __shared__ double dpart[kStatsWaves * 10];
   const int N = a.N;
@@ -129,6 +130,8 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
   double* py = px + N;
   double* ps = py + N;
   double* pd = ps + (2 * N - 1);
+  double* lpx = pd + N;  // ln px (0 where px = 0)
+  double* lpy = lpx + N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
     const uint32_t* P = a.in + (size_t)k * NN;
@@ -138,33 +141,37 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
       if (threadIdx.x < kHaralickStats) f[threadIdx.x] = 0.0f;
       continue;
     }
-    const double dT = (double)T;
+    const double inv = 1.0 / (double)T;  // p = P * (1/T), within an ulp of P / T
     // row marginal: a wavefront per row
     for (int i = wave; i < N; i += kStatsWaves) {
       uint64_t s = 0;
       for (int j = lane; j < N; j += 64) s += P[(size_t)i * N + j];
       for (int o = 32; o; o >>= 1) s += (uint64_t)__shfl_xor((unsigned long long)s, o);
-      if (lane == 0) px[i] = (double)s / dT;
+      if (lane == 0) px[i] = (double)s * inv;
     }
     // column marginal, sum and difference distributions: a thread per entry
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
       uint64_t s = 0;
       for (int i = 0; i < N; ++i) s += P[(size_t)i * N + j];
-      py[j] = (double)s / dT;
+      py[j] = (double)s * inv;
     }
     for (int t = threadIdx.x; t < 2 * N - 1; t += blockDim.x) {
       uint64_t s = 0;
       for (int i = max(0, t - N + 1); i <= min(t, N - 1); ++i) s += P[(size_t)i * N + (t - i)];
-      ps[t] = (double)s / dT;
+      ps[t] = (double)s * inv;
     }
     for (int d = threadIdx.x; d < N; d += blockDim.x) {
       uint64_t s = 0;
       for (int i = 0; i + d < N; ++i) s += P[(size_t)i * N + i + d];
       if (d)
         for (int i = 0; i + d < N; ++i) s += P[(size_t)(i + d) * N + i];
-      pd[d] = (double)s / dT;
+      pd[d] = (double)s * inv;
     }
     __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      lpx[i] = px[i] > 0.0 ? log(px[i]) : 0.0;
+      lpy[i] = py[i] > 0.0 ? log(py[i]) : 0.0;
+    }
     // first moments, entropies of the marginals and distributions, occupied rows/columns
     double m1[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
       m1[2] += t * ps[t];
       m1[6] += neg_plogp(ps[t]);
     }
-    block_sum_f64<10>(m1, dpart);
+    block_sum_f64<10>(m1, dpart);  // (its barriers also publish lpx, lpy)
     const double mux = m1[0], muy = m1[1], sa = m1[2], da = m1[3];
     // second moments about those means
     double m2[4] = {0, 0, 0, 0};
@@ -196,17 +203,17 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
     double b[7] = {0, 0, 0, 0, 0, 0, 0};
     for (uint32_t r = threadIdx.x; r < NN; r += blockDim.x) {
       const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * (uint32_t)N;
-      const double p = (double)P[r] / dT, d = (double)i - (double)j;
-      const double q = px[i] * py[j];
+      const double p = (double)P[r] * inv, d = (double)i - (double)j;
+      const double q = px[i] * py[j], lq = lpx[i] + lpy[j];  // ln q = ln px + ln py
       b[0] += p * p;
       b[1] += d * d * p;
       b[2] += p / (1.0 + d * d);
       b[4] += ((double)i - mux) * ((double)j - muy) * p;
       if (p > 0.0) {
         b[3] -= p * log(p);
-        b[5] -= p * log(q);
+        b[5] -= p * lq;
       }
-      if (q > 0.0) b[6] -= q * log(q);
+      if (q > 0.0) b[6] -= q * lq;
     }
     block_sum_f64<7>(b, dpart);
     if (threadIdx.x == 0) {
@@ -231,6 +238,112 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
   }
 }
 
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  for (int o = 32; o; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o);
+  return v;
+}
+
+// Orders a wavefront's LDS writes before its lanes read each other's words.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kWaveMaxN = 32;
+
+// The same statistics for N <= 32, one matrix per wavefront: the matrix is
+// copied once into the wavefront's LDS (coalesced loads); lane l then forms
+// px[l], py[l], pd[l] (l < N) and ps[l] (l < 2N - 1) from it, other lanes'
+// entries come by shuffles, and every sum is a wavefront butterfly, so no
+// workgroup barrier is needed.  p = P * (1/T) here (within an ulp of P / T).
+__global__ __launch_bounds__(kStatsThreads) void k_haralick_wave(StatsArgs a) {
+  __shared__ uint32_t tiles[kStatsWaves][kWaveMaxN * kWaveMaxN];
+  const int N = a.N;
+  const uint32_t NN = (uint32_t)N * (uint32_t)N;
+  const int lane = threadIdx.x & 63;
+  uint32_t* M = tiles[threadIdx.x >> 6];
+  const int nwaves = gridDim.x * kStatsWaves;
+  for (int k = blockIdx.x * kStatsWaves + (threadIdx.x >> 6); k < a.K; k += nwaves) {
+    const uint32_t* P = a.in + (size_t)k * NN;
+    float* f = a.out_f + (size_t)k * kHaralickStats;
+    wave_lds_sync();  // the previous matrix's reads of M are done
+    uint64_t t = 0;
+    for (uint32_t r = lane; r < NN; r += 64) {
+      const uint32_t v = P[r];
+      M[r] = v;
+      t += v;
+    }
+    const uint64_t T = wave_sum_u64(t);
+    if (T == 0) {
+      if (lane < kHaralickStats) f[lane] = 0.0f;
+      continue;
+    }
+    wave_lds_sync();
+    const double inv = 1.0 / (double)T;
+    uint64_t sx = 0, sy = 0, ss = 0, sd = 0;
+    if (lane < N) {
+      for (int j = 0; j < N; ++j) sx += M[lane * N + j];
+      for (int i = 0; i < N; ++i) sy += M[i * N + lane];
+      for (int i = 0; i + lane < N; ++i) sd += M[i * N + i + lane];
+      if (lane)
+        for (int i = 0; i + lane < N; ++i) sd += M[(i + lane) * N + i];
+    }
+    if (lane < 2 * N - 1)
+      for (int i = max(0, lane - N + 1); i <= min(lane, N - 1); ++i) ss += M[i * N + (lane - i)];
+    const double px = (double)sx * inv, py = (double)sy * inv, ps = (double)ss * inv, pd = (double)sd * inv;
+    const double lpx = px > 0.0 ? log(px) : 0.0, lpy = py > 0.0 ? log(py) : 0.0;
+    const double l = (double)lane;
+    const double mux = wave_sum_f64(l * px), muy = wave_sum_f64(l * py);
+    const double sa = wave_sum_f64(l * ps), da = wave_sum_f64(l * pd);
+    const double hx = wave_sum_f64(-px * lpx), hy = wave_sum_f64(-py * lpy);
+    const double hs = wave_sum_f64(neg_plogp(ps)), hd = wave_sum_f64(neg_plogp(pd));
+    const double rows = wave_sum_f64(px > 0.0 ? 1.0 : 0.0), cols = wave_sum_f64(py > 0.0 ? 1.0 : 0.0);
+    const double varx = wave_sum_f64((l - mux) * (l - mux) * px), vary = wave_sum_f64((l - muy) * (l - muy) * py);
+    const double sv = wave_sum_f64((l - sa) * (l - sa) * ps), dv = wave_sum_f64((l - da) * (l - da) * pd);
+    double b[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t r = lane; r < NN; r += 64) {
+      const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * (uint32_t)N;
+      const double p = (double)M[r] * inv, d = (double)i - (double)j;
+      const double pxi = __shfl(px, (int)i), pyj = __shfl(py, (int)j);
+      const double q = pxi * pyj, lq = __shfl(lpx, (int)i) + __shfl(lpy, (int)j);
+      b[0] += p * p;
+      b[1] += d * d * p;
+      b[2] += p / (1.0 + d * d);
+      b[4] += ((double)i - mux) * ((double)j - muy) * p;
+      if (p > 0.0) {
+        b[3] -= p * log(p);
+        b[5] -= p * lq;
+      }
+      if (q > 0.0) b[6] -= q * lq;
+    }
+#pragma unroll
+    for (int c = 0; c < 7; ++c) b[c] = wave_sum_f64(b[c]);
+    if (lane == 0) {
+      const double ent = b[3], hmax = hx > hy ? hx : hy;
+      const double x = 1.0 - exp(-2.0 * (b[6] - ent));
+      f[0] = (float)b[0];
+      f[1] = (float)b[1];
+      f[2] = (float)((rows == 1.0 || cols == 1.0) ? 1.0 : b[4] / sqrt(varx * vary));
+      f[3] = (float)varx;
+      f[4] = (float)b[2];
+      f[5] = (float)sa;
+      f[6] = (float)sv;
+      f[7] = (float)hs;
+      f[8] = (float)ent;
+      f[9] = (float)dv;
+      f[10] = (float)hd;
+      f[11] = (float)(hmax > 0.0 ? (ent - b[5]) / hmax : 0.0);
+      f[12] = (float)sqrt(x > 0.0 ? x : 0.0);
+    }
+  }
+}
+
 unsigned grid_for(int units) { return (unsigned)(units < 8192 ? (units > 0 ? units : 1) : 8192); }
 
 }  // namespace
@@ -251,7 +364,12 @@ hipError_t launch_average(const StatsArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_haralick(const StatsArgs& a, hipStream_t stream) {
-  const size_t lds = (size_t)(5 * a.N - 1) * sizeof(double);
+  if (a.N <= kWaveMaxN) {
+    hipLaunchKernelGGL(k_haralick_wave, dim3(grid_for((a.K + kStatsWaves - 1) / kStatsWaves)), dim3(kStatsThreads), 0,
+                       stream, a);
+    return hipGetLastError();
+  }
+  const size_t lds = (size_t)(7 * a.N - 1) * sizeof(double);
   hipLaunchKernelGGL(k_haralick, dim3(grid_for(a.K)), dim3(kStatsThreads), (uint32_t)lds, stream, a);
   return hipGetLastError();
 }
