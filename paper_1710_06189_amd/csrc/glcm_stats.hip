@@ -201,6 +201,7 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick(StatsArgs a) {
     block_sum_f64<4>(m2, dpart);
     // sums over the bins
     double b[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
     for (uint32_t r = threadIdx.x; r < NN; r += blockDim.x) {
       const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * (uint32_t)N;
       const double p = (double)P[r] * inv, d = (double)i - (double)j;
@@ -261,18 +262,24 @@ constexpr int kWaveMaxN = 32;
 // copied once into the wavefront's LDS (coalesced loads); lane l then forms
 // px[l], py[l], pd[l] (l < N) and ps[l] (l < 2N - 1) from it, other lanes'
 // entries come by shuffles, and every sum is a wavefront butterfly, so no
-// workgroup barrier is needed.  p = P * (1/T) here (within an ulp of P / T).
-__global__ __launch_bounds__(kStatsThreads) void k_haralick_wave(StatsArgs a) {
+// workgroup barrier is needed.  p = P * (1/T) here (within an ulp of P / T);
+// lane l also holds 1 / (1 + l^2) for the inverse difference moment.  The
+// statistics of the marginals wait in LDS while the bins are summed, which
+// keeps the register count low enough for several wavefronts per SIMD.
+__global__ __launch_bounds__(kStatsThreads, 4) void k_haralick_wave(StatsArgs a) {
   __shared__ uint32_t tiles[kStatsWaves][kWaveMaxN * kWaveMaxN];
+  __shared__ double parked[kStatsWaves][12];
   const int N = a.N;
   const uint32_t NN = (uint32_t)N * (uint32_t)N;
   const int lane = threadIdx.x & 63;
   uint32_t* M = tiles[threadIdx.x >> 6];
+  double* st = parked[threadIdx.x >> 6];
+  const double l = (double)lane, idm_w = 1.0 / (1.0 + l * l);
   const int nwaves = gridDim.x * kStatsWaves;
   for (int k = blockIdx.x * kStatsWaves + (threadIdx.x >> 6); k < a.K; k += nwaves) {
     const uint32_t* P = a.in + (size_t)k * NN;
     float* f = a.out_f + (size_t)k * kHaralickStats;
-    wave_lds_sync();  // the previous matrix's reads of M are done
+    wave_lds_sync();  // the previous matrix's reads of M and st are done
     uint64_t t = 0;
     for (uint32_t r = lane; r < NN; r += 64) {
       const uint32_t v = P[r];
@@ -286,35 +293,46 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick_wave(StatsArgs a) {
     }
     wave_lds_sync();
     const double inv = 1.0 / (double)T;
-    uint64_t sx = 0, sy = 0, ss = 0, sd = 0;
-    if (lane < N) {
-      for (int j = 0; j < N; ++j) sx += M[lane * N + j];
-      for (int i = 0; i < N; ++i) sy += M[i * N + lane];
-      for (int i = 0; i + lane < N; ++i) sd += M[i * N + i + lane];
-      if (lane)
-        for (int i = 0; i + lane < N; ++i) sd += M[(i + lane) * N + i];
+    double px, py, lpx, lpy, mux, muy;
+    {
+      uint64_t sx = 0, sy = 0, ss = 0, sd = 0;
+      if (lane < N) {
+        for (int j = 0; j < N; ++j) sx += M[lane * N + j];
+        for (int i = 0; i < N; ++i) sy += M[i * N + lane];
+        for (int i = 0; i + lane < N; ++i) sd += M[i * N + i + lane];
+        if (lane)
+          for (int i = 0; i + lane < N; ++i) sd += M[(i + lane) * N + i];
+      }
+      if (lane < 2 * N - 1)
+        for (int i = max(0, lane - N + 1); i <= min(lane, N - 1); ++i) ss += M[i * N + (lane - i)];
+      px = (double)sx * inv;
+      py = (double)sy * inv;
+      const double ps = (double)ss * inv, pd = (double)sd * inv;
+      lpx = px > 0.0 ? log(px) : 0.0;
+      lpy = py > 0.0 ? log(py) : 0.0;
+      mux = wave_sum_f64(l * px);
+      muy = wave_sum_f64(l * py);
+      const double sa = wave_sum_f64(l * ps), da = wave_sum_f64(l * pd);
+      const double v0 = wave_sum_f64(-px * lpx), v1 = wave_sum_f64(-py * lpy);
+      const double v2 = wave_sum_f64(neg_plogp(ps)), v3 = wave_sum_f64(neg_plogp(pd));
+      const double v4 = wave_sum_f64(px > 0.0 ? 1.0 : 0.0), v5 = wave_sum_f64(py > 0.0 ? 1.0 : 0.0);
+      const double v6 = wave_sum_f64((l - mux) * (l - mux) * px), v7 = wave_sum_f64((l - muy) * (l - muy) * py);
+      const double v8 = wave_sum_f64((l - sa) * (l - sa) * ps), v9 = wave_sum_f64((l - da) * (l - da) * pd);
+      if (lane == 0) {
+        st[0] = v0; st[1] = v1; st[2] = v2; st[3] = v3; st[4] = v4; st[5] = v5;
+        st[6] = v6; st[7] = v7; st[8] = v8; st[9] = v9; st[10] = sa;
+      }
     }
-    if (lane < 2 * N - 1)
-      for (int i = max(0, lane - N + 1); i <= min(lane, N - 1); ++i) ss += M[i * N + (lane - i)];
-    const double px = (double)sx * inv, py = (double)sy * inv, ps = (double)ss * inv, pd = (double)sd * inv;
-    const double lpx = px > 0.0 ? log(px) : 0.0, lpy = py > 0.0 ? log(py) : 0.0;
-    const double l = (double)lane;
-    const double mux = wave_sum_f64(l * px), muy = wave_sum_f64(l * py);
-    const double sa = wave_sum_f64(l * ps), da = wave_sum_f64(l * pd);
-    const double hx = wave_sum_f64(-px * lpx), hy = wave_sum_f64(-py * lpy);
-    const double hs = wave_sum_f64(neg_plogp(ps)), hd = wave_sum_f64(neg_plogp(pd));
-    const double rows = wave_sum_f64(px > 0.0 ? 1.0 : 0.0), cols = wave_sum_f64(py > 0.0 ? 1.0 : 0.0);
-    const double varx = wave_sum_f64((l - mux) * (l - mux) * px), vary = wave_sum_f64((l - muy) * (l - muy) * py);
-    const double sv = wave_sum_f64((l - sa) * (l - sa) * ps), dv = wave_sum_f64((l - da) * (l - da) * pd);
     double b[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
     for (uint32_t r = lane; r < NN; r += 64) {
       const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * (uint32_t)N;
       const double p = (double)M[r] * inv, d = (double)i - (double)j;
-      const double pxi = __shfl(px, (int)i), pyj = __shfl(py, (int)j);
-      const double q = pxi * pyj, lq = __shfl(lpx, (int)i) + __shfl(lpy, (int)j);
+      const double q = __shfl(px, (int)i) * __shfl(py, (int)j);
+      const double lq = __shfl(lpx, (int)i) + __shfl(lpy, (int)j);
       b[0] += p * p;
       b[1] += d * d * p;
-      b[2] += p / (1.0 + d * d);
+      b[2] += p * __shfl(idm_w, (int)(i > j ? i - j : j - i));
       b[4] += ((double)i - mux) * ((double)j - muy) * p;
       if (p > 0.0) {
         b[3] -= p * log(p);
@@ -324,20 +342,22 @@ __global__ __launch_bounds__(kStatsThreads) void k_haralick_wave(StatsArgs a) {
     }
 #pragma unroll
     for (int c = 0; c < 7; ++c) b[c] = wave_sum_f64(b[c]);
+    wave_lds_sync();
     if (lane == 0) {
+      const double hx = st[0], hy = st[1], varx = st[6], vary = st[7];
       const double ent = b[3], hmax = hx > hy ? hx : hy;
       const double x = 1.0 - exp(-2.0 * (b[6] - ent));
       f[0] = (float)b[0];
       f[1] = (float)b[1];
-      f[2] = (float)((rows == 1.0 || cols == 1.0) ? 1.0 : b[4] / sqrt(varx * vary));
+      f[2] = (float)((st[4] == 1.0 || st[5] == 1.0) ? 1.0 : b[4] / sqrt(varx * vary));
       f[3] = (float)varx;
       f[4] = (float)b[2];
-      f[5] = (float)sa;
-      f[6] = (float)sv;
-      f[7] = (float)hs;
+      f[5] = (float)st[10];
+      f[6] = (float)st[8];
+      f[7] = (float)st[2];
       f[8] = (float)ent;
-      f[9] = (float)dv;
-      f[10] = (float)hd;
+      f[9] = (float)st[9];
+      f[10] = (float)st[3];
       f[11] = (float)(hmax > 0.0 ? (ent - b[5]) / hmax : 0.0);
       f[12] = (float)sqrt(x > 0.0 ? x : 0.0);
     }
