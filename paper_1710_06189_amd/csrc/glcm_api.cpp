@@ -309,6 +309,7 @@ int strip_partitions(const glcm_plan_s* p, int R, int bits) {
 // it walks; otherwise 32-bit counters (fewer GLCMs per partition).
 struct StripLayout {
   int D = 0, kp = 0, kg = 0, P = 0, pair = 0, nregions = 0, region_rows = 0, strip_rows = 0;
+  int pack = 1;  // 16-bit pairs: copies the merge may add packed (pack * largest count < 2^16)
   size_t lds = 0;
 };
 
@@ -338,7 +339,10 @@ bool strip_layout(const glcm_plan_s* p, int W, int rows, int R, bool want_pair, 
     if (pair) {
       const int nstrips = spans * ((region_rows + strip_rows - 1) / strip_rows);
       const uint64_t rows_per_lane = (uint64_t)((nstrips + nwaves - 1) / nwaves) * (uint64_t)strip_rows;
-      if ((uint64_t)wg / (uint64_t)D * 16u * rows_per_lane > 65535u) continue;
+      const uint64_t most = (uint64_t)wg / (uint64_t)D * 16u * rows_per_lane;  // largest count of a copy
+      if (most > 65535u) continue;
+      L->pack = 1;
+      while (L->pack < D && (uint64_t)(2 * L->pack) * most <= 65535u) L->pack *= 2;
     }
     L->D = D; L->kp = kp; L->kg = kg; L->P = P; L->pair = pair; L->lds = lds;
     L->nregions = nregions; L->region_rows = region_rows; L->strip_rows = strip_rows;
@@ -653,6 +657,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     a.kp = sl.kp;
     a.kg = sl.kg;
     a.c16 = sl.pair;
+    a.merge_pack = sl.pack;
     a.part_words = (uint32_t)sl.kp * NN;
     a.P = sl.P;
     a.pitch = (uint32_t)p->N + 1u;

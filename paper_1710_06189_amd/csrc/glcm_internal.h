@@ -51,6 +51,8 @@ struct VoteArgs {
   int kp;                     // strip kernel: GLCMs per partition (<= 4)
   int kg;                     // strip kernel: dword groups per bin (kp, or kp / 2 rounded up with c16)
   int strip_rows;             // strip kernel: first-pixel rows per wavefront strip
+  int merge_pack;             // strip kernel, 16-bit pairs: copies the merge may add before splitting
+                              // the halves (merge_pack times the largest count stays below 2^16)
   int32_t vcode[kMaxK];       // strip kernel: dy * (2 MAXDY + 1) + dx + MAXDY of each canonical offset
                               // (dwords: the kernel reads them with scalar loads)
   uint32_t* partials;         // [nregions][words_total] per-band counts (band-partial merge)

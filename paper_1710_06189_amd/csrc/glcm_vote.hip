@@ -532,48 +532,64 @@ __device__ __forceinline__ void strip_step(const VoteArgs& a, const Geom& geo, T
   load_row<Pix>(raw[CUR], geo, y + 2 * NR, cols);
 }
 
-// Merge of the strip layout: lanes read consecutive 16-byte units (D / 4
-// lanes per GLCM bin), add them up across those lanes, and the first lane of
-// each bin adds the sum to the per-XCD accumulator (or stores it to the band
-// partial), transposed for offsets that were negated.
+// Merge of the strip layout: one lane per (bin, dword group).  The lane reads
+// the group's D dwords as D/4 16-byte units, all at once, in an order rotated
+// by the group index so that the lanes of an LDS pass cover different banks,
+// sums them and adds the sum to the per-XCD accumulator (or stores it to the
+// band partial), transposed for offsets that were negated.  PAIR: the low and
+// high halves belong to GLCMs 2q and 2q + 1; while at most a.merge_pack
+// copies are added a half cannot carry into the other (the host bounds
+// merge_pack times the largest count below 2^16), so the dwords are added
+// packed first and split into halves afterwards.
 template <int D, bool PAIR>
 __device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int region, int kp0, int kp,
                                      uint32_t n1) {
-  constexpr uint32_t QPB = D / 4;  // 16-byte units per bin
+  constexpr uint32_t U = D / 4;                                   // 16-byte units per group
+  constexpr uint32_t ROT = D == 32 ? 0 : (D == 16 ? 1 : (D == 8 ? 2 : 3));  // log2(32 / D)
   __syncthreads();
   const uint32_t N = a.q.nlev, NN = N * N, kg = (uint32_t)a.kg;
-  const uint32_t units = n1 * n1 * kg * QPB;
+  const uint32_t groups = n1 * n1 * kg;
   uint32_t* dst = a.partials + (size_t)region * a.words_total;
   uint32_t xcc = 0;
   if (a.xbuf) asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
   uint32_t* xs = a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total;
-  // unit u = ((i * n1 + j) * kg + q) * QPB + r: r stays fixed for a thread
-  // (blockDim is a multiple of QPB) and (i, j, q) advance by the mixed-radix
-  // digits of blockDim / QPB each pass, so the loop divides nothing
-  const uint32_t S = blockDim.x / QPB;
+  // group b = (i * n1 + j) * kg + q; (i, j, q) advance by the mixed-radix
+  // digits of blockDim each pass, so the loop divides nothing
+  const uint32_t S = blockDim.x;
   const uint32_t sq = S % kg, sj = S / kg % n1, si = S / kg / n1;
-  const uint32_t blk0 = threadIdx.x / QPB;
-  uint32_t q = blk0 % kg, j = blk0 / kg % n1, i = blk0 / kg / n1;
-  const bool lead = threadIdx.x % QPB == 0;
-  for (uint32_t u = threadIdx.x; u < units; u += blockDim.x) {
-    const uint4 v = ((const uint4*)lds)[u];
-    // PAIR: lo = GLCM 2q (low halves), hi = GLCM 2q + 1 (high halves)
-    uint32_t lo = PAIR ? (v.x & 0xffffu) + (v.y & 0xffffu) + (v.z & 0xffffu) + (v.w & 0xffffu)
-                       : (v.x + v.y) + (v.z + v.w);
-    uint32_t hi = PAIR ? (v.x >> 16) + (v.y >> 16) + (v.z >> 16) + (v.w >> 16) : 0u;
-    if (QPB >= 2) {  // quad [1,0,3,2]
-      lo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xb1, 0xf, 0xf, false);
-      if (PAIR) hi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0xb1, 0xf, 0xf, false);
+  uint32_t q = threadIdx.x % kg, j = threadIdx.x / kg % n1, i = threadIdx.x / kg / n1;
+  const uint4* units = (const uint4*)lds;
+  for (uint32_t b = threadIdx.x; b < groups; b += S) {
+    uint4 v[U];
+    const uint32_t rot = b >> ROT;
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) v[u] = units[b * U + ((u + rot) & (U - 1u))];
+    uint32_t lo = 0, hi = 0;
+    if (!PAIR) {
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) lo += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    } else if (U >= 2 && a.merge_pack >= 8) {
+#pragma unroll
+      for (uint32_t u = 0; u + 1 < U; u += 2) {
+        const uint32_t s8 = ((v[u].x + v[u].y) + (v[u].z + v[u].w)) + ((v[u + 1].x + v[u + 1].y) + (v[u + 1].z + v[u + 1].w));
+        lo += s8 & 0xffffu;
+        hi += s8 >> 16;
+      }
+    } else if (a.merge_pack >= 4) {
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t s4 = (v[u].x + v[u].y) + (v[u].z + v[u].w);
+        lo += s4 & 0xffffu;
+        hi += s4 >> 16;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        lo += (v[u].x & 0xffffu) + (v[u].y & 0xffffu) + (v[u].z & 0xffffu) + (v[u].w & 0xffffu);
+        hi += (v[u].x >> 16) + (v[u].y >> 16) + (v[u].z >> 16) + (v[u].w >> 16);
+      }
     }
-    if (QPB >= 4) {  // quad [2,3,0,1]
-      lo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4e, 0xf, 0xf, false);
-      if (PAIR) hi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x4e, 0xf, 0xf, false);
-    }
-    if (QPB >= 8) {  // row_half_mirror: lane i of 8 meets lane 7 - i (the other quad)
-      lo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x141, 0xf, 0xf, false);
-      if (PAIR) hi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x141, 0xf, 0xf, false);
-    }
-    if (lead && i < N && j < N) {
+    if (i < N && j < N) {
 #pragma unroll
       for (uint32_t h = 0; h < (PAIR ? 2u : 1u); ++h) {
         const uint32_t k = PAIR ? 2u * q + h : q;
