@@ -200,3 +200,62 @@ def test_variants_compose_with_compute():
     S = G.glcm_symmetrize(P)
     assert np.array_equal(host(G.glcm_average(S, 4)), oracle.average(oracle.symmetric(Pc), 4).astype(np.float32))
     assert_stats_close(host(G.glcm_haralick(S)), oracle.haralick(oracle.symmetric(Pc)))
+
+
+def test_post_processing_graph_replays():
+    """The four post-processing calls only queue kernels, so they are captured
+    in a graph and replayed; the input is rewritten in place between replays
+    (eager work, synchronised) and every replay is checked against the oracle."""
+    P = random_counts(64, 16, 3000)
+    P[5] = 0
+    t = dev(P)
+    sym = torch.empty_like(t)
+    nrm = torch.empty((64, 16, 16), dtype=torch.float32, device="cuda")
+    avg = torch.empty((16, 16, 16), dtype=torch.float32, device="cuda")
+    har = torch.empty((64, 13), dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+
+    def run(stream):
+        G.glcm_symmetrize(t, out=sym, stream=stream)
+        G.glcm_normalize(t, out=nrm, stream=stream)
+        G.glcm_average(t, 4, out=avg, stream=stream)
+        G.glcm_haralick(sym, out=har, stream=stream)
+
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run(side)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        run(side)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        new = random_counts(64, 16, 3000 + 500 * rep)
+        new[(rep * 7) % 64] = 0
+        t.copy_(dev(new))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        S = oracle.symmetric(new)
+        assert np.array_equal(host(sym), S), f"replay {rep}: symmetric matrices"
+        assert np.array_equal(host(nrm), oracle.normalize(new).astype(np.float32)), f"replay {rep}: normalised"
+        assert np.array_equal(host(avg), oracle.average(new, 4).astype(np.float32)), f"replay {rep}: averaged"
+        assert_stats_close(host(har), oracle.haralick(S))
+
+
+def test_histogram_on_streams_with_one_plan():
+    """Histograms of different images on two streams through one plan are
+    ordered after each other (the plan's partials are shared) and all match."""
+    imgs = [RNG.integers(0, 256, size=(700, 900), dtype=np.uint8) for _ in range(6)]
+    ts = [dev(im) for im in imgs]
+    plan = G.glcm_plan_create(np.uint8, 64, [(0, 0)], 1024, 1024)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()  # the uploads are done before the side streams read the images
+    try:
+        outs = [G.glcm_histogram(t, 64, 0, 255, plan=plan, stream=streams[i % 2]) for i, t in enumerate(ts)]
+        torch.cuda.synchronize()
+        for o, im in zip(outs, imgs):
+            assert np.array_equal(host(o), oracle.histogram(im, 64, 0, 255))
+    finally:
+        plan.close()
