@@ -172,3 +172,30 @@ def haralick(P: np.ndarray) -> np.ndarray:
     if _load().oracle_haralick(P.ctypes.data, K, N, out.ctypes.data) != 0:
         raise MemoryError("oracle_haralick could not allocate")
     return out[0] if squeeze else out
+
+
+def haralick_mcc(P: np.ndarray) -> np.ndarray:
+    """Haralick's fourteenth statistic, the maximal correlation coefficient,
+    per matrix in float64: the square root of the second largest eigenvalue of
+    Q(i, j) = sum_k p(i, k) p(j, k) / (px(i) py(k)), p = P / T (cited in the
+    introduction with the other thirteen).  Terms with px(i) = 0 or py(k) = 0
+    are 0; an empty matrix or a single eigenvalue gives 0.  The eigenvalues
+    come from numpy's general (non-symmetric) eigenvalue routine."""
+    P, squeeze = _stack(P)
+    out = np.zeros(P.shape[0], dtype=np.float64)
+    for k, M in enumerate(P):
+        T = int(M.astype(np.uint64).sum())
+        if T == 0:
+            continue
+        p = M.astype(np.float64) / T
+        px, py = p.sum(axis=1), p.sum(axis=0)
+        N = p.shape[0]
+        Q = np.zeros((N, N))
+        for i in range(N):
+            if px[i] == 0:
+                continue
+            for j in range(N):
+                Q[i, j] = sum(p[i, c] * p[j, c] / (px[i] * py[c]) for c in range(N) if py[c] > 0)
+        ev = np.sort(np.linalg.eigvals(Q).real)[::-1]
+        out[k] = np.sqrt(max(0.0, ev[1])) if N > 1 else 0.0
+    return out[0] if squeeze else out

@@ -265,3 +265,50 @@ def test_haralick_agrees_with_five_features():
     # features: contrast, energy, entropy, homogeneity, correlation
     assert np.allclose(f13[:, [1, 0, 8, 4, 2]], f5, rtol=1e-12, atol=0)
     assert not f13[2].any()
+
+
+# ---------------------------------------------------------------- f14, maximal correlation coefficient
+
+def mcc_symmetric(P):
+    """The same statistic through a different route: Q is similar to the
+    symmetric S = B B^T with B(i, k) = p(i, k) / sqrt(px(i) py(k)), whose
+    eigenvalues numpy's symmetric solver gives."""
+    p = P.astype(np.float64) / P.sum()
+    px, py = p.sum(axis=1), p.sum(axis=0)
+    d = np.sqrt(np.outer(px, py))
+    B = np.divide(p, d, out=np.zeros_like(p), where=d > 0)
+    ev = np.sort(np.linalg.eigvalsh(B @ B.T))[::-1]
+    return np.sqrt(max(0.0, ev[1])) if len(ev) > 1 else 0.0
+
+
+@pytest.mark.parametrize("a,b", [(3, 1), (1, 3), (5, 5), (7, 0), (2, 9)])
+def test_mcc_two_by_two(a, b):
+    P = np.array([[a, b], [b, a]], dtype=np.uint32)
+    # (near 0 the square root turns eigenvalue rounding of 1e-16 into 1e-8)
+    assert abs(oracle.haralick_mcc(P) - abs(a - b) / (a + b)) < 1e-7
+
+
+def test_mcc_closed_forms():
+    assert abs(oracle.haralick_mcc(np.diag(np.full(9, 4)).astype(np.uint32)) - 1.0) < 1e-12
+    ca, cb = RNG.integers(1, 60, size=11), RNG.integers(1, 60, size=11)
+    assert oracle.haralick_mcc(np.outer(ca, cb).astype(np.uint32)) < 1e-6  # independent: 0
+    blocks = np.zeros((8, 8), dtype=np.uint32)  # two independent components
+    blocks[:3, :3] = np.outer(RNG.integers(1, 9, 3), RNG.integers(1, 9, 3))
+    blocks[3:, 3:] = np.outer(RNG.integers(1, 9, 5), RNG.integers(1, 9, 5))
+    assert abs(oracle.haralick_mcc(blocks) - 1.0) < 1e-9
+    assert oracle.haralick_mcc(np.zeros((5, 5), dtype=np.uint32)) == 0.0
+    assert oracle.haralick_mcc(np.full((1, 1), 3, dtype=np.uint32)) == 0.0
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_mcc_vs_symmetric_route_and_transpose(seed):
+    rng = np.random.default_rng(seed)
+    N = int(rng.integers(2, 14))
+    P = rng.integers(0, 200, size=(N, N)).astype(np.uint32)
+    P[rng.random((N, N)) < 0.4] = 0
+    P[int(rng.integers(0, N))] = 0  # an empty row
+    P[0, 0] += 1
+    m = oracle.haralick_mcc(P)
+    assert abs(m - mcc_symmetric(P)) < 1e-9
+    assert abs(m - oracle.haralick_mcc(np.ascontiguousarray(P.T))) < 1e-9
+    assert 0.0 <= m <= 1.0 + 1e-12
