@@ -545,11 +545,13 @@ def bench_variants(args, G, torch, np, oracle, synth, dev, reps=50):
     nrm = torch.empty((K, N, N), dtype=torch.float32, device=dev)
     avg = torch.empty((K // 4, N, N), dtype=torch.float32, device=dev)
     har = torch.empty((K, 13), dtype=torch.float32, device=dev)
+    mcc = torch.empty(K, dtype=torch.float32, device=dev)
     calls = {
         "symmetrize": (lambda: G.glcm_symmetrize(t, out=sym, stream=stream), 2 * K * N * N * 4),
         "normalize": (lambda: G.glcm_normalize(t, out=nrm, stream=stream), 2 * K * N * N * 4),
         "average": (lambda: G.glcm_average(t, 4, out=avg, stream=stream), K * N * N * 4 + K // 4 * N * N * 4),
         "haralick": (lambda: G.glcm_haralick(t, out=har, stream=stream), K * N * N * 4 + K * 13 * 4),
+        "haralick_mcc": (lambda: G.glcm_haralick_mcc(t, out=mcc, stream=stream), K * N * N * 4 + K * 4),
     }
     timing = {}
     for name, (fn, nbytes) in calls.items():
@@ -574,6 +576,9 @@ def bench_variants(args, G, torch, np, oracle, synth, dev, reps=50):
     want = oracle.haralick(P)
     if (np.abs(host(har).astype(np.float64) - want) > 1e-5 * np.abs(want) + 1e-6).any():
         raise SystemExit("bench: Haralick statistics differ from the oracle")
+    wm = oracle.haralick_mcc(P[:1024])  # the maximal correlation coefficient on the first 1024 matrices
+    if (np.abs(host(mcc)[:1024].astype(np.float64) - wm) > 1e-5 * np.abs(wm) + 1e-6).any():
+        raise SystemExit("bench: maximal correlation coefficients differ from the oracle")
     cpu = None
     if not args.no_cpu:
         sample = P[:2048]

@@ -282,8 +282,8 @@ GLCM_API int glcm_histogram(glcm_plan_t plan, const void *img, int W, int H, int
  *                   empty matrix adds nothing but counts in m.  m in [1, 64],
  *                   K a multiple of m.  out: (K/m)*N*N float, not overlapping P.
  * glcm_haralick     Haralick's statistics f1..f13 (cited in the introduction;
- *                   the fourteenth, the maximal correlation coefficient, needs
- *                   an eigenvalue solver and is not provided).  out[k][0..12] =
+ *                   the fourteenth, which needs an eigenvalue solver, is
+ *                   glcm_haralick_mcc below).  out[k][0..12] =
  *                   angular second moment, contrast, correlation, sum of
  *                   squares (variance of the row marginal), inverse difference
  *                   moment, sum average, sum variance (about the sum average),
@@ -301,6 +301,19 @@ GLCM_API int glcm_symmetrize(const uint32_t *glcm, int K, int N, uint32_t *out, 
 GLCM_API int glcm_normalize(const uint32_t *glcm, int K, int N, float *out, void *stream);
 GLCM_API int glcm_average(const uint32_t *glcm, int K, int N, int m, float *out, void *stream);
 GLCM_API int glcm_haralick(const uint32_t *glcm, int K, int N, float *out, void *stream);
+
+/*
+ * Haralick's fourteenth statistic, the maximal correlation coefficient (cited
+ * in the introduction with the others): out[k] = the square root of the
+ * second largest eigenvalue of Q(i, j) = sum_c p(i, c) p(j, c) / (px(i) py(c)),
+ * p = P[k] / T, px and py the row and column marginals; terms with a zero
+ * marginal are 0.  Computed in fp64 from the symmetric matrix S = B B^T,
+ * B(i, c) = p(i, c) / sqrt(px(i) py(c)), which has Q's eigenvalues, with cyclic
+ * Jacobi rotations (at most 30 sweeps); stored as fp32.  T = 0 or N = 1 gives
+ * 0.  glcm as above; N <= 64 (GLCM_EUNSUPPORTED above); out: K float, device
+ * memory.  Errors as for glcm_haralick.
+ */
+GLCM_API int glcm_haralick_mcc(const uint32_t *glcm, int K, int N, float *out, void *stream);
 
 /* One device-resident image of a batch. */
 typedef struct glcm_tile {

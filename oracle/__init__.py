@@ -190,12 +190,10 @@ def haralick_mcc(P: np.ndarray) -> np.ndarray:
         p = M.astype(np.float64) / T
         px, py = p.sum(axis=1), p.sum(axis=0)
         N = p.shape[0]
-        Q = np.zeros((N, N))
-        for i in range(N):
-            if px[i] == 0:
-                continue
-            for j in range(N):
-                Q[i, j] = sum(p[i, c] * p[j, c] / (px[i] * py[c]) for c in range(N) if py[c] > 0)
+        # Q(i, j) = sum_c [p(i, c) / px(i)] [p(j, c) / py(c)], as one matrix product
+        A = np.divide(p, px[:, None], out=np.zeros_like(p), where=px[:, None] > 0)
+        C = np.divide(p, py[None, :], out=np.zeros_like(p), where=py[None, :] > 0)
+        Q = A @ C.T
         ev = np.sort(np.linalg.eigvals(Q).real)[::-1]
         out[k] = np.sqrt(max(0.0, ev[1])) if N > 1 else 0.0
     return out[0] if squeeze else out

@@ -11,6 +11,7 @@ memory and streams.  The functions keep the C names:
     glcm_symmetrize(P, out=None) / glcm_normalize(P) / glcm_average(P, m) / glcm_haralick(P)
         -> P + P^T [K, N, N] uint32 / P / sum P [K, N, N] float32 /
            mean of normalised groups of m [K/m, N, N] float32 / statistics f1..f13 [K, 13] float32
+    glcm_haralick_mcc(P) -> maximal correlation coefficient (f14) [K] float32
     glcm_offset_polar(d, theta_deg) -> (dx, dy)
     glcm_plan_create(dtype, N, offsets, max_W, max_H, flags=0) -> Plan
     glcm_batch_compute(images_or_tileset, plan, ...) -> (counts [T, K, N, N], statistics [T, K, 5])
@@ -41,6 +42,7 @@ __all__ = [
     "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
     "glcm_plan_rebind", "glcm_plan_workspace", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
     "glcm_histogram", "glcm_symmetrize", "glcm_normalize", "glcm_average", "glcm_haralick", "HARALICK_NAMES",
+    "glcm_haralick_mcc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -142,7 +144,7 @@ def _lib():
         lib.glcm_features.argtypes = [vp, i32, i32, vp, vp]
         lib.glcm_histogram.restype = i32
         lib.glcm_histogram.argtypes = [vp, vp, i32, i32, i64, i32, i32, u32, u32, vp, vp]
-        for name in ("glcm_symmetrize", "glcm_normalize", "glcm_haralick"):
+        for name in ("glcm_symmetrize", "glcm_normalize", "glcm_haralick", "glcm_haralick_mcc"):
             getattr(lib, name).restype = i32
             getattr(lib, name).argtypes = [vp, i32, i32, vp, vp]
         lib.glcm_average.restype = i32
@@ -457,6 +459,15 @@ def glcm_haralick(P, out=None, stream=None):
     out = _output(out, (K, 13), torch.float32, P.device)
     _check(_lib().glcm_haralick(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()),
                                 _stream_handle(stream)), "glcm_haralick")
+    return out
+
+
+def glcm_haralick_mcc(P, out=None, stream=None):
+    """Haralick's maximal correlation coefficient (f14) of each matrix, float32 [K]."""
+    P, K, N = _matrices(P)
+    out = _output(out, (K,), torch.float32, P.device)
+    _check(_lib().glcm_haralick_mcc(ctypes.c_void_p(P.data_ptr()), K, N, ctypes.c_void_p(out.data_ptr()),
+                                    _stream_handle(stream)), "glcm_haralick_mcc")
     return out
 
 

@@ -96,4 +96,15 @@ GLCM_API int glcm_haralick(const uint32_t* glcm_u32, int K, int N, float* out, v
   return launched(glcm::launch_haralick(a, (hipStream_t)stream));
 }
 
+GLCM_API int glcm_haralick_mcc(const uint32_t* glcm_u32, int K, int N, float* out, void* stream) {
+  if (K < 1 || K > kMaxMatrices || N < 1 || N > GLCM_MAX_LEVELS) return GLCM_EINVAL;
+  const int rc = check_device_pair(glcm_u32, out);
+  if (rc != GLCM_OK) return rc;
+  if (overlap(glcm_u32, (size_t)K * N * N * 4u, out, (size_t)K * 4u)) return GLCM_EINVAL;
+  if (N > glcm::kMccMaxLevels) return GLCM_EUNSUPPORTED;
+  glcm::StatsArgs a = stats_args(glcm_u32, K, N);
+  a.out_f = out;
+  return launched(glcm::launch_haralick_mcc(a, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -49,5 +49,8 @@ hipError_t launch_symmetrize(const StatsArgs& a, hipStream_t stream);
 hipError_t launch_normalize(const StatsArgs& a, hipStream_t stream);
 hipError_t launch_average(const StatsArgs& a, hipStream_t stream);
 hipError_t launch_haralick(const StatsArgs& a, hipStream_t stream);
+// out_f[k] = maximal correlation coefficient of matrix k (N <= kMccMaxLevels)
+hipError_t launch_haralick_mcc(const StatsArgs& a, hipStream_t stream);
+constexpr int kMccMaxLevels = 64;
 
 }  // namespace glcm

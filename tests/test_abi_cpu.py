@@ -139,7 +139,7 @@ def test_histogram_rejects_bad_arguments(lib):
 
 def test_post_processing_rejects_bad_arguments(lib):
     a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x800000)
-    for fn in (lib.glcm_symmetrize, lib.glcm_normalize, lib.glcm_haralick):
+    for fn in (lib.glcm_symmetrize, lib.glcm_normalize, lib.glcm_haralick, lib.glcm_haralick_mcc):
         assert fn(None, 1, 8, b, None) == -1
         assert fn(a, 1, 8, None, None) == -1
         assert fn(a, 0, 8, b, None) == -1

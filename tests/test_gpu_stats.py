@@ -259,3 +259,31 @@ def test_histogram_on_streams_with_one_plan():
             assert np.array_equal(host(o), oracle.histogram(im, 64, 0, 255))
     finally:
         plan.close()
+
+
+MCC_INPUTS = [v for v in VARIANT_INPUTS if v[0] in ("image N=8", "image N=33 noise", "random N=7",
+                                                       "random N=16 batch", "single level")] + [
+    ("diag and blocks", lambda: np.stack([np.diag(np.full(12, 5)).astype(np.uint32),
+                                          np.kron(np.eye(3, dtype=np.uint32), np.full((4, 4), 2, dtype=np.uint32))])),
+    ("two by two", lambda: np.array([[[3, 1], [1, 3]], [[0, 7], [7, 0]], [[5, 5], [5, 5]]], dtype=np.uint32)),
+    ("N=64 sparse", lambda: random_counts(3, 64, 40, density=0.05)),
+]
+
+
+@pytest.mark.parametrize("name,make", MCC_INPUTS, ids=[v[0] for v in MCC_INPUTS])
+def test_haralick_mcc(name, make):
+    """f14 against the oracle (numpy's eigenvalues of Q): within 1e-5 rel +
+    1e-6 abs (near 0 both sides are the square root of an eigenvalue at
+    rounding level, about 1e-8, which the absolute term covers)."""
+    P = make()
+    if P.shape[0] > 1:
+        P[0] = 0
+    got = host(G.glcm_haralick_mcc(dev(P))).astype(np.float64)
+    want = oracle.haralick_mcc(P)
+    bad = np.abs(got - want) > 1e-5 * np.abs(want) + 1e-6
+    assert not bad.any(), (np.argwhere(bad)[:5], got[bad][:5], want[bad][:5])
+    if P.shape[0] > 1:
+        assert got[0] == 0.0
+    with pytest.raises(G.GlcmError) as e:
+        G.glcm_haralick_mcc(torch.zeros((1, 65, 65), dtype=torch.uint32, device="cuda"))
+    assert e.value.status == -3
