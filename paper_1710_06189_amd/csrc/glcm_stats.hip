@@ -364,100 +364,6 @@ __global__ __launch_bounds__(kStatsThreads, 4) void k_haralick_wave(StatsArgs a)
   }
 }
 
-// Haralick's fourteenth statistic, the maximal correlation coefficient: the
-// square root of the second largest eigenvalue of
-// Q(i, j) = sum_c p(i, c) p(j, c) / (px(i) py(c)).  Q is similar to the
-// symmetric S = B B^T with B(i, c) = p(i, c) / sqrt(px(i) py(c)) (0 where a
-// marginal is 0), so the kernel forms S in LDS and diagonalises it with cyclic
-// Jacobi rotations in fp64 (at most kMccSweeps sweeps, stopping once the
-// off-diagonal part is below rounding).  One 64-lane workgroup per matrix,
-// N <= kMccMaxLevels.
-constexpr int kMccSweeps = 30;
-
-__global__ __launch_bounds__(64) void k_haralick_mcc(StatsArgs a) {
-  extern __shared__ double mcc_sh[];  // B[N][N], S[N][N], rx[N], ry[N]
-  const int N = a.N, lane = threadIdx.x;
-  const uint32_t NN = (uint32_t)N * (uint32_t)N;
-  double* Bm = mcc_sh;
-  double* Sm = Bm + NN;
-  double* rx = Sm + NN;
-  double* ry = rx + N;
-  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
-    const uint32_t* P = a.in + (size_t)k * NN;
-    uint64_t t = 0;
-    for (uint32_t r = lane; r < NN; r += 64) t += P[r];
-    const uint64_t T = wave_sum_u64(t);
-    if (T == 0 || N == 1) {
-      if (lane == 0) a.out_f[k] = 0.0f;
-      continue;
-    }
-    const double inv = 1.0 / (double)T;
-    if (lane < N) {
-      uint64_t sx = 0, sy = 0;
-      for (int c = 0; c < N; ++c) sx += P[lane * N + c];
-      for (int i = 0; i < N; ++i) sy += P[i * N + lane];
-      rx[lane] = sx ? 1.0 / sqrt((double)sx * inv) : 0.0;
-      ry[lane] = sy ? 1.0 / sqrt((double)sy * inv) : 0.0;
-    }
-    __syncthreads();
-    for (uint32_t r = lane; r < NN; r += 64) {
-      const uint32_t i = divide(r, a.nmagic, a.nshift), c = r - i * (uint32_t)N;
-      Bm[r] = (double)P[r] * inv * rx[i] * ry[c];
-    }
-    __syncthreads();
-    for (uint32_t r = lane; r < NN; r += 64) {
-      const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * (uint32_t)N;
-      double acc = 0.0;
-      for (int c = 0; c < N; ++c) acc += Bm[i * N + c] * Bm[j * N + c];
-      Sm[r] = acc;
-    }
-    __syncthreads();
-    for (int sweep = 0; sweep < kMccSweeps; ++sweep) {
-      double off = 0.0, dia = 0.0;
-      for (uint32_t r = lane; r < NN; r += 64) {
-        const uint32_t i = divide(r, a.nmagic, a.nshift), j = r - i * (uint32_t)N;
-        const double v = Sm[r];
-        if (i == j) dia += v * v; else off += v * v;
-      }
-      off = wave_sum_f64(off);
-      dia = wave_sum_f64(dia);
-      if (!(off > 1e-32 * dia)) break;  // the same decision on every lane
-      for (int p = 0; p < N - 1; ++p) {
-        for (int q = p + 1; q < N; ++q) {
-          const double apq = Sm[p * N + q];
-          if (apq == 0.0) continue;
-          const double tau = (Sm[q * N + q] - Sm[p * N + p]) / (2.0 * apq);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
-          __syncthreads();  // every lane has read apq, app, aqq
-          if (lane < N) {  // columns p and q
-            const double skp = Sm[lane * N + p], skq = Sm[lane * N + q];
-            Sm[lane * N + p] = cs * skp - sn * skq;
-            Sm[lane * N + q] = sn * skp + cs * skq;
-          }
-          __syncthreads();
-          if (lane < N) {  // rows p and q
-            const double spk = Sm[p * N + lane], sqk = Sm[q * N + lane];
-            Sm[p * N + lane] = cs * spk - sn * sqk;
-            Sm[q * N + lane] = sn * spk + cs * sqk;
-          }
-          __syncthreads();
-        }
-      }
-    }
-    // the two largest diagonal entries: the first is 1 (eigenvector sqrt(px))
-    const double d = lane < N ? Sm[lane * N + lane] : -1.0;
-    double m1 = d;
-    for (int o = 32; o; o >>= 1) m1 = fmax(m1, __shfl_xor(m1, o));
-    const unsigned long long at = __ballot(d == m1);
-    const int first = __ffsll((long long)at) - 1;  // one lane holding the largest
-    double m2 = lane == first ? -1.0 : d;
-    for (int o = 32; o; o >>= 1) m2 = fmax(m2, __shfl_xor(m2, o));
-    if (lane == 0) a.out_f[k] = (float)sqrt(m2 > 0.0 ? m2 : 0.0);
-    __syncthreads();  // Bm, Sm, rx, ry are rewritten for the next matrix
-  }
-}
-
 unsigned grid_for(int units) { return (unsigned)(units < 8192 ? (units > 0 ? units : 1) : 8192); }
 
 }  // namespace
@@ -474,12 +380,6 @@ hipError_t launch_normalize(const StatsArgs& a, hipStream_t stream) {
 
 hipError_t launch_average(const StatsArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(k_average, dim3(grid_for(a.K / a.m)), dim3(kStatsThreads), 0, stream, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_haralick_mcc(const StatsArgs& a, hipStream_t stream) {
-  const size_t lds = (2 * (size_t)a.N * a.N + 2 * (size_t)a.N) * sizeof(double);
-  hipLaunchKernelGGL(k_haralick_mcc, dim3(grid_for(a.K)), dim3(64), (uint32_t)lds, stream, a);
   return hipGetLastError();
 }
 
