@@ -45,7 +45,7 @@ VOTE_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vote_strips_4096x4096_u8_smooth_traffic.json")
 # the same for the histogram kernel
 HIST_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)
-                for f in ("glcm_hist.hip", "glcm_device.h", "glcm_stats.h", "glcm_internal.h")]
+                for f in ("glcm_hist.hip", "glcm_device.h", "glcm_hist.h", "glcm_internal.h")]
 HIST_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "histogram_4096x4096_u8_smooth_traffic.json")
 # VALU instruction count of the Haralick kernel (an fp64 ALU-bound kernel)
 STATS_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)

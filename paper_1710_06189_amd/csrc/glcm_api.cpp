@@ -15,7 +15,7 @@
 #include "glcm.h"
 #include "glcm_host.h"
 #include "glcm_internal.h"
-#include "glcm_stats.h"
+#include "glcm_hist.h"
 
 using glcm::VoteArgs;
 

@@ -14,7 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "glcm_device.h"
-#include "glcm_stats.h"
+#include "glcm_hist.h"
 
 namespace glcm {
 namespace {

@@ -1,6 +1,5 @@
-// Interface between the host runtime and the histogram and post-processing
-// kernels (1-D histogram, symmetric / normalised / direction-averaged GLCMs,
-// Haralick's statistics).
+// Interface between the host runtime and the post-processing kernels
+// (symmetric / normalised / direction-averaged GLCMs, Haralick's statistics).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,23 +9,6 @@
 #include "glcm_internal.h"
 
 namespace glcm {
-
-// Arguments of the 1-D histogram kernel.  The quantizer fields match VoteArgs
-// so the packed quantizers take either.
-struct HistArgs {
-  const void* img;     // row y at img + y * stride elements
-  int64_t stride;      // elements
-  int W, H;
-  Quant q;             // q.nlev = N levels
-  int qfast;
-  uint32_t qfast_shift, qfast_mask;
-  int vec;             // 1: base and row pitch 16-byte aligned (16-byte chunk loads)
-  uint32_t D;          // LDS copies per level, a power of two <= 32
-  uint32_t cpr;        // 16-pixel chunks per row
-  uint64_t per_block;  // chunks per workgroup
-  uint32_t* partials;  // [gridDim][N] per-workgroup histograms
-};
-constexpr int kHistThreads = 1024;
 
 // Arguments of the post-processing kernels over K matrices of N x N uint32
 // counts (symmetric, normalised, direction-averaged GLCMs and the thirteen
@@ -42,9 +24,6 @@ constexpr int kHaralickStats = 13;
 constexpr int kHaralickMaxN = 1024;  // the marginal arrays (7 N doubles) fit the LDS
 constexpr int kAverageMaxGroup = 64;
 
-// 1-D histogram: `groups` workgroups write a.partials; lds_bytes = 4 N D.
-hipError_t launch_histogram(const HistArgs& a, int dtype_bytes, int groups, size_t lds_bytes, hipStream_t stream,
-                            const LaunchTiming& tm = {});
 hipError_t launch_symmetrize(const StatsArgs& a, hipStream_t stream);
 hipError_t launch_normalize(const StatsArgs& a, hipStream_t stream);
 hipError_t launch_average(const StatsArgs& a, hipStream_t stream);
