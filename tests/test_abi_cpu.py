@@ -208,3 +208,28 @@ def test_prepared_batch_rejects_bad_arguments(lib):
     assert lib.glcm_batch_prepare(ctypes.c_void_p(0x1000), one, 1, None) == -1
     assert lib.glcm_batch_run(None, 0, 255, ctypes.c_void_p(0x20000), None, None) == -1
     assert lib.glcm_batch_destroy(None) == 0
+
+
+def test_header_is_plain_c_and_links(lib, tmp_path):
+    """include/glcm.h compiles as C99 with -pedantic, and a C program linked
+    against libglcm.so runs (it calls only functions that need no GPU)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include "glcm.h"\n#include <string.h>\n'
+        "int main(void) {\n"
+        "  glcm_offset_t o;\n"
+        "  if (glcm_abi_version() != GLCM_ABI_VERSION) return 2;\n"
+        "  if (glcm_offset_polar(2, 135, &o) != GLCM_OK || o.dx != 2 || o.dy != 2) return 3;\n"
+        "  if (strcmp(glcm_strerror(12345), \"unknown status\") != 0) return 4;\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(glcm.library_path())
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                           os.path.join(root, "include"), str(src), "-o", str(exe), "-L", libdir, "-lglcm",
+                           "-Wl,-rpath," + libdir])
+    assert subprocess.run([str(exe)]).returncode == 0
