@@ -1424,12 +1424,15 @@ GLCM_API int glcm_histogram(glcm_plan_t plan, const void* img, int W, int H, int
   if (out_dev != cur || img_dev != cur) return GLCM_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;
   if (!plan) {
-    auto tk = std::make_tuple(cur, dtype, N, 1, std::vector<int32_t>{0, 0});
+    // a plan of its own (K = 0 in the key, which no glcm_compute call uses),
+    // made on the global-atomic path so that it allocates no per-XCD slices:
+    // the histogram needs only the partials
+    auto tk = std::make_tuple(cur, dtype, N, 0, std::vector<int32_t>{});
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(tk);
     if (it == g_cache.end()) {
       glcm_plan_t np = nullptr;
-      rc = glcm_plan_create(&np, dtype, N, 1, &kZero, 65535, 65535, 0);
+      rc = glcm_plan_create(&np, dtype, N, 1, &kZero, 65535, 65535, GLCM_FLAG_FORCE_GLOBAL);
       if (rc != GLCM_OK) return rc;
       it = g_cache.emplace(tk, np).first;
     }
