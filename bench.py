@@ -84,6 +84,20 @@ def recorded_traffic(tuning):
     return rec.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} cores available"
+
+
 def recorded_hist_traffic():
     """HBM bytes per histogram-kernel launch (N = 32) from the committed counter
     summary, or None when the kernel's sources differ from what was measured."""
@@ -284,7 +298,7 @@ def main():
                 break
         cpu = {"value": reps * main_res["pairs"] / el / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
                "sample": f"{reps} full passes over the 4096x4096 {args.kind} image, 4 offsets, single-threaded C "
-                         f"oracle, {el:.1f} s"}
+                         f"oracle, {el:.1f} s; host {host_cpu()}"}
         extra["cpu_all_cores"] = cpu_all_cores(oracle, np, img, N, lo, hi, offs, main_res["pairs"], args.cpu_seconds)
 
     line = {
@@ -514,7 +528,7 @@ def bench_histogram(args, G, torch, np, oracle, synth, dev):
         reps, el = time_oracle(lambda: oracle.histogram(img, 32, 0, 255), args.cpu_seconds)
         cpu = {"value": reps * px / el / 1e9, "unit": "Gpixels/s", "cores": 1, "kind": "oracle",
                "sample": f"{reps} full passes over the 4096x4096 {args.kind} image, N=32, single-threaded C oracle, "
-                         f"{el:.1f} s"}
+                         f"{el:.1f} s; host {host_cpu()}"}
     print(json.dumps({
         "metric": "histogram Gpixels/s (bit-exact)", "value": px / (r["wall_ms"] * 1e-3) / 1e9, "unit": "Gpixels/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall_ms"],
@@ -585,7 +599,7 @@ def bench_variants(args, G, torch, np, oracle, synth, dev, reps=50):
         reps_c, el = time_oracle(lambda: oracle.haralick(sample), args.cpu_seconds)
         cpu = {"value": reps_c * len(sample) / el, "unit": "matrices/s", "cores": 1, "kind": "oracle",
                "sample": f"{reps_c} passes of the C oracle's f1..f13 over the first {len(sample)} matrices, "
-                         f"{el:.1f} s"}
+                         f"{el:.1f} s; host {host_cpu()}"}
     h = timing["haralick"]
     valu = recorded_haralick_valu()
     if valu:
