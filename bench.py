@@ -448,6 +448,19 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
         raise SystemExit("bench: graph-replayed batch differs from glcm_batch_compute")
     del graph
     pb.close()
+    # the batch autotuner: every layout timed on this batch, the fastest kept
+    default_tuning = plan.batch_tuning.as_dict()
+    chosen = plan.batch_autotune(tiles, repeats=3).as_dict()
+    a_out, a_f = torch.empty_like(out), torch.empty_like(feats)
+    G.glcm_batch_compute(tiles, plan, out=a_out, features=a_f, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.glcm_batch_compute(tiles, plan, out=a_out, features=a_f, stream=stream)
+    torch.cuda.synchronize()
+    tuned_wall = (time.perf_counter() - t0) / reps
+    if not (torch.equal(a_out.view(torch.int32), out.view(torch.int32)) and torch.equal(a_f, feats)):
+        raise SystemExit("bench: the autotuned batch layout changed the results")
     plan.close()
     a, b = out.view(torch.int32).cpu().numpy(), out1.view(torch.int32).cpu().numpy()
     if not np.array_equal(a, b):
@@ -465,6 +478,8 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
         "per_image_gpairs_s": pairs / per_wall / 1e9, "per_image_ms": per_wall * 1e3,
         "per_image_device_ms": per_dev * 1e3, "batched_over_per_image": per_wall / batch_wall,
         "graph_replay_ms": graph_wall * 1e3, "graph_replay_gpairs_s": pairs / graph_wall / 1e9,
+        "default_layout": default_tuning, "autotuned_layout": chosen, "autotuned_ms": tuned_wall * 1e3,
+        "autotuned_gpairs_s": pairs / tuned_wall / 1e9,
         "features": True, "check": "batched == per-image calls == graph replay (counts and statistics); "
                                    "64 tiles vs oracle"}),
         flush=True)

@@ -380,6 +380,43 @@ GLCM_API int glcm_batch_run(glcm_batch_t batch, uint32_t lo, uint32_t hi, uint32
 /* Waits for the device to go idle, then releases the handle.  NULL is accepted. */
 GLCM_API int glcm_batch_destroy(glcm_batch_t batch);
 
+/*
+ * Layout of the batch kernel, chosen per plan.  The paper tunes the number of
+ * GLCM copies per block and the block size by measurement (Section II.A,
+ * Table III, Eq. (4)-(6)); the batch engine does the same for its own layout.
+ *
+ *   replicas  LDS copies (dwords) of every bin: 4, 8 or 16; 0 = the default
+ *             rule (the most that leave room for three workgroups per CU).
+ *             More copies mean fewer colliding votes but a heavier merge.
+ *   min_rows  shortest run of rows a wavefront segment walks, 1 .. 256; 0 = 8.
+ *             Shorter runs spread a small image over more wavefronts; longer
+ *             runs cut the per-run set-up.
+ *   wg_size   read-only: threads per workgroup (256).
+ */
+typedef struct glcm_batch_tuning {
+    int replicas;
+    int min_rows;
+    int wg_size;
+} glcm_batch_tuning_t;
+
+/* Reads (set = 0) or sets (set != 0) the plan's batch layout; on return
+ * *tuning holds the effective values.  GLCM_EINVAL for a NULL argument or a
+ * value out of range, GLCM_EUNSUPPORTED when the copies do not fit the LDS. */
+GLCM_API int glcm_batch_tuning(glcm_plan_t plan, glcm_batch_tuning_t *tuning, int set);
+
+/*
+ * Times every batch layout that fits (replicas 4, 8, 16 x min_rows 4, 8, 16,
+ * 32) on the given images, `repeats` runs each after one warm-up run, with the
+ * statistics computed, and keeps the fastest in the plan for later batch calls
+ * (glcm_batch_compute, glcm_batch_prepare).  tiles, T, lo, hi as for
+ * glcm_batch_compute; repeats 1 .. 1000.  Allocates its own outputs and stream
+ * and synchronises before returning.  *chosen (may be NULL) receives the
+ * layout kept.  Errors as for glcm_batch_compute; on a HIP failure the plan
+ * keeps its previous layout.
+ */
+GLCM_API int glcm_batch_autotune(glcm_plan_t plan, const glcm_tile_t *tiles, int T, uint32_t lo, uint32_t hi,
+                                 int repeats, glcm_batch_tuning_t *chosen);
+
 /* ------------------------------------------------------------------------
  * Request server: continuous admission of GLCM jobs of mixed image size, N
  * and offset lists.  A scheduler thread admits queued requests in arrival

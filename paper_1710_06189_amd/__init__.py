@@ -42,7 +42,7 @@ __all__ = [
     "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
     "glcm_plan_rebind", "glcm_plan_workspace", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
     "glcm_histogram", "glcm_symmetrize", "glcm_normalize", "glcm_average", "glcm_haralick", "HARALICK_NAMES",
-    "glcm_haralick_mcc",
+    "glcm_haralick_mcc", "BatchTuning",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -107,6 +107,13 @@ class Tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("replicas", ctypes.c_int), ("min_rows", ctypes.c_int), ("wg_size", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _L = None
 
 
@@ -147,6 +154,10 @@ def _lib():
         for name in ("glcm_symmetrize", "glcm_normalize", "glcm_haralick", "glcm_haralick_mcc"):
             getattr(lib, name).restype = i32
             getattr(lib, name).argtypes = [vp, i32, i32, vp, vp]
+        lib.glcm_batch_tuning.restype = i32
+        lib.glcm_batch_tuning.argtypes = [vp, ctypes.POINTER(BatchTuning), i32]
+        lib.glcm_batch_autotune.restype = i32
+        lib.glcm_batch_autotune.argtypes = [vp, ctypes.POINTER(Tile), i32, u32, u32, i32, ctypes.POINTER(BatchTuning)]
         lib.glcm_average.restype = i32
         lib.glcm_average.argtypes = [vp, i32, i32, i32, vp, vp]
         lib.glcm_batch_compute.restype = i32
@@ -253,6 +264,28 @@ class Plan:
                                          int(repeats), _stream_handle(stream), ctypes.byref(t)),
                "glcm_plan_autotune")
         del keep
+        return t
+
+    @property
+    def batch_tuning(self) -> BatchTuning:
+        t = BatchTuning()
+        _check(_lib().glcm_batch_tuning(self.handle, ctypes.byref(t), 0), "glcm_batch_tuning")
+        return t
+
+    def set_batch_tuning(self, replicas=0, min_rows=0) -> BatchTuning:
+        """Batch-kernel layout (0 = default): LDS copies per bin 4/8/16, shortest row run 1..256."""
+        t = BatchTuning(int(replicas), int(min_rows), 0)
+        _check(_lib().glcm_batch_tuning(self.handle, ctypes.byref(t), 1), "glcm_batch_tuning")
+        return t
+
+    def batch_autotune(self, images, lo=0, hi=None, repeats=3) -> BatchTuning:
+        """Times the batch layouts on `images` (device tensors or a TileSet) and keeps the fastest."""
+        ts = images if isinstance(images, TileSet) else TileSet(images, self.dtype)
+        if hi is None:
+            hi = 255 if self.dtype == U8 else 65535
+        t = BatchTuning()
+        _check(_lib().glcm_batch_autotune(self.handle, ts.tiles, ts.T, int(lo), int(hi), int(repeats),
+                                          ctypes.byref(t)), "glcm_batch_autotune")
         return t
 
     def kernel_time(self):

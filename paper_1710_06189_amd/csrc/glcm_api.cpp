@@ -222,6 +222,10 @@ struct glcm_plan_s {
   hipEvent_t batch_uploaded = nullptr;
   bool batch_pending = false;
 
+  // batch kernel layout: LDS copies per bin (0: the default rule) and the
+  // shortest run of rows a wavefront segment walks (0: 8); glcm_batch_tuning
+  int batch_D = 0, batch_min_rows = 0;
+
   // GLCM_FLAG_TIMING: events around every counting-kernel launch
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
 
@@ -1198,6 +1202,16 @@ struct BatchLayout {
 };
 
 // Checks a batch request against the plan and picks its LDS layout.
+// The default LDS layout of the batch kernel: the most dwords per bin (16, 8
+// or 4) that leave room for three workgroups per CU (their loads and merges
+// then overlap other workgroups' votes).
+int batch_default_copies(const glcm_plan_s* plan) {
+  const size_t lds_cu = (size_t)plan->lds_budget_words * 4u + 1024u;
+  int D = 16;
+  while (D > 4 && glcm::batch_lds_bytes(plan->N, plan->K, D) * 3u > lds_cu) D /= 2;
+  return D;
+}
+
 int batch_layout(glcm_plan_t plan, const glcm_tile_t* tiles, int T, BatchLayout* L) {
   if (!plan || !tiles || T < 1 || T > (1 << 20)) return GLCM_EINVAL;
   const int b = dtype_bytes(plan->dtype);
@@ -1208,11 +1222,8 @@ int batch_layout(glcm_plan_t plan, const glcm_tile_t* tiles, int T, BatchLayout*
   }
   const Canon c = canonicalize(plan->offsets, plan->K);
   if (plan->N > 255 || plan->K > glcm::kStripMaxKp || c.maxdy > 2 || c.maxadx > 2) return GLCM_EUNSUPPORTED;
-  // LDS layout: the most dwords per bin that leave room for three workgroups
-  // per CU (their loads and merges then overlap other workgroups' votes)
   const size_t lds_cu = (size_t)plan->lds_budget_words * 4u + 1024u;
-  int D = 16;
-  while (D > 4 && glcm::batch_lds_bytes(plan->N, plan->K, D) * 3u > lds_cu) D /= 2;
+  const int D = plan->batch_D ? plan->batch_D : batch_default_copies(plan);
   const size_t lds_bytes = glcm::batch_lds_bytes(plan->N, plan->K, D);
   if (lds_bytes > lds_cu - 1024u) return GLCM_EUNSUPPORTED;
   L->D = D;
@@ -1229,7 +1240,7 @@ int batch_layout(glcm_plan_t plan, const glcm_tile_t* tiles, int T, BatchLayout*
   }
   a.tmask = c.tmask;
   a.pitch = (uint32_t)plan->N + 1u;
-  a.min_rows = 8;
+  a.min_rows = plan->batch_min_rows ? plan->batch_min_rows : 8;
   return GLCM_OK;
 }
 
@@ -1308,14 +1319,14 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
                                 uint32_t* out, float* features, void* stream_) {
   if (!plan || !tiles || !out || T < 1 || T > (1 << 20)) return GLCM_EINVAL;  // before touching the plan
   if (lo > hi || hi > (plan->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
-  BatchLayout L;
-  int rc = batch_layout(plan, tiles, T, &L);
-  if (rc != GLCM_OK) return rc;
   int dev = -1;
   if (pointer_kind(out, &dev) != 2) return GLCM_EINVAL;
   if (features && pointer_kind(features, &dev) != 2) return GLCM_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;
   std::lock_guard<std::mutex> lk(plan->mu);
+  BatchLayout L;
+  int rc = batch_layout(plan, tiles, T, &L);
+  if (rc != GLCM_OK) return rc;
   GLCM_TRY_RC(order_after_previous(plan, stream));
   // misaligned images are first copied into the plan's staging buffer with a
   // 16-byte pitch (one realignment launch), so every image takes the strip
@@ -1470,6 +1481,101 @@ GLCM_API int glcm_histogram(glcm_plan_t plan, const void* img, int W, int H, int
   GLCM_TRY(glcm::launch_histogram(a, b, groups, (size_t)N * a.D * 4u, stream, tm));
   GLCM_TRY(glcm::launch_reduce(a.partials, out, (uint32_t)N, groups, false, stream));
   return record_done(plan, stream);
+}
+
+GLCM_API int glcm_batch_tuning(glcm_plan_t plan, glcm_batch_tuning_t* t, int set) {
+  if (!plan || !t) return GLCM_EINVAL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  if (set) {
+    if (t->replicas != 0 && t->replicas != 4 && t->replicas != 8 && t->replicas != 16) return GLCM_EINVAL;
+    if (t->min_rows < 0 || t->min_rows > 256) return GLCM_EINVAL;
+    if (t->replicas) {
+      const size_t lds_cu = (size_t)plan->lds_budget_words * 4u + 1024u;
+      if (glcm::batch_lds_bytes(plan->N, plan->K, t->replicas) > lds_cu - 1024u) return GLCM_EUNSUPPORTED;
+    }
+    plan->batch_D = t->replicas;
+    plan->batch_min_rows = t->min_rows;
+  }
+  t->replicas = plan->batch_D ? plan->batch_D : batch_default_copies(plan);
+  t->min_rows = plan->batch_min_rows ? plan->batch_min_rows : 8;
+  t->wg_size = glcm::kBatchThreads;
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_batch_autotune(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
+                                 int repeats, glcm_batch_tuning_t* chosen) {
+  if (!plan || !tiles || T < 1 || T > (1 << 20) || repeats < 1 || repeats > 1000) return GLCM_EINVAL;
+  if (lo > hi || hi > (plan->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(plan->mu);
+    BatchLayout L;
+    const int rc = batch_layout(plan, tiles, T, &L);  // validates the tiles and the plan
+    if (rc != GLCM_OK) return rc;
+  }
+  const size_t words = (size_t)T * plan->K * plan->N * plan->N;
+  uint32_t* out = nullptr;
+  float* feat = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int old_D = plan->batch_D, old_rows = plan->batch_min_rows;
+  int best_D = 0, best_rows = 0, rc = GLCM_OK;
+  float best = 0.0f;
+  hipError_t e = hipMalloc((void**)&out, words * 4u);
+  if (e == hipSuccess) e = hipMalloc((void**)&feat, (size_t)T * plan->K * 5u * sizeof(float));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) rc = hip_status(e);
+  const int rows_grid[] = {4, 8, 16, 32};
+  for (int D = 4; rc == GLCM_OK && D <= 16; D *= 2) {
+    const size_t lds_cu = (size_t)plan->lds_budget_words * 4u + 1024u;
+    if (glcm::batch_lds_bytes(plan->N, plan->K, D) > lds_cu - 1024u) continue;
+    for (int rows : rows_grid) {
+      {
+        std::lock_guard<std::mutex> lk(plan->mu);
+        plan->batch_D = D;
+        plan->batch_min_rows = rows;
+      }
+      // a prepared batch: the timed runs queue kernels only (no host staging)
+      glcm_batch_t pb = nullptr;
+      rc = glcm_batch_prepare(plan, tiles, T, &pb);
+      if (rc == GLCM_OK) rc = glcm_batch_run(pb, lo, hi, out, feat, s);  // warm-up
+      if (rc == GLCM_OK && (e = hipEventRecord(e0, s)) != hipSuccess) rc = hip_status(e);
+      for (int r = 0; rc == GLCM_OK && r < repeats; ++r) rc = glcm_batch_run(pb, lo, hi, out, feat, s);
+      float ms = 0.0f;
+      if (rc == GLCM_OK && (e = hipEventRecord(e1, s)) != hipSuccess) rc = hip_status(e);
+      if (rc == GLCM_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_status(e);
+      if (rc == GLCM_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) rc = hip_status(e);
+      if (pb) {
+        if (s) (void)hipStreamSynchronize(s);
+        (void)glcm_batch_destroy(pb);
+      }
+      if (rc != GLCM_OK) break;
+      if (best_D == 0 || ms < best) {
+        best = ms;
+        best_D = D;
+        best_rows = rows;
+      }
+    }
+  }
+  if (s) (void)hipStreamSynchronize(s);
+  {
+    std::lock_guard<std::mutex> lk(plan->mu);
+    plan->batch_D = rc == GLCM_OK ? best_D : old_D;
+    plan->batch_min_rows = rc == GLCM_OK ? best_rows : old_rows;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (out) (void)hipFree(out);
+  if (feat) (void)hipFree(feat);
+  if (rc != GLCM_OK) return rc;
+  if (chosen) {
+    chosen->replicas = best_D;
+    chosen->min_rows = best_rows;
+    chosen->wg_size = glcm::kBatchThreads;
+  }
+  return GLCM_OK;
 }
 
 GLCM_API int glcm_features(const uint32_t* glcm_u32, int K, int N, float* out, void* stream) {

@@ -154,6 +154,14 @@ def test_post_processing_rejects_bad_arguments(lib):
     assert lib.glcm_average(a, 4, 8, 2, b, None) == -1  # not device memory
 
 
+def test_batch_tuning_rejects_bad_arguments(lib):
+    t = glcm.BatchTuning()
+    assert lib.glcm_batch_tuning(None, ctypes.byref(t), 0) == -1
+    tiles = (glcm.Tile * 1)()
+    assert lib.glcm_batch_autotune(None, tiles, 1, 0, 255, 3, ctypes.byref(t)) == -1
+    assert lib.glcm_batch_autotune(None, None, 1, 0, 255, 3, None) == -1
+
+
 def test_plan_tuning_rejects_null(lib):
     t = glcm.Tuning()
     assert lib.glcm_plan_tuning(None, ctypes.byref(t), 0) == -1

@@ -199,3 +199,49 @@ def test_prepared_batch_runs_and_graph_replays():
     finally:
         pb.close()
         plan.close()
+
+
+def test_batch_layouts_are_all_exact():
+    """Every batch layout (LDS copies x shortest row run) gives the same counts
+    and statistics, equal to the oracle."""
+    w = synth.batch_tiles(40)
+    imgs, N, offs = w["images"], w["N"], w["offsets"]
+    tens = [to_device(im) for im in imgs]
+    plan = G.glcm_plan_create(np.uint8, N, offs, 512, 512)
+    try:
+        ref_out, ref_f = G.glcm_batch_compute(tens, plan)
+        ref_out, ref_f = host(ref_out), host(ref_f)
+        for t in range(0, 40, 5):
+            assert np.array_equal(ref_out[t], oracle.glcm(imgs[t], N, 0, 255, offs))
+        for D in (4, 8, 16):
+            for rows in (1, 3, 8, 32):
+                bt = plan.set_batch_tuning(replicas=D, min_rows=rows)
+                assert (bt.replicas, bt.min_rows, bt.wg_size) == (D, rows, 256)
+                print(f"[batch layout] D={D} min_rows={rows}", flush=True)
+                o, f = G.glcm_batch_compute(tens, plan)
+                assert np.array_equal(host(o), ref_out), (D, rows)
+                assert np.array_equal(host(f), ref_f), (D, rows)
+        with pytest.raises(G.GlcmError):
+            plan.set_batch_tuning(replicas=32)
+        with pytest.raises(G.GlcmError):
+            plan.set_batch_tuning(min_rows=300)
+    finally:
+        plan.close()
+
+
+def test_batch_autotune_keeps_a_measured_layout():
+    w = synth.batch_tiles(64)
+    imgs, N, offs = w["images"], w["N"], w["offsets"]
+    tens = [to_device(im) for im in imgs]
+    plan = G.glcm_plan_create(np.uint8, N, offs, 512, 512)
+    try:
+        ref_out, ref_f = G.glcm_batch_compute(tens, plan)
+        chosen = plan.batch_autotune(tens, repeats=2)
+        assert chosen.replicas in (4, 8, 16) and chosen.min_rows in (4, 8, 16, 32) and chosen.wg_size == 256
+        assert plan.batch_tuning.as_dict() == chosen.as_dict()
+        o, f = G.glcm_batch_compute(tens, plan)
+        assert np.array_equal(host(o), host(ref_out)) and np.array_equal(host(f), host(ref_f))
+        for t in range(0, 64, 8):
+            assert np.array_equal(host(o)[t], oracle.glcm(imgs[t], N, 0, 255, offs))
+    finally:
+        plan.close()
