@@ -267,7 +267,8 @@ def main():
     achieved_gbs = main_res["bytes"] / (main_res["vote_ms"] * 1e-3) / 1e9
     traffic = recorded_traffic(main_res["tuning"])
 
-    extra = {"step_ms_events": main_res["step_ms"], "vote_kernel_ms": main_res["vote_ms"],
+    extra = {"input_sha256": synth.sha256(main_res["img"]),
+             "step_ms_events": main_res["step_ms"], "vote_kernel_ms": main_res["vote_ms"],
              "pairs_per_step": main_res["pairs"], "algorithmic_bytes_per_step": main_res["bytes"],
              "tuning": main_res["tuning"], "copies_rotated": args.copies,
              "rotated_bytes": args.copies * 4096 * 4096,
@@ -473,6 +474,7 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
             raise SystemExit(f"bench: tile {t} differs from the oracle")
     print(json.dumps({
         "workload": w["name"], "tiles": T, "pixels": px, "pairs": pairs, "aligned_tiles": aligned,
+        "input_sha256": hashlib.sha256("".join(synth.sha256(im) for im in imgs).encode()).hexdigest(),
         "batched_gpairs_s": pairs / batch_wall / 1e9, "batched_ms": batch_wall * 1e3,
         "batched_device_ms": batch_dev * 1e3,
         "per_image_gpairs_s": pairs / per_wall / 1e9, "per_image_ms": per_wall * 1e3,
@@ -552,7 +554,7 @@ def bench_histogram(args, G, torch, np, oracle, synth, dev):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_hist_traffic()},
         "cpu_baseline": cpu,
-        "extra": {"kernel_ms_n32": r["kernel_ms"], "wall_ms_n256": res[256]["wall_ms"],
+        "extra": {"input_sha256": synth.sha256(img), "kernel_ms_n32": r["kernel_ms"], "wall_ms_n256": res[256]["wall_ms"],
                   "kernel_ms_n256": res[256]["kernel_ms"],
                   "gpixels_s_n256": px / (res[256]["wall_ms"] * 1e-3) / 1e9, "copies_rotated": len(copies)},
     }), flush=True)
@@ -633,7 +635,7 @@ def bench_variants(args, G, torch, np, oracle, synth, dev, reps=50):
         "config": {"workload": w["name"], "matrices": K, "levels": N, "resident": "device"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "extra": {"kernels": timing, "check": "symmetric, normalised, averaged bit-exact; statistics within tolerance"},
+        "extra": {"input_sha256": synth.sha256(P), "kernels": timing, "check": "symmetric, normalised, averaged bit-exact; statistics within tolerance"},
     }), flush=True)
 
 
