@@ -147,27 +147,43 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
 
 // Copies each misaligned image of a batch into the staging buffer with a
 // 16-byte row pitch, so the batch kernel reads every image with 16-byte
-// loads.  One workgroup per image; source pixels are read one by one (any
-// alignment), destination dwords written whole (pixels past W as zero).
+// loads.  One workgroup per image; a thread makes one 16-byte group of a
+// destination row from the (up to) five aligned source dwords that span it
+// (v_alignbyte), reading only dwords that hold a byte of the row, zeroes the
+// bytes past W and stores the group whole.  (row, group) advance by the
+// mixed-radix digits of blockDim: no division.
 template <typename Pix>
 __global__ __launch_bounds__(256) void k_batch_realign(const RealignDesc* d, char* stage) {
   const RealignDesc e = d[blockIdx.x];
-  const Pix* src = (const Pix*)e.src;
-  uint32_t* dst = (uint32_t*)(stage + e.dst_off);
-  constexpr int PPD = 4 / (int)sizeof(Pix);          // pixels per dword
-  const uint32_t dw = (uint32_t)(e.W + PPD - 1) / PPD;  // dwords of a row that hold pixels
-  const uint32_t dpd = (uint32_t)e.dpitch / PPD;       // dwords per copy row
-  const uint32_t n = dw * (uint32_t)e.H;
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const uint32_t y = i / dw, q = i - y * dw;
-    const Pix* s = src + (int64_t)y * e.sstride;
-    uint32_t v = 0;
+  uint4* dst = (uint4*)(stage + e.dst_off);
+  const uint32_t rowbytes = (uint32_t)e.W * (uint32_t)sizeof(Pix);
+  const uint32_t gw = (rowbytes + 15u) / 16u;                           // groups of a row that hold pixels
+  const uint32_t gpitch = (uint32_t)e.dpitch * (uint32_t)sizeof(Pix) / 16u;  // groups per copy row
+  const uint32_t sy = blockDim.x / gw, sg = blockDim.x % gw;
+  uint32_t y = threadIdx.x / gw, g = threadIdx.x % gw;
+  while (y < (uint32_t)e.H) {
+    const uintptr_t r0 = (uintptr_t)((const char*)e.src + (int64_t)y * e.sstride * (int64_t)sizeof(Pix));
+    const uint32_t* a0 = (const uint32_t*)(r0 & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(r0 & 3u);  // bytes the row starts past a dword boundary
+    // source dword 4g + i spans row bytes [16g + 4i - sh, 16g + 4i + 4 - sh)
+    uint32_t a[5];
 #pragma unroll
-    for (int p = 0; p < PPD; ++p) {
-      const uint32_t x = q * PPD + (uint32_t)p;
-      if (x < (uint32_t)e.W) v |= (uint32_t)s[x] << (p * 8 * (int)sizeof(Pix));
+    for (uint32_t i = 0; i < 5; ++i) a[i] = 16u * g + 4u * i < rowbytes + sh ? a0[4u * g + i] : 0u;
+    uint32_t v[4];
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+      v[i] = sh ? __builtin_amdgcn_alignbyte(a[i + 1], a[i], sh) : a[i];
+      const int32_t left = (int32_t)rowbytes - (int32_t)(16u * g + 4u * i);  // row bytes from this dword on
+      if (left <= 0) v[i] = 0u;
+      else if (left < 4) v[i] &= (1u << (8u * (uint32_t)left)) - 1u;
     }
-    dst[(size_t)y * dpd + q] = v;
+    dst[(size_t)y * gpitch + g] = make_uint4(v[0], v[1], v[2], v[3]);
+    g += sg;
+    y += sy;
+    if (g >= gw) {
+      g -= gw;
+      ++y;
+    }
   }
 }
 
