@@ -1506,18 +1506,20 @@ GLCM_API int glcm_batch_autotune(glcm_plan_t plan, const glcm_tile_t* tiles, int
                                  int repeats, glcm_batch_tuning_t* chosen) {
   if (!plan || !tiles || T < 1 || T > (1 << 20) || repeats < 1 || repeats > 1000) return GLCM_EINVAL;
   if (lo > hi || hi > (plan->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
+  int old_D = 0, old_rows = 0;
   {
     std::lock_guard<std::mutex> lk(plan->mu);
     BatchLayout L;
     const int rc = batch_layout(plan, tiles, T, &L);  // validates the tiles and the plan
     if (rc != GLCM_OK) return rc;
+    old_D = plan->batch_D;
+    old_rows = plan->batch_min_rows;
   }
   const size_t words = (size_t)T * plan->K * plan->N * plan->N;
   uint32_t* out = nullptr;
   float* feat = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const int old_D = plan->batch_D, old_rows = plan->batch_min_rows;
   int best_D = 0, best_rows = 0, rc = GLCM_OK;
   float best = 0.0f;
   hipError_t e = hipMalloc((void**)&out, words * 4u);
