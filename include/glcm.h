@@ -335,7 +335,8 @@ typedef struct glcm_tile {
  *             4 copies of the K (N+1) x (N+1) matrices in one workgroup's LDS
  *             ((N+1)^2 * K * 16 bytes + 4 K N^2 + 3 KiB <= 159 KiB, e.g. N <= 43
  *             for K = 4), else GLCM_EUNSUPPORTED; images need not be 16-byte
- *             aligned (those that are not are counted per pixel).
+ *             aligned (those that are not are first copied, in one launch,
+ *             into plan-owned staging with a 16-byte row pitch).
  *   tiles     host array of T image descriptors (read before returning).
  *   T         number of images, 1 .. 2^20.
  *   lo, hi    quantization range, as in glcm_compute.
