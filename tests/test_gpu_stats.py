@@ -287,3 +287,30 @@ def test_haralick_mcc(name, make):
     with pytest.raises(G.GlcmError) as e:
         G.glcm_haralick_mcc(torch.zeros((1, 65, 65), dtype=torch.uint32, device="cuda"))
     assert e.value.status == -3
+
+
+def test_post_processing_rejects_overlaps_and_bad_groups():
+    """Argument errors with real device buffers: partial overlaps, K not a
+    multiple of m, m beyond 64 (nothing is queued; the status is EINVAL)."""
+    import ctypes
+    lib = G._lib()
+    buf = torch.zeros(3 * 8 * 8 + 64, dtype=torch.int32, device="cuda")
+    p = buf.data_ptr()
+    vp = ctypes.c_void_p
+    # symmetric output shifted by one word into the input: rejected; exactly in place: accepted
+    assert lib.glcm_symmetrize(vp(p), 3, 8, vp(p + 4), None) == -1
+    assert lib.glcm_symmetrize(vp(p), 3, 8, vp(p), None) == 0
+    assert lib.glcm_normalize(vp(p), 3, 8, vp(p + 64), None) == -1
+    assert lib.glcm_haralick(vp(p), 3, 8, vp(p + 8), None) == -1
+    assert lib.glcm_haralick_mcc(vp(p), 3, 8, vp(p + 8), None) == -1
+    other = torch.zeros(1024, dtype=torch.float32, device="cuda")
+    assert lib.glcm_average(vp(p), 3, 8, 2, vp(other.data_ptr()), None) == -1   # K % m != 0
+    assert lib.glcm_average(vp(p), 130, 8, 65, vp(other.data_ptr()), None) == -1  # m > 64
+    torch.cuda.synchronize()
+
+
+def test_histogram_u16_largest_levels_full_size():
+    img = synth.smooth(2048, 2048, 6.0, 4242, dtype=np.uint16)
+    print("[hist] 2048x2048 u16 N=4096", flush=True)
+    got = host(G.glcm_histogram(dev(img), 4096, 0, 65535))
+    assert np.array_equal(got, oracle.histogram(img, 4096, 0, 65535))
