@@ -335,8 +335,8 @@ typedef struct glcm_tile {
  *             4 copies of the K (N+1) x (N+1) matrices in one workgroup's LDS
  *             ((N+1)^2 * K * 16 bytes + 4 K N^2 + 3 KiB <= 159 KiB, e.g. N <= 43
  *             for K = 4), else GLCM_EUNSUPPORTED; images need not be 16-byte
- *             aligned (those that are not are first copied, in one launch,
- *             into plan-owned staging with a 16-byte row pitch).
+ *             aligned (the rows of those that are not are read as aligned
+ *             dwords and shifted into place; nothing is copied).
  *   tiles     host array of T image descriptors (read before returning).
  *   T         number of images, 1 .. 2^20.
  *   lo, hi    quantization range, as in glcm_compute.
@@ -357,9 +357,9 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t *tiles, int 
 /*
  * A batch prepared once and launched many times, e.g. from a HIP graph.
  * glcm_batch_prepare uploads the T descriptors (sorted as in
- * glcm_batch_compute) and reserves an aligned copy of every misaligned image
- * into device memory owned by the returned handle; it takes the plan's dtype,
- * N, offsets and limits at that moment and blocks until the upload is done.
+ * glcm_batch_compute) into device memory owned by the returned handle; it
+ * takes the plan's dtype, N, offsets and limits at that moment and blocks
+ * until the upload is done.
  * The images must stay at their addresses while the handle is used (their
  * pixels may change between launches).  Errors as glcm_batch_compute;
  * GLCM_ENOMEM / GLCM_EHIP.
@@ -368,11 +368,11 @@ typedef struct glcm_batch_s *glcm_batch_t;
 GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t *tiles, int T, glcm_batch_t *batch);
 
 /*
- * Queues the prepared batch on `stream`: the realignment copies (if any) and
- * the fused kernel, nothing else (no copy from host memory, no allocation, no
- * synchronisation, no memset), so the call can be captured into a HIP graph
- * and replayed.  out / features as in glcm_batch_compute.  One handle must not
- * run on two streams at once (its copies are shared).  GLCM_EINVAL for a NULL
+ * Queues the prepared batch on `stream`: the fused kernel, nothing else (no
+ * copy from host memory, no allocation, no synchronisation, no memset), so the
+ * call can be captured into a HIP graph and replayed.  out / features as in
+ * glcm_batch_compute.  The handle's descriptors are only read, so it may run
+ * on several streams at once (into distinct outputs).  GLCM_EINVAL for a NULL
  * handle or out, lo > hi or hi above the dtype maximum; GLCM_EHIP.
  */
 GLCM_API int glcm_batch_run(glcm_batch_t batch, uint32_t lo, uint32_t hi, uint32_t *out, float *features,

@@ -1248,30 +1248,14 @@ bool tile_aligned(const glcm_tile_t& e, int b) {
   return (uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0;
 }
 
-// Staging bytes the misaligned images of a batch need (16-byte row pitch).
-size_t batch_stage_bytes(const glcm_tile_t* tiles, int T, int b, size_t* n_mis) {
-  size_t need = 0, n = 0;
-  for (int t = 0; t < T; ++t) {
-    if (tile_aligned(tiles[t], b)) continue;
-    ++n;
-    need += (((size_t)tiles[t].W * b + 15) & ~(size_t)15) * (size_t)tiles[t].H;
-  }
-  *n_mis = n;
-  return need;
-}
-
-// Fills the descriptors (largest image first) and, after them, the copies of
-// the misaligned images into `stage` (device address); `host` holds
-// T * sizeof(BatchTile) + n_mis * sizeof(RealignDesc) bytes.
-void batch_descriptors(const glcm_tile_t* tiles, int T, int b, const void* stage, void* host) {
+// Fills the descriptors, largest image first; `host` holds T * sizeof(BatchTile) bytes.
+void batch_descriptors(const glcm_tile_t* tiles, int T, int b, void* host) {
   std::vector<int> order((size_t)T);
   for (int t = 0; t < T; ++t) order[(size_t)t] = t;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return (uint64_t)tiles[x].W * (uint64_t)tiles[x].H > (uint64_t)tiles[y].W * (uint64_t)tiles[y].H;
   });
   glcm::BatchTile* d = (glcm::BatchTile*)host;
-  glcm::RealignDesc* rd = (glcm::RealignDesc*)((char*)host + (size_t)T * sizeof(glcm::BatchTile));
-  size_t off = 0, r = 0;
   for (int i = 0; i < T; ++i) {
     const glcm_tile_t& e = tiles[order[(size_t)i]];
     d[i].img = e.img;
@@ -1279,36 +1263,19 @@ void batch_descriptors(const glcm_tile_t* tiles, int T, int b, const void* stage
     d[i].W = e.W;
     d[i].H = e.H;
     d[i].index = order[(size_t)i];
-    d[i].reserved = 0;
-    if (tile_aligned(e, b)) continue;
-    const size_t pitch = ((size_t)e.W * b + 15) & ~(size_t)15;
-    rd[r].src = e.img;
-    rd[r].sstride = e.stride;
-    rd[r].dst_off = off;
-    rd[r].dpitch = (int32_t)(pitch / b);
-    rd[r].W = e.W;
-    rd[r].H = e.H;
-    rd[r].pad = 0;
-    d[i].img = (const char*)stage + off;
-    d[i].stride = (int64_t)(pitch / b);
-    off += pitch * (size_t)e.H;
-    ++r;
+    d[i].unaligned = tile_aligned(e, b) ? 0 : 1;
   }
 }
 
-// Queues the realignment copies (if any) and the fused batch kernel.
-int batch_launch(const BatchLayout& L, int T, const void* desc_dev, size_t n_mis, void* stage, uint32_t N,
-                 uint32_t lo, uint32_t hi, uint32_t* out, float* features, hipStream_t stream) {
+// Queues the fused batch kernel.
+int batch_launch(const BatchLayout& L, int T, const void* desc_dev, uint32_t N, uint32_t lo, uint32_t hi,
+                 uint32_t* out, float* features, hipStream_t stream) {
   glcm::BatchArgs a = L.args;
   a.q = make_quant((int)N, lo, hi);
   fast_quant(L.b, (int)N, lo, hi, &a.qfast, &a.qfast_shift, &a.qfast_mask);
   a.tiles = (const glcm::BatchTile*)desc_dev;
   a.out = out;
   a.feat = features;
-  if (n_mis)
-    GLCM_TRY(glcm::launch_batch_realign(
-        (const glcm::RealignDesc*)((const char*)desc_dev + (size_t)T * sizeof(glcm::BatchTile)), (int)n_mis,
-        (char*)stage, L.b, stream));
   GLCM_TRY(glcm::launch_batch(a, T, L.b, L.smd, L.D, L.lds_bytes, stream));
   return GLCM_OK;
 }
@@ -1328,13 +1295,7 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
   int rc = batch_layout(plan, tiles, T, &L);
   if (rc != GLCM_OK) return rc;
   GLCM_TRY_RC(order_after_previous(plan, stream));
-  // misaligned images are first copied into the plan's staging buffer with a
-  // 16-byte pitch (one realignment launch), so every image takes the strip
-  // path of the batch kernel
-  size_t n_mis = 0;
-  const size_t stage_need = batch_stage_bytes(tiles, T, L.b, &n_mis);
-  if (n_mis) GLCM_TRY_RC(ensure_stage(plan, stage_need));
-  const size_t need = (size_t)T * sizeof(glcm::BatchTile) + n_mis * sizeof(glcm::RealignDesc);
+  const size_t need = (size_t)T * sizeof(glcm::BatchTile);
   if (plan->batch_pending) GLCM_TRY(hipEventSynchronize(plan->batch_uploaded));
   plan->batch_pending = false;
   if (need > plan->batch_cap) {
@@ -1350,12 +1311,11 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
     plan->batch_cap = need;
   }
   if (!plan->batch_uploaded) GLCM_TRY(hipEventCreateWithFlags(&plan->batch_uploaded, hipEventDisableTiming));
-  batch_descriptors(tiles, T, L.b, plan->stage, plan->batch_pin);
+  batch_descriptors(tiles, T, L.b, plan->batch_pin);
   GLCM_TRY(hipMemcpyAsync(plan->batch_dev, plan->batch_pin, need, hipMemcpyHostToDevice, stream));
   GLCM_TRY(hipEventRecord(plan->batch_uploaded, stream));
   plan->batch_pending = true;
-  GLCM_TRY_RC(batch_launch(L, T, plan->batch_dev, n_mis, plan->stage, (uint32_t)plan->N, lo, hi, out, features,
-                           stream));
+  GLCM_TRY_RC(batch_launch(L, T, plan->batch_dev, (uint32_t)plan->N, lo, hi, out, features, stream));
   return record_done(plan, stream);
 }
 
@@ -1364,10 +1324,7 @@ struct glcm_batch_s {
   int T = 0;
   int dtype = 0;
   uint32_t N = 0;
-  size_t n_mis = 0;
-  void* desc = nullptr;   // device: descriptors, then realignment copies
-  void* stage = nullptr;  // device: aligned copies of the misaligned images
-  size_t bytes = 0;
+  void* desc = nullptr;  // device: descriptors
 };
 
 GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t* tiles, int T, glcm_batch_t* batch) {
@@ -1381,21 +1338,17 @@ GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t* tiles, int 
   h->T = T;
   h->dtype = plan->dtype;
   h->N = (uint32_t)plan->N;
-  const size_t stage_need = batch_stage_bytes(tiles, T, h->layout.b, &h->n_mis);
-  const size_t need = (size_t)T * sizeof(glcm::BatchTile) + h->n_mis * sizeof(glcm::RealignDesc);
+  const size_t need = (size_t)T * sizeof(glcm::BatchTile);
   std::vector<char> host(need);
   hipError_t e = hipMalloc(&h->desc, need);
-  if (e == hipSuccess && stage_need) e = hipMalloc(&h->stage, stage_need);
   if (e == hipSuccess) {
-    batch_descriptors(tiles, T, h->layout.b, h->stage, host.data());
+    batch_descriptors(tiles, T, h->layout.b, host.data());
     e = hipMemcpy(h->desc, host.data(), need, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     if (h->desc) (void)hipFree(h->desc);
-    if (h->stage) (void)hipFree(h->stage);
     return hip_status(e);
   }
-  h->bytes = need + stage_need;
   *batch = h.release();
   return GLCM_OK;
 }
@@ -1404,15 +1357,13 @@ GLCM_API int glcm_batch_run(glcm_batch_t batch, uint32_t lo, uint32_t hi, uint32
                             void* stream) {
   if (!batch || !out) return GLCM_EINVAL;
   if (lo > hi || hi > (batch->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
-  return batch_launch(batch->layout, batch->T, batch->desc, batch->n_mis, batch->stage, batch->N, lo, hi, out,
-                      features, (hipStream_t)stream);
+  return batch_launch(batch->layout, batch->T, batch->desc, batch->N, lo, hi, out, features, (hipStream_t)stream);
 }
 
 GLCM_API int glcm_batch_destroy(glcm_batch_t batch) {
   if (!batch) return GLCM_OK;
   (void)hipDeviceSynchronize();  // a queued or captured launch may still read its buffers
   if (batch->desc) (void)hipFree(batch->desc);
-  if (batch->stage) (void)hipFree(batch->stage);
   delete batch;
   return GLCM_OK;
 }

@@ -18,12 +18,13 @@ namespace {
 // Images arrive largest first, so the hardware dispatcher balances the
 // workgroups over the CUs.
 //
-// Images (16-byte aligned: misaligned ones are first copied by
-// k_batch_realign) use the strip machinery with the wavefront split into row
+// Every image uses the strip machinery with the wavefront split into row
 // segments when the image is narrower than 1024 columns: lane l handles chunk
 // l mod cw of segment l / cw (cw = chunks per row), each segment walking its
 // own run of rows; halo pixels outside [0, W) take the sentinel.  Votes go to
-// the strip LDS layout (kp = K GLCMs, D dwords per bin).
+// the strip LDS layout (kp = K GLCMs, D dwords per bin).  Rows of an image
+// whose base or pitch is not 16-byte aligned are assembled from dword loads
+// (load_row_unaligned) instead of 16-byte loads.
 // ---------------------------------------------------------------------------
 template <int MAXDY, int D, int KI, int CUR>
 __device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermRow<MAXDY> (&ring)[MAXDY + 1],
@@ -34,7 +35,51 @@ __device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermR
   }
 }
 
-template <typename Pix, int MAXDY, int D, int CUR>
+// Row loads of an image whose base or row pitch is not 16-byte aligned: the
+// lane's 16-pixel chunk and its 4-pixel halos are assembled from the aligned
+// dwords that span them (v_alignbyte_b32).  Only dwords that hold a byte of
+// the row are read; the others count as zero, and to_terms replaces every
+// pixel outside [0, W) by the sentinel anyway.
+template <typename Pix>
+__device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom& g, int y, int x0) {
+  constexpr int B = (int)sizeof(Pix);
+  constexpr int NC = 4 * B;  // chunk dwords (16 pixels)
+  constexpr int NH = B;      // halo dwords (4 pixels) on each side
+  const uintptr_t r0 = (uintptr_t)((const char*)g.img + (int64_t)min(y, g.H - 1) * g.stride * (int64_t)B);
+  const uint32_t* a0 = (const uint32_t*)(r0 & ~(uintptr_t)3);
+  const uint32_t sh = (uint32_t)(r0 & 3u);  // bytes the row starts past a dword boundary
+  const int lim = g.W * B + (int)sh;       // source dword j holds a byte of the row iff 0 <= j and 4 j < lim
+  const int j0 = x0 * B / 4 - NH;          // source dword of the left halo's first byte
+  uint32_t d[NC + 2 * NH + 1];
+#pragma unroll
+  for (int k = 0; k < NC + 2 * NH + 1; ++k) {
+    const int j = j0 + k;
+    d[k] = (j >= 0 && 4 * j < lim) ? a0[j] : 0u;
+  }
+  // dword m of the halo-chunk-halo run covers row bytes [4 (j0 + m), +4)
+  uint32_t o[NC + 2 * NH];
+#pragma unroll
+  for (int m = 0; m < NC + 2 * NH; ++m) o[m] = __builtin_amdgcn_alignbyte(d[m + 1], d[m], sh);
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    rc.lh[h] = o[h];
+    rc.rh[h] = o[NH + NC + h];
+  }
+#pragma unroll
+  for (int v = 0; v < B; ++v) rc.v[v] = make_uint4(o[NH + 4 * v], o[NH + 4 * v + 1], o[NH + 4 * v + 2], o[NH + 4 * v + 3]);
+}
+
+// UNAL: the image is read by load_row_unaligned (cols unused), else by the
+// 16-byte loads of the strip machinery.
+template <typename Pix, bool UNAL>
+__device__ __forceinline__ void batch_load(RawChunk<Pix>& rc, const Geom& g, int y, int x0, const LaneCols& cols) {
+  if constexpr (UNAL)
+    load_row_unaligned<Pix>(rc, g, y, x0);
+  else
+    load_row<Pix>(rc, g, y, cols);
+}
+
+template <typename Pix, int MAXDY, int D, int CUR, bool UNAL>
 __device__ __forceinline__ void batch_step(const BatchArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
                                            RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, const LaneCols& cols,
                                            uint32_t C, uint32_t n1,
@@ -45,7 +90,54 @@ __device__ __forceinline__ void batch_step(const BatchArgs& a, const Geom& geo, 
   for (int t = 0; t < 16; ++t) fa[t] = mad_u24(ring[CUR].s[MAXDY + t], n1, C);
   batch_vote<MAXDY, D, 0, CUR>(fa, ring, code, a.K, 1u);
   to_terms<Pix, MAXDY, true>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, true);
-  load_row<Pix>(raw[CUR], geo, y + 2 * NR, cols);
+  batch_load<Pix, UNAL>(raw[CUR], geo, y + 2 * NR, x0, cols);
+}
+
+// The votes of one image: lane -> (segment, chunk), every wavefront walking
+// runs of rows of its segments.
+template <typename Pix, int MAXDY, int D, bool UNAL>
+__device__ __forceinline__ void batch_votes(const BatchArgs& a, const BatchTile& t, const Geom& geo, uint32_t C,
+                                            uint32_t n1, uint32_t mb, uint32_t sent4) {
+  constexpr int NR = MAXDY + 1;
+  const int K = a.K;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  int code[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) code[q] = q < K ? a.vcode[q] : -1;
+  const int chunks = (t.W + 15) >> 4;
+  const int cw = min(chunks, 64), segs = 64 / cw, spans = (chunks + 63) >> 6;
+  const int seg = lane / cw, c = lane - seg * cw;
+  const bool live = seg < segs;
+  const int slots = nwaves * segs;  // row segments walked at once by the workgroup
+  const int h = max(a.min_rows, (t.H * spans + slots - 1) / slots);
+  const int blocks = (t.H + segs * h - 1) / (segs * h);
+  for (int u = wave; u < spans * blocks; u += nwaves) {
+    const int span = u % spans, blk = u / spans;
+    const int x0 = live ? ((span << 6) + c) << 4 : spans << 10;  // idle lanes: past the right edge
+    const int ya = (blk * segs + (live ? seg : 0)) * h;
+    TermRow<MAXDY> ring[NR];
+    RawChunk<Pix> raw[NR];
+    LaneCols cols{};
+    if constexpr (!UNAL) cols = lane_cols<Pix>(geo, x0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) batch_load<Pix, UNAL>(raw[r], geo, ya + r, x0, cols);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      to_terms<Pix, MAXDY, true>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb, true);
+      batch_load<Pix, UNAL>(raw[r], geo, ya + NR + r, x0, cols);
+    }
+    // every lane takes h steps; rows past the image or the lane's segment
+    // end carry the sentinel or belong to this segment's own run
+    for (int j = 0; j < h; j += NR) {
+      batch_step<Pix, MAXDY, D, 0, UNAL>(a, geo, ring, raw, ya + j, x0, cols, C, n1, mb, sent4, code);
+      if (j + 1 >= h) break;
+      batch_step<Pix, MAXDY, D, 1, UNAL>(a, geo, ring, raw, ya + j + 1, x0, cols, C, n1, mb, sent4, code);
+      if constexpr (NR > 2) {
+        if (j + 2 >= h) break;
+        batch_step<Pix, MAXDY, D, 2, UNAL>(a, geo, ring, raw, ya + j + 2, x0, cols, C, n1, mb, sent4, code);
+      }
+    }
+  }
 }
 
 template <typename Pix, int MAXDY, int D>
@@ -64,46 +156,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
   const uint32_t sent4 = N * 0x01010101u;
   zero_lds(lds, vote_words);
   __syncthreads();
-
-  {
-    int code[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) code[q] = q < K ? a.vcode[q] : -1;
-    // lane -> (segment, chunk)
-    const int chunks = (t.W + 15) >> 4;
-    const int cw = min(chunks, 64), segs = 64 / cw, spans = (chunks + 63) >> 6;
-    const int seg = lane / cw, c = lane - seg * cw;
-    const bool live = seg < segs;
-    const int slots = nwaves * segs;  // row segments walked at once by the workgroup
-    const int h = max(a.min_rows, (t.H * spans + slots - 1) / slots);
-    const int blocks = (t.H + segs * h - 1) / (segs * h);
-    for (int u = wave; u < spans * blocks; u += nwaves) {
-      const int span = u % spans, blk = u / spans;
-      const int x0 = live ? ((span << 6) + c) << 4 : spans << 10;  // idle lanes: past the right edge
-      const int ya = (blk * segs + (live ? seg : 0)) * h;
-      TermRow<MAXDY> ring[NR];
-      RawChunk<Pix> raw[NR];
-      const LaneCols cols = lane_cols<Pix>(geo, x0);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        to_terms<Pix, MAXDY, true>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb, true);
-        load_row<Pix>(raw[r], geo, ya + NR + r, cols);
-      }
-      // every lane takes h steps; rows past the image or the lane's segment
-      // end carry the sentinel or belong to this segment's own run
-      for (int j = 0; j < h; j += NR) {
-        batch_step<Pix, MAXDY, D, 0>(a, geo, ring, raw, ya + j, x0, cols, C, n1, mb, sent4, code);
-        if (j + 1 >= h) break;
-        batch_step<Pix, MAXDY, D, 1>(a, geo, ring, raw, ya + j + 1, x0, cols, C, n1, mb, sent4, code);
-        if constexpr (NR > 2) {
-          if (j + 2 >= h) break;
-          batch_step<Pix, MAXDY, D, 2>(a, geo, ring, raw, ya + j + 2, x0, cols, C, n1, mb, sent4, code);
-        }
-      }
-    }
-  }
+  if (t.unaligned)
+    batch_votes<Pix, MAXDY, D, true>(a, t, geo, C, n1, mb, sent4);
+  else
+    batch_votes<Pix, MAXDY, D, false>(a, t, geo, C, n1, mb, sent4);
 
   // merge: consecutive 16-byte units, D / 4 lanes per bin, into out and into
   // an LDS copy for the statistics
@@ -145,57 +201,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
     glcm_features_wg(merged + k * NN, N, a.feat + ((size_t)t.index * K + k) * 5, redu, redf);
 }
 
-// Copies each misaligned image of a batch into the staging buffer with a
-// 16-byte row pitch, so the batch kernel reads every image with 16-byte
-// loads.  One workgroup per image; a thread makes one 16-byte group of a
-// destination row from the (up to) five aligned source dwords that span it
-// (v_alignbyte), reading only dwords that hold a byte of the row, zeroes the
-// bytes past W and stores the group whole.  (row, group) advance by the
-// mixed-radix digits of blockDim: no division.
-template <typename Pix>
-__global__ __launch_bounds__(256) void k_batch_realign(const RealignDesc* d, char* stage) {
-  const RealignDesc e = d[blockIdx.x];
-  uint4* dst = (uint4*)(stage + e.dst_off);
-  const uint32_t rowbytes = (uint32_t)e.W * (uint32_t)sizeof(Pix);
-  const uint32_t gw = (rowbytes + 15u) / 16u;                           // groups of a row that hold pixels
-  const uint32_t gpitch = (uint32_t)e.dpitch * (uint32_t)sizeof(Pix) / 16u;  // groups per copy row
-  const uint32_t sy = blockDim.x / gw, sg = blockDim.x % gw;
-  uint32_t y = threadIdx.x / gw, g = threadIdx.x % gw;
-  while (y < (uint32_t)e.H) {
-    const uintptr_t r0 = (uintptr_t)((const char*)e.src + (int64_t)y * e.sstride * (int64_t)sizeof(Pix));
-    const uint32_t* a0 = (const uint32_t*)(r0 & ~(uintptr_t)3);
-    const uint32_t sh = (uint32_t)(r0 & 3u);  // bytes the row starts past a dword boundary
-    // source dword 4g + i spans row bytes [16g + 4i - sh, 16g + 4i + 4 - sh)
-    uint32_t a[5];
-#pragma unroll
-    for (uint32_t i = 0; i < 5; ++i) a[i] = 16u * g + 4u * i < rowbytes + sh ? a0[4u * g + i] : 0u;
-    uint32_t v[4];
-#pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) {
-      v[i] = sh ? __builtin_amdgcn_alignbyte(a[i + 1], a[i], sh) : a[i];
-      const int32_t left = (int32_t)rowbytes - (int32_t)(16u * g + 4u * i);  // row bytes from this dword on
-      if (left <= 0) v[i] = 0u;
-      else if (left < 4) v[i] &= (1u << (8u * (uint32_t)left)) - 1u;
-    }
-    dst[(size_t)y * gpitch + g] = make_uint4(v[0], v[1], v[2], v[3]);
-    g += sg;
-    y += sy;
-    if (g >= gw) {
-      g -= gw;
-      ++y;
-    }
-  }
-}
-
 }  // namespace
-
-hipError_t launch_batch_realign(const RealignDesc* d, int n, char* stage, int dtype_bytes, hipStream_t stream) {
-  if (dtype_bytes == 1)
-    hipLaunchKernelGGL(k_batch_realign<uint8_t>, dim3(n), dim3(256), 0, stream, d, stage);
-  else
-    hipLaunchKernelGGL(k_batch_realign<uint16_t>, dim3(n), dim3(256), 0, stream, d, stage);
-  return hipGetLastError();
-}
 
 template <typename Pix, int MAXDY>
 static hipError_t launch_batch_t(const BatchArgs& a, int T, int D, size_t lds_bytes, hipStream_t stream) {

@@ -66,17 +66,7 @@ struct BatchTile {
   int64_t stride;   // elements
   int32_t W, H;
   int32_t index;    // slot of this image in the caller's order (output position)
-  int32_t reserved; // base and row pitch are 16-byte aligned (misaligned images are copied first)
-};
-
-// One misaligned image of a batch to copy into the staging buffer (40 bytes).
-struct RealignDesc {
-  const void* src;   // device pixels, any alignment of the pixel type
-  int64_t sstride;   // source row pitch, elements
-  uint64_t dst_off;  // byte offset of the copy in the staging buffer (16-byte aligned)
-  int32_t dpitch;    // copy row pitch, elements (a multiple of 16 bytes)
-  int32_t W, H;
-  int32_t pad;
+  int32_t unaligned; // 1: base or row pitch not 16-byte aligned (rows read as dwords), else 0
 };
 
 // Arguments of the fused batch kernel (quantize, vote, merge, features per
@@ -129,8 +119,6 @@ hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipSt
 hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, size_t lds_bytes,
                         hipStream_t stream);
 constexpr int kBatchThreads = 256;
-// Copies the n misaligned images described by d into stage (one workgroup each).
-hipError_t launch_batch_realign(const RealignDesc* d, int n, char* stage, int dtype_bytes, hipStream_t stream);
 inline size_t batch_lds_bytes(int N, int K, int D) {
   const size_t n1 = (size_t)N + 1u;
   // vote copies, merged counts, 8-byte alignment pad, u64 + f32 reduction scratch

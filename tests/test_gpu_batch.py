@@ -106,6 +106,18 @@ def test_batch_misaligned_and_strided_views():
     run_batch(imgs, 16, 0, 255, synth.offsets_for([1]), views=views)
 
 
+@pytest.mark.parametrize("dt,N,lo,hi", [(np.uint8, 32, 0, 255), (np.uint16, 24, 0, 4095)])
+def test_batch_misaligned_wide_views(dt, N, lo, hi):
+    """Views whose base and row pitch are not 16-byte aligned, wider than one
+    wavefront's 1024 columns, with reach-2 offsets."""
+    base = synth.smooth(150, 2300, 5.0, 950, dt, noise_frac=0.05)
+    tb = to_device(base)
+    cuts = [(0, 150, 1, 2300), (2, 149, 3, 1030), (5, 60, 7, 1029), (1, 90, 1001, 2299), (9, 10, 11, 12)]
+    imgs = [base[y0:y1, x0:x1] for y0, y1, x0, x1 in cuts]
+    views = [tb[y0:y1, x0:x1] for y0, y1, x0, x1 in cuts]
+    run_batch(imgs, N, lo, hi, synth.offsets_for([2]), views=views)
+
+
 def test_batch_without_features_and_plan_reuse():
     offs = synth.offsets_for([1])
     plan = G.glcm_plan_create(np.uint8, 16, offs, 512, 512)
