@@ -425,10 +425,16 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
     } else {
       uint64_t P1 = (words + budget - 1) / budget;
       if (p->flags & GLCM_FLAG_FORCE_PARTITIONED) P1 = std::max<uint64_t>(P1, std::min<uint64_t>(words, 3));
-      if (P1 > 16) {
+      // the passes the partitioned kernel runs: half as many with 16-bit
+      // counters, which need the XCD slices and rows below 2^16 pixels
+      const bool c16 = P1 > 1 && l2_slices_fit(p) && p->max_W <= 65535;
+      const uint64_t passes = c16 ? (words + 2 * budget - 1) / (2 * budget) : P1;
+      if (passes > 16) {
         // more LDS passes than pay off: pairs straight into the per-XCD
         // slices when they fit (never slower than device-wide atomics on
-        // MI355X, faster on smooth images), else device-wide atomics
+        // MI355X, faster on smooth images), else device-wide atomics.
+        // Measured on MI355X, 4096^2 u8 at N = 256 with 12 offsets: 10
+        // 16-bit passes beat the slices 6-10x (smooth and noise images).
         d.path = l2_slices_fit(p) ? kPathL2 : kPathGlobal;
         d.replicas = 1;
         d.partitions = 1;
@@ -1021,9 +1027,9 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
     const uint64_t words = (uint64_t)plan->K * plan->N * plan->N, budget = (uint64_t)plan->lds_budget_words;
     for (int R = 1; R <= 16; R *= 2) {
       const uint64_t P = (words * R + budget - 1) / budget;
-      if (P > 16) continue;
       for (int bits : {32, 16}) {
         if (bits == 16 && (R != 1 || P < 2)) continue;  // 16-bit bins: one copy, several passes
+        if ((bits == 16 ? (P + 1) / 2 : P) > 16) continue;  // image passes the kernel would run
         for (int wg : {256, 512, 1024}) {
           glcm_tuning_t t = start;
           t.replicas = R;
