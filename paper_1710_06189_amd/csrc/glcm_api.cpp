@@ -361,6 +361,13 @@ bool l2_slices_fit(const glcm_plan_s* p) {
   return (uint64_t)glcm::kXcdSlots * (uint64_t)p->k_cap * (uint64_t)p->N * (uint64_t)p->N * 4ull <= (256ull << 20);
 }
 
+// Image passes of the partitioned kernel worth one GLCM's pairs added into
+// the per-XCD L2 slices: measured on MI355X, 4096^2 u8 images, a pass costs
+// 0.04-0.05 ms and a GLCM in the slices 0.63 ms on noise (more on smooth
+// images, where the slice atomics collide: 0.5-1.5 ms).  The slices take
+// over beyond this many passes per GLCM.
+constexpr int kPassesPerSliceGlcm = 13;
+
 int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   // Path and LDS layout for this plan's (dtype, N, K, offsets, flags).
   const uint32_t NN = (uint32_t)p->N * (uint32_t)p->N;
@@ -429,12 +436,10 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
       // counters, which need the XCD slices and rows below 2^16 pixels
       const bool c16 = P1 > 1 && l2_slices_fit(p) && p->max_W <= 65535;
       const uint64_t passes = c16 ? (words + 2 * budget - 1) / (2 * budget) : P1;
-      if (passes > 16) {
+      if (passes > (uint64_t)kPassesPerSliceGlcm * (uint64_t)p->K) {
         // more LDS passes than pay off: pairs straight into the per-XCD
         // slices when they fit (never slower than device-wide atomics on
-        // MI355X, faster on smooth images), else device-wide atomics.
-        // Measured on MI355X, 4096^2 u8 at N = 256 with 12 offsets: 10
-        // 16-bit passes beat the slices 6-10x (smooth and noise images).
+        // MI355X, faster on smooth images), else device-wide atomics
         d.path = l2_slices_fit(p) ? kPathL2 : kPathGlobal;
         d.replicas = 1;
         d.partitions = 1;
@@ -1029,7 +1034,7 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
       const uint64_t P = (words * R + budget - 1) / budget;
       for (int bits : {32, 16}) {
         if (bits == 16 && (R != 1 || P < 2)) continue;  // 16-bit bins: one copy, several passes
-        if ((bits == 16 ? (P + 1) / 2 : P) > 16) continue;  // image passes the kernel would run
+        if ((bits == 16 ? (P + 1) / 2 : P) > (uint64_t)kPassesPerSliceGlcm * (uint64_t)plan->K) continue;
         for (int wg : {256, 512, 1024}) {
           glcm_tuning_t t = start;
           t.replicas = R;

@@ -490,6 +490,8 @@ def test_misaligned_large_views_staged(dtype, offs):
     (256, np.uint8, (700, 300), synth.offsets_for([1, 2, 4])[:9]),
     (256, np.uint8, (301, 1500), synth.offsets_for([1, 2, 4])),        # 12 GLCMs: 10 passes of 16-bit bins
     (400, np.uint16, (130, 700), [(1, 0), (0, 1), (1, 1), (-1, 1), (2, 0)]),  # 5 GLCMs of 160000 bins: 10 passes
+    (1024, np.uint8, (150, 900), [(1, 0), (-2, 2)]),                    # 2 GLCMs of 2^20 bins: 26 passes
+    (1024, np.uint16, (90, 700), synth.offsets_for([1])),               # 4 GLCMs of 2^20 bins: 52 passes
     (400, np.uint16, (257, 1030), [(1, 0), (-2, 3), (0, -4)]),
     (256, np.uint8, (1, 70000), [(1, 0), (3, 0)]),                      # one row wider than 2^16
 ])
