@@ -140,7 +140,7 @@ def main():
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
     ap.add_argument("--workload", default="square",
-                    choices=["square", "multispectral", "batch", "serving", "histogram", "variants"],
+                    choices=["square", "multispectral", "batch", "serving", "histogram", "variants", "large_n"],
                     help="square: the 4096^2 device-resident image (the default line); multispectral: "
                          "the 8-band 8192^2 uint16 stack streamed from pinned host memory")
     ap.add_argument("--bands", type=int, default=8)
@@ -178,6 +178,9 @@ def main():
         return
     if args.workload == "variants":
         bench_variants(args, G, torch, np, oracle, synth, dev)
+        return
+    if args.workload == "large_n":
+        bench_large_n(args, G, torch, np, oracle, synth, dev)
         return
     oracle_cache, image_cache = {}, {}
     fixed = None
@@ -495,6 +498,57 @@ def time_oracle(fn, seconds):
         el = time.perf_counter() - t0
         if el >= seconds:
             return reps, el
+
+
+def bench_large_n(args, G, torch, np, oracle, synth, dev):
+    """GLCMs too large for one workgroup's LDS: 4096x4096 uint8 smooth and
+    noise images at N = 256 with all 12 offsets (d = 1, 2, 4) and N = 1024
+    with 2, N = 1536 with 1, each with the plan's default path (bin
+    partitions over several image passes, or pairs added straight into the
+    per-XCD L2 slices).  Every configuration's counts are checked bit-exact
+    against the oracle; times are HIP events around `steps` calls."""
+    all12 = synth.offsets_for([1, 2, 4])
+    cases = [(256, all12), (1024, all12[:2]), (1536, all12[:1])]
+    stream = torch.cuda.current_stream()
+    rows, pairs_total, ms_total = [], 0, 0.0
+    steps = max(1, min(args.steps, 50))
+    for kind in ("smooth", "uniform"):
+        img = synth.square_4096(kind)["images"][0]
+        H, W = img.shape
+        t = torch.from_numpy(img).to(dev)
+        for N, offs in cases:
+            plan = G.glcm_plan_create(np.uint8, N, offs, W, H)
+            tun = plan.tuning
+            out = torch.empty((len(offs), N, N), dtype=torch.int32, device=dev)
+            print(f"[large_n] {kind} N={N} K={len(offs)} path={G.PATH_NAMES[tun.path]}", flush=True)
+            for _ in range(min(args.warmup, 5)):
+                G.glcm_compute(t, N, 0, 255, offs, out=out, stream=stream, plan=plan)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                G.glcm_compute(t, N, 0, 255, offs, out=out, stream=stream, plan=plan)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            want = oracle.glcm(img, N, 0, 255, offs)
+            if not np.array_equal(out.cpu().numpy().view(np.uint32), want):
+                raise SystemExit(f"bench: large-N counts differ from the oracle ({kind}, N={N}, K={len(offs)})")
+            pairs = int(want.sum(dtype=np.uint64))
+            pairs_total += pairs
+            ms_total += ms
+            passes = tun.partitions if tun.counter_bits == 32 else (tun.partitions + 1) // 2
+            rows.append({"image": kind, "N": N, "K": len(offs), "path": G.PATH_NAMES[tun.path],
+                         "image_passes": passes if tun.path == 2 else 1, "counter_bits": tun.counter_bits,
+                         "ms": ms, "gpairs_s": pairs / (ms * 1e-3) / 1e9})
+            plan.close()
+    print(json.dumps({
+        "metric": "large-N GLCM Gpairs/s (bit-exact)", "value": pairs_total / (ms_total * 1e-3) / 1e9,
+        "unit": "Gpairs/s", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 5), "ms_per_step": ms_total,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "4096x4096-u8-smooth+noise-N256K12-N1024K2-N1536K1", "resident": "device"},
+        "roofline": None, "cpu_baseline": None,
+        "extra": {"cases": rows, "check": "every case bit-exact against the oracle"},
+    }), flush=True)
 
 
 def bench_histogram(args, G, torch, np, oracle, synth, dev):
