@@ -485,6 +485,26 @@ def test_misaligned_large_views_staged(dtype, offs):
         plan.close()
 
 
+@pytest.mark.parametrize("N,K,W,path", [
+    (256, 12, 4096, "partitioned"),    # 10 passes of 16-bit bins
+    (1024, 2, 4096, "partitioned"),    # 26 passes: 13 per GLCM
+    (1024, 4, 4096, "partitioned"),    # 52 passes: 13 per GLCM
+    (1280, 1, 4096, "l2"),             # 21 passes for one GLCM
+    (2048, 1, 4096, "l2"),
+    (1024, 2, 70000, "l2"),            # rows too long for 16-bit bands: 52 passes of 32-bit bins
+])
+def test_large_n_path_choice(N, K, W, path):
+    """LDS bin partitions while they cost at most 13 image passes per GLCM
+    (counted as the kernel runs them), else pairs straight into the per-XCD
+    L2 slices.  Plan creation only."""
+    offs = synth.offsets_for([1, 2, 4])[:K]
+    plan = G.glcm_plan_create(np.uint8, N, offs, W, 64)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == path, plan.tuning.as_dict()
+    finally:
+        plan.close()
+
+
 @pytest.mark.parametrize("N,dtype,shape,offs", [
     (256, np.uint8, (60, 8200), synth.offsets_for([1, 2, 4])[:6]),   # bands of 7 rows (W > 4369)
     (256, np.uint8, (700, 300), synth.offsets_for([1, 2, 4])[:9]),
