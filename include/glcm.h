@@ -389,7 +389,7 @@ GLCM_API int glcm_batch_destroy(glcm_batch_t batch);
  *   replicas  LDS copies (dwords) of every bin: 4, 8 or 16; 0 = the default
  *             rule (the most that leave room for three workgroups per CU).
  *             More copies mean fewer colliding votes but a heavier merge.
- *   min_rows  shortest run of rows a wavefront segment walks, 1 .. 256; 0 = 8.
+ *   min_rows  shortest run of rows a wavefront segment walks, 1 .. 256; 0 = 4.
  *             Shorter runs spread a small image over more wavefronts; longer
  *             runs cut the per-run set-up.
  *   wg_size   read-only: threads per workgroup (256).
