@@ -348,8 +348,11 @@ typedef struct glcm_tile {
  * by the next batch call after this one's upload has completed.  Errors:
  * GLCM_EINVAL (nothing queued) for NULL pointers, T out of range, a tile with
  * W or H < 1, W > max_W, H > max_H, stride < W, W*H > 2^32-1 or a misaligned
- * img, lo > hi or hi above the dtype maximum; GLCM_EUNSUPPORTED as above;
- * GLCM_EHIP / GLCM_ENOMEM on HIP failures while queueing.
+ * img, a tile that is not inside one device allocation of the current device
+ * (host memory included), out or features not device memory of the current
+ * device, out or features overlapping a tile or each other, lo > hi or hi
+ * above the dtype maximum; GLCM_EUNSUPPORTED as above; GLCM_EHIP /
+ * GLCM_ENOMEM on HIP failures while queueing.
  */
 GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t *tiles, int T, uint32_t lo, uint32_t hi,
                                 uint32_t *out, float *features, void *stream);
@@ -361,7 +364,8 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t *tiles, int 
  * takes the plan's dtype, N, offsets and limits at that moment and blocks
  * until the upload is done.
  * The images must stay at their addresses while the handle is used (their
- * pixels may change between launches).  Errors as glcm_batch_compute;
+ * pixels may change between launches).  Errors as glcm_batch_compute (the
+ * tiles are checked here, the outputs at each glcm_batch_run);
  * GLCM_ENOMEM / GLCM_EHIP.
  */
 typedef struct glcm_batch_s *glcm_batch_t;
@@ -373,12 +377,19 @@ GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t *tiles, int 
  * call can be captured into a HIP graph and replayed.  out / features as in
  * glcm_batch_compute.  The handle's descriptors are only read, so it may run
  * on several streams at once (into distinct outputs).  GLCM_EINVAL for a NULL
- * handle or out, lo > hi or hi above the dtype maximum; GLCM_EHIP.
+ * handle or out, out or features not device memory of the current device or
+ * overlapping a tile or each other, lo > hi or hi above the dtype maximum;
+ * GLCM_EHIP.
  */
 GLCM_API int glcm_batch_run(glcm_batch_t batch, uint32_t lo, uint32_t hi, uint32_t *out, float *features,
                             void *stream);
 
-/* Waits for the device to go idle, then releases the handle.  NULL is accepted. */
+/*
+ * Waits for the last launch glcm_batch_run queued outside a graph capture,
+ * then releases the handle.  Launches still running on other streams, and
+ * graphs that replay a captured launch, must have completed before this call
+ * (the caller synchronises them).  NULL is accepted.
+ */
 GLCM_API int glcm_batch_destroy(glcm_batch_t batch);
 
 /*

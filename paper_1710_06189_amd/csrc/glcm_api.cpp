@@ -223,7 +223,7 @@ struct glcm_plan_s {
   bool batch_pending = false;
 
   // batch kernel layout: LDS copies per bin (0: the default rule) and the
-  // shortest run of rows a wavefront segment walks (0: 8); glcm_batch_tuning
+  // shortest run of rows a wavefront segment walks (0: kBatchDefaultMinRows, 4); glcm_batch_tuning
   int batch_D = 0, batch_min_rows = 0;
 
   // GLCM_FLAG_TIMING: events around every counting-kernel launch
@@ -795,7 +795,9 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
 
 // Host-resident image: uploads it in tiles of `tile_rows` first-pixel rows,
 // each with the halo rows its offsets reach (the 2-D form of the chunk bounds
-// of Eq. (7)-(9): a tile owns the pairs whose first pixel lies in its rows),
+// of Eq. (7)-(9): a tile owns the pairs whose first pixel lies in its rows,
+// or, on the kernels that count an upward offset as its opposite, whose upper
+// pixel does),
 // through two pinned staging slots and two device tile buffers.  Copies run on
 // the plan's upload stream and counting on `stream`, so the upload of tile
 // t+1 overlaps the counting of tile t (Section III); tile results are summed
@@ -805,7 +807,12 @@ int count_host(glcm_plan_t p, const void* img, bool pinned, int W, int H, int64_
                uint32_t* out, hipStream_t stream) {
   const int b = dtype_bytes(p->dtype);
   const Canon c = canonicalize(p->offsets, p->K);
-  const int up = std::min(c.up, H), down = std::min(c.down, H);
+  // Halo rows: the generic, partitioned, L2 and global kernels pair a first
+  // pixel in the tile with the pixel dy rows away, so they need max(-dy)
+  // rows above and max(dy) below; the strip and slab kernels count an offset
+  // with dy < 0 as its opposite from the upper pixel, so they need max|dy|
+  // rows below.  The tile carries both (extra rows are never first pixels).
+  const int up = std::min(c.up, H), down = std::min(std::max(c.down, c.maxdy), H);
   const int T = std::max(1, p->tuning.tile_rows);
   const bool serial = (p->flags & GLCM_FLAG_SERIAL_UPLOAD) != 0;
   // device rows padded to 256 bytes so the row kernel's alignment holds
@@ -1264,6 +1271,70 @@ bool tile_aligned(const glcm_tile_t& e, int b) {
   return (uintptr_t)e.img % 16u == 0 && ((uint64_t)e.stride * (uint64_t)b) % 16u == 0;
 }
 
+// Byte range [first, end) of a tile's pixels.
+std::pair<uintptr_t, uintptr_t> tile_extent(const glcm_tile_t& e, int b) {
+  const uintptr_t i0 = (uintptr_t)e.img;
+  return {i0, i0 + (uintptr_t)(((uint64_t)(e.H - 1) * (uint64_t)e.stride + (uint64_t)e.W) * (uint64_t)b)};
+}
+
+// Every tile must lie inside one device allocation of the current device (the
+// kernel reads it with plain loads; a host pointer would fault the GPU).
+// Allocations are looked up once each (hipMemGetAddressRange), then tiles
+// inside a known allocation cost one map lookup.
+int check_tile_memory(const glcm_tile_t* tiles, int T, int b) {
+  int cur = 0;
+  GLCM_TRY(hipGetDevice(&cur));
+  std::map<uintptr_t, uintptr_t> known;  // allocation base -> end
+  for (int t = 0; t < T; ++t) {
+    const auto x = tile_extent(tiles[t], b);
+    auto it = known.upper_bound(x.first);
+    if (it != known.begin() && x.first >= std::prev(it)->first && x.second <= std::prev(it)->second) continue;
+    int dev = -1;
+    if (pointer_kind(tiles[t].img, &dev) != 2 || dev != cur) return GLCM_EINVAL;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)tiles[t].img) != hipSuccess) {
+      (void)hipGetLastError();
+      return GLCM_EINVAL;
+    }
+    const uintptr_t a0 = (uintptr_t)base, a1 = a0 + size;
+    if (x.first < a0 || x.second > a1) return GLCM_EINVAL;
+    known[a0] = a1;
+  }
+  return GLCM_OK;
+}
+
+// No tile may overlap [o0, o1) (an output the kernel writes while it reads
+// the tiles).
+bool tiles_clear_of(const std::vector<std::pair<uintptr_t, uintptr_t>>& ext, uintptr_t o0, uintptr_t o1) {
+  for (const auto& x : ext)
+    if (x.first < o1 && o0 < x.second) return false;
+  return true;
+}
+
+// Output pointers of a batch launch: device memory of the current device,
+// clear of every tile.
+int check_batch_outputs(const std::vector<std::pair<uintptr_t, uintptr_t>>& ext, int T, int K, int N,
+                        const uint32_t* out, const float* features) {
+  int cur = 0, dev = -1;
+  GLCM_TRY(hipGetDevice(&cur));
+  if (pointer_kind(out, &dev) != 2 || dev != cur) return GLCM_EINVAL;
+  if (features && (pointer_kind(features, &dev) != 2 || dev != cur)) return GLCM_EINVAL;
+  const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (uintptr_t)T * (uintptr_t)K * (uintptr_t)N * (uintptr_t)N * 4u;
+  if (!tiles_clear_of(ext, o0, o1)) return GLCM_EINVAL;
+  if (features) {
+    const uintptr_t f0 = (uintptr_t)features, f1 = f0 + (uintptr_t)T * (uintptr_t)K * 5u * 4u;
+    if (!tiles_clear_of(ext, f0, f1) || (f0 < o1 && o0 < f1)) return GLCM_EINVAL;
+  }
+  return GLCM_OK;
+}
+
+std::vector<std::pair<uintptr_t, uintptr_t>> tile_extents(const glcm_tile_t* tiles, int T, int b) {
+  std::vector<std::pair<uintptr_t, uintptr_t>> ext((size_t)T);
+  for (int t = 0; t < T; ++t) ext[(size_t)t] = tile_extent(tiles[t], b);
+  return ext;
+}
+
 // Fills the descriptors, largest image first; `host` holds T * sizeof(BatchTile) bytes.
 void batch_descriptors(const glcm_tile_t* tiles, int T, int b, void* host) {
   std::vector<int> order((size_t)T);
@@ -1302,14 +1373,13 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
                                 uint32_t* out, float* features, void* stream_) {
   if (!plan || !tiles || !out || T < 1 || T > (1 << 20)) return GLCM_EINVAL;  // before touching the plan
   if (lo > hi || hi > (plan->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
-  int dev = -1;
-  if (pointer_kind(out, &dev) != 2) return GLCM_EINVAL;
-  if (features && pointer_kind(features, &dev) != 2) return GLCM_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;
   std::lock_guard<std::mutex> lk(plan->mu);
   BatchLayout L;
   int rc = batch_layout(plan, tiles, T, &L);
   if (rc != GLCM_OK) return rc;
+  GLCM_TRY_RC(check_tile_memory(tiles, T, L.b));
+  GLCM_TRY_RC(check_batch_outputs(tile_extents(tiles, T, L.b), T, plan->K, plan->N, out, features));
   GLCM_TRY_RC(order_after_previous(plan, stream));
   const size_t need = (size_t)T * sizeof(glcm::BatchTile);
   if (plan->batch_pending) GLCM_TRY(hipEventSynchronize(plan->batch_uploaded));
@@ -1340,7 +1410,12 @@ struct glcm_batch_s {
   int T = 0;
   int dtype = 0;
   uint32_t N = 0;
+  int K = 0;
   void* desc = nullptr;  // device: descriptors
+  std::vector<std::pair<uintptr_t, uintptr_t>> extents;  // the tiles' byte ranges (output checks)
+  std::mutex mu;
+  hipEvent_t ran = nullptr;  // recorded after each launch queued outside a graph capture
+  bool has_ran = false;
 };
 
 GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t* tiles, int T, glcm_batch_t* batch) {
@@ -1351,18 +1426,23 @@ GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t* tiles, int 
   std::lock_guard<std::mutex> lk(plan->mu);
   int rc = batch_layout(plan, tiles, T, &h->layout);
   if (rc != GLCM_OK) return rc;
+  GLCM_TRY_RC(check_tile_memory(tiles, T, h->layout.b));
   h->T = T;
   h->dtype = plan->dtype;
   h->N = (uint32_t)plan->N;
+  h->K = plan->K;
+  h->extents = tile_extents(tiles, T, h->layout.b);
   const size_t need = (size_t)T * sizeof(glcm::BatchTile);
   std::vector<char> host(need);
-  hipError_t e = hipMalloc(&h->desc, need);
+  hipError_t e = hipEventCreateWithFlags(&h->ran, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&h->desc, need);
   if (e == hipSuccess) {
     batch_descriptors(tiles, T, h->layout.b, host.data());
     e = hipMemcpy(h->desc, host.data(), need, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     if (h->desc) (void)hipFree(h->desc);
+    if (h->ran) (void)hipEventDestroy(h->ran);
     return hip_status(e);
   }
   *batch = h.release();
@@ -1370,16 +1450,38 @@ GLCM_API int glcm_batch_prepare(glcm_plan_t plan, const glcm_tile_t* tiles, int 
 }
 
 GLCM_API int glcm_batch_run(glcm_batch_t batch, uint32_t lo, uint32_t hi, uint32_t* out, float* features,
-                            void* stream) {
+                            void* stream_) {
   if (!batch || !out) return GLCM_EINVAL;
   if (lo > hi || hi > (batch->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
-  return batch_launch(batch->layout, batch->T, batch->desc, batch->N, lo, hi, out, features, (hipStream_t)stream);
+  GLCM_TRY_RC(check_batch_outputs(batch->extents, batch->T, batch->K, (int)batch->N, out, features));
+  hipStream_t stream = (hipStream_t)stream_;
+  GLCM_TRY_RC(batch_launch(batch->layout, batch->T, batch->desc, batch->N, lo, hi, out, features, stream));
+  // remember the launch for glcm_batch_destroy (a launch captured into a
+  // graph is the caller's to wait for)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    cs = hipStreamCaptureStatusActive;  // unknown: record nothing
+  }
+  if (cs == hipStreamCaptureStatusNone) {
+    std::lock_guard<std::mutex> lk(batch->mu);
+    GLCM_TRY(hipEventRecord(batch->ran, stream));
+    batch->has_ran = true;
+  }
+  return GLCM_OK;
 }
 
 GLCM_API int glcm_batch_destroy(glcm_batch_t batch) {
   if (!batch) return GLCM_OK;
-  (void)hipDeviceSynchronize();  // a queued or captured launch may still read its buffers
+  {
+    // the last launch queued through glcm_batch_run may still read the
+    // descriptors (on one stream per run, launches complete in order; runs on
+    // several streams at once are the caller's to wait for, as are graphs)
+    std::lock_guard<std::mutex> lk(batch->mu);
+    if (batch->has_ran) (void)hipEventSynchronize(batch->ran);
+  }
   if (batch->desc) (void)hipFree(batch->desc);
+  if (batch->ran) (void)hipEventDestroy(batch->ran);
   delete batch;
   return GLCM_OK;
 }
@@ -1431,12 +1533,7 @@ GLCM_API int glcm_histogram(glcm_plan_t plan, const void* img, int W, int H, int
   a.D = 32;
   while (a.D > 1 && (uint64_t)N * a.D * 4u > 65536u) a.D >>= 1;
   a.cpr = (uint32_t)((W + 15) / 16);
-  const uint64_t chunks = (uint64_t)H * a.cpr;
-  // at least two chunks per thread, at most one workgroup per CU
-  const uint64_t want = (chunks + 2u * glcm::kHistThreads - 1u) / (2u * glcm::kHistThreads);
-  int groups = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)plan->num_cus));
-  a.per_block = (chunks + groups - 1) / groups;
-  groups = (int)((chunks + a.per_block - 1) / a.per_block);
+  const int groups = glcm::hist_geometry((uint64_t)H * a.cpr, plan->num_cus, &a.per_block);
   GLCM_TRY_RC(ensure_partials(plan, (size_t)groups * N * 4u));
   a.partials = plan->partials;
   glcm::LaunchTiming tm;

@@ -45,16 +45,15 @@ __device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom
   constexpr int B = (int)sizeof(Pix);
   constexpr int NC = 4 * B;  // chunk dwords (16 pixels)
   constexpr int NH = B;      // halo dwords (4 pixels) on each side
-  const uintptr_t r0 = (uintptr_t)((const char*)g.img + (int64_t)min(y, g.H - 1) * g.stride * (int64_t)B);
-  const uint32_t* a0 = (const uint32_t*)(r0 & ~(uintptr_t)3);
-  const uint32_t sh = (uint32_t)(r0 & 3u);  // bytes the row starts past a dword boundary
-  const int lim = g.W * B + (int)sh;       // source dword j holds a byte of the row iff 0 <= j and 4 j < lim
-  const int j0 = x0 * B / 4 - NH;          // source dword of the left halo's first byte
+  const UnalignedRow u = unaligned_row<Pix>(g, y, x0);
+  const uint32_t* a0 = (const uint32_t*)u.a0;
+  const uint32_t sh = u.sh;
+  static_assert(NC + 2 * NH + 1 == unaligned_row_dwords<Pix>(), "dwords per unaligned row");
   uint32_t d[NC + 2 * NH + 1];
 #pragma unroll
   for (int k = 0; k < NC + 2 * NH + 1; ++k) {
-    const int j = j0 + k;
-    d[k] = (j >= 0 && 4 * j < lim) ? a0[j] : 0u;
+    const int j = u.j0 + k;
+    d[k] = unaligned_dword_in_row(j, u.lim) ? a0[j] : 0u;
   }
   // dword m of the halo-chunk-halo run covers row bytes [4 (j0 + m), +4)
   uint32_t o[NC + 2 * NH];

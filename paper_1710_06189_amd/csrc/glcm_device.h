@@ -129,9 +129,12 @@ struct LaneCols {
   uint32_t c, c2, l, r;
 };
 
+// (The address helpers below are also compiled for the host, where a CPU
+// test replays every lane's loads against the image bounds.)
 template <typename Pix>
-__device__ __forceinline__ LaneCols lane_cols(const Geom& a, int x0) {
-  const int xc = min(x0, (a.W - 1) & ~15);
+__host__ __device__ inline LaneCols lane_cols(const Geom& a, int x0) {
+  const int last = (a.W - 1) & ~15;
+  const int xc = x0 < last ? x0 : last;
   const int xl = (x0 >= 16 && x0 - 4 < a.W) ? x0 - 4 : xc;
   const int xr = x0 + 16 < a.W ? x0 + 16 : xc;
   const int xc2 = xc + 8 < a.W ? xc + 8 : xc;
@@ -139,11 +142,64 @@ __device__ __forceinline__ LaneCols lane_cols(const Geom& a, int x0) {
   return {(uint32_t)xc * b, (uint32_t)xc2 * b, (uint32_t)xl * b, (uint32_t)xr * b};
 }
 
+// Byte offset of row y of the image, rows below the last read as the last.
+template <typename Pix>
+__host__ __device__ inline int64_t row_offset(const Geom& a, int y) {
+  return (int64_t)(y < a.H - 1 ? y : a.H - 1) * a.stride * (int64_t)sizeof(Pix);
+}
+
+// Rows of an image whose base or pitch is not 16-byte aligned are read as the
+// aligned dwords that span a lane's chunk and halos: dword j (from a0) for
+// j = j0 .. j0 + 6 B, and only those that hold a byte of the row.
+struct UnalignedRow {
+  uintptr_t a0;  // the dword boundary at or before the row's first byte
+  uint32_t sh;   // bytes the row starts past a0
+  int lim;       // dword j holds a byte of the row iff 0 <= j and 4 j < lim
+  int j0;        // dword of the left halo's first byte
+};
+
+template <typename Pix>
+__host__ __device__ inline UnalignedRow unaligned_row(const Geom& g, int y, int x0) {
+  constexpr int B = (int)sizeof(Pix);
+  const uintptr_t r0 = (uintptr_t)g.img + (uintptr_t)row_offset<Pix>(g, y);
+  const uint32_t sh = (uint32_t)(r0 & 3u);
+  return {r0 & ~(uintptr_t)3, sh, g.W * B + (int)sh, x0 * B / 4 - B};
+}
+
+__host__ __device__ inline bool unaligned_dword_in_row(int j, int lim) { return j >= 0 && 4 * j < lim; }
+
+// Dwords load_row_unaligned reads per row: chunk (4 B), halos (B each side),
+// and one more for the byte shift.
+template <typename Pix>
+constexpr int unaligned_row_dwords() { return 6 * (int)sizeof(Pix) + 1; }
+
+// The histogram's chunk loads (16-byte aligned rows): the block at x0 and, for
+// 16-bit pixels, the block at x0 + 8 when it starts inside the row.
+__host__ __device__ inline bool chunk_second_block(int x0, int W) { return x0 + 8 < W; }
+
+// Position of a histogram thread in its workgroup's run of chunks: chunk index
+// i, row y, column chunk c (x0 = 16 c); step() advances by n chunks (sy rows
+// and sc chunks, sc < cpr) with a mixed-radix carry.
+struct ChunkPos {
+  uint64_t i;
+  int y;
+  uint32_t c;
+  __host__ __device__ inline void step(uint32_t n, uint32_t sy, uint32_t sc, uint32_t cpr) {
+    i += n;
+    c += sc;
+    y += (int)sy;
+    if (c >= cpr) {
+      c -= cpr;
+      ++y;
+    }
+  }
+};
+
 // (In the strip kernel y is the same on every lane, so the row address stays
 // in scalar registers and each load is a scalar base plus the lane's offset.)
 template <typename Pix>
 __device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y, const LaneCols& o) {
-  const char* row = (const char*)a.img + (int64_t)min(y, a.H - 1) * a.stride * (int64_t)sizeof(Pix);
+  const char* row = (const char*)a.img + row_offset<Pix>(a, y);
   rc.v[0] = *(const uint4*)(row + o.c);
   if (sizeof(Pix) == 1) {
     rc.lh[0] = *(const uint32_t*)(row + o.l);

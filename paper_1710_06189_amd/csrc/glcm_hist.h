@@ -26,6 +26,17 @@ struct HistArgs {
 };
 constexpr int kHistThreads = 1024;
 
+// Launch geometry of the histogram over H rows of cpr chunks: at least two
+// chunks per thread, at most one workgroup per CU; workgroup b owns chunks
+// [b per_block, (b + 1) per_block).  Returns the workgroup count.
+inline int hist_geometry(uint64_t chunks, int num_cus, uint64_t* per_block) {
+  const uint64_t want = (chunks + 2u * kHistThreads - 1u) / (2u * kHistThreads);
+  const uint64_t cap = num_cus > 0 ? (uint64_t)num_cus : 1u;
+  const uint64_t groups = want < 1 ? 1 : (want < cap ? want : cap);
+  *per_block = (chunks + groups - 1) / groups;
+  return (int)((chunks + *per_block - 1) / *per_block);
+}
+
 // 1-D histogram: `groups` workgroups write a.partials; lds_bytes = 4 N D.
 hipError_t launch_histogram(const HistArgs& a, int dtype_bytes, int groups, size_t lds_bytes, hipStream_t stream,
                             const LaunchTiming& tm = {});

@@ -39,7 +39,7 @@ __device__ __forceinline__ ChunkRaw load_chunk(const HistArgs& a, const char* ro
   ChunkRaw r;
   r.v0 = *(const uint4*)(row + (size_t)x0 * sizeof(Pix));
   r.v1 = r.v0;
-  if (sizeof(Pix) == 2 && x0 + 8 < a.W) r.v1 = *(const uint4*)(row + (size_t)(x0 + 8) * 2u);
+  if (sizeof(Pix) == 2 && chunk_second_block(x0, a.W)) r.v1 = *(const uint4*)(row + (size_t)(x0 + 8) * 2u);
   return r;
 }
 
@@ -70,23 +70,6 @@ __device__ __forceinline__ void vote_chunk(const HistArgs& a, const ChunkRaw& r,
     }
   }
 }
-
-// Position of a thread in its workgroup's run of chunks: chunk index i, row y,
-// column chunk c; step() advances by blockDim chunks with a mixed-radix carry.
-struct ChunkPos {
-  uint64_t i;
-  int y;
-  uint32_t c;
-  __device__ __forceinline__ void step(uint32_t n, uint32_t sy, uint32_t sc, uint32_t cpr) {
-    i += n;
-    c += sc;
-    y += (int)sy;
-    if (c >= cpr) {
-      c -= cpr;
-      ++y;
-    }
-  }
-};
 
 constexpr int kHistUnroll = 4;  // chunk loads a thread keeps in flight
 

@@ -168,6 +168,58 @@ def test_batch_rejects_oversize_images():
         plan.close()
 
 
+def test_batch_rejects_memory_the_kernel_cannot_read_or_write():
+    """Tiles must lie in device memory of the current device, outputs too,
+    and no output may overlap a tile: GLCM_EINVAL before anything is queued
+    (a host pointer read by the kernel would fault the GPU)."""
+    import ctypes
+    lib = G._lib()
+    offs = [(1, 0)]
+    plan = G.glcm_plan_create(np.uint8, 16, offs, 64, 64)
+    dev_img = to_device(synth.uniform(64, 64, 5))
+    pageable = torch.from_numpy(synth.uniform(64, 64, 6))
+    pinned = pageable.pin_memory()
+    out = torch.zeros((2, 1, 16, 16), dtype=torch.uint32, device="cuda")
+    feat = torch.zeros((2, 1, 5), dtype=torch.float32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call(imgs, o=None, f=None):
+        arr = (G.Tile * len(imgs))(*[G.Tile(t.data_ptr(), 64, 64, 64) for t in imgs])
+        return lib.glcm_batch_compute(plan.handle, arr, len(imgs), 0, 255,
+                                      ctypes.c_void_p((o if o is not None else out).data_ptr()),
+                                      ctypes.c_void_p(f.data_ptr()) if f is not None else None, stream)
+    try:
+        assert call([dev_img, dev_img], f=feat) == 0
+        torch.cuda.synchronize()
+        want = oracle.glcm(dev_img.cpu().numpy(), 16, 0, 255, offs)
+        assert np.array_equal(host(out)[1], want)
+        out.zero_()
+        assert call([dev_img, pageable]) == -1, "pageable host tile accepted"
+        assert call([pinned, dev_img]) == -1, "pinned host tile accepted"
+        big = torch.zeros(64 * 64 * 4, dtype=torch.uint8, device="cuda")
+        big[: 64 * 64].copy_(dev_img.flatten())
+        assert call([big, dev_img], o=big.view(torch.uint32)[512:1024]) == -1, "out over a tile accepted"
+        assert call([dev_img, dev_img], f=out.view(torch.float32).flatten()[:10]) == -1, "features over out accepted"
+        host_out = torch.zeros((2, 1, 16, 16), dtype=torch.int32).pin_memory()
+        assert call([dev_img, dev_img], o=host_out) == -1, "host output accepted"
+        torch.cuda.synchronize()
+        assert not host(out).any(), "a rejected call wrote the output"
+        # a prepared batch checks its tiles once and its outputs at every run
+        arr = (G.Tile * 2)(G.Tile(dev_img.data_ptr(), 64, 64, 64), G.Tile(pageable.data_ptr(), 64, 64, 64))
+        h = ctypes.c_void_p()
+        assert lib.glcm_batch_prepare(plan.handle, arr, 2, ctypes.byref(h)) == -1
+        pb = G.PreparedBatch([dev_img, dev_img], plan)
+        try:
+            assert lib.glcm_batch_run(pb.handle, 0, 255, ctypes.c_void_p(host_out.data_ptr()), None, stream) == -1
+            assert lib.glcm_batch_run(pb.handle, 0, 255, ctypes.c_void_p(dev_img.data_ptr()), None, stream) == -1
+            o2, _ = pb.run()
+            assert np.array_equal(host(o2)[0], want)
+        finally:
+            pb.close()
+    finally:
+        plan.close()
+
+
 def test_prepared_batch_runs_and_graph_replays():
     """A prepared batch equals glcm_batch_compute; captured in a graph it is
     replayed several times, with eager work on the same images in between

@@ -405,6 +405,35 @@ def test_host_image_tiles(tile_rows, pinned, serial, merge):
         plan.close()
 
 
+@pytest.mark.parametrize("offs,flags,path", [
+    ([(0, -1)], 0, "strips"),
+    ([(1, -1), (0, -2), (-2, -1)], 0, "strips"),
+    ([(1, 1), (-2, -3)], 0, "slabs"),
+    ([(0, -1), (-1, -1)], G.FLAG_FORCE_SLABS, "slabs"),
+    ([(0, -4), (3, -2)], 0, "slabs"),
+])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("tile_rows", [1, 6, 64])
+def test_host_tiles_upward_offsets(offs, flags, path, dtype, tile_rows):
+    """Offsets whose dy is negative, alone or larger than every positive dy:
+    the strip and slab kernels count them from the upper pixel, so a tile needs
+    max|dy| rows below it, whatever the positive offsets reach."""
+    W, H = 203, 77
+    img = synth.smooth(H, W, 2.0, 33, dtype) if dtype == np.uint8 else synth.smooth(H, W, 2.0, 33, dtype,
+                                                                                    noise_frac=0.05)
+    N, hi = (16, 255) if dtype == np.uint8 else (64, 65535)
+    plan = G.glcm_plan_create(dtype, N, offs, W, H, flags)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == path, plan.tuning.as_dict()
+        plan.set_tuning(tile_rows=tile_rows)
+        src = torch.from_numpy(img if dtype == np.uint8 else img.view(np.int16))
+        if dtype == np.uint16:
+            src = src.view(torch.uint16)
+        check(img, N, 0, hi, offs, plan=plan, t=src, label=f"host upward offs={offs} tiles={tile_rows} {path}")
+    finally:
+        plan.close()
+
+
 def test_host_numpy_strided_view():
     base = synth.uniform(200, 300, 32)
     view = base[5:190, 7:290]
