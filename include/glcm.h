@@ -194,6 +194,19 @@ GLCM_API int glcm_plan_workspace(glcm_plan_t plan, size_t *device_bytes);
 GLCM_API int glcm_plan_destroy(glcm_plan_t plan);
 
 /*
+ * The internal plans behind calls with plan = NULL (glcm_compute,
+ * glcm_histogram): one per device and call signature, reused by later calls.
+ * The cache holds at most 32 plans and 512 MiB of their device workspace;
+ * when a call ends over either bound, idle plans are destroyed least recently
+ * used first (after their queued work completes).  Plans in use by a running
+ * call are never destroyed.
+ * glcm_plan_cache_stats: plans held and their device bytes (either pointer
+ * may be NULL).  glcm_plan_cache_clear: destroys every idle cached plan.
+ */
+GLCM_API int glcm_plan_cache_stats(int *plans, uint64_t *device_bytes);
+GLCM_API int glcm_plan_cache_clear(void);
+
+/*
  * Computes out[k][i][j] (Eq. (1)) for the K offsets.
  *
  *   plan     NULL, or a plan created with the same dtype, N, K, offsets and

@@ -40,7 +40,7 @@ __all__ = [
     "glcm_compute",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
     "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
-    "glcm_plan_rebind", "glcm_plan_workspace", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
+    "glcm_plan_rebind", "glcm_plan_workspace", "glcm_plan_cache_stats", "glcm_plan_cache_clear", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
     "glcm_histogram", "glcm_symmetrize", "glcm_normalize", "glcm_average", "glcm_haralick", "HARALICK_NAMES",
     "glcm_haralick_mcc", "BatchTuning",
 ]
@@ -172,6 +172,10 @@ def _lib():
         lib.glcm_plan_rebind.argtypes = [vp, ctypes.POINTER(Offset), i32]
         lib.glcm_plan_workspace.restype = i32
         lib.glcm_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        lib.glcm_plan_cache_stats.restype = i32
+        lib.glcm_plan_cache_stats.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]
+        lib.glcm_plan_cache_clear.restype = i32
+        lib.glcm_plan_cache_clear.argtypes = []
         u64 = ctypes.c_uint64
         lib.glcm_server_create.restype = i32
         lib.glcm_server_create.argtypes = [ctypes.POINTER(vp), i32, u64, u64, u32]
@@ -317,6 +321,18 @@ def glcm_plan_create(dtype, N, offsets, max_W, max_H, flags=0) -> Plan:
 
 def glcm_plan_tuning(plan: Plan) -> Tuning:
     return plan.tuning
+
+
+def glcm_plan_cache_stats():
+    """(plans, device bytes) held by the internal cache behind plan=None calls."""
+    n, b = ctypes.c_int32(), ctypes.c_uint64()
+    _check(_lib().glcm_plan_cache_stats(ctypes.byref(n), ctypes.byref(b)), "glcm_plan_cache_stats")
+    return n.value, b.value
+
+
+def glcm_plan_cache_clear():
+    """Destroys every idle plan of the internal cache."""
+    _check(_lib().glcm_plan_cache_clear(), "glcm_plan_cache_clear")
 
 
 def glcm_plan_autotune(plan: Plan, img, lo=0, hi=None, repeats=5, stream=None) -> Tuning:

@@ -879,8 +879,125 @@ int count_host(glcm_plan_t p, const void* img, bool pinned, int W, int H, int64_
   return GLCM_OK;
 }
 
-std::mutex g_cache_mu;
-std::map<std::tuple<int, int, int, int, std::vector<int32_t>>, glcm_plan_t> g_cache;
+size_t plan_device_bytes(const glcm_plan_s* p) {
+  size_t b = p->partials_bytes + p->batch_cap + p->stage_bytes;
+  if (p->xbuf) b += (size_t)glcm::kXcdSlots * (size_t)p->k_cap * p->N * p->N * 4u;
+  for (int s = 0; s < glcm_plan_s::kSlots; ++s)
+    if (p->dev_tile[s]) b += p->tile_bytes;
+  return b;
+}
+
+// Plans made for calls with plan = NULL, one per (device, dtype, N, K,
+// offsets), kept for reuse but bounded: at most kCachePlans plans and
+// kCacheBytes of device workspace.  When a call ends over a bound, idle plans
+// (no call using them) go, least recently used first; a plan in use is never
+// destroyed, so the bounds can be exceeded while many calls run at once.
+class PlanCache {
+ public:
+  using Key = std::tuple<int, int, int, int, std::vector<int32_t>>;
+  static constexpr size_t kCachePlans = 32;
+  static constexpr size_t kCacheBytes = 512ull << 20;
+
+  // The cached plan for `key` (made by `make` if absent), marked in use until
+  // release(); GLCM_OK or make's error.
+  template <class Make>
+  int acquire(const Key& key, Make make, glcm_plan_t* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = map_.find(key);
+    if (it == map_.end()) {
+      glcm_plan_t np = nullptr;
+      const int rc = make(&np);
+      if (rc != GLCM_OK) return rc;
+      it = map_.emplace(key, Entry{np, 0, 0, plan_device_bytes(np)}).first;
+    }
+    it->second.users += 1;
+    it->second.last_use = ++tick_;
+    *out = it->second.plan;
+    return GLCM_OK;
+  }
+
+  // Ends a use of `p`, then trims the cache to its bounds.
+  void release(glcm_plan_t p) {
+    std::vector<glcm_plan_t> gone;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (auto& kv : map_)
+        if (kv.second.plan == p) {
+          kv.second.users -= 1;
+          if (kv.second.users == 0) kv.second.bytes = plan_device_bytes(p);
+          break;
+        }
+      trim_locked(kCachePlans, kCacheBytes, &gone);
+    }
+    destroy(gone);
+  }
+
+  // Destroys every idle plan.
+  void clear() {
+    std::vector<glcm_plan_t> gone;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      trim_locked(0, 0, &gone);
+    }
+    destroy(gone);
+  }
+
+  void stats(int* plans, uint64_t* bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    uint64_t b = 0;
+    for (const auto& kv : map_) b += kv.second.bytes;
+    if (plans) *plans = (int)map_.size();
+    if (bytes) *bytes = b;
+  }
+
+ private:
+  struct Entry {
+    glcm_plan_t plan;
+    int users;
+    uint64_t last_use;
+    size_t bytes;  // device workspace when last idle
+  };
+
+  void trim_locked(size_t max_plans, size_t max_bytes, std::vector<glcm_plan_t>* gone) {
+    for (;;) {
+      size_t bytes = 0;
+      for (const auto& kv : map_) bytes += kv.second.bytes;
+      if (map_.size() <= max_plans && bytes <= max_bytes) return;
+      auto victim = map_.end();
+      for (auto it = map_.begin(); it != map_.end(); ++it)
+        if (it->second.users == 0 && (victim == map_.end() || it->second.last_use < victim->second.last_use))
+          victim = it;
+      if (victim == map_.end()) return;  // everything left is in use
+      gone->push_back(victim->second.plan);
+      map_.erase(victim);
+    }
+  }
+
+  // (outside the lock: destroying a plan waits for its queued work)
+  static void destroy(const std::vector<glcm_plan_t>& gone) {
+    for (glcm_plan_t p : gone) {
+      plan_release(p);
+      delete p;
+    }
+  }
+
+  std::mutex mu_;
+  std::map<Key, Entry> map_;
+  uint64_t tick_ = 0;
+};
+
+PlanCache& plan_cache() {
+  static PlanCache* c = new PlanCache();  // never destroyed: plans may outlive static destruction order
+  return *c;
+}
+
+// Holds a cached plan for the duration of one call.
+struct CachedPlanUse {
+  glcm_plan_t plan = nullptr;
+  ~CachedPlanUse() {
+    if (plan) plan_cache().release(plan);
+  }
+};
 
 }  // namespace
 
@@ -1151,11 +1268,17 @@ GLCM_API int glcm_plan_rebind(glcm_plan_t plan, const glcm_offset_t* offsets, in
 GLCM_API int glcm_plan_workspace(glcm_plan_t plan, size_t* device_bytes) {
   if (!plan || !device_bytes) return GLCM_EINVAL;
   std::lock_guard<std::mutex> lk(plan->mu);
-  size_t b = plan->partials_bytes + plan->batch_cap + plan->stage_bytes;
-  if (plan->xbuf) b += (size_t)glcm::kXcdSlots * (size_t)plan->k_cap * plan->N * plan->N * 4u;
-  for (int s = 0; s < glcm_plan_s::kSlots; ++s)
-    if (plan->dev_tile[s]) b += plan->tile_bytes;
-  *device_bytes = b;
+  *device_bytes = plan_device_bytes(plan);
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_plan_cache_stats(int* plans, uint64_t* device_bytes) {
+  plan_cache().stats(plans, device_bytes);
+  return GLCM_OK;
+}
+
+GLCM_API int glcm_plan_cache_clear(void) {
+  plan_cache().clear();
   return GLCM_OK;
 }
 
@@ -1185,22 +1308,18 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void* img, int W, int H, int64
   GLCM_TRY(hipGetDevice(&cur));
   if (out_dev != cur || (kind == 2 && img_dev != cur)) return GLCM_EINVAL;
 
+  CachedPlanUse cached;
   if (!plan) {
     std::vector<int32_t> key;
     for (int k = 0; k < K; ++k) {
       key.push_back(offsets[k].dx);
       key.push_back(offsets[k].dy);
     }
-    auto tk = std::make_tuple(cur, dtype, N, K, key);
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto it = g_cache.find(tk);
-    if (it == g_cache.end()) {
-      glcm_plan_t np = nullptr;
-      rc = glcm_plan_create(&np, dtype, N, K, offsets, 65535, 65535, 0);
-      if (rc != GLCM_OK) return rc;
-      it = g_cache.emplace(tk, np).first;
-    }
-    plan = it->second;
+    rc = plan_cache().acquire(
+        std::make_tuple(cur, dtype, N, K, key),
+        [&](glcm_plan_t* np) { return glcm_plan_create(np, dtype, N, K, offsets, 65535, 65535, 0); }, &plan);
+    if (rc != GLCM_OK) return rc;
+    cached.plan = plan;
   }
 
   std::lock_guard<std::mutex> lk(plan->mu);
@@ -1503,20 +1622,19 @@ GLCM_API int glcm_histogram(glcm_plan_t plan, const void* img, int W, int H, int
   GLCM_TRY(hipGetDevice(&cur));
   if (out_dev != cur || img_dev != cur) return GLCM_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;
+  CachedPlanUse cached;
   if (!plan) {
     // a plan of its own (K = 0 in the key, which no glcm_compute call uses),
     // made on the global-atomic path so that it allocates no per-XCD slices:
     // the histogram needs only the partials
-    auto tk = std::make_tuple(cur, dtype, N, 0, std::vector<int32_t>{});
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto it = g_cache.find(tk);
-    if (it == g_cache.end()) {
-      glcm_plan_t np = nullptr;
-      rc = glcm_plan_create(&np, dtype, N, 1, &kZero, 65535, 65535, GLCM_FLAG_FORCE_GLOBAL);
-      if (rc != GLCM_OK) return rc;
-      it = g_cache.emplace(tk, np).first;
-    }
-    plan = it->second;
+    rc = plan_cache().acquire(
+        std::make_tuple(cur, dtype, N, 0, std::vector<int32_t>{}),
+        [&](glcm_plan_t* np) {
+          return glcm_plan_create(np, dtype, N, 1, &kZero, 65535, 65535, GLCM_FLAG_FORCE_GLOBAL);
+        },
+        &plan);
+    if (rc != GLCM_OK) return rc;
+    cached.plan = plan;
   }
   std::lock_guard<std::mutex> lk(plan->mu);
   GLCM_TRY_RC(order_after_previous(plan, stream));

@@ -434,6 +434,30 @@ def test_host_tiles_upward_offsets(offs, flags, path, dtype, tile_rows):
         plan.close()
 
 
+def test_plan_cache_is_bounded():
+    """100 calls with plan=None and 100 distinct offset sets (16 MiB of per-XCD
+    accumulators each at N = 256, K = 4) keep at most 32 cached plans and
+    512 MiB of device workspace; the results stay exact."""
+    G.glcm_plan_cache_clear()
+    img = synth.smooth(96, 80, 2.0, 41)
+    t = to_device(img)
+    free0 = torch.cuda.mem_get_info()[0]
+    last = None
+    for s in range(100):
+        offs = [(1, 0), (0, 1), (s % 10 - 5, s // 10 - 5), (2, 2)]
+        out = G.glcm_compute(t, 256, 0, 255, offs)
+        n, b = G.glcm_plan_cache_stats()
+        assert n <= 32 and b <= 512 << 20, (s, n, b)
+        last = (offs, out)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    assert used < 700 << 20, f"device memory grew by {used >> 20} MiB"
+    offs, out = last
+    assert np.array_equal(to_host(out), oracle.glcm(img, 256, 0, 255, offs))
+    G.glcm_plan_cache_clear()
+    assert G.glcm_plan_cache_stats()[0] == 0
+
+
 def test_host_numpy_strided_view():
     base = synth.uniform(200, 300, 32)
     view = base[5:190, 7:290]
