@@ -245,8 +245,10 @@ GLCM_API int glcm_compute(glcm_plan_t plan, const void *img, int W, int H, int64
  * entropy (natural log), homogeneity (inverse difference moment,
  * 1/(1+(i-j)^2)), correlation.  p = P/T with T = sum of P[k].  T = 0 gives
  * five zeros; a row or column marginal with a single occupied level gives
- * correlation 1.  Computed in fp32 except the correlation, whose moments are
- * exact integers combined in fp64.
+ * correlation 1.  Energy, entropy and homogeneity are summed in fp32; the
+ * contrast and the correlation come from exact integer moments (the contrast
+ * as one fp64 quotient, the correlation's variances and covariance combined
+ * in fp64).
  *
  *   glcm     device memory, K*N*N uint32 (the layout glcm_compute writes).
  *   out      device memory, K*5 float, overwritten.

@@ -606,7 +606,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   if (y_end <= y_begin) {
     // nothing to count: clear (or keep) the output
     if (xcd && finish) GLCM_TRY(glcm::launch_finish(p->xbuf, out, words, p->xslots, accumulate, stream));
-    else if (!accumulate && !xcd) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
+    else if (!accumulate && !xcd) GLCM_TRY(glcm::launch_zero(out, words, stream));
     return GLCM_OK;
   }
 
@@ -615,7 +615,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
       a.dx[k] = p->offsets[k].dx;
       a.dy[k] = p->offsets[k].dy;
     }
-    if (!accumulate) GLCM_TRY(hipMemsetAsync(out, 0, (size_t)words * 4, stream));
+    if (!accumulate) GLCM_TRY(glcm::launch_zero(out, words, stream));
     GLCM_TRY(glcm::launch_vote_global(a, b, stream));
     return GLCM_OK;
   }
@@ -637,7 +637,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     hipError_t e = glcm::launch_vote_l2(a, b, groups, stream, tm);
     if (e == hipSuccess && finish) e = glcm::launch_finish(p->xbuf, out, words, p->xslots, accumulate, stream);
     if (e != hipSuccess) {
-      (void)hipMemsetAsync(p->xbuf, 0, (size_t)p->xslots * words * 4u, stream);
+      (void)glcm::launch_zero(p->xbuf, (uint64_t)p->xslots * words, stream);
       return hip_status(e);
     }
     return GLCM_OK;
@@ -787,7 +787,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   }
   if (e != hipSuccess) {
     // leave the accumulators clean for the next call
-    if (xcd) (void)hipMemsetAsync(p->xbuf, 0, (size_t)p->xslots * words * 4u, stream);
+    if (xcd) (void)glcm::launch_zero(p->xbuf, (uint64_t)p->xslots * words, stream);
     return hip_status(e);
   }
   return GLCM_OK;

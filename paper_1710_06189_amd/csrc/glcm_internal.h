@@ -106,6 +106,8 @@ hipError_t launch_reduce(const uint32_t* partials, uint32_t* out, uint32_t M, in
 // out[w] = (accumulate ? out[w] : 0) + sum_{x < nslots} xbuf[x * M + w]; zeroes those slices.
 hipError_t launch_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, uint32_t nslots, bool accumulate,
                          hipStream_t stream);
+// p[w] = 0 for w < words (a kernel, not a memset node: capturable in a graph).
+hipError_t launch_zero(uint32_t* p, uint64_t words, hipStream_t stream);
 // ids[b] = XCC_ID of the XCD that ran workgroup b (b < blocks).
 hipError_t launch_xcc_probe(uint32_t* ids, int blocks, hipStream_t stream);
 hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t stream);

@@ -12,6 +12,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "glcm_device.h"
@@ -119,6 +120,13 @@ __global__ __launch_bounds__(256) void k_finish(uint32_t* xbuf, uint32_t* out, u
     if (x < nslots) xbuf[(size_t)x * M + w] = 0u;
   }
   out[w] = s;
+}
+
+// p[w] = 0 for w < n (a kernel rather than a memset node, so that a caller
+// may capture it into a HIP graph).
+__global__ __launch_bounds__(256) void k_zero(uint32_t* p, uint64_t n) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n; w += (uint64_t)gridDim.x * blockDim.x)
+    p[w] = 0u;
 }
 
 // Each workgroup records the XCC_ID of the XCD it runs on.
@@ -758,6 +766,13 @@ hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int
     return dtype_bytes == 1 ? launch_strips_t<uint8_t, 2>(a, D, wg, lds_bytes, stream, tm)
                             : launch_strips_t<uint16_t, 2>(a, D, wg, lds_bytes, stream, tm);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_zero(uint32_t* p, uint64_t words, hipStream_t stream) {
+  if (words == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((words + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, stream, p, words);
+  return hipGetLastError();
 }
 
 hipError_t launch_xcc_probe(uint32_t* ids, int blocks, hipStream_t stream) {

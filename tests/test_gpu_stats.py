@@ -2,7 +2,7 @@
 through the C ABI: histograms and symmetric matrices bit for bit, normalised
 and averaged matrices equal to the oracle's fp64 value rounded to fp32, and
 Haralick's thirteen statistics (fp64 on the device, stored as fp32) within
-1e-5 relative plus 1e-6 absolute of the oracle."""
+1e-5 relative of the oracle, plus 1e-6 absolute on f3, f12 and f13 (cancellations near zero)."""
 
 import numpy as np
 import pytest
@@ -154,8 +154,20 @@ def test_average(m):
     assert np.array_equal(got, oracle.average(P, m).astype(np.float32))
 
 
+# Statistics that are a cancellation near zero for nearly independent
+# matrices and so need an absolute term besides the relative one: f3, the
+# correlation (a covariance over a product of deviations); f12, a difference
+# of two entropies over a third; f13, the square root of 1 - exp(-2 (HXY2 -
+# HXY)), which turns a rounding-level difference of entropies into its
+# square root.  Every other statistic is held to 1e-5 relative alone (exact
+# zeros must come out as zeros).
+NEAR_ZERO_STATS = [2, 11, 12]
+
+
 def assert_stats_close(got, want):
-    bad = np.abs(got.astype(np.float64) - want) > 1e-5 * np.abs(want) + 1e-6
+    tol = 1e-5 * np.abs(want)
+    tol[..., NEAR_ZERO_STATS] += 1e-6
+    bad = np.abs(got.astype(np.float64) - want) > tol
     assert not bad.any(), (np.argwhere(bad)[:5], got[bad][:5], want[bad][:5])
 
 
