@@ -87,6 +87,11 @@ enum glcm_status {
 #define GLCM_FLAG_FORCE_L2          (1u << 6) /* large-N path: pairs added straight into
                                                  per-XCD accumulators in L2, no LDS copies
                                                  (when those fit in 256 MiB) */
+#define GLCM_FLAG_FORCE_BLOCKS      (1u << 7) /* block-code kernel where it applies (every
+                                                 offset one of the four d = 1 directions
+                                                 of Eq. (2) or its opposite, N <= 50,
+                                                 max_W <= 65536): two codes per 2x2 pixel
+                                                 block carry its four pairs */
 
 typedef struct glcm_plan_s *glcm_plan_t;
 
@@ -106,7 +111,7 @@ typedef struct glcm_tuning {
                            a small kernel sums the 8 slices; 1: per-band partial counts,
                            summed by a reduce kernel */
     int path;           /* read-only: 0 generic, 1 slab kernel, 2 partitioned, 3 global,
-                           4 strip kernel, 5 L2 slices (large N) */
+                           4 strip kernel, 5 L2 slices (large N), 6 block codes (d = 1) */
     int partitions;     /* read-only: bin partitions per pass */
 } glcm_tuning_t;
 

@@ -39,7 +39,7 @@ __all__ = [
     "glcm_offset_polar", "glcm_plan_create", "glcm_plan_destroy", "glcm_plan_tuning", "glcm_plan_autotune",
     "glcm_compute",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
-    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
+    "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "FLAG_FORCE_BLOCKS", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
     "glcm_plan_rebind", "glcm_plan_workspace", "glcm_plan_cache_stats", "glcm_plan_cache_clear", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
     "glcm_histogram", "glcm_symmetrize", "glcm_normalize", "glcm_average", "glcm_haralick", "HARALICK_NAMES",
     "glcm_haralick_mcc", "BatchTuning",
@@ -56,7 +56,8 @@ FLAG_SERIAL_UPLOAD = 1 << 3
 FLAG_TIMING = 1 << 4
 FLAG_FORCE_SLABS = 1 << 5
 FLAG_FORCE_L2 = 1 << 6
-PATH_NAMES = {0: "generic", 1: "slabs", 2: "partitioned", 3: "global", 4: "strips", 5: "l2"}
+FLAG_FORCE_BLOCKS = 1 << 7
+PATH_NAMES = {0: "generic", 1: "slabs", 2: "partitioned", 3: "global", 4: "strips", 5: "l2", 6: "blocks"}
 
 STATUS = {0: "GLCM_OK", -1: "GLCM_EINVAL", -2: "GLCM_ENOMEM", -3: "GLCM_EUNSUPPORTED",
           -4: "GLCM_EHIP", -5: "GLCM_EBUSY"}

@@ -43,9 +43,12 @@ int hip_status(hipError_t e) {
 
 constexpr uint32_t kKnownFlags = GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED |
                                  GLCM_FLAG_FORCE_GLOBAL | GLCM_FLAG_SERIAL_UPLOAD | GLCM_FLAG_TIMING |
-                                 GLCM_FLAG_FORCE_SLABS | GLCM_FLAG_FORCE_L2;
+                                 GLCM_FLAG_FORCE_SLABS | GLCM_FLAG_FORCE_L2 | GLCM_FLAG_FORCE_BLOCKS;
 
-enum Path { kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3, kPathStrips = 4, kPathL2 = 5 };
+enum Path {
+  kPathGeneric = 0, kPathRows = 1, kPathPartitioned = 2, kPathGlobal = 3, kPathStrips = 4, kPathL2 = 5,
+  kPathBlocks = 6
+};
 
 // Misaligned device images of at least this many pixels are copied into an
 // aligned staging buffer and counted by the strip / slab kernels (measured on
@@ -361,6 +364,37 @@ bool l2_slices_fit(const glcm_plan_s* p) {
   return (uint64_t)glcm::kXcdSlots * (uint64_t)p->k_cap * (uint64_t)p->N * (uint64_t)p->N * 4ull <= (256ull << 20);
 }
 
+// Block-code kernel: every offset is one of the four d = 1 directions or its
+// opposite, the code bins and block GLCMs fit one workgroup's LDS, and the
+// plan keeps the per-XCD slices (its merge adds into them).
+int block_glcm(const glcm_offset_t& o) {
+  int dx = o.dx, dy = o.dy;
+  if (dy < 0 || (dy == 0 && dx < 0)) {
+    dx = -dx;
+    dy = -dy;
+  }
+  if (dy == 0 && dx == 1) return 0;
+  if (dy == 1 && dx == -1) return 1;
+  if (dy == 1 && dx == 0) return 2;
+  if (dy == 1 && dx == 1) return 3;
+  return -1;
+}
+
+// Copies of the block kernel's block GLCMs: the most of 4, 2, 1 whose LDS
+// fits (0: none).
+int block_fb_copies(const glcm_plan_s* p) {
+  for (int c = 4; c >= 1; c /= 2)
+    if (glcm::block_lds_bytes(p->N, c) <= (size_t)p->lds_budget_words * 4u) return c;
+  return 0;
+}
+
+bool blocks_fit(const glcm_plan_s* p) {
+  if (p->N > 255 || p->max_W > 65536 || block_fb_copies(p) == 0) return false;
+  for (int k = 0; k < p->K; ++k)
+    if (block_glcm(p->offsets[k]) < 0) return false;
+  return true;
+}
+
 // Image passes of the partitioned kernel worth one GLCM's pairs added into
 // the per-XCD L2 slices: measured on MI355X, 4096^2 u8 images, a pass costs
 // 0.04-0.05 ms and a GLCM in the slices 0.63 ms on noise (more on smooth
@@ -395,10 +429,16 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
     d.partitions = 1;
   } else {
     const bool any_rows = !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) && p->N <= 255;
+    const bool blocks_ok = any_rows && (p->flags & GLCM_FLAG_FORCE_BLOCKS) && blocks_fit(p);
     const bool strips_ok = any_rows && !(p->flags & GLCM_FLAG_FORCE_SLABS) && c.maxadx <= 2 && c.maxdy <= 2 &&
                            strip_partitions(p, 4, 16) > 0;
     const bool rows_ok = any_rows && c.maxadx <= 4 && c.maxdy <= 4 && row_partitions(p, 1, 32) > 0;
-    if (strips_ok) {
+    if (blocks_ok) {
+      d.path = kPathBlocks;
+      d.replicas = 32;
+      d.counter_bits = 16;
+      d.partitions = 1;
+    } else if (strips_ok) {
       d.path = kPathStrips;
       // The most dwords per bin (32 put every lane of a 32-lane LDS pass on
       // its own bank) that costs at most max(2, minimum) image passes, with
@@ -586,7 +626,9 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
 
   int path = t.path;
   const Canon c = canonicalize(p->offsets, p->K);
-  if (path == kPathRows || path == kPathStrips) {
+  // the block kernel merges into the per-XCD slices only
+  if (path == kPathBlocks && (t.merge != 0 || !p->xbuf)) path = kPathStrips;
+  if (path == kPathRows || path == kPathStrips || path == kPathBlocks) {
     const bool aligned = ((uintptr_t)img % 16 == 0) && (((uint64_t)stride * b) % 16 == 0);
     if (!aligned && (uint64_t)W * (uint64_t)H >= kStageMinPixels && y_begin == 0 && y_end == H) {
       // one pitched copy into the plan's aligned buffer, then the fast kernels
@@ -643,8 +685,63 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     return GLCM_OK;
   }
 
+  if (path == kPathBlocks) {
+    glcm::BlockArgs ba;
+    std::memset(&ba, 0, sizeof(ba));
+    ba.img = img;
+    ba.stride = stride;
+    ba.W = W;
+    ba.H = H;
+    ba.y_begin = y_begin;
+    ba.y_end = y_end;
+    ba.q = a.q;
+    ba.qfast = a.qfast;
+    ba.qfast_shift = a.qfast_shift;
+    ba.qfast_mask = a.qfast_mask;
+    ba.K = p->K;
+    for (int k = 0; k < p->K; ++k) ba.gmap[k] = block_glcm(p->offsets[k]);
+    ba.tmask = c.tmask;
+    ba.nbins = 16u * (uint32_t)p->N + 6u;
+    ba.fb_copies = block_fb_copies(p);
+    ba.div_n = a.div_n;
+    ba.words_total = words;
+    ba.xbuf = p->xbuf;
+    // bands: one workgroup of 16 wavefronts per band, as many bands as the
+    // CUs hold at once, each tall enough for strips of >= 4 rows on every
+    // wavefront; a band holds fewer than 2^17 chunk pixels (the merge adds
+    // the copies of half the lanes packed, 16 bits per code)
+    constexpr int kWg = 1024, kWaves = kWg / 64;
+    const int rows = y_end - y_begin;
+    const int spans = (((W + 15) / 16) + 63) / 64;
+    const size_t lds = glcm::block_lds_bytes(p->N, ba.fb_copies);
+    const int per_cu =
+        std::max(1, std::min((int)(((size_t)p->lds_budget_words * 4u + 1024u) / lds), 32 / kWaves));
+    int nregions = std::min(rows, std::max(1, p->num_cus * per_cu));
+    nregions = std::max(1, std::min(nregions, rows * spans / (4 * kWaves)));
+    int region_rows = (rows + nregions - 1) / nregions;
+    region_rows = std::min(region_rows, std::max(1, 131070 / (spans * 1024)));
+    nregions = (rows + region_rows - 1) / region_rows;
+    const int strips_per_span = std::max(1, kWaves / spans);
+    ba.nregions = nregions;
+    ba.region_rows = region_rows;
+    ba.strip_rows = std::max(1, (region_rows + strips_per_span - 1) / strips_per_span);
+    glcm::LaunchTiming tm;
+    if (p->flags & GLCM_FLAG_TIMING) {
+      GLCM_TRY(hipEventCreate(&tm.start));
+      GLCM_TRY(hipEventCreate(&tm.stop));
+      p->timing.emplace_back(tm.start, tm.stop);
+    }
+    hipError_t e = glcm::launch_vote_blocks(ba, b, kWg, stream, tm);
+    if (e == hipSuccess && finish) e = glcm::launch_finish(p->xbuf, out, words, p->xslots, accumulate, stream);
+    if (e != hipSuccess) {
+      (void)glcm::launch_zero(p->xbuf, (uint64_t)p->xslots * words, stream);
+      return hip_status(e);
+    }
+    return GLCM_OK;
+  }
+
   int R = t.replicas, P = t.partitions;  // R may drop below if 16-bit counters cannot be used
-  if (path != t.path && (t.path == kPathRows || t.path == kPathStrips)) {
+  if (path != t.path && (path == kPathGeneric || path == kPathPartitioned)) {
     // fell back from the row kernel: size the generic partitions
     const uint64_t budget = (uint64_t)p->lds_budget_words;
     P = (int)((words + budget - 1) / budget);
@@ -1075,7 +1172,12 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
     glcm_tuning_t& t = plan->tuning;
     if (n.counter_bits != 0 && n.counter_bits != 16 && n.counter_bits != 32) return GLCM_EINVAL;
     int bits = n.counter_bits == 0 ? t.counter_bits : n.counter_bits;
-    if (t.path == kPathStrips) {
+    if (t.path == kPathBlocks) {
+      // the block kernel's layout is fixed (32 copies, 16-bit halves, 1024
+      // threads); only the upload tile height and the merge are tunable
+      if (n.wg_size != 1024 || n.rows_per_wave != 0) return GLCM_EINVAL;
+      if (n.replicas != 32 || bits != 16) return GLCM_EINVAL;
+    } else if (t.path == kPathStrips) {
       if (n.rows_per_wave != 0) return GLCM_EINVAL;  // strips have no slab height
       const int P = strip_partitions(plan, n.replicas, bits);
       if (P == 0) return GLCM_EINVAL;

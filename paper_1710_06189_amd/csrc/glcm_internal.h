@@ -60,6 +60,44 @@ struct VoteArgs {
   uint32_t* out;              // global-atomic kernel: [words_total] counts, zeroed beforehand
 };
 
+// Block-code kernel (the four d = 1 directions).  Each first pixel (x, y) and
+// its 2x2 block [a b; d e] (a = (x, y), b = (x+1, y), d = (x, y+1), e =
+// (x+1, y+1)) hold exactly one pair of each d = 1 GLCM: (1,0) -> (a, b),
+// (-1,1) -> (b, d), (0,1) -> (a, d), (1,1) -> (a, e).  The kernel votes two
+// codes per block instead of four pairs:
+//   code 1 = 16 a + 4 (d - a + 1) + (b - a + 1) = 11 a + b + 4 d + 5
+//            (the block's (1,0), (-1,1) and (0,1) pairs),
+//   code 2 = 12 a + (e - a + 1)                = 11 a + e + 1
+//            (its (1,1) pair),
+// exact whenever the three differences lie in [-1, 2]; blocks outside that
+// window are corrected one pair at a time.  Block GLCM g of the four above.
+constexpr int kBlockGlcms = 4;
+struct BlockArgs {
+  const void* img;            // 16-byte aligned base and row pitch
+  int64_t stride;             // elements
+  int W, H;
+  int y_begin, y_end;         // first-pixel rows
+  Quant q;
+  int qfast;
+  uint32_t qfast_shift, qfast_mask;
+  int K;                      // requested offsets
+  int32_t gmap[kMaxK];        // block GLCM of offset k (0..3)
+  unsigned long long tmask;   // bit k: offset k is the opposite of its block direction (stored transposed)
+  int nregions, region_rows, strip_rows;
+  uint32_t nbins;             // code bins: 16 N + 6 (every level combination, sentinel included, lands inside)
+  int fb_copies;              // copies of the block GLCMs (1, 2 or 4; lane mod fb_copies)
+  Quant div_n;                // magic/shift for dividing by N
+  uint32_t words_total;       // K N N
+  uint32_t* xbuf;             // [kXcdSlots][words_total] per-XCD accumulators
+};
+// LDS bytes of the block kernel: code bins (32 dwords each), the four block
+// GLCMs in fbc copies (N^2 words each), one trash word per lane and a queue
+// of 128 blocks (8 bytes each) per wavefront of a 1024-thread workgroup.
+inline size_t block_lds_bytes(int N, int fbc) {
+  return (16u * (size_t)N + 6u) * 128u + (size_t)kBlockGlcms * (size_t)N * (size_t)N * (size_t)fbc * 4u + 64u * 4u +
+         16u * 128u * 8u;
+}
+
 // One image of a batch as the batch kernel reads it (device memory, 32 bytes).
 struct BatchTile {
   const void* img;  // device pixels, row y at img + y * stride elements
@@ -116,6 +154,9 @@ hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t st
 hipError_t launch_vote_l2(const VoteArgs& a, int dtype_bytes, int groups, hipStream_t stream,
                           const LaunchTiming& tm = {});
 hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream);
+// Block-code kernel: a.nregions workgroups of `wg` threads, block_lds_bytes(N, a.fb_copies) of LDS.
+hipError_t launch_vote_blocks(const BlockArgs& a, int dtype_bytes, int wg, hipStream_t stream,
+                              const LaunchTiming& tm = {});
 // One workgroup per image of the batch (T images); D = dwords per bin (4, 8
 // or 16), maxdy = 1 or 2.  lds_bytes from batch_lds_bytes().
 hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, size_t lds_bytes,
