@@ -199,8 +199,10 @@ struct glcm_plan_s {
   size_t partials_bytes = 0;
   void* stage = nullptr;  // aligned copy of a misaligned device image (row pitch a multiple of 16 bytes)
   size_t stage_bytes = 0;
-  uint32_t* xbuf = nullptr;  // [kXcdSlots][K*N*N] per-XCD accumulators, kept zero between calls
+  uint32_t* xbuf = nullptr;  // [xalloc][K*N*N] accumulation slices, kept zero between calls
   uint32_t xslots = glcm::kXcdSlots;  // slices the device's XCC_IDs reach (the rest stay zero)
+  uint32_t spread = 1;                // block kernel: slices per XCD (xslots * spread in use)
+  uint32_t xalloc = glcm::kXcdSlots;  // slices allocated
 
 
   // ordering across streams
@@ -389,7 +391,9 @@ int block_fb_copies(const glcm_plan_s* p) {
 }
 
 bool blocks_fit(const glcm_plan_s* p) {
-  if (p->N > 255 || p->max_W > 65536 || block_fb_copies(p) == 0) return false;
+  // N <= 62: the window test's biased digit bytes X - a + 0x40 (X up to N + 1,
+  // a up to the sentinel N) stay in [0, 0x80) without a borrow
+  if (p->N > 62 || p->max_W > 65536 || block_fb_copies(p) == 0) return false;
   for (int k = 0; k < p->K; ++k)
     if (block_glcm(p->offsets[k]) < 0) return false;
   return true;
@@ -514,14 +518,23 @@ int plan_init(glcm_plan_t p) {
   p->lds_budget_words = (lds - 1024) / 4;
   choose_tuning(p, &p->tuning);
   if (p->tuning.path != kPathGlobal) {
-    const size_t bytes = (size_t)glcm::kXcdSlots * (size_t)p->K * p->N * p->N * 4u;
-    if (bytes <= (256u << 20)) {
+    const size_t glcm_bytes = (size_t)p->K * p->N * p->N * 4u;
+    if ((size_t)glcm::kXcdSlots * glcm_bytes <= (256u << 20)) {
+      p->xslots = xcc_slots(p->device);
+      // the block kernel spreads each XCD's workgroups over up to 8 slices
+      // (fewer workgroups adding into one address when they finish), as far
+      // as 16 MiB of slices allow
+      if (p->tuning.path == kPathBlocks) {
+        p->spread = 8;
+        while (p->spread > 1 && (size_t)p->xslots * p->spread * glcm_bytes > (16u << 20)) p->spread /= 2;
+      }
+      p->xalloc = std::max<uint32_t>(glcm::kXcdSlots, p->xslots * p->spread);
+      const size_t bytes = (size_t)p->xalloc * glcm_bytes;
       GLCM_TRY(hipMalloc((void**)&p->xbuf, bytes));
       // zeroed before the plan is returned: its first call may come on a
       // non-blocking stream, which is not ordered after the null stream
       GLCM_TRY(hipMemsetAsync(p->xbuf, 0, bytes, nullptr));
       GLCM_TRY(hipStreamSynchronize(nullptr));
-      p->xslots = xcc_slots(p->device);
     } else {
       p->tuning.merge = 1;  // band partials only
     }
@@ -698,14 +711,15 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     ba.qfast = a.qfast;
     ba.qfast_shift = a.qfast_shift;
     ba.qfast_mask = a.qfast_mask;
-    ba.K = p->K;
-    for (int k = 0; k < p->K; ++k) ba.gmap[k] = block_glcm(p->offsets[k]);
+    for (int k = 0; k < p->K; ++k) ba.kmask[block_glcm(p->offsets[k])] |= 1ull << k;
     ba.tmask = c.tmask;
     ba.nbins = 16u * (uint32_t)p->N + 6u;
     ba.fb_copies = block_fb_copies(p);
     ba.div_n = a.div_n;
     ba.words_total = words;
     ba.xbuf = p->xbuf;
+    ba.xslots = p->xslots;
+    ba.spread = p->spread;
     // bands: one workgroup of 16 wavefronts per band, as many bands as the
     // CUs hold at once, each tall enough for strips of >= 4 rows on every
     // wavefront; a band holds fewer than 2^17 chunk pixels (the merge adds
@@ -731,10 +745,11 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
       GLCM_TRY(hipEventCreate(&tm.stop));
       p->timing.emplace_back(tm.start, tm.stop);
     }
+    const uint32_t nslots = p->xslots * p->spread;
     hipError_t e = glcm::launch_vote_blocks(ba, b, kWg, stream, tm);
-    if (e == hipSuccess && finish) e = glcm::launch_finish(p->xbuf, out, words, p->xslots, accumulate, stream);
+    if (e == hipSuccess && finish) e = glcm::launch_finish(p->xbuf, out, words, nslots, accumulate, stream);
     if (e != hipSuccess) {
-      (void)glcm::launch_zero(p->xbuf, (uint64_t)p->xslots * words, stream);
+      (void)glcm::launch_zero(p->xbuf, (uint64_t)nslots * words, stream);
       return hip_status(e);
     }
     return GLCM_OK;
@@ -978,7 +993,7 @@ int count_host(glcm_plan_t p, const void* img, bool pinned, int W, int H, int64_
 
 size_t plan_device_bytes(const glcm_plan_s* p) {
   size_t b = p->partials_bytes + p->batch_cap + p->stage_bytes;
-  if (p->xbuf) b += (size_t)glcm::kXcdSlots * (size_t)p->k_cap * p->N * p->N * 4u;
+  if (p->xbuf) b += (size_t)p->xalloc * (size_t)p->k_cap * p->N * p->N * 4u;
   for (int s = 0; s < glcm_plan_s::kSlots; ++s)
     if (p->dev_tile[s]) b += p->tile_bytes;
   return b;

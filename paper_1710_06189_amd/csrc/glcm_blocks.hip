@@ -8,10 +8,11 @@
 // so a block is summarised by two codes that carry its four pairs:
 //
 //   code 1 = 16 a + 4 (d - a + 1) + (b - a + 1) = 11 a + b + 4 d + 5
-//   code 2 = 12 a + (e - a + 1)                = 11 a + e + 1
+//   code 2 = 16 a + 4 (e - a + 1) + (b - a + 1) = 11 a + b + 4 e + 5
 //
 // Both are exact (decodable back to the pairs) when b - a, d - a and e - a lie
-// in [-1, 2].  Every block votes both codes unconditionally (two LDS atomics
+// in [-1, 2]; code 1 carries the pairs (a, b), (b, d), (a, d), code 2 the pair
+// (a, e), and the two share their first-row part 11 a + b.  Every block votes both codes unconditionally (two LDS atomics
 // per first pixel instead of four); a cheap byte-wise test then finds the
 // blocks outside the window, whose two votes are taken back and whose four
 // pairs are counted one by one.  The codes are linear in the four levels, so
@@ -47,8 +48,7 @@ struct Lower {
 
 // A row as the upper row (its pixels are the first pixels a).
 struct Upper {
-  uint32_t u[16];  // kBin * 11 a + lane offset
-  uint32_t w[16];  // u + kBin * b
+  uint32_t w[16];  // kBin * (11 a + b) + lane offset
   uint32_t l[4];   // levels a, packed
   uint32_t r1[4];  // levels + 1 of the right neighbours b, packed
 };
@@ -136,10 +136,7 @@ __device__ __forceinline__ void to_lower(Lower& o, const BlockRaw<Pix>& rc, cons
 
 __device__ __forceinline__ void to_upper(Upper& t, const Lower& lo, uint32_t lane_off) {
 #pragma unroll
-  for (int x = 0; x < 16; ++x) {
-    t.u[x] = __umul24(lo.s[x], 11u) + lane_off;
-    t.w[x] = t.u[x] + lo.s[x + 1];
-  }
+  for (int x = 0; x < 16; ++x) t.w[x] = __umul24(lo.s[x], 11u) + lo.s[x + 1] + lane_off;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     t.l[m] = lo.l1[m] - kOnes;
@@ -170,44 +167,46 @@ __device__ __forceinline__ void fb_add(const Fb& f, uint32_t g, uint32_t i, uint
   lds_add((i < f.N && j < f.N) ? at : f.trash, 1u);
 }
 
-// Blocks outside the window, queued per wavefront and corrected 64 at a time
-// (one per lane) instead of one lane at a time.  An entry holds the block's
-// levels a, b + 1, d + 1, e + 1 (one byte each) and the code copy its votes
-// went to.  The queue is a ring of kQueue entries; `head` and `n` are the
-// same on every lane.
-constexpr uint32_t kQueue = 128;
+// Blocks outside the window.  A lane's dword m of a row (four blocks) with
+// any block outside the window is queued for the whole workgroup: the four
+// level dwords it needs (a, b + 1, d + 1, e + 1 of its four pixels), the
+// mask of its blocks outside the window and the code copy its votes went to.
+// After the rows, every thread of the workgroup takes queued dwords and
+// corrects their blocks: both code votes taken back, the four pairs counted
+// one by one.  A dword that finds the queue full is corrected at once by its
+// own lane.
+constexpr uint32_t kQueue = 512;  // queued dwords per workgroup
 
-struct Queue {
-  uint2* ring;  // this wavefront's ring (in LDS)
-  uint32_t head, n;
+struct Pending {
+  uint32_t a, b1, d1, e1;  // packed levels of four blocks: a, b + 1, d + 1, e + 1
+  uint32_t out;            // bytes of the blocks outside the window (bits of kWindow)
+  uint32_t copy;           // code copy of the votes (lane mod 32)
 };
 
-// Takes back both code votes of the queued blocks head .. head + cnt - 1 and
-// counts their four pairs (the lanes below cnt each take one block).
-__device__ __forceinline__ void flush_blocks(Queue& q, uint32_t cnt, uint32_t code_base, const Fb& f) {
-  const uint32_t lane = __lane_id();
-  if (lane < cnt) {
-    const uint2 e = q.ring[(q.head + lane) & (kQueue - 1u)];
-    const uint32_t av = e.x & 0xffu, bv = ((e.x >> 8) & 0xffu) - 1u, dv = ((e.x >> 16) & 0xffu) - 1u,
-                   ev = (e.x >> 24) - 1u;
-    const uint32_t lane_off = code_base + 4u * e.y;
+// Corrects the blocks of p marked in p.out.
+__device__ __forceinline__ void correct_blocks(const Pending& p, uint32_t code_base, const Fb& f) {
+  uint32_t pend = p.out;
+  const uint32_t lane_off = code_base + 4u * p.copy;
+  while (pend) {
+    const uint32_t sh = (uint32_t)__builtin_ctz(pend) & ~7u;
+    pend &= ~(0xffu << sh);
+    const uint32_t av = (p.a >> sh) & 0xffu, bv = ((p.b1 >> sh) & 0xffu) - 1u, dv = ((p.d1 >> sh) & 0xffu) - 1u,
+                   ev = ((p.e1 >> sh) & 0xffu) - 1u;
     lds_sub(kBin * (11u * av + bv + 4u * dv + 5u) + lane_off, 1u);
-    lds_sub(kBin * (11u * av + ev + 1u) + lane_off, 1u << 16);
+    lds_sub(kBin * (11u * av + bv + 4u * ev + 5u) + lane_off, 1u << 16);
     fb_add(f, 0u, av, bv);
     fb_add(f, 1u, bv, dv);
     fb_add(f, 2u, av, dv);
     fb_add(f, 3u, av, ev);
   }
-  q.head += cnt;
-  q.n -= cnt;
 }
 
-// One first-pixel row: both codes of all 16 blocks of the lane; the blocks
-// outside the window go to the wavefront's queue.  A row whose lower row lies
-// below the image (the last image row) holds only (1,0) pairs, counted
-// directly.
+// One first-pixel row: both codes of all 16 blocks of the lane; the dwords
+// with blocks outside the window go to the workgroup's queue.  A row whose
+// lower row lies below the image (the last image row) holds only (1,0)
+// pairs, counted directly.
 __device__ __forceinline__ void block_row(const Upper& t, const Lower& lo, uint32_t copy, uint32_t code_base,
-                                          const Fb& f, Queue& q, bool last) {
+                                          const Fb& f, uint4* queue, uint32_t* qcount, bool last) {
   if (last) {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -218,43 +217,51 @@ __device__ __forceinline__ void block_row(const Upper& t, const Lower& lo, uint3
   }
 #pragma unroll
   for (int x = 0; x < 16; ++x) {
-    lds_add((lo.s[x] << 2) + t.w[x] + 5u * kBin, 1u);    // code 1
-    lds_add(t.u[x] + lo.s[x + 1] + 1u * kBin, 1u << 16);  // code 2
+    lds_add((lo.s[x] << 2) + t.w[x] + 5u * kBin, 1u);            // code 1
+    lds_add((lo.s[x + 1] << 2) + t.w[x] + 5u * kBin, 1u << 16);  // code 2
   }
-  // Digits b - a + 1, d - a + 1, e - a + 1, four per dword: a digit outside
-  // [0, 3] sets a bit of kWindow, or, when negative, borrows from the byte
-  // above it, which moves only higher bytes of the same dword; so any dword
-  // holding a block outside the window shows a set bit.  Then every digit is
-  // tested exactly, byte by byte, biased by 0x40 (no borrow).
-  uint32_t any = 0;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) any |= (t.r1[m] - t.l[m]) | (lo.l1[m] - t.l[m]) | (lo.r1[m] - t.l[m]);
-  if (__ballot((any & kWindow) != 0u) == 0ull) return;
+  // Digits b - a + 1, d - a + 1, e - a + 1, four per dword, each biased by
+  // 0x40 (X - (a - 0x40404040) = X - a + 0x40 per byte, every byte in
+  // [0, 0x80) for N <= 62, no borrow): a block lies in the window iff its
+  // three digit bytes are in [0x40, 0x43], i.e. have bit 6 set and bits 2..5
+  // clear.
   constexpr uint32_t kBias = 0x40404040u;
+  uint32_t bad[4], any = 0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const uint32_t lb = t.l[m] - kBias;  // X - lb = X - a + 0x40 per byte: every byte in [0x21, 0x61]
-    uint32_t pend = (((t.r1[m] - lb) ^ kBias) | ((lo.l1[m] - lb) ^ kBias) | ((lo.r1[m] - lb) ^ kBias)) & kWindow;
-    for (;;) {
-      const bool has = pend != 0u;
-      const unsigned long long bal = __ballot(has);
-      if (bal == 0ull) break;
-      if (has) {
-        const uint32_t j = (uint32_t)__builtin_ctz(pend) >> 3;  // pixel 4 m + j
-        pend &= ~(0xffu << (8u * j));
-        // bytes a, b + 1 (from the upper row) and d + 1, e + 1 (lower row) of pixel 4 m + j
-        const uint32_t sel = j | ((j + 4u) << 8) | 0x0c0c0000u;  // 0x0c: a zero byte
-        const uint32_t entry = __builtin_amdgcn_perm(t.r1[m], t.l[m], sel) |
-                               (__builtin_amdgcn_perm(lo.r1[m], lo.l1[m], sel) << 16);
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        q.ring[(q.head + q.n + rank) & (kQueue - 1u)] = make_uint2(entry, copy);
-      }
-      q.n += (uint32_t)__popcll(bal);
-      if (q.n >= 64u) {
-        __builtin_amdgcn_wave_barrier();
-        flush_blocks(q, 64u, code_base, f);
+    const uint32_t lb = t.l[m] - kBias;
+    const uint32_t db = t.r1[m] - lb, dd = lo.l1[m] - lb, de = lo.r1[m] - lb;
+    bad[m] = (~(db & dd & de) & kBias) | ((db | dd | de) & 0x3c3c3c3cu);  // nonzero bytes: outside the window
+    any |= bad[m];
+  }
+  if (__ballot(any != 0u) == 0ull) return;
+  // one queue reservation for the row: the dwords m = 0..3 of every lane, in
+  // that order
+  unsigned long long bal[4];
+  uint32_t total = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    bal[m] = __ballot(bad[m] != 0u);
+    total += (uint32_t)__popcll(bal[m]);
+  }
+  uint32_t first = 0;
+  if (__lane_id() == 0u)
+    first = __hip_atomic_fetch_add(qcount, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane((int)first);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    if (bad[m]) {
+      const uint32_t s = slot + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[m] >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal[m], 0u));
+      const Pending p{t.l[m], t.r1[m], lo.l1[m], lo.r1[m], bad[m], copy};
+      if (s < kQueue) {
+        queue[2u * s] = make_uint4(p.a, p.b1, p.d1, p.e1);
+        queue[2u * s + 1u] = make_uint4(p.out, p.copy, 0u, 0u);
+      } else {
+        correct_blocks(p, code_base, f);
       }
     }
+    slot += (uint32_t)__popcll(bal[m]);
   }
 }
 
@@ -275,6 +282,20 @@ __device__ __forceinline__ uint32_t next_span_offset(int span, int W) {
   return x < W ? (uint32_t)x * (uint32_t)sizeof(Pix) : 0u;
 }
 
+// A uniform value the compiler must keep (it cannot load it again from the
+// kernel arguments later: a late scalar load would wait for the LDS atomics
+// in flight, which share its wait counter).
+__device__ __forceinline__ uint32_t keep(uint32_t v) {
+  uint32_t r;
+  asm volatile("s_mov_b32 %0, %1" : "=s"(r) : "s"(v));
+  return r;
+}
+__device__ __forceinline__ unsigned long long keep64(unsigned long long v) {
+  unsigned long long r;
+  asm volatile("s_mov_b64 %0, %1" : "=s"(r) : "s"(v));
+  return r;
+}
+
 // A uniform value moved into a vector register (so that loads addressed by it
 // stay vector loads).
 __device__ __forceinline__ uint32_t vgpr(uint32_t v) {
@@ -292,12 +313,14 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
   const int nwaves = blockDim.x >> 6;
   const uint32_t base = lds_address(lds);
   const uint32_t lane_off = base + 4u * (uint32_t)(lane & 31);
-  const uint32_t fbc = (uint32_t)a.fb_copies;
-  const uint32_t fbw0 = a.nbins * (kBin / 4u);                    // word index of FB
+  const uint32_t fbc = keep((uint32_t)a.fb_copies), nbins = keep(a.nbins);
+  const uint32_t fbw0 = nbins * (kBin / 4u);                      // word index of FB
   const uint32_t fbwords = (uint32_t)kBlockGlcms * N * N * fbc;
   const Fb f{base + fbw0 * 4u, base + (fbw0 + fbwords) * 4u + 4u * (uint32_t)lane, 4u * ((uint32_t)lane & (fbc - 1u)),
              4u * fbc, N};
-  Queue q{(uint2*)(lds + fbw0 + fbwords + 64u) + (uint32_t)wave * kQueue, 0u, 0u};
+  // the workgroup's queue of dwords with blocks outside the window, and its count
+  uint4* queue = (uint4*)(lds + fbw0 + fbwords + 64u);
+  uint32_t* qcount = lds + fbw0 + fbwords + 64u + kQueue * 8u;
   const uint32_t copy = (uint32_t)lane & 31u;
   const uint32_t sent4 = N * kOnes;
   const int y0 = a.y_begin + region * a.region_rows;
@@ -321,8 +344,17 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
     for (int r = 0; r < RING; ++r) load_block_row<Pix>(raw[r], geo, ya + r, cols, xn);
   }
   zero_lds(lds, fbw0 + fbwords);
+  if (threadIdx.x == 0) *qcount = 0u;
+  // the kernel arguments read after the rows, held from here on (a first
+  // read there would wait for the LDS atomics in flight as well)
+  const unsigned long long km[kBlockGlcms] = {keep64(a.kmask[0]), keep64(a.kmask[1]), keep64(a.kmask[2]),
+                                              keep64(a.kmask[3])};
+  const unsigned long long tmask = keep64(a.tmask);
+  uint32_t* const xbuf = (uint32_t*)keep64((unsigned long long)a.xbuf);
+  const uint32_t xslots = keep(a.xslots), spread = keep(a.spread);
+  const uint32_t words_total = keep(a.words_total), dmagic = keep(a.div_n.magic), dshift = keep(a.div_n.shift);
   asm volatile("" ::"s"(a.qfast), "s"(a.qfast_shift), "s"(a.qfast_mask), "s"(a.q.lo), "s"(a.q.hi), "s"(a.q.nlev),
-               "s"(a.q.magic), "s"(a.q.shift));
+               "s"(a.q.magic), "s"(a.q.shift), "s"(a.H), "s"(a.W));
   __syncthreads();
 
   for (; strip < nstrips; strip += nwaves) {
@@ -351,7 +383,7 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
         if (!done) {
           to_lower<Pix, QF>(lo, raw[r % RING], a, y + r, x0, sent4, edge);
           load_block_row<Pix>(raw[r % RING], geo, y + r + RING, cols, xn);
-          block_row(up, lo, copy, base, f, q, y + r >= a.H);
+          block_row(up, lo, copy, base, f, queue, qcount, y + r >= a.H);
           if (y + r >= yb) done = true;
           else to_upper(up, lo, lane_off);
         }
@@ -359,9 +391,12 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
       if (done) break;
     }
   }
-  if (q.n) {
-    __builtin_amdgcn_wave_barrier();
-    flush_blocks(q, q.n, base, f);
+  __syncthreads();
+  // the queued dwords, one per thread at a time
+  const uint32_t queued = min(*qcount, kQueue);
+  for (uint32_t e = threadIdx.x; e < queued; e += blockDim.x) {
+    const uint4 v = queue[2u * e], w = queue[2u * e + 1u];
+    correct_blocks(Pending{v.x, v.y, v.z, v.w, w.x, w.y}, base, f);
   }
   __syncthreads();
 
@@ -369,7 +404,7 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
   // 16 by two threads (packed: a group holds the votes of half the lanes and
   // the host keeps a band below 2^17 first pixels, so a group's halves stay
   // below 2^16), decoded and added into the block GLCMs (copy job mod fbc).
-  for (uint32_t job = threadIdx.x; job < 2u * a.nbins; job += blockDim.x) {
+  for (uint32_t job = threadIdx.x; job < 2u * nbins; job += blockDim.x) {
     const uint32_t bin = job >> 1, half = job & 1u;
     const uint4* units = (const uint4*)(lds + bin * (kBin / 4u)) + 4u * half;
     uint32_t s = 0;
@@ -388,10 +423,9 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
       if (bok && dok) lds_add(at + ((N + bv) * N + dv) * f.stride, c1);
       if (dok) lds_add(at + ((2u * N + av) * N + dv) * f.stride, c1);
     }
-    if (c2) {
-      const uint32_t av = bin / 12u, de = bin - 12u * av;
-      const uint32_t ev = av + de - 1u;
-      if (de <= 3u && av < N && ev < N) lds_add(at + ((3u * N + av) * N + ev) * f.stride, c2);
+    if (c2 && bin < 16u * N) {
+      const uint32_t av = bin >> 4, ev = av + ((bin >> 2) & 3u) - 1u;
+      if (ev < N) lds_add(at + ((3u * N + av) * N + ev) * f.stride, c2);
     }
   }
   __syncthreads();
@@ -400,23 +434,25 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
   // per requested offset (transposed for the opposite directions).
   uint32_t xcc;
   asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
-  uint32_t* xs = a.xbuf + (size_t)(xcc & (kXcdSlots - 1u)) * a.words_total;
+  // the slice of this XCD (the hardware's XCC_ID, so no two XCDs ever share
+  // one) and of this workgroup's group: fewer workgroups adding to one
+  // address in L2 at the end of the kernel
+  const uint32_t slice = (xcc & (kXcdSlots - 1u)) + xslots * (((uint32_t)blockIdx.x >> 3) & (spread - 1u));
+  uint32_t* xs = xbuf + (size_t)slice * words_total;
   const uint32_t NN = N * N;
   const uint32_t* fbw = lds + fbw0;
   for (uint32_t w = threadIdx.x; w < NN; w += blockDim.x) {
-    const uint32_t i = divide(w, a.div_n.magic, a.div_n.shift), j = w - i * N;
-    uint32_t v[kBlockGlcms];
+    const uint32_t i = divide(w, dmagic, dshift), j = w - i * N;
 #pragma unroll
     for (int g = 0; g < kBlockGlcms; ++g) {
-      v[g] = 0;
-      for (uint32_t c = 0; c < fbc; ++c) v[g] += fbw[((uint32_t)g * NN + w) * fbc + ((c + w) & (fbc - 1u))];
-    }
-    for (int k = 0; k < a.K; ++k) {
-      const int g = a.gmap[k];
-      const uint32_t val = g == 0 ? v[0] : (g == 1 ? v[1] : (g == 2 ? v[2] : v[3]));
-      if (val)
-        __hip_atomic_fetch_add(xs + (size_t)k * NN + (((a.tmask >> k) & 1ull) ? j * N + i : w), val,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      uint32_t v = 0;
+      for (uint32_t c = 0; c < fbc; ++c) v += fbw[((uint32_t)g * NN + w) * fbc + ((c + w) & (fbc - 1u))];
+      if (v == 0u) continue;
+      for (unsigned long long m = km[g]; m; m &= m - 1ull) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(m);
+        __hip_atomic_fetch_add(xs + (size_t)k * NN + (((tmask >> k) & 1ull) ? j * N + i : w), v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
     }
   }
 }

@@ -67,7 +67,7 @@ struct VoteArgs {
 // codes per block instead of four pairs:
 //   code 1 = 16 a + 4 (d - a + 1) + (b - a + 1) = 11 a + b + 4 d + 5
 //            (the block's (1,0), (-1,1) and (0,1) pairs),
-//   code 2 = 12 a + (e - a + 1)                = 11 a + e + 1
+//   code 2 = 16 a + 4 (e - a + 1) + (b - a + 1) = 11 a + b + 4 e + 5
 //            (its (1,1) pair),
 // exact whenever the three differences lie in [-1, 2]; blocks outside that
 // window are corrected one pair at a time.  Block GLCM g of the four above.
@@ -80,22 +80,23 @@ struct BlockArgs {
   Quant q;
   int qfast;
   uint32_t qfast_shift, qfast_mask;
-  int K;                      // requested offsets
-  int32_t gmap[kMaxK];        // block GLCM of offset k (0..3)
+  unsigned long long kmask[kBlockGlcms];  // bit k of kmask[g]: offset k is block direction g or its opposite
   unsigned long long tmask;   // bit k: offset k is the opposite of its block direction (stored transposed)
   int nregions, region_rows, strip_rows;
   uint32_t nbins;             // code bins: 16 N + 6 (every level combination, sentinel included, lands inside)
   int fb_copies;              // copies of the block GLCMs (1, 2 or 4; lane mod fb_copies)
   Quant div_n;                // magic/shift for dividing by N
   uint32_t words_total;       // K N N
-  uint32_t* xbuf;             // [kXcdSlots][words_total] per-XCD accumulators
+  uint32_t* xbuf;             // accumulation slices [xslots * spread][words_total]: slice
+                              // XCC_ID + xslots * s for the workgroups b with (b / 8) mod spread = s
+  uint32_t xslots, spread;    // XCC_IDs the device reports; slices per XCD (a power of two)
 };
 // LDS bytes of the block kernel: code bins (32 dwords each), the four block
-// GLCMs in fbc copies (N^2 words each), one trash word per lane and a queue
-// of 128 blocks (8 bytes each) per wavefront of a 1024-thread workgroup.
+// GLCMs in fbc copies (N^2 words each), one trash word per lane, a queue of
+// 512 dwords with blocks outside the code window (32 bytes each) and its count.
 inline size_t block_lds_bytes(int N, int fbc) {
   return (16u * (size_t)N + 6u) * 128u + (size_t)kBlockGlcms * (size_t)N * (size_t)N * (size_t)fbc * 4u + 64u * 4u +
-         16u * 128u * 8u;
+         512u * 32u + 16u;
 }
 
 // One image of a batch as the batch kernel reads it (device memory, 32 bytes).

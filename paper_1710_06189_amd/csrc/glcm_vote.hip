@@ -104,20 +104,22 @@ __device__ void store_partial_bin_pairs(const VoteArgs& a, const uint32_t* lds, 
   }
 }
 
-// out[w] = (accumulate ? out[w] : 0) + sum of the first nslots XCD slices
-// (the slices of XCC_IDs the device has; the others stay zero); clears them.
+// out[w] = (accumulate ? out[w] : 0) + sum of the first nslots accumulation
+// slices (the others stay zero); clears them.
 __global__ __launch_bounds__(256) void k_finish(uint32_t* xbuf, uint32_t* out, uint32_t M, uint32_t nslots,
                                                 int accumulate) {
   const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= M) return;
-  uint32_t v[kXcdSlots];
-#pragma unroll
-  for (uint32_t x = 0; x < kXcdSlots; ++x) v[x] = x < nslots ? xbuf[(size_t)x * M + w] : 0u;
   uint32_t s = accumulate ? out[w] : 0u;
+  for (uint32_t x0 = 0; x0 < nslots; x0 += kXcdSlots) {
+    uint32_t v[kXcdSlots];
 #pragma unroll
-  for (uint32_t x = 0; x < kXcdSlots; ++x) {
-    s += v[x];
-    if (x < nslots) xbuf[(size_t)x * M + w] = 0u;
+    for (uint32_t x = 0; x < kXcdSlots; ++x) v[x] = x0 + x < nslots ? xbuf[(size_t)(x0 + x) * M + w] : 0u;
+#pragma unroll
+    for (uint32_t x = 0; x < kXcdSlots; ++x) {
+      s += v[x];
+      if (x0 + x < nslots) xbuf[(size_t)(x0 + x) * M + w] = 0u;
+    }
   }
   out[w] = s;
 }

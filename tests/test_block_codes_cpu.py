@@ -1,15 +1,14 @@
 """CPU replay of the block-code kernel's arithmetic (no GPU).
 
 The block kernel (d = 1 directions) votes two codes per 2x2 block,
-    code 1 = 11 a + b + 4 d + 5,   code 2 = 11 a + e + 1,
-finds the blocks whose differences b - a, d - a, e - a leave [-1, 2] with a
-byte-wise test on packed levels (3 subtractions and a mask per 4 pixels, where
-a negative digit borrows from the byte above it, so every pixel from the lowest
-set byte of a dword upwards is corrected), takes those votes back and counts
-their four pairs one by one, and finally decodes the code counts.  This
+    code 1 = 11 a + b + 4 d + 5,   code 2 = 11 a + b + 4 e + 5,
+finds the blocks whose differences b - a, d - a, e - a leave [-1, 2] with an
+exact byte-wise test on packed levels (each digit X - a biased by 0x40, so no
+byte borrows from the next), takes those votes back and counts their four
+pairs one by one, and finally decodes the code counts.  This
 test replays exactly that arithmetic in numpy (32-bit wrap-around included) and
 checks:
-  * every block outside the window is found (no block escapes the correction);
+  * the byte test flags exactly the blocks outside the window;
   * every code, of any level combination with the sentinel, lies inside the
     code table (16 N + 6 bins), so no vote or take-back leaves it;
   * the decoded counts plus the corrections equal the oracle's four GLCMs on
@@ -46,31 +45,27 @@ def replay(q, N):
     e = L[1:H + 1, 1:Wp + 1]
     nbins = 16 * N + 6
     k1 = 11 * a + b + 4 * d + 5
-    k2 = 11 * a + e + 1
+    k2 = 11 * a + b + 4 * e + 5
     assert k1.min() >= 0 and k1.max() < nbins and k2.min() >= 0 and k2.max() < nbins
     c1 = np.bincount(k1.ravel(), minlength=nbins).astype(np.int64)
     c2 = np.bincount(k2.ravel(), minlength=nbins).astype(np.int64)
 
-    # the byte test, per lane chunk of 16 pixels as 4 packed dwords
+    # the window test, per lane chunk of 16 pixels as 4 packed dwords: digits
+    # X - a + 0x40 for X = b + 1, d + 1, e + 1, in window iff 0x40..0x43
     shp = (H, chunks, 16)
-    La = pack(a.reshape(shp))
-    Rb1 = pack((b + 1).reshape(shp))
-    Ld1 = pack((d + 1).reshape(shp))
-    Re1 = pack((e + 1).reshape(shp))
     m32 = np.uint64(0xFFFFFFFF)
-    o = (((Rb1 - La) & m32) | ((Ld1 - La) & m32) | ((Re1 - La) & m32)) & np.uint64(0xFCFCFCFC)
-    # a borrow only moves the bytes above the one it comes from, so every
-    # pixel from the lowest set byte of a dword upwards is corrected
+    lb = (pack(a.reshape(shp)) - np.uint64(0x40404040)) & m32
+    db = (pack((b + 1).reshape(shp)) - lb) & m32
+    dd = (pack((d + 1).reshape(shp)) - lb) & m32
+    de = (pack((e + 1).reshape(shp)) - lb) & m32
+    o = ((~(db & dd & de) & np.uint64(0x40404040)) | ((db | dd | de) & np.uint64(0x3C3C3C3C))) & m32
     flagged = np.zeros(shp, dtype=bool)
-    seen = np.zeros(o.shape, dtype=bool)
     for j in range(4):
-        byte = (o >> np.uint64(8 * j)) & np.uint64(0xFF)
-        seen |= byte != 0
-        flagged[..., j::4] = seen
+        flagged[..., j::4] = ((o >> np.uint64(8 * j)) & np.uint64(0xFF)) != 0
     flagged = flagged.reshape(H, Wp)
     outside = ~(((b - a) >= -1) & ((b - a) <= 2) & ((d - a) >= -1) & ((d - a) <= 2) &
                 ((e - a) >= -1) & ((e - a) <= 2))
-    assert not np.any(outside & ~flagged), "a block outside the window was not found"
+    assert np.array_equal(outside, flagged), "the byte test differs from the window"
 
     # corrections: take back both codes, count the four pairs into the
     # block GLCMs with a sentinel row and column
@@ -97,10 +92,10 @@ def replay(q, N):
             fb[1, bv, dv] += c
         if 0 <= dv < N:
             fb[2, av, dv] += c
-    for bin_ in np.nonzero(c2)[0]:
-        av, de = divmod(int(bin_), 12)
-        ev = av + de - 1
-        if de <= 3 and av < N and 0 <= ev < N:
+    for bin_ in np.nonzero(c2[:16 * N])[0]:
+        av = bin_ >> 4
+        ev = av + ((bin_ >> 2) & 3) - 1
+        if 0 <= ev < N:
             fb[3, av, ev] += c2[bin_]
     return fb[:, :N, :N]
 
@@ -130,10 +125,13 @@ def test_block_codes_equal_oracle(name, make, N):
 
 
 def test_every_code_inside_table_for_all_level_combinations():
-    for N in (1, 2, 7, 32, 54):
+    for N in (1, 2, 7, 32, 54, 62):
         lv = np.arange(N + 1)
         a, b, d, e = np.meshgrid(lv, lv, lv, lv, indexing="ij")
         k1 = 11 * a + b + 4 * d + 5
-        k2 = 11 * a + e + 1
+        k2 = 11 * a + b + 4 * e + 5
         assert k1.min() >= 0 and k1.max() < 16 * N + 6
         assert k2.min() >= 0 and k2.max() < 16 * N + 6
+        # biased digits of the window test: no borrow, bit 7 clear
+        x = (lv + 1)[:, None] - lv[None, :] + 0x40
+        assert x.min() >= 0 and x.max() < 0x80
