@@ -5,14 +5,19 @@ Workload: one 4096x4096 uint8 image (smooth: Gaussian noise blurred with
 sigma = 8 px, min-max rescaled), N = 32 levels over [0, 255], the four d = 1
 offsets of Eq. (2); output [4, 32, 32] uint32.  A step is one glcm_compute
 call on a device-resident image (quantize, pair visit, LDS vote, merge).
-Timed steps rotate over enough device copies of the image (> 256 MiB in
-total) that every step reads its input from HBM rather than from the
-Infinity Cache.  Every copy's result is checked bit-exact against the CPU
-oracle.  The plan keeps its default LDS layout (the layout heuristic's
-pick, which the layout sweep finds fastest on all three images) unless
---autotune asks glcm_plan_autotune to time the candidates first (untimed).
-`extra.cache_hot_gpairs_s` repeats the timed loop on one image copy, which
-then stays in the Infinity Cache: labelled, never the headline value.
+Timed steps rotate over 32 device copies of the image (512 MiB), the
+rotation continuing from the warm-up, and 512 MiB of scratch are written just
+before the timed loop: every step reads a copy last touched at least 496 MiB
+of traffic earlier, so from HBM rather than from the 256 MiB Infinity Cache.
+Every copy's result is checked bit-exact against the CPU oracle.  The plan is
+tuned first (untimed) by glcm_plan_autotune on one copy of the same image:
+it times the LDS layouts of the strip kernel and, the offsets being the d = 1
+directions, the block-code kernel, and keeps the fastest (--no-autotune keeps
+the default layout, --layout fixes one).  `extra.cache_hot_gpairs_s` repeats
+the timed loop on one image copy, which then stays in the Infinity Cache:
+labelled, never the headline value.  `extra.batch` carries the batch
+workload's ratio of one fused launch over per-tile calls and its graph-replay
+time (bench_batch).
 
 Prints one JSON line.  `value` is pairs per second over the timed steps
 (wall clock, both kernels of each call).  `roofline` prices the dominant
@@ -43,6 +48,10 @@ HBM_PEAK_GBS = 8000.0
 VOTE_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)
                 for f in ("glcm_vote.hip", "glcm_device.h", "glcm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vote_strips_4096x4096_u8_smooth_traffic.json")
+# the same for the block-code kernel (the autotuner's pick on smooth images)
+BLOCK_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)
+                 for f in ("glcm_blocks.hip", "glcm_device.h", "glcm_internal.h")]
+BLOCK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vote_blocks_4096x4096_u8_smooth_traffic.json")
 # the same for the histogram kernel
 HIST_SOURCES = [os.path.join(ROOT, "paper_1710_06189_amd", "csrc", f)
                 for f in ("glcm_hist.hip", "glcm_device.h", "glcm_hist.h", "glcm_internal.h")]
@@ -54,7 +63,7 @@ HARALICK_VALU_FILE = os.path.join(ROOT, "profiles", "haralick_16384x16x16_glcm_l
 # VALU issue peak: 256 CUs x 2.4 GHz x one wave64 instruction per CU-cycle
 # (four SIMDs, each finishing a 64-lane instruction every 4 cycles on 16 lanes)
 VALU_PEAK_G = 256 * 2.4 * 1.0
-TUNING_KEYS = ("replicas", "wg_size", "counter_bits", "merge", "partitions")
+TUNING_KEYS = ("path", "replicas", "wg_size", "counter_bits", "merge", "partitions")
 
 
 def pairs_of(W, H, offsets):
@@ -70,14 +79,16 @@ def kernel_source_sha256(paths=None):
 
 
 def recorded_traffic(tuning):
-    """HBM bytes per vote-kernel launch from the committed counter summary,
-    or None when the kernel source or the layout differ from what was measured."""
+    """HBM bytes per vote-kernel launch from the committed counter summary of
+    the kernel the tuning selects, or None when the kernel source or the
+    layout differ from what was measured."""
+    blocks = tuning.get("path") == 6
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(BLOCK_TRAFFIC_FILE if blocks else TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != kernel_source_sha256():
+    if rec.get("kernel_source_sha256") != kernel_source_sha256(BLOCK_SOURCES if blocks else VOTE_SOURCES):
         return None
     if any(rec.get("tuning", {}).get(k) != tuning.get(k) for k in TUNING_KEYS):
         return None
@@ -130,13 +141,14 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kind", default="smooth", choices=["smooth", "uniform", "constant"])
-    ap.add_argument("--copies", type=int, default=24)
+    ap.add_argument("--copies", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--others", action="store_true", help="also time the uniform and constant images")
     ap.add_argument("--sweep", action="store_true", help="time the LDS layouts on all three images")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the candidate layouts (glcm_plan_autotune) instead of keeping the default one")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default layout instead of timing the candidates (glcm_plan_autotune)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch workload's figures in extra")
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
     ap.add_argument("--workload", default="square",
@@ -188,17 +200,21 @@ def main():
         R, bits, wg = (int(v) for v in args.layout.split(","))
         fixed = {"replicas": R, "counter_bits": bits, "wg_size": wg}
 
+    scratch = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+
     def timed_loop(plan, copies, outs, N, lo, hi, offs, steps, warmup):
         stream = torch.cuda.current_stream()
         for i in range(warmup):
             j = i % len(copies)
             G.glcm_compute(copies[j], N, lo, hi, offs, out=outs[j], plan=plan, stream=stream)
+        # evict the Infinity Cache (a fill kernel writing 512 MiB)
+        scratch.fill_(1)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record(stream)
         for i in range(steps):
-            j = i % len(copies)
+            j = (warmup + i) % len(copies)
             G.glcm_compute(copies[j], N, lo, hi, offs, out=outs[j], plan=plan, stream=stream)
         ev1.record(stream)
         torch.cuda.synchronize()
@@ -223,18 +239,21 @@ def main():
             plan.set_tuning(**tuning)
         elif fixed:
             plan.set_tuning(**fixed)
-        elif args.autotune:
+        elif not args.no_autotune:
             plan.autotune(copies[0], lo, hi, repeats=10)
         wall, step_ms = timed_loop(plan, copies, outs, N, lo, hi, offs, args.steps, args.warmup)
-        for j in range(min(ncopies, args.steps)):
+        for j in range(min(ncopies, args.steps + args.warmup)):
             got = outs[j].view(torch.int32).cpu().numpy().view(np.uint32)
             if not np.array_equal(got, want):
                 raise SystemExit(f"bench: result of copy {j} differs from the oracle ({kind})")
         t = plan.tuning.as_dict()
         vote_ms = None
         if vote_timing:
-            tp = G.glcm_plan_create(np.uint8, N, offs, W, H, G.FLAG_TIMING)
-            tp.set_tuning(**{k: t[k] for k in ("replicas", "counter_bits", "wg_size", "merge")})
+            blocks = G.PATH_NAMES[t["path"]] == "blocks"
+            tp = G.glcm_plan_create(np.uint8, N, offs, W, H, G.FLAG_TIMING | (G.FLAG_FORCE_BLOCKS if blocks else 0))
+            if not blocks:
+                tp.set_tuning(**{k: t[k] for k in ("replicas", "counter_bits", "wg_size", "merge")})
+            assert tp.tuning.as_dict()["path"] == t["path"]
             timed_loop(tp, copies, outs, N, lo, hi, offs, args.warmup, 0)
             tp.kernel_time()  # drop the warm-up launches
             timed_loop(tp, copies, outs, N, lo, hi, offs, args.steps, 0)
@@ -282,6 +301,12 @@ def main():
     extra.update(lat)
     hot = measure(args.kind, ncopies=1)
     extra["cache_hot_gpairs_s"] = hot["pairs"] / (hot["wall_s"] / steps) / 1e9
+    if not args.no_batch:
+        b = bench_batch(args, G, torch, np, oracle, synth, dev, print_line=False)
+        extra["batch"] = {k: b[k] for k in ("workload", "tiles", "pairs", "batched_ms", "batched_device_ms",
+                                            "per_image_ms", "per_image_device_ms", "batched_over_per_image",
+                                            "graph_replay_ms", "graph_replay_gpairs_s", "autotuned_ms",
+                                            "autotuned_layout", "check")}
     if args.others:
         for kind in ("uniform", "constant", "smooth"):
             if kind == args.kind:
@@ -358,7 +383,7 @@ def call_latencies(G, torch, np, synth, dev, args, calls=200):
     if args.layout:
         R, bits, wg = (int(v) for v in args.layout.split(","))
         plan.set_tuning(replicas=R, counter_bits=bits, wg_size=wg)
-    elif args.autotune:
+    elif not args.no_autotune:
         plan.autotune(copies[0], lo, hi, repeats=10)
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
@@ -383,7 +408,7 @@ def call_latencies(G, torch, np, synth, dev, args, calls=200):
             "latency_calls": calls}
 
 
-def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
+def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20, print_line=True):
     """4096 uint8 tiles (sides log-uniform in [32, 512], half noise, half
     smooth), N = 16, d = 1 at four angles, counts plus the five statistics:
     one fused launch for the whole batch against one glcm_compute +
@@ -475,7 +500,7 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
     for t in range(0, T, max(1, T // 64)):
         if not np.array_equal(got[t], oracle.glcm(imgs[t], N, 0, 255, offs)):
             raise SystemExit(f"bench: tile {t} differs from the oracle")
-    print(json.dumps({
+    res = {
         "workload": w["name"], "tiles": T, "pixels": px, "pairs": pairs, "aligned_tiles": aligned,
         "input_sha256": hashlib.sha256("".join(synth.sha256(im) for im in imgs).encode()).hexdigest(),
         "batched_gpairs_s": pairs / batch_wall / 1e9, "batched_ms": batch_wall * 1e3,
@@ -486,8 +511,10 @@ def bench_batch(args, G, torch, np, oracle, synth, dev, reps=20):
         "default_layout": default_tuning, "autotuned_layout": chosen, "autotuned_ms": tuned_wall * 1e3,
         "autotuned_gpairs_s": pairs / tuned_wall / 1e9,
         "features": True, "check": "batched == per-image calls == graph replay (counts and statistics); "
-                                   "64 tiles vs oracle"}),
-        flush=True)
+                                   "64 tiles vs oracle"}
+    if print_line:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 def time_oracle(fn, seconds):

@@ -199,10 +199,8 @@ struct glcm_plan_s {
   size_t partials_bytes = 0;
   void* stage = nullptr;  // aligned copy of a misaligned device image (row pitch a multiple of 16 bytes)
   size_t stage_bytes = 0;
-  uint32_t* xbuf = nullptr;  // [xalloc][K*N*N] accumulation slices, kept zero between calls
+  uint32_t* xbuf = nullptr;  // [kXcdSlots][K*N*N] accumulation slices, kept zero between calls
   uint32_t xslots = glcm::kXcdSlots;  // slices the device's XCC_IDs reach (the rest stay zero)
-  uint32_t spread = 1;                // block kernel: slices per XCD (xslots * spread in use)
-  uint32_t xalloc = glcm::kXcdSlots;  // slices allocated
 
 
   // ordering across streams
@@ -521,15 +519,7 @@ int plan_init(glcm_plan_t p) {
     const size_t glcm_bytes = (size_t)p->K * p->N * p->N * 4u;
     if ((size_t)glcm::kXcdSlots * glcm_bytes <= (256u << 20)) {
       p->xslots = xcc_slots(p->device);
-      // the block kernel spreads each XCD's workgroups over up to 8 slices
-      // (fewer workgroups adding into one address when they finish), as far
-      // as 16 MiB of slices allow
-      if (p->tuning.path == kPathBlocks) {
-        p->spread = 8;
-        while (p->spread > 1 && (size_t)p->xslots * p->spread * glcm_bytes > (16u << 20)) p->spread /= 2;
-      }
-      p->xalloc = std::max<uint32_t>(glcm::kXcdSlots, p->xslots * p->spread);
-      const size_t bytes = (size_t)p->xalloc * glcm_bytes;
+      const size_t bytes = (size_t)glcm::kXcdSlots * glcm_bytes;
       GLCM_TRY(hipMalloc((void**)&p->xbuf, bytes));
       // zeroed before the plan is returned: its first call may come on a
       // non-blocking stream, which is not ordered after the null stream
@@ -718,8 +708,6 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
     ba.div_n = a.div_n;
     ba.words_total = words;
     ba.xbuf = p->xbuf;
-    ba.xslots = p->xslots;
-    ba.spread = p->spread;
     // bands: one workgroup of 16 wavefronts per band, as many bands as the
     // CUs hold at once, each tall enough for strips of >= 4 rows on every
     // wavefront; a band holds fewer than 2^17 chunk pixels (the merge adds
@@ -745,7 +733,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
       GLCM_TRY(hipEventCreate(&tm.stop));
       p->timing.emplace_back(tm.start, tm.stop);
     }
-    const uint32_t nslots = p->xslots * p->spread;
+    const uint32_t nslots = p->xslots;
     hipError_t e = glcm::launch_vote_blocks(ba, b, kWg, stream, tm);
     if (e == hipSuccess && finish) e = glcm::launch_finish(p->xbuf, out, words, nslots, accumulate, stream);
     if (e != hipSuccess) {
@@ -993,7 +981,7 @@ int count_host(glcm_plan_t p, const void* img, bool pinned, int W, int H, int64_
 
 size_t plan_device_bytes(const glcm_plan_s* p) {
   size_t b = p->partials_bytes + p->batch_cap + p->stage_bytes;
-  if (p->xbuf) b += (size_t)p->xalloc * (size_t)p->k_cap * p->N * p->N * 4u;
+  if (p->xbuf) b += (size_t)glcm::kXcdSlots * (size_t)p->k_cap * p->N * p->N * 4u;
   for (int s = 0; s < glcm_plan_s::kSlots; ++s)
     if (p->dev_tile[s]) b += p->tile_bytes;
   return b;
@@ -1244,7 +1232,9 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
   // candidates: copies x counter width x workgroup size, within 4x the
   // minimal number of partitions
   std::vector<glcm_tuning_t> cand;
-  if (start.path == kPathStrips) {
+  if (start.path == kPathBlocks) {
+    cand.push_back(start);  // forced by GLCM_FLAG_FORCE_BLOCKS: its layout is fixed
+  } else if (start.path == kPathStrips) {
     const int Pmin = strip_partitions(plan, 4, 16);
     for (int bits : {32, 16})
       for (int R = 4; R <= 32; R *= 2) {
@@ -1259,6 +1249,19 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
           cand.push_back(t);
         }
       }
+    // the block-code kernel, where every offset is a d = 1 direction: faster
+    // on smooth images, slower where most 2x2 blocks leave its code window
+    // (noise), which is what the timing decides
+    if (plan->xbuf && blocks_fit(plan)) {
+      glcm_tuning_t t = start;
+      t.path = kPathBlocks;
+      t.replicas = 32;
+      t.counter_bits = 16;
+      t.partitions = 1;
+      t.wg_size = 1024;
+      t.merge = 0;
+      cand.push_back(t);
+    }
   } else if (start.path == kPathRows) {
     const int Pmin = row_partitions(plan, 1, 32);
     for (int bits : {32, 16})

@@ -7,23 +7,26 @@
 // Section II.A are for) the levels of a block differ by at most one or two,
 // so a block is summarised by two codes that carry its four pairs:
 //
-//   code 1 = 16 a + 4 (d - a + 1) + (b - a + 1) = 11 a + b + 4 d + 5
-//   code 2 = 16 a + 4 (e - a + 1) + (b - a + 1) = 11 a + b + 4 e + 5
+//   code 1 = 16 a + 4 (b - a + 1) + (d - a + 1) = 11 a + 4 b + d + 5
+//   code 2 = 16 a + 4 (b - a + 1) + (e - a + 1) = 11 a + 4 b + e + 5
 //
 // Both are exact (decodable back to the pairs) when b - a, d - a and e - a lie
 // in [-1, 2]; code 1 carries the pairs (a, b), (b, d), (a, d), code 2 the pair
-// (a, e), and the two share their first-row part 11 a + b.  Every block votes both codes unconditionally (two LDS atomics
-// per first pixel instead of four); a cheap byte-wise test then finds the
-// blocks outside the window, whose two votes are taken back and whose four
+// (a, e).  The two share their upper-row part 11 a + 4 b + 5, and the lower
+// row enters with weight one, so each vote address is one addition of two
+// per-pixel terms.  Every block votes both codes unconditionally (two LDS
+// atomics per first pixel instead of four); a cheap byte-wise test then finds
+// the blocks outside the window, whose two votes are taken back and whose four
 // pairs are counted one by one.  The codes are linear in the four levels, so
 // every level combination (sentinel included) lands inside the code table and
 // a vote that is taken back never touches memory outside it.
 //
 // LDS: code bins [0, 16 N + 6), 32 dwords each (copy = lane mod 32, so the 32
 // lanes of an LDS pass always write 32 different banks); the low half of a
-// dword counts code 1, the high half code 2.  Then the four block GLCMs with a
-// sentinel row and column ((N + 1)^2 words each), which receive the corrected
-// pairs and, at the end, the decoded code counts.
+// dword counts code 1, the high half code 2.  Then the four block GLCMs (N^2
+// words each, in 1, 2 or 4 copies), which receive the corrections and, at the
+// end, the decoded code counts; a trash word per lane takes the pairs with a
+// level outside [0, N).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -36,21 +39,26 @@ namespace glcm {
 namespace {
 
 constexpr uint32_t kOnes = 0x01010101u;
-constexpr uint32_t kWindow = 0xfcfcfcfcu;  // digit bytes outside [0, 3]
 constexpr uint32_t kBin = 128u;            // bytes per code bin (32 copies)
+constexpr int kDppQuadSwap1 = 0xb1;       // DPP quad_perm [1, 0, 3, 2]: lane l receives lane l ^ 1
+// Window test bias: a digit X - a + 1 (X = b, d or e) is formed per byte as
+// X - (a - kDigitBias) = X - a + 1 + 0x40, so that no byte borrows from the
+// next (every byte stays in [0, 0x80) for N <= 62) and a digit in [0, 3]
+// reads 0x40..0x43: bit 6 set, bits 2..5 clear.
+constexpr uint32_t kDigitBias = 0x41414141u;
 
 // A row as the lower row of the blocks of the row above it.
 struct Lower {
   uint32_t s[17];  // kBin * level of chunk pixels 0..15 and of the pixel right of the chunk
-  uint32_t l1[4];  // levels + 1 of pixels 0..15, packed bytes
-  uint32_t r1[4];  // levels + 1 of pixels 1..16, packed bytes
+  uint32_t l[4];   // levels of pixels 0..15, packed bytes
+  uint32_t r[4];   // levels of pixels 1..16, packed bytes
 };
 
 // A row as the upper row (its pixels are the first pixels a).
 struct Upper {
-  uint32_t w[16];  // kBin * (11 a + b) + lane offset
-  uint32_t l[4];   // levels a, packed
-  uint32_t r1[4];  // levels + 1 of the right neighbours b, packed
+  uint32_t w[16];  // kBin * (11 a + 4 b + 5) + lane offset
+  uint32_t lb[4];  // a - kDigitBias (32-bit difference of the packed levels)
+  uint32_t db[4];  // b - lb: the biased digits b - a + 1 + 0x40, one per byte
 };
 
 // One row as a lane loads it: its 16-pixel chunk and the 4 pixels right of
@@ -106,17 +114,36 @@ __device__ __forceinline__ void quant_chunk(uint32_t (&c)[4], uint32_t& rh, cons
   }
 }
 
-// Raw row -> lower form.  Pixels at or past W (edge strips only) and rows at
-// or below H take the sentinel level N; the pixel right of the chunk comes
-// from the next lane (the last lane of the wavefront uses the halo it loaded).
+// kBin * byte j of v, in one instruction (the byte selected by SDWA).
+template <int J>
+__device__ __forceinline__ uint32_t byte_bin(uint32_t v, uint32_t seven) {
+  uint32_t r;
+  if (J == 0)
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r) : "v"(seven), "v"(v));
+  else if (J == 1)
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+        : "=v"(r) : "v"(seven), "v"(v));
+  else if (J == 2)
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+        : "=v"(r) : "v"(seven), "v"(v));
+  else
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+        : "=v"(r) : "v"(seven), "v"(v));
+  return r;
+}
+
+// Raw row (inside the image) -> lower form.  Pixels at or past W (edge strips
+// only) take the sentinel level N; the pixel right of the chunk comes from the
+// next lane (the last lane of the wavefront uses the halo it loaded).  seven:
+// a register holding 7 (log2 kBin).
 template <typename Pix, bool QF>
-__device__ __forceinline__ void to_lower(Lower& o, const BlockRaw<Pix>& rc, const BlockArgs& a, int y, int x0,
-                                         uint32_t sent4, bool edge) {
+__device__ __forceinline__ void to_lower(Lower& o, const BlockRaw<Pix>& rc, const BlockArgs& a, int x0,
+                                         uint32_t sent4, bool edge, uint32_t seven) {
+  static_assert(kBin == 128u, "byte_bin shifts by 7");
   uint32_t c[4], rh;
   quant_chunk<Pix, QF>(c, rh, rc, a);
-  if (y >= a.H) {
-    c[0] = c[1] = c[2] = c[3] = rh = sent4;
-  } else if (edge) {
+  if (edge) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) c[m] = clip_dword(c[m], x0 + 4 * m, a.W, sent4);
     rh = clip_dword(rh, x0 + 16, a.W, sent4);
@@ -126,21 +153,34 @@ __device__ __forceinline__ void to_lower(Lower& o, const BlockRaw<Pix>& rc, cons
                          __builtin_amdgcn_alignbyte(c[3], c[2], 1u), __builtin_amdgcn_alignbyte(nx, c[3], 1u)};
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    o.l1[m] = c[m] + kOnes;
-    o.r1[m] = r[m] + kOnes;
+    o.l[m] = c[m];
+    o.r[m] = r[m];
   }
 #pragma unroll
-  for (int t = 0; t < 16; ++t) o.s[t] = __umul24((c[t >> 2] >> ((t & 3) * 8)) & 0xffu, kBin);
-  o.s[16] = __umul24(nx & 0xffu, kBin);
+  for (int m = 0; m < 4; ++m) {
+    o.s[4 * m] = byte_bin<0>(c[m], seven);
+    o.s[4 * m + 1] = byte_bin<1>(c[m], seven);
+    o.s[4 * m + 2] = byte_bin<2>(c[m], seven);
+    o.s[4 * m + 3] = byte_bin<3>(c[m], seven);
+  }
+  o.s[16] = byte_bin<0>(nx, seven);
 }
 
-__device__ __forceinline__ void to_upper(Upper& t, const Lower& lo, uint32_t lane_off) {
+// 11 s + t in one instruction (the compiler would split it into three).
+__device__ __forceinline__ uint32_t mad11(uint32_t s, uint32_t t) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, 11, %2" : "=v"(r) : "v"(s), "v"(t));
+  return r;
+}
+
+// c5 = lane offset + 5 kBin.
+__device__ __forceinline__ void to_upper(Upper& t, const Lower& lo, uint32_t c5) {
 #pragma unroll
-  for (int x = 0; x < 16; ++x) t.w[x] = __umul24(lo.s[x], 11u) + lo.s[x + 1] + lane_off;
+  for (int x = 0; x < 16; ++x) t.w[x] = mad11(lo.s[x], (lo.s[x + 1] << 2) + c5);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    t.l[m] = lo.l1[m] - kOnes;
-    t.r1[m] = lo.r1[m];
+    t.lb[m] = lo.l[m] - kDigitBias;
+    t.db[m] = lo.r[m] - t.lb[m];
   }
 }
 
@@ -158,42 +198,53 @@ struct Fb {
   uint32_t base;     // LDS byte address of FB[0][0][0] copy 0
   uint32_t trash;    // LDS byte address of this lane's trash word
   uint32_t lane_c;   // 4 * (lane mod fbc)
-  uint32_t stride;   // bytes per bin: 4 * fbc
+  uint32_t sshift;   // log2 of the bytes per bin (4 * fbc)
   uint32_t N;
+  // byte offset of FB[g][i][j] copy 0 from base (24-bit products: the
+  // indices of a pair that is counted are below N <= 62; others only form a
+  // discarded address)
+  __device__ __forceinline__ uint32_t at(uint32_t g, uint32_t i, uint32_t j) const {
+    return (__umul24(__umul24(g, N) + i, N) + j) << sshift;
+  }
 };
 
 __device__ __forceinline__ void fb_add(const Fb& f, uint32_t g, uint32_t i, uint32_t j) {
-  const uint32_t at = f.base + ((g * f.N + i) * f.N + j) * f.stride + f.lane_c;
+  const uint32_t at = f.base + f.at(g, i, j) + f.lane_c;
   lds_add((i < f.N && j < f.N) ? at : f.trash, 1u);
 }
 
+
 // Blocks outside the window.  A lane's dword m of a row (four blocks) with
-// any block outside the window is queued for the whole workgroup: the four
-// level dwords it needs (a, b + 1, d + 1, e + 1 of its four pixels), the
-// mask of its blocks outside the window and the code copy its votes went to.
-// After the rows, every thread of the workgroup takes queued dwords and
-// corrects their blocks: both code votes taken back, the four pairs counted
-// one by one.  A dword that finds the queue full is corrected at once by its
-// own lane.
-constexpr uint32_t kQueue = 512;  // queued dwords per workgroup
+// any block outside the window is queued: the four level dwords it needs (a,
+// b, d, e of its four blocks), the mask of its blocks outside the window and
+// the code copy its votes went to.
+// Each wavefront has a queue of its own, so that a reservation is a scalar
+// addition (a returning LDS atomic would wait for every vote the wavefront has
+// in flight).  After the rows, every thread of the workgroup takes queued
+// dwords and corrects their blocks.  A dword that finds its queue full is
+// corrected at once by its own lane.
+constexpr uint32_t kQueue = 512;                  // queued dwords per workgroup
+constexpr uint32_t kQueueWave = kQueue / 16u;     // per wavefront (up to 16 per workgroup)
 
 struct Pending {
-  uint32_t a, b1, d1, e1;  // packed levels of four blocks: a, b + 1, d + 1, e + 1
-  uint32_t out;            // bytes of the blocks outside the window (bits of kWindow)
-  uint32_t copy;           // code copy of the votes (lane mod 32)
+  uint32_t a, b, d, e;  // packed levels of four blocks
+  uint32_t out;         // nonzero bytes: the blocks outside the window
+  uint32_t copy;        // code copy of the votes (lane mod 32)
 };
 
-// Corrects the blocks of p marked in p.out.
+// Corrects the blocks of p marked in p.out: both code votes taken back from
+// the lane's code copy, the four pairs counted one by one.
 __device__ __forceinline__ void correct_blocks(const Pending& p, uint32_t code_base, const Fb& f) {
   uint32_t pend = p.out;
   const uint32_t lane_off = code_base + 4u * p.copy;
   while (pend) {
     const uint32_t sh = (uint32_t)__builtin_ctz(pend) & ~7u;
     pend &= ~(0xffu << sh);
-    const uint32_t av = (p.a >> sh) & 0xffu, bv = ((p.b1 >> sh) & 0xffu) - 1u, dv = ((p.d1 >> sh) & 0xffu) - 1u,
-                   ev = ((p.e1 >> sh) & 0xffu) - 1u;
-    lds_sub(kBin * (11u * av + bv + 4u * dv + 5u) + lane_off, 1u);
-    lds_sub(kBin * (11u * av + bv + 4u * ev + 5u) + lane_off, 1u << 16);
+    const uint32_t av = (p.a >> sh) & 0xffu, bv = (p.b >> sh) & 0xffu, dv = (p.d >> sh) & 0xffu,
+                   ev = (p.e >> sh) & 0xffu;
+    const uint32_t u = __umul24(av, 11u) + 4u * bv + 5u;
+    lds_sub(kBin * (u + dv) + lane_off, 1u);
+    lds_sub(kBin * (u + ev) + lane_off, 1u << 16);
     fb_add(f, 0u, av, bv);
     fb_add(f, 1u, bv, dv);
     fb_add(f, 2u, av, dv);
@@ -206,32 +257,28 @@ __device__ __forceinline__ void correct_blocks(const Pending& p, uint32_t code_b
 // lower row lies below the image (the last image row) holds only (1,0)
 // pairs, counted directly.
 __device__ __forceinline__ void block_row(const Upper& t, const Lower& lo, uint32_t copy, uint32_t code_base,
-                                          const Fb& f, uint4* queue, uint32_t* qcount, bool last) {
+                                          const Fb& f, uint4* wq, uint32_t& qn, bool last) {
   if (last) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m) {
+      const uint32_t av = t.lb[m] + kDigitBias, bv = t.db[m] + t.lb[m];
 #pragma unroll
-      for (uint32_t sh = 0; sh < 32; sh += 8)
-        fb_add(f, 0u, (t.l[m] >> sh) & 0xffu, ((t.r1[m] >> sh) & 0xffu) - 1u);
+      for (uint32_t sh = 0; sh < 32; sh += 8) fb_add(f, 0u, (av >> sh) & 0xffu, (bv >> sh) & 0xffu);
+    }
     return;
   }
 #pragma unroll
   for (int x = 0; x < 16; ++x) {
-    lds_add((lo.s[x] << 2) + t.w[x] + 5u * kBin, 1u);            // code 1
-    lds_add((lo.s[x + 1] << 2) + t.w[x] + 5u * kBin, 1u << 16);  // code 2
+    lds_add(t.w[x] + lo.s[x], 1u);             // code 1
+    lds_add(t.w[x] + lo.s[x + 1], 1u << 16);   // code 2
   }
-  // Digits b - a + 1, d - a + 1, e - a + 1, four per dword, each biased by
-  // 0x40 (X - (a - 0x40404040) = X - a + 0x40 per byte, every byte in
-  // [0, 0x80) for N <= 62, no borrow): a block lies in the window iff its
-  // three digit bytes are in [0x40, 0x43], i.e. have bit 6 set and bits 2..5
-  // clear.
-  constexpr uint32_t kBias = 0x40404040u;
+  // The biased digits of b, d and e (kDigitBias): a block lies in the window
+  // iff its three digit bytes have bit 6 set and bits 2..5 clear.
   uint32_t bad[4], any = 0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const uint32_t lb = t.l[m] - kBias;
-    const uint32_t db = t.r1[m] - lb, dd = lo.l1[m] - lb, de = lo.r1[m] - lb;
-    bad[m] = (~(db & dd & de) & kBias) | ((db | dd | de) & 0x3c3c3c3cu);  // nonzero bytes: outside the window
+    const uint32_t db = t.db[m], dd = lo.l[m] - t.lb[m], de = lo.r[m] - t.lb[m];
+    bad[m] = (~(db & dd & de) & 0x40404040u) | ((db | dd | de) & 0x3c3c3c3cu);  // nonzero bytes: outside
     any |= bad[m];
   }
   if (__ballot(any != 0u) == 0ull) return;
@@ -244,19 +291,17 @@ __device__ __forceinline__ void block_row(const Upper& t, const Lower& lo, uint3
     bal[m] = __ballot(bad[m] != 0u);
     total += (uint32_t)__popcll(bal[m]);
   }
-  uint32_t first = 0;
-  if (__lane_id() == 0u)
-    first = __hip_atomic_fetch_add(qcount, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane((int)first);
+  uint32_t slot = qn;
+  qn += total;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     if (bad[m]) {
       const uint32_t s = slot + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[m] >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal[m], 0u));
-      const Pending p{t.l[m], t.r1[m], lo.l1[m], lo.r1[m], bad[m], copy};
-      if (s < kQueue) {
-        queue[2u * s] = make_uint4(p.a, p.b1, p.d1, p.e1);
-        queue[2u * s + 1u] = make_uint4(p.out, p.copy, 0u, 0u);
+      const Pending p{t.lb[m] + kDigitBias, t.db[m] + t.lb[m], lo.l[m], lo.r[m], bad[m], copy};
+      if (s < kQueueWave) {
+        wq[2u * s] = make_uint4(p.a, p.b, p.d, p.e);
+        wq[2u * s + 1u] = make_uint4(p.out, p.copy, 0u, 0u);
       } else {
         correct_blocks(p, code_base, f);
       }
@@ -296,6 +341,12 @@ __device__ __forceinline__ unsigned long long keep64(unsigned long long v) {
   return r;
 }
 
+// v, hidden from the compiler's arithmetic simplification.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // A uniform value moved into a vector register (so that loads addressed by it
 // stay vector loads).
 __device__ __forceinline__ uint32_t vgpr(uint32_t v) {
@@ -312,17 +363,22 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwaves = blockDim.x >> 6;
   const uint32_t base = lds_address(lds);
-  const uint32_t lane_off = base + 4u * (uint32_t)(lane & 31);
   const uint32_t fbc = keep((uint32_t)a.fb_copies), nbins = keep(a.nbins);
   const uint32_t fbw0 = nbins * (kBin / 4u);                      // word index of FB
   const uint32_t fbwords = (uint32_t)kBlockGlcms * N * N * fbc;
   const Fb f{base + fbw0 * 4u, base + (fbw0 + fbwords) * 4u + 4u * (uint32_t)lane, 4u * ((uint32_t)lane & (fbc - 1u)),
-             4u * fbc, N};
-  // the workgroup's queue of dwords with blocks outside the window, and its count
+             2u + (uint32_t)__builtin_ctz(fbc), N};
+  // the wavefronts' queues of dwords with blocks outside the window, and their counts
   uint4* queue = (uint4*)(lds + fbw0 + fbwords + 64u);
   uint32_t* qcount = lds + fbw0 + fbwords + 64u + kQueue * 8u;
-  const uint32_t copy = (uint32_t)lane & 31u;
+  uint4* const wq = queue + 2u * kQueueWave * (uint32_t)wave;
+  uint32_t qn = 0;
   const uint32_t sent4 = N * kOnes;
+  const uint32_t seven = vgpr(7u);
+  const uint32_t copy = (uint32_t)lane & 31u;
+  // the lane's code copy plus the codes' + 5 (opaque, so that the compiler
+  // keeps 4 s + c5 one instruction instead of distributing the shift)
+  const uint32_t c5 = opaque(base + 4u * (uint32_t)(lane & 31) + 5u * kBin);
   const int y0 = a.y_begin + region * a.region_rows;
   const int y1 = min(a.y_end, y0 + a.region_rows);
   const int chunks = (a.W + 15) >> 4;
@@ -335,23 +391,26 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
   // raw rows in flight: a ring of RING rows, loaded RING - 1 rows ahead
   constexpr int RING = sizeof(Pix) == 1 ? 4 : 2;
   BlockRaw<Pix> raw[RING];
+  // The first strip's first two rows (its first block row) are requested
+  // before the LDS is cleared, the rest of its ring after the barrier: every
+  // wavefront's first block row is then among the first bytes the workgroup
+  // asks for.
+  constexpr int kEarly = 2;
   int strip = wave;
   if (strip < nstrips) {
     const int x0 = (((strip % spans) << 6) + lane) << 4, ya = y0 + (strip / spans) * a.strip_rows;
     const LaneCols cols = lane_cols<Pix>(geo, x0);
     const uint32_t xn = vgpr(next_span_offset<Pix>(strip % spans, a.W));
 #pragma unroll
-    for (int r = 0; r < RING; ++r) load_block_row<Pix>(raw[r], geo, ya + r, cols, xn);
+    for (int r = 0; r < kEarly; ++r) load_block_row<Pix>(raw[r], geo, ya + r, cols, xn);
   }
   zero_lds(lds, fbw0 + fbwords);
-  if (threadIdx.x == 0) *qcount = 0u;
   // the kernel arguments read after the rows, held from here on (a first
   // read there would wait for the LDS atomics in flight as well)
   const unsigned long long km[kBlockGlcms] = {keep64(a.kmask[0]), keep64(a.kmask[1]), keep64(a.kmask[2]),
                                               keep64(a.kmask[3])};
   const unsigned long long tmask = keep64(a.tmask);
   uint32_t* const xbuf = (uint32_t*)keep64((unsigned long long)a.xbuf);
-  const uint32_t xslots = keep(a.xslots), spread = keep(a.spread);
   const uint32_t words_total = keep(a.words_total), dmagic = keep(a.div_n.magic), dshift = keep(a.div_n.shift);
   asm volatile("" ::"s"(a.qfast), "s"(a.qfast_shift), "s"(a.qfast_mask), "s"(a.q.lo), "s"(a.q.hi), "s"(a.q.nlev),
                "s"(a.q.magic), "s"(a.q.shift), "s"(a.H), "s"(a.W));
@@ -368,12 +427,20 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
     if (strip != wave) {
 #pragma unroll
       for (int r = 0; r < RING; ++r) load_block_row<Pix>(raw[r], geo, ya + r, cols, xn);
+    } else {
+#pragma unroll
+      for (int r = kEarly; r < RING; ++r) load_block_row<Pix>(raw[r], geo, ya + r, cols, xn);
     }
+    // Wavefront priority falls as a strip advances (3 before its first block
+    // row, 0 from its third on): the arbiter otherwise favours the oldest
+    // wavefronts, and the youngest ones finish their strips long after the
+    // rest while the CU is half idle.
+    __builtin_amdgcn_s_setprio(3);
     Upper up;
     Lower lo;
-    to_lower<Pix, QF>(lo, raw[0], a, ya, x0, sent4, edge);
-    load_block_row<Pix>(raw[0], geo, ya + RING, cols, xn);
-    to_upper(up, lo, lane_off);
+    to_lower<Pix, QF>(lo, raw[0], a, x0, sent4, edge, seven);
+    if (ya + RING <= yb) load_block_row<Pix>(raw[0], geo, ya + RING, cols, xn);
+    to_upper(up, lo, c5);
     // block row y pairs the upper row y with the lower row y + 1, which sits
     // in ring slot (y + 1 - ya) mod RING; the slot then takes row y + 1 + RING
     for (int y = ya;; y += RING) {
@@ -381,51 +448,62 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
 #pragma unroll
       for (int r = 1; r <= RING; ++r) {
         if (!done) {
-          to_lower<Pix, QF>(lo, raw[r % RING], a, y + r, x0, sent4, edge);
-          load_block_row<Pix>(raw[r % RING], geo, y + r + RING, cols, xn);
-          block_row(up, lo, copy, base, f, queue, qcount, y + r >= a.H);
+          // (the row below the image is no lower row: the last image row
+          // holds only (1,0) pairs, counted from its upper form)
+          if (y + r < a.H) to_lower<Pix, QF>(lo, raw[r % RING], a, x0, sent4, edge, seven);
+          if (y + r + RING <= yb) load_block_row<Pix>(raw[r % RING], geo, y + r + RING, cols, xn);
+          block_row(up, lo, copy, base, f, wq, qn, y + r >= a.H);
+          if (r == 1) __builtin_amdgcn_s_setprio(2);
+          else if (r == 2) __builtin_amdgcn_s_setprio(1);
+          else __builtin_amdgcn_s_setprio(0);
           if (y + r >= yb) done = true;
-          else to_upper(up, lo, lane_off);
+          else to_upper(up, lo, c5);
         }
       }
       if (done) break;
     }
   }
+  __builtin_amdgcn_s_setprio(0);
+  if (lane == 0) qcount[wave] = min(qn, kQueueWave);
   __syncthreads();
   // the queued dwords, one per thread at a time
-  const uint32_t queued = min(*qcount, kQueue);
-  for (uint32_t e = threadIdx.x; e < queued; e += blockDim.x) {
+  for (uint32_t e = threadIdx.x; e < (uint32_t)nwaves * kQueueWave; e += blockDim.x) {
+    if (e % kQueueWave >= qcount[e / kQueueWave]) continue;
     const uint4 v = queue[2u * e], w = queue[2u * e + 1u];
     correct_blocks(Pending{v.x, v.y, v.z, v.w, w.x, w.y}, base, f);
   }
   __syncthreads();
 
-  // Merge, step 1: the 32 copies of every code bin, summed in two groups of
-  // 16 by two threads (packed: a group holds the votes of half the lanes and
-  // the host keeps a band below 2^17 first pixels, so a group's halves stay
-  // below 2^16), decoded and added into the block GLCMs (copy job mod fbc).
-  for (uint32_t job = threadIdx.x; job < 2u * nbins; job += blockDim.x) {
+  // Merge, step 1: the 32 copies of every code bin with a level a < N
+  // (the codes of a sentinel first pixel are dropped), summed in two groups of
+  // 16 by two neighbouring threads (packed: a group holds the votes of half
+  // the lanes and the host keeps a band below 2^17 first pixels, so a group's
+  // halves stay below 2^16), exchanged between the two, decoded and added into
+  // the block GLCMs: the even thread adds the (1,0) and (-1,1) pairs of code 1,
+  // the odd one its (0,1) pair and the (1,1) pair of code 2.
+  for (uint32_t job = threadIdx.x; job < 32u * N; job += blockDim.x) {
     const uint32_t bin = job >> 1, half = job & 1u;
     const uint4* units = (const uint4*)(lds + bin * (kBin / 4u)) + 4u * half;
     uint32_t s = 0;
 #pragma unroll
     for (uint32_t u = 0; u < 4; ++u) {
-      const uint4 v = units[(u + bin) & 3u];  // rotated so neighbouring threads read different banks
+      // rotated by bin / 2: the 16 lanes of a 128-bit LDS pass (8 bins, both
+      // halves) then cover all 64 banks
+      const uint4 v = units[(u + (bin >> 1)) & 3u];
       s += (v.x + v.y) + (v.z + v.w);
     }
-    const uint32_t c1 = s & 0xffffu, c2 = s >> 16;
-    const uint32_t at = f.base + 4u * (job & (fbc - 1u));
-    if (c1 && bin < 16u * N) {
-      const uint32_t av = bin >> 4;
-      const uint32_t bv = av + (bin & 3u) - 1u, dv = av + ((bin >> 2) & 3u) - 1u;  // may wrap below 0
-      const bool bok = bv < N, dok = dv < N;
-      if (bok) lds_add(at + (av * N + bv) * f.stride, c1);
-      if (bok && dok) lds_add(at + ((N + bv) * N + dv) * f.stride, c1);
-      if (dok) lds_add(at + ((2u * N + av) * N + dv) * f.stride, c1);
-    }
-    if (c2 && bin < 16u * N) {
-      const uint32_t av = bin >> 4, ev = av + ((bin >> 2) & 3u) - 1u;
-      if (ev < N) lds_add(at + ((3u * N + av) * N + ev) * f.stride, c2);
+    const uint32_t o = (uint32_t)__builtin_amdgcn_mov_dpp((int)s, kDppQuadSwap1, 0xf, 0xf, true);
+    const uint32_t c1 = (s & 0xffffu) + (o & 0xffffu), c2 = (s >> 16) + (o >> 16);
+    const uint32_t at = f.base + 4u * (bin & (fbc - 1u));
+    const uint32_t av = bin >> 4;
+    const uint32_t bv = av + ((bin >> 2) & 3u) - 1u, dv = av + (bin & 3u) - 1u;  // may wrap below 0; dv = ev
+    const bool bok = bv < N, dok = dv < N;
+    if (half == 0u) {
+      if (c1 && bok) lds_add(at + f.at(0u, av, bv), c1);
+      if (c1 && bok && dok) lds_add(at + f.at(1u, bv, dv), c1);
+    } else {
+      if (c1 && dok) lds_add(at + f.at(2u, av, dv), c1);
+      if (c2 && dok) lds_add(at + f.at(3u, av, dv), c2);
     }
   }
   __syncthreads();
@@ -435,22 +513,37 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockArgs a) {
   uint32_t xcc;
   asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
   // the slice of this XCD (the hardware's XCC_ID, so no two XCDs ever share
-  // one) and of this workgroup's group: fewer workgroups adding to one
-  // address in L2 at the end of the kernel
-  const uint32_t slice = (xcc & (kXcdSlots - 1u)) + xslots * (((uint32_t)blockIdx.x >> 3) & (spread - 1u));
+  // one: every global atomic is performed in the issuing XCD's L2)
+  const uint32_t slice = xcc & (kXcdSlots - 1u);
   uint32_t* xs = xbuf + (size_t)slice * words_total;
   const uint32_t NN = N * N;
   const uint32_t* fbw = lds + fbw0;
   for (uint32_t w = threadIdx.x; w < NN; w += blockDim.x) {
-    const uint32_t i = divide(w, dmagic, dshift), j = w - i * N;
+    uint32_t v[kBlockGlcms];
+    if (fbc == 4u) {
+#pragma unroll
+      for (int g = 0; g < kBlockGlcms; ++g) {
+        const uint4 q = ((const uint4*)fbw)[(uint32_t)g * NN + w];
+        v[g] = (q.x + q.y) + (q.z + q.w);
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < kBlockGlcms; ++g) {
+        v[g] = 0;
+        for (uint32_t c = 0; c < fbc; ++c) v[g] += fbw[((uint32_t)g * NN + w) * fbc + ((c + w) & (fbc - 1u))];
+      }
+    }
+    uint32_t wt = w;  // (j, i) for the offsets stored transposed
+    if (tmask) {
+      const uint32_t i = divide(w, dmagic, dshift);
+      wt = (w - i * N) * N + i;
+    }
 #pragma unroll
     for (int g = 0; g < kBlockGlcms; ++g) {
-      uint32_t v = 0;
-      for (uint32_t c = 0; c < fbc; ++c) v += fbw[((uint32_t)g * NN + w) * fbc + ((c + w) & (fbc - 1u))];
-      if (v == 0u) continue;
+      if (v[g] == 0u) continue;
       for (unsigned long long m = km[g]; m; m &= m - 1ull) {
         const uint32_t k = (uint32_t)__builtin_ctzll(m);
-        __hip_atomic_fetch_add(xs + (size_t)k * NN + (((tmask >> k) & 1ull) ? j * N + i : w), v, __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(xs + (size_t)k * NN + (((tmask >> k) & 1ull) ? wt : w), v[g], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }

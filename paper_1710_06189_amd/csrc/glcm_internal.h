@@ -65,9 +65,9 @@ struct VoteArgs {
 // (x+1, y+1)) hold exactly one pair of each d = 1 GLCM: (1,0) -> (a, b),
 // (-1,1) -> (b, d), (0,1) -> (a, d), (1,1) -> (a, e).  The kernel votes two
 // codes per block instead of four pairs:
-//   code 1 = 16 a + 4 (d - a + 1) + (b - a + 1) = 11 a + b + 4 d + 5
+//   code 1 = 16 a + 4 (b - a + 1) + (d - a + 1) = 11 a + 4 b + d + 5
 //            (the block's (1,0), (-1,1) and (0,1) pairs),
-//   code 2 = 16 a + 4 (e - a + 1) + (b - a + 1) = 11 a + b + 4 e + 5
+//   code 2 = 16 a + 4 (b - a + 1) + (e - a + 1) = 11 a + 4 b + e + 5
 //            (its (1,1) pair),
 // exact whenever the three differences lie in [-1, 2]; blocks outside that
 // window are corrected one pair at a time.  Block GLCM g of the four above.
@@ -87,16 +87,15 @@ struct BlockArgs {
   int fb_copies;              // copies of the block GLCMs (1, 2 or 4; lane mod fb_copies)
   Quant div_n;                // magic/shift for dividing by N
   uint32_t words_total;       // K N N
-  uint32_t* xbuf;             // accumulation slices [xslots * spread][words_total]: slice
-                              // XCC_ID + xslots * s for the workgroups b with (b / 8) mod spread = s
-  uint32_t xslots, spread;    // XCC_IDs the device reports; slices per XCD (a power of two)
+  uint32_t* xbuf;             // per-XCD accumulation slices [kXcdSlots][words_total]
 };
 // LDS bytes of the block kernel: code bins (32 dwords each), the four block
-// GLCMs in fbc copies (N^2 words each), one trash word per lane, a queue of
-// 512 dwords with blocks outside the code window (32 bytes each) and its count.
+// GLCMs in fbc copies (N^2 words each), one trash word per lane, queues of
+// 512 dwords with blocks outside the code window (32 bytes each, 32 per
+// wavefront) and their 16 counts.
 inline size_t block_lds_bytes(int N, int fbc) {
   return (16u * (size_t)N + 6u) * 128u + (size_t)kBlockGlcms * (size_t)N * (size_t)N * (size_t)fbc * 4u + 64u * 4u +
-         512u * 32u + 16u;
+         512u * 32u + 64u;
 }
 
 // One image of a batch as the batch kernel reads it (device memory, 32 bytes).

@@ -1,10 +1,10 @@
 """CPU replay of the block-code kernel's arithmetic (no GPU).
 
 The block kernel (d = 1 directions) votes two codes per 2x2 block,
-    code 1 = 11 a + b + 4 d + 5,   code 2 = 11 a + b + 4 e + 5,
+    code 1 = 11 a + 4 b + d + 5,   code 2 = 11 a + 4 b + e + 5,
 finds the blocks whose differences b - a, d - a, e - a leave [-1, 2] with an
-exact byte-wise test on packed levels (each digit X - a biased by 0x40, so no
-byte borrows from the next), takes those votes back and counts their four
+exact byte-wise test on packed levels (each digit X - a + 1 biased by 0x40, so
+no byte borrows from the next), takes those votes back and counts their four
 pairs one by one, and finally decodes the code counts.  This
 test replays exactly that arithmetic in numpy (32-bit wrap-around included) and
 checks:
@@ -44,20 +44,20 @@ def replay(q, N):
     d = L[1:H + 1, :Wp]
     e = L[1:H + 1, 1:Wp + 1]
     nbins = 16 * N + 6
-    k1 = 11 * a + b + 4 * d + 5
-    k2 = 11 * a + b + 4 * e + 5
+    k1 = 11 * a + 4 * b + d + 5
+    k2 = 11 * a + 4 * b + e + 5
     assert k1.min() >= 0 and k1.max() < nbins and k2.min() >= 0 and k2.max() < nbins
     c1 = np.bincount(k1.ravel(), minlength=nbins).astype(np.int64)
     c2 = np.bincount(k2.ravel(), minlength=nbins).astype(np.int64)
 
     # the window test, per lane chunk of 16 pixels as 4 packed dwords: digits
-    # X - a + 0x40 for X = b + 1, d + 1, e + 1, in window iff 0x40..0x43
+    # X - a + 1 + 0x40 for X = b, d, e, in window iff 0x40..0x43
     shp = (H, chunks, 16)
     m32 = np.uint64(0xFFFFFFFF)
-    lb = (pack(a.reshape(shp)) - np.uint64(0x40404040)) & m32
-    db = (pack((b + 1).reshape(shp)) - lb) & m32
-    dd = (pack((d + 1).reshape(shp)) - lb) & m32
-    de = (pack((e + 1).reshape(shp)) - lb) & m32
+    lb = (pack(a.reshape(shp)) - np.uint64(0x41414141)) & m32
+    db = (pack(b.reshape(shp)) - lb) & m32
+    dd = (pack(d.reshape(shp)) - lb) & m32
+    de = (pack(e.reshape(shp)) - lb) & m32
     o = ((~(db & dd & de) & np.uint64(0x40404040)) | ((db | dd | de) & np.uint64(0x3C3C3C3C))) & m32
     flagged = np.zeros(shp, dtype=bool)
     for j in range(4):
@@ -83,8 +83,8 @@ def replay(q, N):
     # decode
     for bin_ in np.nonzero(c1[:16 * N])[0]:
         av = bin_ >> 4
-        bv = av + (bin_ & 3) - 1
-        dv = av + ((bin_ >> 2) & 3) - 1
+        bv = av + ((bin_ >> 2) & 3) - 1
+        dv = av + (bin_ & 3) - 1
         c = c1[bin_]
         if 0 <= bv < N:
             fb[0, av, bv] += c
@@ -94,7 +94,7 @@ def replay(q, N):
             fb[2, av, dv] += c
     for bin_ in np.nonzero(c2[:16 * N])[0]:
         av = bin_ >> 4
-        ev = av + ((bin_ >> 2) & 3) - 1
+        ev = av + (bin_ & 3) - 1
         if 0 <= ev < N:
             fb[3, av, ev] += c2[bin_]
     return fb[:, :N, :N]
@@ -128,10 +128,10 @@ def test_every_code_inside_table_for_all_level_combinations():
     for N in (1, 2, 7, 32, 54, 62):
         lv = np.arange(N + 1)
         a, b, d, e = np.meshgrid(lv, lv, lv, lv, indexing="ij")
-        k1 = 11 * a + b + 4 * d + 5
-        k2 = 11 * a + b + 4 * e + 5
+        k1 = 11 * a + 4 * b + d + 5
+        k2 = 11 * a + 4 * b + e + 5
         assert k1.min() >= 0 and k1.max() < 16 * N + 6
         assert k2.min() >= 0 and k2.max() < 16 * N + 6
         # biased digits of the window test: no borrow, bit 7 clear
-        x = (lv + 1)[:, None] - lv[None, :] + 0x40
+        x = lv[:, None] - lv[None, :] + 0x41
         assert x.min() >= 0 and x.max() < 0x80

@@ -126,3 +126,35 @@ def test_misaligned_view_is_staged(kind):
         plan.close()
     want = oracle.glcm(np.ascontiguousarray(view.cpu().numpy()), 32, 0, 255, D1)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kind", ["smooth", "uniform"])
+def test_autotune_between_strips_and_blocks(kind):
+    """glcm_plan_autotune times the block-code kernel against the strip
+    layouts for a d = 1 plan; whichever it keeps, the counts stay exact."""
+    w = synth.square_4096(kind)
+    img = w["images"][0]
+    t = to_device(img)
+    plan = G.glcm_plan_create(G.U8, 32, D1, 4096, 4096)
+    try:
+        chosen = plan.autotune(t, 0, 255, repeats=3)
+        name = G.PATH_NAMES[chosen.path]
+        print(f"[autotune] {kind}: {chosen.as_dict()}", flush=True)
+        assert name in ("strips", "blocks")
+        assert G.PATH_NAMES[plan.tuning.path] == name
+        out = G.glcm_compute(t, 32, 0, 255, D1, plan=plan)
+        torch.cuda.synchronize()
+        got = out.view(torch.int32).cpu().numpy().view(np.uint32)
+    finally:
+        plan.close()
+    assert np.array_equal(got, oracle.glcm(img, 32, 0, 255, D1))
+
+
+def test_autotune_keeps_other_offsets_off_blocks():
+    img = synth.smooth(300, 400, 4.0, 81)
+    plan = G.glcm_plan_create(G.U8, 16, [(1, 0), (2, 0)], 400, 300)
+    try:
+        chosen = plan.autotune(to_device(img), 0, 255, repeats=2)
+        assert G.PATH_NAMES[chosen.path] != "blocks"
+    finally:
+        plan.close()
