@@ -148,6 +148,9 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time the LDS layouts on all three images")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default layout instead of timing the candidates (glcm_plan_autotune)")
+    ap.add_argument("--path", default="auto", choices=["auto", "strips", "blocks"],
+                    help="auto: the autotuner's pick; strips / blocks: that kernel, untuned (for profiling runs, "
+                         "whose per-dispatch overhead would blur the autotuner's timing)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload's figures in extra")
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
@@ -234,12 +237,12 @@ def main():
         base = torch.from_numpy(img).to(dev)
         copies = [base.clone() for _ in range(ncopies)]
         outs = [torch.empty((K, N, N), dtype=torch.uint32, device=dev) for _ in range(ncopies)]
-        plan = G.glcm_plan_create(np.uint8, N, offs, W, H)
+        plan = G.glcm_plan_create(np.uint8, N, offs, W, H, G.FLAG_FORCE_BLOCKS if args.path == "blocks" else 0)
         if tuning:
             plan.set_tuning(**tuning)
         elif fixed:
             plan.set_tuning(**fixed)
-        elif not args.no_autotune:
+        elif not args.no_autotune and args.path == "auto":
             plan.autotune(copies[0], lo, hi, repeats=10)
         wall, step_ms = timed_loop(plan, copies, outs, N, lo, hi, offs, args.steps, args.warmup)
         for j in range(min(ncopies, args.steps + args.warmup)):
@@ -379,11 +382,12 @@ def call_latencies(G, torch, np, synth, dev, args, calls=200):
     base = torch.from_numpy(img).to(dev)
     copies = [base.clone() for _ in range(args.copies)]
     out = torch.empty((len(offs), N, N), dtype=torch.uint32, device=dev)
-    plan = G.glcm_plan_create(np.uint8, N, offs, img.shape[1], img.shape[0])
+    plan = G.glcm_plan_create(np.uint8, N, offs, img.shape[1], img.shape[0],
+                              G.FLAG_FORCE_BLOCKS if args.path == "blocks" else 0)
     if args.layout:
         R, bits, wg = (int(v) for v in args.layout.split(","))
         plan.set_tuning(replicas=R, counter_bits=bits, wg_size=wg)
-    elif not args.no_autotune:
+    elif not args.no_autotune and args.path == "auto":
         plan.autotune(copies[0], lo, hi, repeats=10)
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
