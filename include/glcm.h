@@ -115,6 +115,10 @@ typedef struct glcm_tuning {
     int partitions;     /* read-only: bin partitions per pass */
 } glcm_tuning_t;
 
+/* Largest K * N * N that glcm_compute_static accepts (its accumulation
+ * slices: 16 of these, 16 MiB per GPU). */
+#define GLCM_STATIC_MAX_WORDS (1u << 18)
+
 /* Version of this ABI (GLCM_ABI_VERSION). */
 GLCM_API int glcm_abi_version(void);
 
@@ -170,6 +174,28 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t *tuning, int set);
  */
 GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void *img, int W, int H, int64_t stride, uint32_t lo,
                                 uint32_t hi, int repeats, void *stream, glcm_tuning_t *chosen);
+
+/*
+ * glcm_compute for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * computes exactly what glcm_compute computes (Eq. (1) for each offset) for a
+ * DEVICE image on the current device, with the same kernels, but takes no plan
+ * and calls no hipMalloc, hipFree or other allocating routine: the per-XCD
+ * accumulation slices of its merge live in a file-scope device array of
+ * 16 MiB that each GPU the library runs on holds until the process ends
+ * (found once per device with hipGetSymbolAddress on its first call there).
+ * A misaligned image (base or row pitch not a multiple of 16 bytes) is read
+ * by the per-pixel kernels instead of being copied.  Calls are queued on
+ * `stream` like glcm_compute; every call on one GPU shares that array, so
+ * calls that overlap on one GPU (several streams, or host threads) race and
+ * must be ordered by the caller.  The array is cleared at the start of each
+ * call (by a kernel, so the call can be captured in a graph).
+ * Errors: those of glcm_compute; GLCM_EINVAL when K * N * N exceeds
+ * GLCM_STATIC_MAX_WORDS or img / out is not device memory of the current
+ * device.
+ */
+GLCM_API int glcm_compute_static(const void *img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo,
+                                 uint32_t hi, const glcm_offset_t *offsets, int K, uint32_t *out, void *stream);
 
 /*
  * For plans created with GLCM_FLAG_TIMING: waits for the recorded launches and

@@ -38,6 +38,7 @@ __all__ = [
     "GlcmError", "Plan", "Tuning", "glcm_abi_version", "glcm_strerror", "glcm_last_hip_error",
     "glcm_offset_polar", "glcm_plan_create", "glcm_plan_destroy", "glcm_plan_tuning", "glcm_plan_autotune",
     "glcm_compute",
+    "glcm_compute_static",
     "glcm_features", "library_path", "U8", "U16", "FLAG_FORCE_GENERIC", "FLAG_FORCE_PARTITIONED",
     "FLAG_FORCE_GLOBAL", "FLAG_SERIAL_UPLOAD", "FLAG_TIMING", "FLAG_FORCE_SLABS", "FLAG_FORCE_L2", "FLAG_FORCE_BLOCKS", "glcm_batch_compute", "Tile", "TileSet", "prepare_tiles", "PATH_NAMES", "glcm_plan_kernel_time",
     "glcm_plan_rebind", "glcm_plan_workspace", "glcm_plan_cache_stats", "glcm_plan_cache_clear", "Server", "RequestInfo", "ServerStats", "PreparedBatch",
@@ -57,6 +58,7 @@ FLAG_TIMING = 1 << 4
 FLAG_FORCE_SLABS = 1 << 5
 FLAG_FORCE_L2 = 1 << 6
 FLAG_FORCE_BLOCKS = 1 << 7
+STATIC_MAX_WORDS = 1 << 18  # GLCM_STATIC_MAX_WORDS: largest K * N * N of glcm_compute_static
 PATH_NAMES = {0: "generic", 1: "slabs", 2: "partitioned", 3: "global", 4: "strips", 5: "l2", 6: "blocks"}
 
 STATUS = {0: "GLCM_OK", -1: "GLCM_EINVAL", -2: "GLCM_ENOMEM", -3: "GLCM_EUNSUPPORTED",
@@ -148,6 +150,9 @@ def _lib():
         lib.glcm_plan_destroy.argtypes = [vp]
         lib.glcm_compute.restype = i32
         lib.glcm_compute.argtypes = [vp, vp, i32, i32, i64, i32, i32, u32, u32, ctypes.POINTER(Offset), i32, vp, vp]
+        lib.glcm_compute_static.restype = i32
+        lib.glcm_compute_static.argtypes = [vp, i32, i32, i64, i32, i32, u32, u32, ctypes.POINTER(Offset), i32, vp,
+                                            vp]
         lib.glcm_features.restype = i32
         lib.glcm_features.argtypes = [vp, i32, i32, vp, vp]
         lib.glcm_histogram.restype = i32
@@ -411,6 +416,28 @@ def glcm_compute(img, N, lo=0, hi=None, offsets=((1, 0),), out=None, stream=None
     _check(_lib().glcm_compute(plan.handle if plan is not None else None, ctypes.c_void_p(ptr), W, H, stride, dt,
                                int(N), int(lo), int(hi), arr, K, ctypes.c_void_p(out.data_ptr()), s),
            "glcm_compute")
+    del keep
+    return out
+
+
+def glcm_compute_static(img, N, lo=0, hi=None, offsets=((1, 0),), out=None, stream=None):
+    """glcm_compute for a device image without a plan and without device
+    allocation inside the call (its merge uses the library's static per-GPU
+    array; calls that overlap on one GPU race).  `out` should be given by
+    callers that may not allocate; K * N * N <= STATIC_MAX_WORDS."""
+    if not (isinstance(img, torch.Tensor) and img.is_cuda):
+        raise ValueError("img must be a CUDA tensor")
+    ptr, W, H, stride, dt, keep = _image_args(img)
+    if hi is None:
+        hi = 255 if dt == U8 else 65535
+    arr, K = _offsets(offsets)
+    if out is None:
+        out = torch.empty((K, N, N), dtype=torch.uint32, device=img.device)
+    elif not (out.is_cuda and out.is_contiguous() and out.numel() == K * N * N and out.element_size() == 4):
+        raise ValueError("out must be a contiguous CUDA tensor of K*N*N 32-bit elements")
+    _check(_lib().glcm_compute_static(ctypes.c_void_p(ptr), W, H, stride, dt, int(N), int(lo), int(hi), arr, K,
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+           "glcm_compute_static")
     del keep
     return out
 

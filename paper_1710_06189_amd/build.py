@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libglcm.so")
-SOURCES = ["glcm_vote.hip", "glcm_blocks.hip", "glcm_features.hip", "glcm_batch.hip", "glcm_hist.hip", "glcm_stats.hip", "glcm_mcc.hip",
+SOURCES = ["glcm_vote.hip", "glcm_blocks.hip", "glcm_features.hip", "glcm_batch.hip", "glcm_hist.hip", "glcm_stats.hip", "glcm_mcc.hip", "glcm_static.hip",
            "glcm_api.cpp",
            "glcm_post.cpp", "glcm_server.cpp"]
 

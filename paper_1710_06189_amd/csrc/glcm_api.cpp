@@ -201,6 +201,7 @@ struct glcm_plan_s {
   size_t stage_bytes = 0;
   uint32_t* xbuf = nullptr;  // [kXcdSlots][K*N*N] accumulation slices, kept zero between calls
   uint32_t xslots = glcm::kXcdSlots;  // slices the device's XCC_IDs reach (the rest stay zero)
+  bool no_alloc = false;  // a transient plan of compute_in_workspace: never allocate (no staging copy)
 
 
   // ordering across streams
@@ -633,7 +634,7 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   if (path == kPathBlocks && (t.merge != 0 || !p->xbuf)) path = kPathStrips;
   if (path == kPathRows || path == kPathStrips || path == kPathBlocks) {
     const bool aligned = ((uintptr_t)img % 16 == 0) && (((uint64_t)stride * b) % 16 == 0);
-    if (!aligned && (uint64_t)W * (uint64_t)H >= kStageMinPixels && y_begin == 0 && y_end == H) {
+    if (!aligned && !p->no_alloc && (uint64_t)W * (uint64_t)H >= kStageMinPixels && y_begin == 0 && y_end == H) {
       // one pitched copy into the plan's aligned buffer, then the fast kernels
       const size_t pitch = ((size_t)W * b + 15) & ~(size_t)15;
       GLCM_TRY_RC(ensure_stage(p, pitch * (size_t)H));
@@ -1408,6 +1409,48 @@ GLCM_API int glcm_plan_destroy(glcm_plan_t plan) {
   delete plan;
   return GLCM_OK;
 }
+
+extern "C++" {
+namespace glcm {
+
+int compute_in_workspace(uint32_t* slices, size_t slice_words, const void* img, int W, int H, int64_t stride,
+                         int dtype, int N, uint32_t lo, uint32_t hi, const glcm_offset_t* offsets, int K,
+                         uint32_t* out, hipStream_t stream) {
+  int rc = check_compute_args(img, W, H, stride, dtype, N, lo, hi, offsets, K, out);
+  if (rc != GLCM_OK) return rc;
+  const uint64_t words = (uint64_t)K * (uint64_t)N * (uint64_t)N;
+  if (!slices || (uint64_t)kXcdSlots * words > (uint64_t)slice_words) return GLCM_EINVAL;
+  int out_dev = -1, img_dev = -1, cur = 0;
+  if (pointer_kind(out, &out_dev) != 2 || pointer_kind(img, &img_dev) != 2) return GLCM_EINVAL;
+  GLCM_TRY(hipGetDevice(&cur));
+  if (out_dev != cur || img_dev != cur) return GLCM_EINVAL;
+  // a plan for this one call: no events, no workspace of its own
+  glcm_plan_s p;
+  p.device = cur;
+  p.dtype = dtype;
+  p.N = N;
+  p.K = K;
+  p.k_cap = K;
+  std::memcpy(p.offsets, offsets, sizeof(glcm_offset_t) * (size_t)K);
+  p.max_W = W;
+  p.max_H = H;
+  int lds = 0;
+  GLCM_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, cur));
+  GLCM_TRY(hipDeviceGetAttribute(&p.num_cus, hipDeviceAttributeMultiprocessorCount, cur));
+  p.lds_budget_words = (lds - 1024) / 4;
+  choose_tuning(&p, &p.tuning);
+  p.tuning.merge = 0;  // the slices, never band partials
+  p.xbuf = slices;
+  p.xslots = kXcdSlots;
+  p.no_alloc = true;
+  // the slices start at zero whatever an earlier call left (a fill kernel:
+  // the call stays capturable in a graph)
+  GLCM_TRY(launch_zero(slices, (uint64_t)kXcdSlots * words, stream));
+  return count_device(&p, img, W, H, stride, 0, H, lo, hi, out, false, true, stream);
+}
+
+}  // namespace glcm
+}  // extern "C++"
 
 GLCM_API int glcm_compute(glcm_plan_t plan, const void* img, int W, int H, int64_t stride, int dtype, int N, uint32_t lo,
                  uint32_t hi, const glcm_offset_t* offsets, int K, uint32_t* out, void* stream_) {

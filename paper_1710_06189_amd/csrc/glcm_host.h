@@ -22,4 +22,14 @@ int check_request_args(const void* img, int W, int H, int64_t stride, int dtype,
 // 0 = pageable host, 1 = pinned host, 2 = device memory; *device = its device.
 int memory_kind(const void* p, int* device);
 
+// glcm_compute on a device image without a plan and without allocating:
+// a plan lives on the stack for the call, its per-XCD accumulation slices are
+// `slices` (device memory of slice_words 32-bit words, any content on entry,
+// zero on return), misaligned images take the per-pixel kernels instead of a
+// staging copy.  GLCM_EINVAL when kXcdSlots * K * N * N > slice_words or
+// either pointer is not device memory of the current device.
+int compute_in_workspace(uint32_t* slices, size_t slice_words, const void* img, int W, int H, int64_t stride,
+                         int dtype, int N, uint32_t lo, uint32_t hi, const glcm_offset_t* offsets, int K,
+                         uint32_t* out, hipStream_t stream);
+
 }  // namespace glcm

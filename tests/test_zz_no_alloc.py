@@ -1,0 +1,94 @@
+"""glcm_compute_static, the allocation-free variant of glcm_compute: through
+the C ABI (the ctypes binding) it must give the same counts as glcm_compute,
+bit for bit, on two calls in a row, the second on a smaller image; reject
+K N^2 beyond its static array; and leave the device's free memory unchanged."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_1710_06189_amd")
+
+D1 = [(1, 0), (-1, 1), (0, 1), (1, 1)]
+
+
+def to_device(img):
+    if img.dtype == np.uint16:
+        return torch.from_numpy(np.ascontiguousarray(img).view(np.int16)).cuda().view(torch.uint16)
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def counts(t):
+    return t.view(torch.int32).cpu().numpy().view(np.uint32)
+
+
+def both(img_t, N, lo, hi, offs):
+    K = len(offs)
+    a = torch.empty((K, N, N), dtype=torch.uint32, device="cuda")
+    b = torch.empty_like(a)
+    G.glcm_compute_static(img_t, N, lo, hi, offs, out=a)
+    G.glcm_compute(img_t, N, lo, hi, offs, out=b)
+    torch.cuda.synchronize()
+    return counts(a), counts(b)
+
+
+CASES = [
+    # (first image, second smaller image, N, lo, hi, offsets)
+    ("square_smooth_d1", lambda: synth.square_4096("smooth")["images"][0], lambda: synth.smooth(300, 200, 4.0, 7),
+     32, 0, 255, D1),
+    ("noise_reach2", lambda: synth.uniform(1500, 2100, 3), lambda: synth.uniform(77, 65, 4), 16, 0, 255,
+     [(2, 0), (0, 2), (-1, 1), (1, -2)]),
+    ("slab_reach4_u16", lambda: synth.smooth(1000, 1200, 3.0, 5, np.uint16), lambda: synth.smooth(90, 100, 3.0, 6, np.uint16),
+     64, 0, 65535, [(4, 0), (0, 4), (-3, 3), (1, 1)]),
+    ("large_n", lambda: synth.smooth(1024, 1024, 6.0, 9), lambda: synth.uniform(130, 300, 10), 256, 0, 255, D1),
+]
+
+
+@pytest.mark.parametrize("name,first,second,N,lo,hi,offs", CASES, ids=[c[0] for c in CASES])
+def test_static_equals_compute_twice(name, first, second, N, lo, hi, offs):
+    for make in (first, second):
+        img = make()
+        print(f"[static] {name} shape={img.shape} dtype={img.dtype} N={N} K={len(offs)}", flush=True)
+        got, ref = both(to_device(img), N, lo, hi, offs)
+        assert np.array_equal(got, ref)
+    # the second (small) image against the oracle too
+    assert np.array_equal(got, oracle.glcm(img, N, lo, hi, offs))
+
+
+def test_static_misaligned_view():
+    t = to_device(synth.smooth(700, 901, 4.0, 12))
+    view = t[:, 1:]  # base + 1 byte, pitch 901: the per-pixel kernels, no staging copy
+    got, ref = both(view, 32, 0, 255, D1)
+    assert np.array_equal(got, ref)
+    small = t[:50, 3:40]
+    got, ref = both(small, 32, 0, 255, D1)
+    assert np.array_equal(got, ref)
+
+
+def test_static_rejects_beyond_its_array():
+    t = to_device(synth.uniform(64, 64, 13))
+    with pytest.raises(G.GlcmError):
+        G.glcm_compute_static(t, 512, 0, 255, [(1, 0), (0, 1)])  # 2 * 512^2 > 2^18
+    # host images are not taken either
+    with pytest.raises(ValueError):
+        G.glcm_compute_static(synth.uniform(8, 8, 14), 8, 0, 255, [(1, 0)])
+
+
+def test_static_allocates_no_device_memory():
+    img = to_device(synth.square_4096("smooth")["images"][0])
+    small = to_device(synth.smooth(200, 300, 4.0, 15))
+    out = torch.empty((4, 32, 32), dtype=torch.uint32, device="cuda")
+    G.glcm_compute_static(img, 32, 0, 255, D1, out=out)  # first call on the device: finds the array
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    for t in (img, small, img):
+        G.glcm_compute_static(t, 32, 0, 255, D1, out=out)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 == free0
+    assert np.array_equal(counts(out), oracle.glcm(synth.square_4096("smooth")["images"][0], 32, 0, 255, D1))
