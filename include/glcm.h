@@ -448,12 +448,16 @@ GLCM_API int glcm_batch_destroy(glcm_batch_t batch);
  * Table III, Eq. (4)-(6)); the batch engine does the same for its own layout.
  *
  *   replicas  LDS copies (dwords) of every bin: 4, 8 or 16; 0 = the default
- *             rule (the most that leave room for three workgroups per CU).
+ *             rule (the most that leave room for two workgroups per CU).
  *             More copies mean fewer colliding votes but a heavier merge.
  *   min_rows  shortest run of rows a wavefront segment walks, 1 .. 256; 0 = 4.
  *             Shorter runs spread a small image over more wavefronts; longer
  *             runs cut the per-run set-up.
- *   wg_size   read-only: threads per workgroup (256).
+ *   wg_size   threads per workgroup: 256 or 512; 0 = 256.  The workgroups
+ *             are persistent (as many as the CUs hold at once) and take the
+ *             batch's images, largest first, from a counter; an image above
+ *             2^20 pixels is split into bands of rows counted by several
+ *             workgroups and summed afterwards.
  */
 typedef struct glcm_batch_tuning {
     int replicas;
@@ -467,8 +471,8 @@ typedef struct glcm_batch_tuning {
 GLCM_API int glcm_batch_tuning(glcm_plan_t plan, glcm_batch_tuning_t *tuning, int set);
 
 /*
- * Times every batch layout that fits (replicas 4, 8, 16 x min_rows 4, 8, 16,
- * 32) on the given images, `repeats` runs each after one warm-up run, with the
+ * Times every batch layout that fits (wg_size 256, 512 x replicas 4, 8, 16 x
+ * min_rows 4, 8, 16, 32) on the given images, `repeats` runs each after one warm-up run, with the
  * statistics computed, and keeps the fastest in the plan for later batch calls
  * (glcm_batch_compute, glcm_batch_prepare).  tiles, T, lo, hi as for
  * glcm_batch_compute; repeats 1 .. 1000.  Allocates its own outputs and stream

@@ -282,9 +282,10 @@ class Plan:
         _check(_lib().glcm_batch_tuning(self.handle, ctypes.byref(t), 0), "glcm_batch_tuning")
         return t
 
-    def set_batch_tuning(self, replicas=0, min_rows=0) -> BatchTuning:
-        """Batch-kernel layout (0 = default): LDS copies per bin 4/8/16, shortest row run 1..256."""
-        t = BatchTuning(int(replicas), int(min_rows), 0)
+    def set_batch_tuning(self, replicas=0, min_rows=0, wg_size=0) -> BatchTuning:
+        """Batch-kernel layout (0 = default): LDS copies per bin 4/8/16, shortest row run 1..256,
+        threads per workgroup 256/512."""
+        t = BatchTuning(int(replicas), int(min_rows), int(wg_size))
         _check(_lib().glcm_batch_tuning(self.handle, ctypes.byref(t), 1), "glcm_batch_tuning")
         return t
 

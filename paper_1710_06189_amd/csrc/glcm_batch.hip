@@ -78,23 +78,27 @@ __device__ __forceinline__ void batch_load(RawChunk<Pix>& rc, const Geom& g, int
     load_row<Pix>(rc, g, y, cols);
 }
 
-template <typename Pix, int MAXDY, int D, int CUR, bool UNAL>
+// BAND: the item is a band of an image's first-pixel rows; rows at or past
+// y_end (still read as second pixels) vote as the sentinel level (fsent).
+template <typename Pix, int MAXDY, int D, int CUR, bool UNAL, bool BAND>
 __device__ __forceinline__ void batch_step(const BatchArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
                                            RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, const LaneCols& cols,
                                            uint32_t C, uint32_t n1,
-                                           uint32_t mb, uint32_t sent4, const int (&code)[4]) {
+                                           uint32_t mb, uint32_t sent4, const int (&code)[4], int y_end,
+                                           uint32_t fsent) {
   constexpr int NR = MAXDY + 1;
   uint32_t fa[16];
+  const bool first = !BAND || y < y_end;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) fa[t] = mad_u24(ring[CUR].s[MAXDY + t], n1, C);
+  for (int t = 0; t < 16; ++t) fa[t] = first ? mad_u24(ring[CUR].s[MAXDY + t], n1, C) : fsent;
   batch_vote<MAXDY, D, 0, CUR>(fa, ring, code, a.K, 1u);
   to_terms<Pix, MAXDY, true>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, true);
   batch_load<Pix, UNAL>(raw[CUR], geo, y + 2 * NR, x0, cols);
 }
 
-// The votes of one image: lane -> (segment, chunk), every wavefront walking
-// runs of rows of its segments.
-template <typename Pix, int MAXDY, int D, bool UNAL>
+// The votes of one item (first-pixel rows [t.y0, t.y1) of an image): lane ->
+// (segment, chunk), every wavefront walking runs of rows of its segments.
+template <typename Pix, int MAXDY, int D, bool UNAL, bool BAND>
 __device__ __forceinline__ void batch_votes(const BatchArgs& a, const BatchTile& t, const Geom& geo, uint32_t C,
                                             uint32_t n1, uint32_t mb, uint32_t sent4) {
   constexpr int NR = MAXDY + 1;
@@ -108,12 +112,14 @@ __device__ __forceinline__ void batch_votes(const BatchArgs& a, const BatchTile&
   const int seg = lane / cw, c = lane - seg * cw;
   const bool live = seg < segs;
   const int slots = nwaves * segs;  // row segments walked at once by the workgroup
-  const int h = max(a.min_rows, (t.H * spans + slots - 1) / slots);
-  const int blocks = (t.H + segs * h - 1) / (segs * h);
+  const int rows = t.y1 - t.y0;
+  const int h = max(a.min_rows, (rows * spans + slots - 1) / slots);
+  const int blocks = (rows + segs * h - 1) / (segs * h);
+  const uint32_t fsent = mad_u24(a.q.nlev * mb, n1, C);
   for (int u = wave; u < spans * blocks; u += nwaves) {
     const int span = u % spans, blk = u / spans;
     const int x0 = live ? ((span << 6) + c) << 4 : spans << 10;  // idle lanes: past the right edge
-    const int ya = (blk * segs + (live ? seg : 0)) * h;
+    const int ya = t.y0 + (blk * segs + (live ? seg : 0)) * h;
     TermRow<MAXDY> ring[NR];
     RawChunk<Pix> raw[NR];
     LaneCols cols{};
@@ -128,44 +134,51 @@ __device__ __forceinline__ void batch_votes(const BatchArgs& a, const BatchTile&
     // every lane takes h steps; rows past the image or the lane's segment
     // end carry the sentinel or belong to this segment's own run
     for (int j = 0; j < h; j += NR) {
-      batch_step<Pix, MAXDY, D, 0, UNAL>(a, geo, ring, raw, ya + j, x0, cols, C, n1, mb, sent4, code);
+      batch_step<Pix, MAXDY, D, 0, UNAL, BAND>(a, geo, ring, raw, ya + j, x0, cols, C, n1, mb, sent4, code, t.y1,
+                                               fsent);
       if (j + 1 >= h) break;
-      batch_step<Pix, MAXDY, D, 1, UNAL>(a, geo, ring, raw, ya + j + 1, x0, cols, C, n1, mb, sent4, code);
+      batch_step<Pix, MAXDY, D, 1, UNAL, BAND>(a, geo, ring, raw, ya + j + 1, x0, cols, C, n1, mb, sent4, code,
+                                               t.y1, fsent);
       if constexpr (NR > 2) {
         if (j + 2 >= h) break;
-        batch_step<Pix, MAXDY, D, 2, UNAL>(a, geo, ring, raw, ya + j + 2, x0, cols, C, n1, mb, sent4, code);
+        batch_step<Pix, MAXDY, D, 2, UNAL, BAND>(a, geo, ring, raw, ya + j + 2, x0, cols, C, n1, mb, sent4, code,
+                                                 t.y1, fsent);
       }
     }
   }
 }
 
+// One item (an image or a band of one) into the workgroup's LDS copies,
+// which are zero on entry and zero again on return (the merge clears what it
+// reads, so the next item needs no clearing pass).
 template <typename Pix, int MAXDY, int D>
-__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
-  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-  constexpr int NR = MAXDY + 1;
-  const BatchTile t = a.tiles[blockIdx.x];
+__device__ __forceinline__ void batch_item(const BatchArgs& a, const BatchTile& t, uint32_t* lds) {
   const Geom geo{t.img, t.stride, t.W, t.H};
   const int K = a.K;
   const uint32_t N = a.q.nlev, n1 = a.pitch, NN = N * N;
   const uint32_t mb = 4u * D * (uint32_t)K;
   const uint32_t vote_words = n1 * n1 * (uint32_t)K * D;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
   const uint32_t g = threadIdx.x & (D - 1u);
   const uint32_t C = lds_address(lds) + 4u * g;
   const uint32_t sent4 = N * 0x01010101u;
-  zero_lds(lds, vote_words);
-  __syncthreads();
-  if (t.unaligned)
-    batch_votes<Pix, MAXDY, D, true>(a, t, geo, C, n1, mb, sent4);
-  else
-    batch_votes<Pix, MAXDY, D, false>(a, t, geo, C, n1, mb, sent4);
+  const bool band = t.slot >= 0;
+  if (t.unaligned) {
+    if (band) batch_votes<Pix, MAXDY, D, true, true>(a, t, geo, C, n1, mb, sent4);
+    else batch_votes<Pix, MAXDY, D, true, false>(a, t, geo, C, n1, mb, sent4);
+  } else {
+    if (band) batch_votes<Pix, MAXDY, D, false, true>(a, t, geo, C, n1, mb, sent4);
+    else batch_votes<Pix, MAXDY, D, false, false>(a, t, geo, C, n1, mb, sent4);
+  }
 
   // merge: consecutive 16-byte units, D / 4 lanes per bin, into out and into
-  // an LDS copy for the statistics
+  // an LDS copy for the statistics; each unit is cleared once read
   __syncthreads();
   constexpr uint32_t QPB = D / 4;
   uint32_t* merged = lds + vote_words;
-  uint32_t* dst = a.out + (size_t)t.index * K * NN;
+  // a whole image: its counts; a band: its partial counts, summed (and the
+  // statistics taken) by k_batch_fin
+  uint32_t* dst = band ? a.partials + (size_t)t.slot * K * NN : a.out + (size_t)t.index * K * NN;
   // unit u = ((i * n1 + j) * K + k) * QPB + r: (i, j, k) step by the
   // mixed-radix digits of blockDim / QPB each pass, so nothing is divided
   const uint32_t S = blockDim.x / QPB, uK = (uint32_t)K;
@@ -175,6 +188,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
   const bool lead = threadIdx.x % QPB == 0;
   for (uint32_t u = threadIdx.x; u < vote_words / 4u; u += blockDim.x) {
     const uint4 v = ((const uint4*)lds)[u];
+    ((uint4*)lds)[u] = make_uint4(0u, 0u, 0u, 0u);
     uint32_t sum = (v.x + v.y) + (v.z + v.w);
     if (QPB >= 2) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0xb1, 0xf, 0xf, false);
     if (QPB >= 4) sum += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sum, 0x4e, 0xf, 0xf, false);
@@ -192,36 +206,93 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
     mj -= cj ? n1 : 0u;
     mi += si + cj;
   }
+  if (!a.feat || band) return;
+  __syncthreads();
+  // one wavefront per GLCM (K <= 4 = the workgroup's wavefronts)
+  if (wave < K) glcm_features_wave(merged + wave * NN, N, a.feat + ((size_t)t.index * K + wave) * 5);
+}
+
+// Persistent workgroups: each takes the next item from a counter (items are
+// ordered largest first) until none is left.  The counter is zero at launch;
+// k_batch_fin, which always follows, sets it back to zero.
+template <typename Pix, int MAXDY, int D, int WG>
+__global__ __launch_bounds__(WG) void k_batch(BatchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  __shared__ uint32_t s_item;
+  const uint32_t vote_words = a.pitch * a.pitch * (uint32_t)a.K * D;
+  zero_lds(lds, vote_words);
+  if (threadIdx.x == 0) s_item = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  for (;;) {
+    const uint32_t item = s_item;
+    if (item >= (uint32_t)a.nitems) break;
+    // the next item's number is fetched while this one is counted
+    uint32_t next = 0;
+    if (threadIdx.x == 0) next = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    batch_item<Pix, MAXDY, D>(a, a.tiles[item], lds);
+    __syncthreads();  // the item's LDS use and its read of s_item are over
+    if (threadIdx.x == 0) s_item = next;
+    __syncthreads();
+  }
+}
+
+// The images split into bands: one workgroup per image sums its bands'
+// partial counts (in band order) into out and takes the statistics.
+__global__ __launch_bounds__(kBatchThreads) void k_batch_fin(BatchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.counter = 0u;  // for the next launch of k_batch
+  if ((int)blockIdx.x >= a.nfins) return;
+  const BatchFin f = a.fins[blockIdx.x];
+  const uint32_t N = a.q.nlev, NN = N * N, KNN = (uint32_t)a.K * NN;
+  uint32_t* dst = a.out + (size_t)f.index * KNN;
+  const uint32_t* src = a.partials + (size_t)f.slot0 * KNN;
+  for (uint32_t w = threadIdx.x; w < KNN; w += blockDim.x) {
+    uint32_t s = 0;
+    for (int p = 0; p < f.parts; ++p) s += src[(size_t)p * KNN + w];
+    dst[w] = s;
+    lds[w] = s;
+  }
   if (!a.feat) return;
   __syncthreads();
-  unsigned long long* redu = (unsigned long long*)(merged + K * NN + ((K * NN) & 1u));
-  float* redf = (float*)(redu + blockDim.x);
-  for (int k = 0; k < K; ++k)
-    glcm_features_wg(merged + k * NN, N, a.feat + ((size_t)t.index * K + k) * 5, redu, redf);
+  const int wave = (int)(threadIdx.x >> 6);
+  if (wave < a.K) glcm_features_wave(lds + wave * NN, N, a.feat + ((size_t)f.index * a.K + wave) * 5);
 }
 
 }  // namespace
 
-template <typename Pix, int MAXDY>
-static hipError_t launch_batch_t(const BatchArgs& a, int T, int D, size_t lds_bytes, hipStream_t stream) {
-  const dim3 grid(T), block(kBatchThreads);
+template <typename Pix, int MAXDY, int WG>
+static hipError_t launch_batch_w(const BatchArgs& a, int T, int D, size_t lds_bytes, hipStream_t stream) {
+  const dim3 grid(T), block(WG);  // T persistent workgroups
   switch (D) {
-    case 4: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 4>), grid, block, lds_bytes, stream, a); break;
-    case 8: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 8>), grid, block, lds_bytes, stream, a); break;
-    case 16: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 16>), grid, block, lds_bytes, stream, a); break;
+    case 4: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 4, WG>), grid, block, lds_bytes, stream, a); break;
+    case 8: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 8, WG>), grid, block, lds_bytes, stream, a); break;
+    case 16: hipLaunchKernelGGL((k_batch<Pix, MAXDY, 16, WG>), grid, block, lds_bytes, stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, size_t lds_bytes,
+template <typename Pix, int MAXDY>
+static hipError_t launch_batch_t(const BatchArgs& a, int T, int D, int wg, size_t lds_bytes, hipStream_t stream) {
+  if (wg == 256) return launch_batch_w<Pix, MAXDY, 256>(a, T, D, lds_bytes, stream);
+  if (wg == 512) return launch_batch_w<Pix, MAXDY, 512>(a, T, D, lds_bytes, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_fin(const BatchArgs& a, int F, hipStream_t stream) {
+  const size_t lds = batch_fin_lds_bytes((int)a.q.nlev, a.K);
+  hipLaunchKernelGGL(k_batch_fin, dim3(F > 0 ? F : 1), dim3(kBatchThreads), lds, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
                         hipStream_t stream) {
   if (maxdy == 1)
-    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 1>(a, T, D, lds_bytes, stream)
-                            : launch_batch_t<uint16_t, 1>(a, T, D, lds_bytes, stream);
+    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 1>(a, T, D, wg, lds_bytes, stream)
+                            : launch_batch_t<uint16_t, 1>(a, T, D, wg, lds_bytes, stream);
   if (maxdy == 2)
-    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 2>(a, T, D, lds_bytes, stream)
-                            : launch_batch_t<uint16_t, 2>(a, T, D, lds_bytes, stream);
+    return dtype_bytes == 1 ? launch_batch_t<uint8_t, 2>(a, T, D, wg, lds_bytes, stream)
+                            : launch_batch_t<uint16_t, 2>(a, T, D, wg, lds_bytes, stream);
   return hipErrorInvalidValue;
 }
 

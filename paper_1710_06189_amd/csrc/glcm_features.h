@@ -53,6 +53,25 @@ __device__ __forceinline__ T wave_sum(T v) {
   return lane63(v);
 }
 
+// The five statistics from the exact integer sums and the fp32 sums.
+__device__ __forceinline__ void features_store(unsigned long long T, unsigned long long sc, unsigned long long si,
+                                               unsigned long long sj, unsigned long long sii, unsigned long long sjj,
+                                               unsigned long long sij, float energy, float ent, float homog,
+                                               float* o) {
+  using i128 = __int128;
+  const i128 tT = (i128)T;
+  const i128 vi = (i128)sii * tT - (i128)si * (i128)si;  // T^2 var_i
+  const i128 vj = (i128)sjj * tT - (i128)sj * (i128)sj;  // T^2 var_j
+  const i128 cv = (i128)sij * tT - (i128)si * (i128)sj;  // T^2 cov
+  double corr = 1.0;
+  if (vi != 0 && vj != 0) corr = (double)cv / sqrt((double)vi * (double)vj);
+  o[0] = (float)((double)sc / (double)T);
+  o[1] = energy;
+  o[2] = ent;
+  o[3] = homog;
+  o[4] = (float)corr;
+}
+
 __device__ __forceinline__ void glcm_features_wg(const uint32_t* P, uint32_t N, float* o, unsigned long long* redu, float* redf) {
   const uint32_t NN = N * N, nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // pass 1: total (needed for p)
@@ -114,20 +133,54 @@ __device__ __forceinline__ void glcm_features_wg(const uint32_t* P, uint32_t N, 
       sii += ru[6 * x + 3]; sjj += ru[6 * x + 4]; sij += ru[6 * x + 5];
       energy += redf[3 * x + 0]; ent += redf[3 * x + 1]; homog += redf[3 * x + 2];
     }
-    using i128 = __int128;
-    const i128 tT = (i128)T;
-    const i128 vi = (i128)sii * tT - (i128)si * (i128)si;  // T^2 var_i
-    const i128 vj = (i128)sjj * tT - (i128)sj * (i128)sj;  // T^2 var_j
-    const i128 cv = (i128)sij * tT - (i128)si * (i128)sj;  // T^2 cov
-    double corr = 1.0;
-    if (vi != 0 && vj != 0) corr = (double)cv / sqrt((double)vi * (double)vj);
-    o[0] = (float)((double)sc / (double)T);
-    o[1] = energy;
-    o[2] = ent;
-    o[3] = homog;
-    o[4] = (float)corr;
+    features_store(T, sc, si, sj, sii, sjj, sij, energy, ent, homog, o);
   }
   __syncthreads();  // the scratch may be reused once every thread is past it
+}
+
+// The same statistics computed by one wavefront, with no LDS and no barrier:
+// bit for bit what glcm_features_wg gives in a workgroup of one wavefront
+// (there the sums of the single wavefront are added to zero, which changes
+// nothing).  Every lane must call it; lane 0 writes o.
+__device__ __forceinline__ void glcm_features_wave(const uint32_t* P, uint32_t N, float* o) {
+  const uint32_t NN = N * N, lane = threadIdx.x & 63;
+  unsigned long long T = 0;
+  for (uint32_t t = lane; t < NN; t += 64u) T += P[t];
+  T = wave_sum(T);
+  if (T == 0 || T > 0xffffffffull) {
+    if (lane < 5) o[lane] = T == 0 ? 0.0f : __builtin_nanf("");
+    return;
+  }
+  const float invT = 1.0f / (float)T;
+  unsigned long long sc = 0, si = 0, sj = 0, sii = 0, sjj = 0, sij = 0;
+  float energy = 0.f, ent = 0.f, homog = 0.f;
+  const uint32_t di = 64u / N, dj = 64u % N;
+  uint32_t i = lane / N, j = lane % N;
+  for (uint32_t t = lane; t < NN; t += 64u) {
+    const uint32_t c = P[t];
+    if (c != 0) {
+      const unsigned long long d = i > j ? i - j : j - i;
+      sc += d * d * c;
+      si += (unsigned long long)i * c; sj += (unsigned long long)j * c;
+      sii += (unsigned long long)i * i * c; sjj += (unsigned long long)j * j * c;
+      sij += (unsigned long long)i * j * c;
+      const float p = (float)c * invT;
+      energy += p * p;
+      const float lp = (2ull * c > T) ? log1pf(-(float)(T - c) * invT) : logf(p);
+      ent -= p * lp;
+      homog += p / (1.0f + (float)(d * d));
+    }
+    j += dj;
+    i += di;
+    if (j >= N) {
+      j -= N;
+      ++i;
+    }
+  }
+  sc = wave_sum(sc); si = wave_sum(si); sj = wave_sum(sj);
+  sii = wave_sum(sii); sjj = wave_sum(sjj); sij = wave_sum(sij);
+  energy = wave_sum(energy); ent = wave_sum(ent); homog = wave_sum(homog);
+  if (lane == 0) features_store(T, sc, si, sj, sii, sjj, sij, 0.f + energy, 0.f + ent, 0.f + homog, o);
 }
 
 }  // namespace

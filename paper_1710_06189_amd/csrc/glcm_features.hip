@@ -17,10 +17,21 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t* glcm, int N, f
                    redu, redf);
 }
 
+// N <= kFeaturesWaveMaxN: one wavefront per GLCM, four per workgroup (the
+// batch kernel takes its statistics the same way, so both agree bit for bit).
+__global__ __launch_bounds__(256) void k_features_wave(const uint32_t* glcm, int K, int N, float* out) {
+  const int k = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (k >= K) return;
+  glcm_features_wave(glcm + (size_t)k * (uint32_t)N * (uint32_t)N, (uint32_t)N, out + (size_t)k * 5);
+}
+
 }  // namespace
 
 hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_features, dim3(K), dim3(256), 0, stream, glcm, N, out);
+  if (N <= kFeaturesWaveMaxN)
+    hipLaunchKernelGGL(k_features_wave, dim3((K + 3) / 4), dim3(256), 0, stream, glcm, K, N, out);
+  else
+    hipLaunchKernelGGL(k_features, dim3(K), dim3(256), 0, stream, glcm, N, out);
   return hipGetLastError();
 }
 

@@ -98,13 +98,22 @@ inline size_t block_lds_bytes(int N, int fbc) {
          512u * 32u + 64u;
 }
 
-// One image of a batch as the batch kernel reads it (device memory, 32 bytes).
+// One work item of a batch as the batch kernel reads it (device memory, 48
+// bytes): an image, or a band of first-pixel rows of an image too large for
+// one workgroup to finish with the others.
 struct BatchTile {
   const void* img;  // device pixels, row y at img + y * stride elements
   int64_t stride;   // elements
   int32_t W, H;
   int32_t index;    // slot of this image in the caller's order (output position)
   int32_t unaligned; // 1: base or row pitch not 16-byte aligned (rows read as dwords), else 0
+  int32_t y0, y1;   // first-pixel rows of the item (0, H for a whole image)
+  int32_t slot;     // -1: a whole image; else the band's row of partial counts
+  int32_t pad;
+};
+// An image split into bands: its bands' partial rows are slot0 .. slot0 + parts - 1.
+struct BatchFin {
+  int32_t index, slot0, parts, pad;
 };
 
 // Arguments of the fused batch kernel (quantize, vote, merge, features per
@@ -119,7 +128,11 @@ struct BatchArgs {
   unsigned long long tmask;            // bit k: offset k counted as its opposite, stored transposed
   uint32_t pitch;                      // N + 1
   int min_rows;                        // shortest row segment a lane walks
-  const BatchTile* tiles;              // [T], largest first
+  const BatchTile* tiles;              // [nitems], largest first
+  const BatchFin* fins;                // [nfins] images split into bands
+  uint32_t* partials;                  // [band slots][K][N][N] partial counts of the bands
+  uint32_t* counter;                   // next item (zero at launch; k_batch_fin clears it)
+  int nitems, nfins;
   uint32_t* out;                       // [T][K][N][N]
   float* feat;                         // [T][K][5] or null
 };
@@ -153,19 +166,26 @@ hipError_t launch_vote_global(const VoteArgs& a, int dtype_bytes, hipStream_t st
 // in runs of a.region_rows; `groups` workgroups of 256 threads.
 hipError_t launch_vote_l2(const VoteArgs& a, int dtype_bytes, int groups, hipStream_t stream,
                           const LaunchTiming& tm = {});
+// Statistics of K GLCMs: one wavefront per GLCM up to this N, one workgroup above.
+constexpr int kFeaturesWaveMaxN = 128;
 hipError_t launch_features(const uint32_t* glcm, int K, int N, float* out, hipStream_t stream);
 // Block-code kernel: a.nregions workgroups of `wg` threads, block_lds_bytes(N, a.fb_copies) of LDS.
 hipError_t launch_vote_blocks(const BlockArgs& a, int dtype_bytes, int wg, hipStream_t stream,
                               const LaunchTiming& tm = {});
-// One workgroup per image of the batch (T images); D = dwords per bin (4, 8
-// or 16), maxdy = 1 or 2.  lds_bytes from batch_lds_bytes().
-hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, size_t lds_bytes,
+// T persistent workgroups of wg threads (256 or 512) over the a.nitems items
+// of a batch; D = dwords per bin (4, 8 or 16), maxdy = 1 or 2.  lds_bytes
+// from batch_lds_bytes().
+hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
                         hipStream_t stream);
 constexpr int kBatchThreads = 256;
+// Sums the bands of the F split images into out (and their statistics) and
+// clears a.counter; launched after every launch_batch, also when F = 0.
+hipError_t launch_batch_fin(const BatchArgs& a, int F, hipStream_t stream);
+inline size_t batch_fin_lds_bytes(int N, int K) { return (size_t)K * N * N * 4u; }
 inline size_t batch_lds_bytes(int N, int K, int D) {
   const size_t n1 = (size_t)N + 1u;
-  // vote copies, merged counts, 8-byte alignment pad, u64 + f32 reduction scratch
-  return (n1 * n1 * (size_t)K * (size_t)D + (size_t)K * N * N) * 4u + 8u + (size_t)kBatchThreads * 12u;
+  // vote copies, then the merged counts the statistics read
+  return (n1 * n1 * (size_t)K * (size_t)D + (size_t)K * N * N) * 4u;
 }
 
 }  // namespace glcm

@@ -301,11 +301,45 @@ def test_batch_autotune_keeps_a_measured_layout():
     try:
         ref_out, ref_f = G.glcm_batch_compute(tens, plan)
         chosen = plan.batch_autotune(tens, repeats=2)
-        assert chosen.replicas in (4, 8, 16) and chosen.min_rows in (4, 8, 16, 32) and chosen.wg_size == 256
+        assert chosen.replicas in (4, 8, 16) and chosen.min_rows in (4, 8, 16, 32) and chosen.wg_size in (256, 512)
         assert plan.batch_tuning.as_dict() == chosen.as_dict()
         o, f = G.glcm_batch_compute(tens, plan)
         assert np.array_equal(host(o), host(ref_out)) and np.array_equal(host(f), host(ref_f))
         for t in range(0, 64, 8):
             assert np.array_equal(host(o)[t], oracle.glcm(imgs[t], N, 0, 255, offs))
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("dt,N,lo,hi", [(np.uint8, 16, 0, 255), (np.uint16, 24, 100, 60000)])
+def test_batch_large_images_split_into_bands(dt, N, lo, hi):
+    """Images above 2^20 pixels are counted as bands of rows by several
+    workgroups and summed by k_batch_fin: band edges must neither drop nor
+    double a pair, for offsets reaching two rows down or up (counted
+    transposed), narrow and wide images, next to small whole images."""
+    shapes = [(4200, 260), (1030, 1100), (129, 9000), (300, 301), (33, 35), (1, 70000)]
+    imgs = [synth.smooth(h, w, 3.0, 900 + i, dt, noise_frac=0.05) for i, (h, w) in enumerate(shapes)]
+    offs = [(1, 0), (-2, 2), (0, -2), (2, 1)]
+    run_batch(imgs, N, lo, hi, offs)
+
+
+def test_batch_misaligned_bands():
+    base = to_device(synth.smooth(1500, 1301, 4.0, 950))
+    views = [base[:, 1:], base[3:1450, 5:801], base[:500, 7:1000]]
+    imgs = [v.cpu().numpy() for v in views]
+    run_batch(imgs, 32, 0, 255, [(1, 0), (-1, 1), (0, 1), (1, 1)], views=views)
+
+
+@pytest.mark.parametrize("wg", [256, 512])
+@pytest.mark.parametrize("D", [4, 16])
+def test_batch_workgroup_sizes(wg, D):
+    w = synth.batch_tiles(160)
+    imgs, N, offs = w["images"], w["N"], w["offsets"]
+    imgs = imgs + [synth.smooth(1100, 1000, 4.0, 977)]  # one image split into bands
+    plan = G.glcm_plan_create(np.uint8, N, offs, 1100, 1100)
+    try:
+        t = plan.set_batch_tuning(replicas=D, min_rows=8, wg_size=wg)
+        assert (t.replicas, t.wg_size) == (D, wg)
+        run_batch(imgs, N, w["lo"], w["hi"], offs, plan=plan)
     finally:
         plan.close()
