@@ -805,6 +805,23 @@ def bench_multispectral(args, G, torch, np, oracle, synth, dev):
         "resident": "pinned host", "check": "band 0 bit-exact vs oracle; all bands per-offset totals"}), flush=True)
 
 
+def served_bound(reqs, alone_ms, t_sync, t_closed):
+    """How far any server can get above one request at a time on this mix.
+    A request of side >= 4096 (16 Mi pixels) keeps every CU busy by itself
+    for most of its run (its counting kernels launch hundreds of 512-1024
+    thread workgroups per image pass), so such requests cannot together run
+    much faster than one after the other: their summed device time alone is
+    close to a floor under any schedule's wall time.  For side >= 2048 the
+    same sum is only indicative (the measured server beats it: those kernels
+    leave CUs idle at their ends, which other requests fill)."""
+    out = {"requests_alone_device_ms": sum(alone_ms), "one_at_a_time_ms": t_sync * 1e3, "served_ms": t_closed * 1e3}
+    for side in (2048, 4096):
+        big = [ms for r, ms in zip(reqs, alone_ms) if r["side"] >= side]
+        out[f"side_ge_{side}"] = {"requests": len(big), "device_ms": sum(big),
+                                  "one_at_a_time_over_it": t_sync * 1e3 / sum(big) if big else None}
+    return out
+
+
 def bench_serving(args, G, torch, np, oracle, synth, dev):
     """The serving workload: requests are square crops (side uniform in
     [256, 8192]) of a smooth or a noise 8192^2 pool image, N from {8, 16, 32,
@@ -865,16 +882,19 @@ def bench_serving(args, G, torch, np, oracle, synth, dev):
             evs.append((r["N"], path, e0, e1))
         torch.cuda.synchronize()
         agg = {}
+        alone.clear()
         for (N, path, e0, e1), pr in zip(evs, pairs):
             a = agg.setdefault(str(N), {"requests": 0, "pairs": 0, "ms": 0.0, "paths": {}})
             a["requests"] += 1
             a["pairs"] += pr
             a["ms"] += e0.elapsed_time(e1)
             a["paths"][path] = a["paths"].get(path, 0) + 1
+            alone.append(e0.elapsed_time(e1))
         for a in agg.values():
             a["gpairs_s"] = a["pairs"] / (a["ms"] * 1e-3) / 1e9
         return agg
 
+    alone = []  # device ms of each request alone (counts + statistics)
     one_stream(False)  # warm-up
     per_n = by_n()
     print(f"[serving] per N: {json.dumps(per_n)}", file=sys.stderr, flush=True)
@@ -973,6 +993,7 @@ def bench_serving(args, G, torch, np, oracle, synth, dev):
             "served_closed_loop_gpairs_s": total_pairs / t_closed / 1e9, "capacity_req_s": capacity,
             "served_over_one_at_a_time": t_sync / t_closed, "served_over_one_stream": t_stream / t_closed,
             "open_loop": open_loop, "max_inflight": st.max_inflight, "alone_by_N": per_n,
+            "served_bound": served_bound(reqs, alone, t_sync, t_closed),
             "max_budgeted_gib": st.max_bytes_in_use / 2 ** 30,
             "check": "every served result == the same request alone (counts and statistics, bit for bit); "
                      "16 smallest requests == oracle"}

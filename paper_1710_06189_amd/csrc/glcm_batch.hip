@@ -213,8 +213,10 @@ __device__ __forceinline__ void batch_item(const BatchArgs& a, const BatchTile& 
 }
 
 // Persistent workgroups: each takes the next item from a counter (items are
-// ordered largest first) until none is left.  The counter is zero at launch;
-// k_batch_fin, which always follows, sets it back to zero.
+// ordered largest first) until none is left.  The counter is zero at launch.
+// Every workgroup takes one number past the last item before it stops, so
+// the counter ends at nitems + gridDim.x, and the workgroup that drew the
+// last number sets it back to zero: no other workgroup touches it after.
 template <typename Pix, int MAXDY, int D, int WG>
 __global__ __launch_bounds__(WG) void k_batch(BatchArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
@@ -225,7 +227,11 @@ __global__ __launch_bounds__(WG) void k_batch(BatchArgs a) {
   __syncthreads();
   for (;;) {
     const uint32_t item = s_item;
-    if (item >= (uint32_t)a.nitems) break;
+    if (item >= (uint32_t)a.nitems) {
+      if (threadIdx.x == 0 && item == (uint32_t)a.nitems + gridDim.x - 1u)
+        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
     // the next item's number is fetched while this one is counted
     uint32_t next = 0;
     if (threadIdx.x == 0) next = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -240,8 +246,6 @@ __global__ __launch_bounds__(WG) void k_batch(BatchArgs a) {
 // partial counts (in band order) into out and takes the statistics.
 __global__ __launch_bounds__(kBatchThreads) void k_batch_fin(BatchArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.counter = 0u;  // for the next launch of k_batch
-  if ((int)blockIdx.x >= a.nfins) return;
   const BatchFin f = a.fins[blockIdx.x];
   const uint32_t N = a.q.nlev, NN = N * N, KNN = (uint32_t)a.K * NN;
   uint32_t* dst = a.out + (size_t)f.index * KNN;
@@ -280,8 +284,9 @@ static hipError_t launch_batch_t(const BatchArgs& a, int T, int D, int wg, size_
 }
 
 hipError_t launch_batch_fin(const BatchArgs& a, int F, hipStream_t stream) {
+  if (F <= 0) return hipSuccess;
   const size_t lds = batch_fin_lds_bytes((int)a.q.nlev, a.K);
-  hipLaunchKernelGGL(k_batch_fin, dim3(F > 0 ? F : 1), dim3(kBatchThreads), lds, stream, a);
+  hipLaunchKernelGGL(k_batch_fin, dim3(F), dim3(kBatchThreads), lds, stream, a);
   return hipGetLastError();
 }
 

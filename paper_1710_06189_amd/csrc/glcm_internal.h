@@ -131,7 +131,7 @@ struct BatchArgs {
   const BatchTile* tiles;              // [nitems], largest first
   const BatchFin* fins;                // [nfins] images split into bands
   uint32_t* partials;                  // [band slots][K][N][N] partial counts of the bands
-  uint32_t* counter;                   // next item (zero at launch; k_batch_fin clears it)
+  uint32_t* counter;                   // next item (zero at launch and again at the end)
   int nitems, nfins;
   uint32_t* out;                       // [T][K][N][N]
   float* feat;                         // [T][K][5] or null
@@ -178,8 +178,8 @@ hipError_t launch_vote_blocks(const BlockArgs& a, int dtype_bytes, int wg, hipSt
 hipError_t launch_batch(const BatchArgs& a, int T, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
                         hipStream_t stream);
 constexpr int kBatchThreads = 256;
-// Sums the bands of the F split images into out (and their statistics) and
-// clears a.counter; launched after every launch_batch, also when F = 0.
+// Sums the bands of the F split images into out (and their statistics);
+// nothing is launched when F = 0.
 hipError_t launch_batch_fin(const BatchArgs& a, int F, hipStream_t stream);
 inline size_t batch_fin_lds_bytes(int N, int K) { return (size_t)K * N * N * 4u; }
 inline size_t batch_lds_bytes(int N, int K, int D) {
