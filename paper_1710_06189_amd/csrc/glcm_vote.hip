@@ -216,6 +216,81 @@ __device__ __forceinline__ int2 band_of_block(int b, int P, int nregions) {
 // first pixel, loads through the cache, votes into the LDS copies of the
 // partition this workgroup owns.
 // ---------------------------------------------------------------------------
+// A uniform value the compiler must keep in a register: reading it again from
+// the kernel arguments inside the loop would be a scalar load, whose wait
+// also waits for every LDS vote in flight (they share one counter).
+__device__ __forceinline__ int keep_s(int v) {
+  int r;
+  asm volatile("s_mov_b32 %0, %1" : "=s"(r) : "s"(v));
+  return r;
+}
+
+// The loop of a partition whose bins belong to NK consecutive offsets k0 ..
+// k0 + NK - 1 (NK <= 4, the usual case: a partition holds about one GLCM of
+// the large N that need partitions).  Each thread takes 4 pixels of a row (2
+// for NK > 2) at once and issues all their first- and second-pixel loads
+// before any vote,
+// with the offsets held in registers; a pair whose bin lies outside the
+// partition (or whose second pixel lies outside the image) votes nowhere.
+template <typename Pix, int NK>
+__device__ __forceinline__ void generic_votes(const VoteArgs& a, uint32_t* lds, int k0, uint32_t pbase,
+                                              uint32_t pwords, uint32_t r, int y0, int y1, int tw, int tr, int tx,
+                                              int ty) {
+  constexpr int U = NK <= 2 ? 4 : 2;  // (more would spill at 1024 threads)
+  const Pix* img = (const Pix*)a.img;
+  const uint32_t N = a.q.nlev, NN = N * N;
+  int dx[NK], dy[NK];
+  int64_t off[NK];
+  uint32_t wbase[NK];  // k N^2 - pbase (wraps: a bin below the partition reads as >= pwords)
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    dx[j] = keep_s(a.dx[k0 + j]);
+    dy[j] = keep_s(a.dy[k0 + j]);
+    off[j] = (int64_t)dy[j] * a.stride + dx[j];
+    wbase[j] = (uint32_t)(k0 + j) * NN - pbase;
+  }
+  const int W = keep_s(a.W), H = keep_s(a.H);
+  const bool qf = a.qfast != 0;
+  const uint32_t qs = (uint32_t)keep_s((int)a.qfast_shift);
+  const Quant q{(uint32_t)keep_s((int)a.q.lo), (uint32_t)keep_s((int)a.q.hi), N, (uint32_t)keep_s((int)a.q.magic),
+                (uint32_t)keep_s((int)a.q.shift)};
+  const bool c16 = a.c16 != 0;
+  const int log2R = keep_s(a.log2R);
+  for (int y = y0 + ty; y < y1; y += tr) {
+    const Pix* row = img + (int64_t)y * a.stride;
+    for (int x = tx; x < W; x += U * tw) {
+      uint32_t v1[U], v2[U][NK];
+      bool ok[U][NK];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int xu = x + u * tw;
+        const bool in = xu < W;
+        v1[u] = in ? (uint32_t)row[xu] : 0u;
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+          ok[u][j] = in && (unsigned)(xu + dx[j]) < (unsigned)W && (unsigned)(y + dy[j]) < (unsigned)H;
+          v2[u][j] = ok[u][j] ? (uint32_t)row[xu + off[j]] : 0u;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t av = qf ? v1[u] >> qs : quantize(v1[u], q);
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+          const uint32_t w = wbase[j] + av * N + (qf ? v2[u][j] >> qs : quantize(v2[u][j], q));
+          if (ok[u][j] && w < pwords) {
+            if (c16)
+              __hip_atomic_fetch_add(&lds[w >> 1], 1u << ((w & 1u) << 4), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+            else
+              __hip_atomic_fetch_add(&lds[(w << log2R) + r], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename Pix>
 __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
@@ -243,6 +318,12 @@ __global__ __launch_bounds__(1024) void k_vote_generic(VoteArgs a) {
   int tw = 64;
   while (tw < a.W && tw < (int)blockDim.x) tw *= 2;
   const int tr = (int)blockDim.x / tw, tx = (int)threadIdx.x & (tw - 1), ty = (int)threadIdx.x / tw;
+  const int nk = k1 - k0;
+  if (nk == 1) generic_votes<Pix, 1>(a, lds, k0, pbase, pwords, r, y0, y1, tw, tr, tx, ty);
+  else if (nk == 2) generic_votes<Pix, 2>(a, lds, k0, pbase, pwords, r, y0, y1, tw, tr, tx, ty);
+  else if (nk == 3) generic_votes<Pix, 3>(a, lds, k0, pbase, pwords, r, y0, y1, tw, tr, tx, ty);
+  else if (nk == 4) generic_votes<Pix, 4>(a, lds, k0, pbase, pwords, r, y0, y1, tw, tr, tx, ty);
+  else
   for (int y = y0 + ty; y < y1; y += tr) {
     for (int x = tx; x < a.W; x += tw) {
       const uint32_t v = img[(int64_t)y * a.stride + x];
