@@ -319,14 +319,6 @@ __device__ __forceinline__ int block_band(int b, int nregions) {
   return (b % 8) * (full / 8) + b / 8;
 }
 
-// Byte offset of the first pixel right of span `span` (1024 pixels per span),
-// or 0 when it lies outside the row.
-template <typename Pix>
-__device__ __forceinline__ uint32_t next_span_offset(int span, int W) {
-  const int x = (span + 1) << 10;
-  return x < W ? (uint32_t)x * (uint32_t)sizeof(Pix) : 0u;
-}
-
 // A uniform value the compiler must keep (it cannot load it again from the
 // kernel arguments later: a late scalar load would wait for the LDS atomics
 // in flight, which share its wait counter).

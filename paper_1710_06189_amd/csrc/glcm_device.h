@@ -142,6 +142,15 @@ __host__ __device__ inline LaneCols lane_cols(const Geom& a, int x0) {
   return {(uint32_t)xc * b, (uint32_t)xc2 * b, (uint32_t)xl * b, (uint32_t)xr * b};
 }
 
+// Block-code kernel: byte offset of the first pixel right of span `span`
+// (64 lanes of 16 pixels), where the span's last lane reads its right halo,
+// or 0 when that pixel lies outside the row.
+template <typename Pix>
+__host__ __device__ inline uint32_t next_span_offset(int span, int W) {
+  const int x = (span + 1) << 10;
+  return x < W ? (uint32_t)x * (uint32_t)sizeof(Pix) : 0u;
+}
+
 // Byte offset of row y of the image, rows below the last read as the last.
 template <typename Pix>
 __host__ __device__ inline int64_t row_offset(const Geom& a, int y) {

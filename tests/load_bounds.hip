@@ -2,10 +2,11 @@
 //
 // Built by tests/test_load_bounds_cpu.py with hipcc and run on the host (no
 // GPU): it calls the same __host__ __device__ address helpers the kernels use
-// (lane_cols, row_offset, unaligned_row, unaligned_dword_in_row,
-// chunk_second_block, ChunkPos, hist_geometry) for every lane position a
+// (lane_cols, row_offset, next_span_offset, unaligned_row,
+// unaligned_dword_in_row, chunk_second_block, ChunkPos, hist_geometry) for every lane position a
 // kernel can take, and checks each access:
-//  * 16-byte aligned rows (strip, slab-halo and batch loads, histogram chunks):
+//  * 16-byte aligned rows (strip, slab-halo, block-code and batch loads,
+//    histogram chunks):
 //    the access stays inside one 16-byte block of the row, and that block
 //    holds at least one pixel of the row;
 //  * rows read as dwords (batch images that are not 16-byte aligned): every
@@ -53,6 +54,32 @@ static void aligned_rows(int W, int H, int extra_blocks) {
       if (B == 2) check_block("chunk2", B, W, H, pitch, x0, y, row + o.c2, 16);
       check_block("left halo", B, W, H, pitch, x0, y, row + o.l, 4 * B);
       check_block("right halo", B, W, H, pitch, x0, y, row + o.r, 4 * B);
+    }
+  }
+}
+
+// Block-code kernel loads (16-byte aligned rows): each lane's chunk (and its
+// second half for 16-bit pixels) at lane_cols, and the 4-pixel right halo at
+// next_span_offset that the last lane of a 64-lane span reads (the other lanes
+// load it too, at the same address), for every span and lane, rows past the
+// image included.
+template <typename Pix>
+static void block_rows(int W, int H, int extra_blocks) {
+  constexpr int B = (int)sizeof(Pix);
+  const long pitch = ((long)W * B + 15) / 16 * 16 + 16L * extra_blocks;
+  const Geom g{nullptr, pitch / B, W, H};
+  const int chunks = (W + 15) / 16, spans = (chunks + 63) / 64;
+  for (int span = 0; span < spans; ++span) {
+    const uint32_t xn = next_span_offset<Pix>(span, W);
+    for (int lane = 0; lane < 64; ++lane) {
+      const int x0 = ((span << 6) + lane) << 4;
+      const LaneCols o = lane_cols<Pix>(g, x0);
+      for (int y = 0; y < H + 7; ++y) {
+        const long row = (long)row_offset<Pix>(g, y);
+        check_block("block chunk", B, W, H, pitch, x0, y, row + o.c, 16);
+        if (B == 2) check_block("block chunk2", B, W, H, pitch, x0, y, row + o.c2, 16);
+        check_block("block halo", B, W, H, pitch, x0, y, row + xn, 4 * B);
+      }
     }
   }
 }
@@ -119,6 +146,8 @@ int main() {
     for (int H : {1, 2, 3}) {
       aligned_rows<uint8_t>(W, H, 0);
       aligned_rows<uint16_t>(W, H, 0);
+      block_rows<uint8_t>(W, H, 0);
+      block_rows<uint16_t>(W, H, 0);
       for (int base : {0, 1, 2, 3, 5, 7, 13}) {
         for (int extra : {0, 1, 3}) {
           unaligned_rows<uint8_t>(W, H, base, extra);
@@ -129,6 +158,8 @@ int main() {
     if (W % 3 == 0) {
       aligned_rows<uint8_t>(W, 2, 1);
       aligned_rows<uint16_t>(W, 2, 1);
+      block_rows<uint8_t>(W, 2, 1);
+      block_rows<uint16_t>(W, 2, 1);
     }
     histogram<uint8_t>(W, 1, 256);
     histogram<uint16_t>(W, 2, 256);

@@ -1,8 +1,8 @@
 """Regression guard for the kernels' global loads (CPU only, no GPU).
 
 tests/load_bounds.hip calls the same __host__ __device__ address helpers the
-kernels use (the strip/batch row loads, the in-place reads of misaligned batch
-images, the histogram's chunk walk) for every lane position the kernels can
+kernels use (the strip, block-code and batch row loads, the in-place reads
+of misaligned batch images, the histogram's chunk walk) for every lane position the kernels can
 take: widths 1..2100, u8 and u16, aligned and misaligned bases and pitches,
 rows past the image, several CU counts.  Every access must stay within a
 16-byte block (aligned rows) or a dword (misaligned rows) that holds a pixel
