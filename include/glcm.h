@@ -160,13 +160,16 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t *tuning, int set);
 
 /*
  * Picks the plan's launch parameters by timing the candidate layouts (LDS
- * copies, counter width, workgroup size and, for a plan whose offsets are all
- * d = 1 directions of Eq. (2) or their opposites, the block-code kernel
- * against the strip kernel) on a representative DEVICE image: each candidate
- * counts the image `repeats` times after two warm-up runs, on `stream`; the
- * fastest is kept (a later candidate must be 3% faster to replace an earlier
- * one) and written to *chosen (may be NULL).  A plan created with
- * GLCM_FLAG_FORCE_BLOCKS keeps the block-code kernel.  The
+ * copies, counter width, workgroup size; for row-kernel plans both the strip
+ * kernel, where every offset has |dx|, |dy| <= 2, and the slab kernel, and,
+ * for a plan whose offsets are all d = 1 directions of Eq. (2) or their
+ * opposites, the block-code kernel) on a representative DEVICE image: each
+ * candidate counts the image `repeats` times after two warm-up runs, on
+ * `stream`, starting with the plan's current parameters; the fastest is kept
+ * (a later candidate must be 3% faster to replace an earlier one) and written
+ * to *chosen (may be NULL).  A plan created with GLCM_FLAG_FORCE_BLOCKS keeps
+ * the block-code kernel; one created with GLCM_FLAG_FORCE_SLABS keeps the
+ * slab kernel.  The
  * call blocks until the timing is done and leaves the plan's results
  * unchanged in meaning (every candidate computes the same counts).
  * Errors: GLCM_EINVAL for a NULL plan or image, a host image, sizes beyond the

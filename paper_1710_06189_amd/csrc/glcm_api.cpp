@@ -411,6 +411,27 @@ constexpr int kPassesPerSliceGlcm = 13;
 // over 8 in every run measured on MI355X (0.291 against 0.309 ms per batch).
 constexpr int kBatchDefaultMinRows = 4;
 
+// Row kernels (strips, slabs, blocks) store a level and the sentinel N in one
+// byte; the strip kernel reaches |dx|, dy <= 2, the slab kernel 4.
+bool row_kernels_ok(const glcm_plan_s* p) {
+  return !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) && p->N <= 255;
+}
+bool strips_eligible(const glcm_plan_s* p, const Canon& c) {
+  return row_kernels_ok(p) && !(p->flags & GLCM_FLAG_FORCE_SLABS) && c.maxadx <= 2 && c.maxdy <= 2 &&
+         strip_partitions(p, 4, 16) > 0;
+}
+bool slabs_eligible(const glcm_plan_s* p, const Canon& c) {
+  return row_kernels_ok(p) && c.maxadx <= 4 && c.maxdy <= 4 && row_partitions(p, 1, 32) > 0;
+}
+
+// Whether the strip layout with R dwords per bin beats the slab kernel by
+// default.  Measured on MI355X (4096^2 smooth and noise images and an 8192^2
+// band, u8 and u16, N = 8 to 64, d = 1, 2 and both): with 16 or 32 dwords per
+// bin, and with 8 at a reach of 1, strips are 1.0-1.5x faster; with 8 at a
+// reach of 2, or 4, they tie on smooth images and are up to 1.5x slower on
+// noise and on 8192-pixel rows (the few copies concentrate same-bank votes).
+bool strips_beat_slabs(int R, int reach) { return R >= 16 || (R == 8 && reach <= 1); }
+
 int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   // Path and LDS layout for this plan's (dtype, N, K, offsets, flags).
   const uint32_t NN = (uint32_t)p->N * (uint32_t)p->N;
@@ -432,18 +453,12 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
     d.replicas = 1;
     d.partitions = 1;
   } else {
-    const bool any_rows = !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) && p->N <= 255;
-    const bool blocks_ok = any_rows && (p->flags & GLCM_FLAG_FORCE_BLOCKS) && blocks_fit(p);
-    const bool strips_ok = any_rows && !(p->flags & GLCM_FLAG_FORCE_SLABS) && c.maxadx <= 2 && c.maxdy <= 2 &&
-                           strip_partitions(p, 4, 16) > 0;
-    const bool rows_ok = any_rows && c.maxadx <= 4 && c.maxdy <= 4 && row_partitions(p, 1, 32) > 0;
-    if (blocks_ok) {
-      d.path = kPathBlocks;
-      d.replicas = 32;
-      d.counter_bits = 16;
-      d.partitions = 1;
-    } else if (strips_ok) {
-      d.path = kPathStrips;
+    const bool blocks_ok = row_kernels_ok(p) && (p->flags & GLCM_FLAG_FORCE_BLOCKS) && blocks_fit(p);
+    const bool rows_ok = slabs_eligible(p, c);
+    bool strips_ok = strips_eligible(p, c);
+    glcm_tuning_t st = d;
+    if (strips_ok) {
+      st.path = kPathStrips;
       // The most dwords per bin (32 put every lane of a 32-lane LDS pass on
       // its own bank) that costs at most max(2, minimum) image passes, with
       // two GLCMs per dword (16-bit counters) unless 32-bit counters fit in as
@@ -455,12 +470,21 @@ int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
         const int bits = (P16 > 0 && (P32 == 0 || P16 < P32)) ? 16 : 32;
         const int P = bits == 16 ? P16 : P32;
         if (P > 0 && P <= std::max(2, Pmin)) {
-          d.replicas = R;
-          d.counter_bits = bits;
-          d.partitions = P;
+          st.replicas = R;
+          st.counter_bits = bits;
+          st.partitions = P;
           break;
         }
       }
+      if (rows_ok && !strips_beat_slabs(st.replicas, std::max(c.maxdy, c.maxadx))) strips_ok = false;
+    }
+    if (blocks_ok) {
+      d.path = kPathBlocks;
+      d.replicas = 32;
+      d.counter_bits = 16;
+      d.partitions = 1;
+    } else if (strips_ok) {
+      d = st;
     } else if (rows_ok) {
       d.path = kPathRows;
       d.rows_per_wave = 4;
@@ -1233,52 +1257,71 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
   }
   // candidates: copies x counter width x workgroup size, within 4x the
   // minimal number of partitions
-  std::vector<glcm_tuning_t> cand;
+  // (the plan's own tuning first: a later candidate must beat it by 3%)
+  std::vector<glcm_tuning_t> cand{start};
+  auto add = [&](const glcm_tuning_t& t) {
+    for (const glcm_tuning_t& u : cand)
+      if (u.path == t.path && u.replicas == t.replicas && u.counter_bits == t.counter_bits &&
+          u.partitions == t.partitions && u.wg_size == t.wg_size && u.rows_per_wave == t.rows_per_wave &&
+          u.merge == t.merge)
+        return;
+    cand.push_back(t);
+  };
+  const Canon cn = canonicalize(plan->offsets, plan->K);
   if (start.path == kPathBlocks) {
-    cand.push_back(start);  // forced by GLCM_FLAG_FORCE_BLOCKS: its layout is fixed
-  } else if (start.path == kPathStrips) {
-    const int Pmin = strip_partitions(plan, 4, 16);
-    for (int bits : {32, 16})
-      for (int R = 4; R <= 32; R *= 2) {
-        const int P = strip_partitions(plan, R, bits);
-        if (P == 0 || P > 4 * Pmin) continue;
-        for (int wg : {512, 1024}) {
-          glcm_tuning_t t = start;
-          t.replicas = R;
-          t.counter_bits = bits;
-          t.partitions = P;
-          t.wg_size = wg;
-          cand.push_back(t);
+    // forced by GLCM_FLAG_FORCE_BLOCKS: its layout is fixed
+  } else if (start.path == kPathStrips || start.path == kPathRows) {
+    // both row-kernel families wherever the offsets allow them
+    if (strips_eligible(plan, cn)) {
+      const int Pmin = strip_partitions(plan, 4, 16);
+      for (int bits : {32, 16})
+        for (int R = 4; R <= 32; R *= 2) {
+          const int P = strip_partitions(plan, R, bits);
+          if (P == 0 || P > 4 * Pmin) continue;
+          for (int wg : {512, 1024}) {
+            glcm_tuning_t t = start;
+            t.path = kPathStrips;
+            t.rows_per_wave = 0;
+            t.replicas = R;
+            t.counter_bits = bits;
+            t.partitions = P;
+            t.wg_size = wg;
+            add(t);
+          }
         }
-      }
+    }
+    if (slabs_eligible(plan, cn)) {
+      const int Pmin = row_partitions(plan, 1, 32);
+      for (int bits : {32, 16})
+        for (int R = bits == 16 ? 2 : 1; R <= 64; R *= 2) {
+          const int P = row_partitions(plan, R, bits);
+          if (P == 0 || P > 4 * Pmin) continue;
+          for (int wg : {512, 1024}) {
+            glcm_tuning_t t = start;
+            t.path = kPathRows;
+            t.rows_per_wave = 4;
+            t.replicas = R;
+            t.counter_bits = bits;
+            t.partitions = P;
+            t.wg_size = wg;
+            add(t);
+          }
+        }
+    }
     // the block-code kernel, where every offset is a d = 1 direction: faster
     // on smooth images, slower where most 2x2 blocks leave its code window
     // (noise), which is what the timing decides
-    if (plan->xbuf && blocks_fit(plan)) {
+    if (plan->xbuf && blocks_fit(plan) && row_kernels_ok(plan) && !(plan->flags & GLCM_FLAG_FORCE_SLABS)) {
       glcm_tuning_t t = start;
       t.path = kPathBlocks;
+      t.rows_per_wave = 0;
       t.replicas = 32;
       t.counter_bits = 16;
       t.partitions = 1;
       t.wg_size = 1024;
       t.merge = 0;
-      cand.push_back(t);
+      add(t);
     }
-  } else if (start.path == kPathRows) {
-    const int Pmin = row_partitions(plan, 1, 32);
-    for (int bits : {32, 16})
-      for (int R = bits == 16 ? 2 : 1; R <= 64; R *= 2) {
-        const int P = row_partitions(plan, R, bits);
-        if (P == 0 || P > 4 * Pmin) continue;
-        for (int wg : {512, 1024}) {
-          glcm_tuning_t t = start;
-          t.replicas = R;
-          t.counter_bits = bits;
-          t.partitions = P;
-          t.wg_size = wg;
-          cand.push_back(t);
-        }
-      }
   } else {
     const uint64_t words = (uint64_t)plan->K * plan->N * plan->N, budget = (uint64_t)plan->lds_budget_words;
     for (int R = 1; R <= 16; R *= 2) {
@@ -1293,7 +1336,7 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
           t.path = P > 1 ? kPathPartitioned : kPathGeneric;
           t.counter_bits = bits;
           t.wg_size = wg;
-          cand.push_back(t);
+          add(t);
         }
       }
     }
@@ -1303,7 +1346,7 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void* img, int W, int H,
       t.replicas = 1;
       t.partitions = 1;
       t.merge = 0;
-      cand.push_back(t);
+      add(t);
     }
   }
   const size_t words = (size_t)plan->K * plan->N * plan->N;

@@ -129,9 +129,9 @@ def test_misaligned_view_is_staged(kind):
 
 
 @pytest.mark.parametrize("kind", ["smooth", "uniform"])
-def test_autotune_between_strips_and_blocks(kind):
-    """glcm_plan_autotune times the block-code kernel against the strip
-    layouts for a d = 1 plan; whichever it keeps, the counts stay exact."""
+def test_autotune_between_row_kernels_and_blocks(kind):
+    """glcm_plan_autotune times the block-code kernel against the strip and
+    slab layouts for a d = 1 plan; whichever it keeps, the counts stay exact."""
     w = synth.square_4096(kind)
     img = w["images"][0]
     t = to_device(img)
@@ -140,7 +140,7 @@ def test_autotune_between_strips_and_blocks(kind):
         chosen = plan.autotune(t, 0, 255, repeats=3)
         name = G.PATH_NAMES[chosen.path]
         print(f"[autotune] {kind}: {chosen.as_dict()}", flush=True)
-        assert name in ("strips", "blocks")
+        assert name in ("strips", "slabs", "blocks")
         assert G.PATH_NAMES[plan.tuning.path] == name
         out = G.glcm_compute(t, 32, 0, 255, D1, plan=plan)
         torch.cuda.synchronize()

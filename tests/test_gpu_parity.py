@@ -238,10 +238,10 @@ def test_strip_u16_pitch_of_8_pixels(W):
     for the strip kernel, with the last chunk ending inside the last row."""
     img = synth.smooth(37, W, 2.5, 60 + W, np.uint16)
     offs = synth.offsets_for([1, 2])
-    plan = G.glcm_plan_create(np.uint16, 64, offs, W, 37)
+    plan = G.glcm_plan_create(np.uint16, 16, offs, W, 37)
     try:
         assert G.PATH_NAMES[plan.tuning.path] == "strips"
-        check(img, 64, 0, 65535, offs, plan=plan, label=f"u16 pitch W={W}")
+        check(img, 16, 0, 65535, offs, plan=plan, label=f"u16 pitch W={W}")
     finally:
         plan.close()
 
@@ -421,7 +421,7 @@ def test_host_tiles_upward_offsets(offs, flags, path, dtype, tile_rows):
     W, H = 203, 77
     img = synth.smooth(H, W, 2.0, 33, dtype) if dtype == np.uint8 else synth.smooth(H, W, 2.0, 33, dtype,
                                                                                     noise_frac=0.05)
-    N, hi = (16, 255) if dtype == np.uint8 else (64, 65535)
+    N, hi = (16, 255) if dtype == np.uint8 else (32, 65535)
     plan = G.glcm_plan_create(dtype, N, offs, W, H, flags)
     try:
         assert G.PATH_NAMES[plan.tuning.path] == path, plan.tuning.as_dict()
@@ -500,6 +500,51 @@ def test_autotune_keeps_results(flags):
         check(img, 32, 0, 255, offs, plan=plan, label=f"after autotune {t.as_dict()}")
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("dtype,N,dists,path", [
+    (np.uint8, 32, [1, 2], "strips"),     # 16 dwords per bin
+    (np.uint8, 64, [1], "strips"),        # 8 dwords per bin, reach 1
+    (np.uint8, 64, [2], "slabs"),         # 8 dwords per bin, reach 2
+    (np.uint16, 64, [1, 2], "slabs"),     # 4 dwords per bin
+    (np.uint16, 64, [1, 2, 4], "slabs"),  # beyond the strip kernel's reach
+])
+def test_strip_or_slab_default(dtype, N, dists, path):
+    """The strip kernel is the default only with 16 or more dwords per bin, or
+    8 at a reach of 1; otherwise the slab kernel (measured faster or equal).
+    Both give the oracle's counts."""
+    W, H = 1037, 93
+    img = synth.smooth(H, W, 3.0, 90 + N, dtype) if dtype == np.uint8 else synth.smooth(H, W, 3.0, 90 + N, dtype,
+                                                                                           noise_frac=0.05)
+    hi = 255 if dtype == np.uint8 else 65535
+    offs = synth.offsets_for(dists)
+    plan = G.glcm_plan_create(dtype, N, offs, W, H)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == path, plan.tuning.as_dict()
+        check(img, N, 0, hi, offs, plan=plan, label=f"default {path} N={N} d={dists}")
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("kind", ["smooth", "uniform"])
+def test_autotune_across_row_kernels(kind):
+    """A plan whose offsets both row kernels reach: the autotuner times strip
+    and slab layouts together and keeps one; the counts stay exact, and a
+    plan created with FLAG_FORCE_SLABS stays on the slab kernel."""
+    W, H = 2048, 512
+    img = synth.smooth(H, W, 6.0, 95, np.uint16) if kind == "smooth" else synth.uniform(H, W, 96, np.uint16)
+    offs = synth.offsets_for([2])
+    t = torch.from_numpy(img.view(np.int16)).view(torch.uint16).cuda()
+    for flags in (0, G.FLAG_FORCE_SLABS):
+        plan = G.glcm_plan_create(np.uint16, 64, offs, W, H, flags)
+        try:
+            chosen = plan.autotune(t, 0, 65535, repeats=2)
+            name = G.PATH_NAMES[chosen.path]
+            print(f"[autotune] {kind} flags={flags}: {chosen.as_dict()}", flush=True)
+            assert name in (("strips", "slabs") if flags == 0 else ("slabs",))
+            check(img, 64, 0, 65535, offs, plan=plan, label=f"autotuned {name} {kind}")
+        finally:
+            plan.close()
 
 
 def test_kernel_timing_flag():
