@@ -987,6 +987,7 @@ def bench_serving(args, G, torch, np, oracle, synth, dev):
     srv.close()
     for p in plans.values():
         p.close()
+    tile_stream = serve_tile_stream(args, G, torch, np, synth, dev)
     line = {"workload": f"serving-{len(reqs)}-requests-u8-256to{args.size}-N8to256-K1to12",
             "requests": len(reqs), "pairs": total_pairs, "lanes": args.lanes, "hbm_budget_gib": args.budget_gib,
             "one_at_a_time_gpairs_s": total_pairs / t_sync / 1e9, "one_stream_gpairs_s": total_pairs / t_stream / 1e9,
@@ -995,9 +996,76 @@ def bench_serving(args, G, torch, np, oracle, synth, dev):
             "open_loop": open_loop, "max_inflight": st.max_inflight, "alone_by_N": per_n,
             "served_bound": served_bound(reqs, alone, t_sync, t_closed),
             "max_budgeted_gib": st.max_bytes_in_use / 2 ** 30,
+            "fused_launches": st.fused_launches, "fused_requests": st.fused_requests,
+            "tile_stream": tile_stream,
             "check": "every served result == the same request alone (counts and statistics, bit for bit); "
                      "16 smallest requests == oracle"}
     print(json.dumps(line), flush=True)
+
+
+def serve_tile_stream(args, G, torch, np, synth, dev):
+    """The batch workload's tiles (sides log-uniform in [32, 512], N = 16, the
+    four d = 1 offsets, statistics) as one request each: the request server,
+    which fuses queued requests of one job into batch launches, against one
+    request at a time (counts, then statistics, then a wait) and against all
+    of them queued on one stream.  Every served result must equal the request
+    alone, bit for bit."""
+    w = synth.batch_tiles(args.tiles)
+    N, offs = w["N"], w["offsets"]
+    imgs = [torch.from_numpy(im).to(dev) for im in w["images"]]
+    K = len(offs)
+    outs = [torch.empty((K, N, N), dtype=torch.uint32, device=dev) for _ in imgs]
+    feats = [torch.empty((K, 5), dtype=torch.float32, device=dev) for _ in imgs]
+    stream = torch.cuda.current_stream()
+    plan = G.glcm_plan_create(np.uint8, N, offs, 512, 512)
+
+    def one_by_one(sync):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for im, o, f in zip(imgs, outs, feats):
+            G.glcm_compute(im, N, 0, 255, offs, out=o, plan=plan, stream=stream)
+            G.glcm_features(o, out=f, stream=stream)
+            if sync:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    one_by_one(False)  # warm-up
+    t_sync, t_stream = one_by_one(True), one_by_one(False)
+    plan.close()
+    srv = G.Server(lanes=args.lanes, hbm_budget=8 << 30, result_pool_bytes=1 << 30)
+
+    def served():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = [srv.submit(im, N, 0, 255, offs, features=True) for im in imgs]
+        srv.drain()
+        wall = time.perf_counter() - t0
+        infos = [srv.query(t) for t in tickets]
+        for i, (t, info) in enumerate(zip(tickets, infos)):
+            if info.status != 0:
+                raise SystemExit(f"bench: tile request {i} failed with status {info.status}")
+            P, F = srv.fetch(t)
+            if not (torch.equal(P.view(torch.int32), outs[i].view(torch.int32)) and torch.equal(F, feats[i])):
+                raise SystemExit(f"bench: served tile {i} differs from the request alone")
+            srv.release(t)
+        return wall, infos
+
+    served()  # warm-up: the lanes' plans
+    before = srv.stats()
+    t_served, infos = served()
+    st = srv.stats()
+    srv.close()
+    launches = st.fused_launches - before.fused_launches
+    fused = st.fused_requests - before.fused_requests
+    res = {"workload": f"{len(imgs)}-tile-requests-u8-32to512-N16-K4-features", "requests": len(imgs),
+           "one_at_a_time_ms": t_sync * 1e3, "one_stream_ms": t_stream * 1e3, "served_ms": t_served * 1e3,
+           "served_over_one_at_a_time": t_sync / t_served, "served_over_one_stream": t_stream / t_served,
+           "fused_launches": launches, "fused_requests": fused,
+           "mean_requests_per_fused_launch": fused / launches if launches else 0.0,
+           "largest_fused_launch": max(i.fused for i in infos)}
+    print(f"[serving] tile stream: {json.dumps(res)}", file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":

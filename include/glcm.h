@@ -496,6 +496,14 @@ GLCM_API int glcm_batch_autotune(glcm_plan_t plan, const glcm_tile_t *tiles, int
  * (a host function queued behind it).  Images stay the caller's; counts and
  * statistics go to caller buffers or to the server's device result pool,
  * where they stay until fetched or released.
+ * Continuous batching: a small request (at most 2^20 pixels, at most four
+ * offsets with |dx|, |dy| <= 2, N <= 255) takes along the queued requests of
+ * the same job (dtype, N, lo, hi, offsets in the same order, statistics or
+ * not) that are small too, up to 1024, in arrival order while their results
+ * fit: the group is one launch of the fused batch kernel (glcm_batch_compute)
+ * on its lane, each image's results written to its own request's buffers,
+ * and its requests complete together.  The results equal those of each
+ * request computed alone.
  * ------------------------------------------------------------------------ */
 typedef struct glcm_server_s *glcm_server_t;
 
@@ -517,7 +525,7 @@ typedef struct glcm_request_info {
     int32_t done;                   /* 1 once the request's work has completed (or failed) */
     int32_t status;                 /* GLCM_OK, or the error the request ended with */
     int32_t lane;                   /* lane it ran on, -1 while queued */
-    int32_t reserved;
+    int32_t fused;                  /* requests in the launch that carried it (1: alone) */
     double submit_us, admit_us, done_us;  /* host steady clock, us since server creation */
     const uint32_t *out;            /* device counts [K][N][N] (valid once done) */
     const float *feat;              /* device statistics [K][5], or NULL */
@@ -529,6 +537,8 @@ typedef struct glcm_server_stats {
     uint64_t budget_bytes;          /* the HBM budget */
     uint64_t bytes_in_use;          /* budgeted bytes held now (plans + results) */
     uint64_t max_bytes_in_use;      /* most budgeted bytes held at once */
+    uint64_t fused_launches;        /* launches that carried two or more requests */
+    uint64_t fused_requests;        /* requests those launches carried */
 } glcm_server_stats_t;
 
 /*

@@ -91,14 +91,15 @@ class Request(ctypes.Structure):
 
 class RequestInfo(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("lane", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("fused", ctypes.c_int32), ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
                 ("done_us", ctypes.c_double), ("out", ctypes.c_void_p), ("feat", ctypes.c_void_p)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
                 ("lanes", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64),
-                ("bytes_in_use", ctypes.c_uint64), ("max_bytes_in_use", ctypes.c_uint64)]
+                ("bytes_in_use", ctypes.c_uint64), ("max_bytes_in_use", ctypes.c_uint64),
+                ("fused_launches", ctypes.c_uint64), ("fused_requests", ctypes.c_uint64)]
 
 
 class Tuning(ctypes.Structure):

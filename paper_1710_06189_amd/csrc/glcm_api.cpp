@@ -1684,13 +1684,17 @@ constexpr size_t kBatchDescOff = 256;
 struct BatchItems {
   std::vector<glcm::BatchTile> items;
   std::vector<glcm::BatchFin> fins;
-  int slots = 0;  // band rows of partial counts
+  int slots = 0;   // band rows of partial counts
+  int tables = 0;  // entries of the per-image destination tables (0: one contiguous output)
   // device layout: the item counter (at offset 0 whatever the batch, so a
   // buffer reused for another batch keeps it zero), the items from offset
-  // kBatchDescOff, the fins, then the partial rows (256-byte aligned)
+  // kBatchDescOff, the fins, the destination tables (counts, then
+  // statistics), then the partial rows (256-byte aligned)
   size_t fins_off() const { return kBatchDescOff + items.size() * sizeof(glcm::BatchTile); }
-  size_t partials_off() const { return (fins_off() + fins.size() * sizeof(glcm::BatchFin) + 255u) & ~(size_t)255u; }
-  size_t desc_bytes() const { return fins_off() + fins.size() * sizeof(glcm::BatchFin) - kBatchDescOff; }
+  size_t tables_off() const { return (fins_off() + fins.size() * sizeof(glcm::BatchFin) + 7u) & ~(size_t)7u; }
+  size_t tables_end() const { return tables_off() + 2u * (size_t)tables * sizeof(void*); }
+  size_t partials_off() const { return (tables_end() + 255u) & ~(size_t)255u; }
+  size_t desc_bytes() const { return tables_end() - kBatchDescOff; }
   size_t dev_bytes(int K, int N) const { return partials_off() + (size_t)slots * K * N * N * 4u; }
 };
 
@@ -1698,6 +1702,7 @@ void batch_items(const glcm_tile_t* tiles, int T, int b, BatchItems* it) {
   it->items.clear();
   it->fins.clear();
   it->slots = 0;
+  it->tables = 0;
   for (int t = 0; t < T; ++t) {
     const glcm_tile_t& e = tiles[t];
     glcm::BatchTile d{};
@@ -1747,7 +1752,7 @@ void batch_descriptors(const BatchItems& it, void* host) {
 // The item counter (the buffer's first word) must be zero.
 int batch_launch(const BatchLayout& L, int nitems, int nfins, size_t fins_off, size_t partials_off,
                  const void* desc_dev, uint32_t N, uint32_t lo, uint32_t hi, uint32_t* out, float* features,
-                 hipStream_t stream) {
+                 hipStream_t stream, uint32_t* const* outs = nullptr, float* const* feats = nullptr) {
   glcm::BatchArgs a = L.args;
   a.q = make_quant((int)N, lo, hi);
   fast_quant(L.b, (int)N, lo, hi, &a.qfast, &a.qfast_shift, &a.qfast_mask);
@@ -1759,27 +1764,34 @@ int batch_launch(const BatchLayout& L, int nitems, int nfins, size_t fins_off, s
   a.nfins = nfins;
   a.out = out;
   a.feat = features;
+  a.outs = outs;
+  a.feats = feats;
   GLCM_TRY(glcm::launch_batch(a, std::min(nitems, L.groups), L.b, L.smd, L.D, L.wg, L.lds_bytes, stream));
   GLCM_TRY(glcm::launch_batch_fin(a, nfins, stream));
   return GLCM_OK;
 }
 
-}  // namespace
-
-GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
-                                uint32_t* out, float* features, void* stream_) {
-  if (!plan || !tiles || !out || T < 1 || T > (1 << 20)) return GLCM_EINVAL;  // before touching the plan
+// glcm_batch_compute's work, into one contiguous output (out, features) or,
+// with outs set, image t's counts into outs[t] and its statistics into
+// feats[t] (feats or feats[t] null: none).
+int batch_compute_common(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
+                         uint32_t* out, float* features, uint32_t* const* outs, float* const* feats,
+                         hipStream_t stream) {
+  if (!plan || !tiles || (!out && !outs) || T < 1 || T > (1 << 20)) return GLCM_EINVAL;  // before touching the plan
   if (lo > hi || hi > (plan->dtype == GLCM_U8 ? 255u : 65535u)) return GLCM_EINVAL;
-  hipStream_t stream = (hipStream_t)stream_;
+  if (outs)
+    for (int t = 0; t < T; ++t)
+      if (!outs[t]) return GLCM_EINVAL;
   std::lock_guard<std::mutex> lk(plan->mu);
   BatchLayout L;
   int rc = batch_layout(plan, tiles, T, &L);
   if (rc != GLCM_OK) return rc;
   GLCM_TRY_RC(check_tile_memory(tiles, T, L.b));
-  GLCM_TRY_RC(check_batch_outputs(tile_extents(tiles, T, L.b), T, plan->K, plan->N, out, features));
+  if (!outs) GLCM_TRY_RC(check_batch_outputs(tile_extents(tiles, T, L.b), T, plan->K, plan->N, out, features));
   GLCM_TRY_RC(order_after_previous(plan, stream));
   BatchItems it;
   batch_items(tiles, T, L.b, &it);
+  if (outs) it.tables = T;
   const size_t need = it.dev_bytes(plan->K, plan->N);
   if (plan->batch_pending) GLCM_TRY(hipEventSynchronize(plan->batch_uploaded));
   plan->batch_pending = false;
@@ -1799,13 +1811,43 @@ GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int 
   }
   if (!plan->batch_uploaded) GLCM_TRY(hipEventCreateWithFlags(&plan->batch_uploaded, hipEventDisableTiming));
   batch_descriptors(it, plan->batch_pin);
+  uint32_t* const* outs_dev = nullptr;
+  float* const* feats_dev = nullptr;
+  if (outs) {
+    char* tab = (char*)plan->batch_pin + (it.tables_off() - kBatchDescOff);
+    std::memcpy(tab, outs, (size_t)T * sizeof(void*));
+    if (feats) std::memcpy(tab + (size_t)T * sizeof(void*), feats, (size_t)T * sizeof(void*));
+    else std::memset(tab + (size_t)T * sizeof(void*), 0, (size_t)T * sizeof(void*));
+    outs_dev = (uint32_t* const*)((char*)plan->batch_dev + it.tables_off());
+    if (feats) feats_dev = (float* const*)((char*)plan->batch_dev + it.tables_off() + (size_t)T * sizeof(void*));
+  }
   GLCM_TRY(hipMemcpyAsync((char*)plan->batch_dev + kBatchDescOff, plan->batch_pin, it.desc_bytes(),
                            hipMemcpyHostToDevice, stream));
   GLCM_TRY(hipEventRecord(plan->batch_uploaded, stream));
   plan->batch_pending = true;
   GLCM_TRY_RC(batch_launch(L, (int)it.items.size(), (int)it.fins.size(), it.fins_off(), it.partials_off(),
-                           plan->batch_dev, (uint32_t)plan->N, lo, hi, out, features, stream));
+                           plan->batch_dev, (uint32_t)plan->N, lo, hi, out, features, stream, outs_dev, feats_dev));
   return record_done(plan, stream);
+}
+
+}  // namespace
+
+extern "C++" {
+namespace glcm {
+
+int batch_compute_to(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
+                     uint32_t* const* outs, float* const* feats, hipStream_t stream) {
+  if (!outs) return GLCM_EINVAL;
+  return batch_compute_common(plan, tiles, T, lo, hi, nullptr, nullptr, outs, feats, stream);
+}
+
+}  // namespace glcm
+}  // extern "C++"
+
+GLCM_API int glcm_batch_compute(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
+                                uint32_t* out, float* features, void* stream_) {
+  if (!out) return GLCM_EINVAL;
+  return batch_compute_common(plan, tiles, T, lo, hi, out, features, nullptr, nullptr, (hipStream_t)stream_);
 }
 
 struct glcm_batch_s {

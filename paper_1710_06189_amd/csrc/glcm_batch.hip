@@ -178,7 +178,8 @@ __device__ __forceinline__ void batch_item(const BatchArgs& a, const BatchTile& 
   uint32_t* merged = lds + vote_words;
   // a whole image: its counts; a band: its partial counts, summed (and the
   // statistics taken) by k_batch_fin
-  uint32_t* dst = band ? a.partials + (size_t)t.slot * K * NN : a.out + (size_t)t.index * K * NN;
+  uint32_t* dst = band ? a.partials + (size_t)t.slot * K * NN
+                       : (a.outs ? a.outs[t.index] : a.out + (size_t)t.index * K * NN);
   // unit u = ((i * n1 + j) * K + k) * QPB + r: (i, j, k) step by the
   // mixed-radix digits of blockDim / QPB each pass, so nothing is divided
   const uint32_t S = blockDim.x / QPB, uK = (uint32_t)K;
@@ -206,10 +207,13 @@ __device__ __forceinline__ void batch_item(const BatchArgs& a, const BatchTile& 
     mj -= cj ? n1 : 0u;
     mi += si + cj;
   }
-  if (!a.feat || band) return;
+  if (band) return;
+  float* const fdst = a.outs ? (a.feats ? a.feats[t.index] : nullptr)
+                             : (a.feat ? a.feat + (size_t)t.index * K * 5 : nullptr);
+  if (!fdst) return;  // (the same on every thread of the workgroup)
   __syncthreads();
   // one wavefront per GLCM (K <= 4 = the workgroup's wavefronts)
-  if (wave < K) glcm_features_wave(merged + wave * NN, N, a.feat + ((size_t)t.index * K + wave) * 5);
+  if (wave < K) glcm_features_wave(merged + wave * NN, N, fdst + wave * 5);
 }
 
 // Persistent workgroups: each takes the next item from a counter (items are
@@ -248,7 +252,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_fin(BatchArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const BatchFin f = a.fins[blockIdx.x];
   const uint32_t N = a.q.nlev, NN = N * N, KNN = (uint32_t)a.K * NN;
-  uint32_t* dst = a.out + (size_t)f.index * KNN;
+  uint32_t* dst = a.outs ? a.outs[f.index] : a.out + (size_t)f.index * KNN;
   const uint32_t* src = a.partials + (size_t)f.slot0 * KNN;
   for (uint32_t w = threadIdx.x; w < KNN; w += blockDim.x) {
     uint32_t s = 0;
@@ -256,10 +260,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_fin(BatchArgs a) {
     dst[w] = s;
     lds[w] = s;
   }
-  if (!a.feat) return;
+  float* const fdst = a.outs ? (a.feats ? a.feats[f.index] : nullptr)
+                             : (a.feat ? a.feat + (size_t)f.index * a.K * 5 : nullptr);
+  if (!fdst) return;
   __syncthreads();
   const int wave = (int)(threadIdx.x >> 6);
-  if (wave < a.K) glcm_features_wave(lds + wave * NN, N, a.feat + ((size_t)f.index * a.K + wave) * 5);
+  if (wave < a.K) glcm_features_wave(lds + wave * NN, N, fdst + wave * 5);
 }
 
 }  // namespace

@@ -32,4 +32,11 @@ int compute_in_workspace(uint32_t* slices, size_t slice_words, const void* img, 
                          int dtype, int N, uint32_t lo, uint32_t hi, const glcm_offset_t* offsets, int K,
                          uint32_t* out, hipStream_t stream);
 
+// glcm_batch_compute with a destination per image: image t's counts go to
+// outs[t] (device, K*N*N words) and its statistics to feats[t] (K*5 floats;
+// feats or feats[t] NULL: none).  Same checks and errors otherwise, except
+// that the destinations are not checked against the tiles.
+int batch_compute_to(glcm_plan_t plan, const glcm_tile_t* tiles, int T, uint32_t lo, uint32_t hi,
+                     uint32_t* const* outs, float* const* feats, hipStream_t stream);
+
 }  // namespace glcm

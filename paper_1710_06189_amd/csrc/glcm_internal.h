@@ -135,6 +135,10 @@ struct BatchArgs {
   int nitems, nfins;
   uint32_t* out;                       // [T][K][N][N]
   float* feat;                         // [T][K][5] or null
+  // or, when outs is set, image t's counts go to outs[t] ([K][N][N]) and its
+  // statistics to feats[t] ([K][5]; feats or feats[t] null: none); device tables
+  uint32_t* const* outs;
+  float* const* feats;
 };
 
 // Optional events the counting kernel's dispatch stamps with its own start

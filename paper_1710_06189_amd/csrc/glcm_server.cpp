@@ -12,12 +12,21 @@
 // scheduler for the next request.  Requests on different lanes overlap on the
 // GPU; results stay in device memory until fetched or released.
 //
+// Continuous batching: when the admitted request is small (at most
+// kFusePixels pixels, at most four offsets of reach <= 2), queued requests of
+// the same job (dtype, N, range, offsets, statistics or not) that are small
+// too join it, in arrival order, as far as their results fit: the group runs
+// as one persistent batch launch (the fused batch kernel of glcm_batch_compute,
+// each image's counts and statistics written straight to its request's
+// buffers) and completes together.
+//
 // Locking: one mutex guards the server state.  No HIP call is made while it
 // is held (hipMalloc / hipFree may wait for queued work, whose completion
 // callbacks take the mutex).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -41,6 +50,12 @@ constexpr uint64_t kAlign = 256;
 constexpr int kPlanMinK = 12;
 constexpr int kPlanMaxSide = 65535;
 constexpr uint64_t kXbufCap = 256ull << 20;  // plans keep per-XCD accumulators up to this size
+// continuous batching: requests of at most kFusePixels pixels, groups of at
+// most kFuseMax requests, companions looked for among the first kFuseScan
+// queued requests
+constexpr uint64_t kFusePixels = 1ull << 20;
+constexpr int kFuseMax = 1024;
+constexpr int kFuseScan = 4096;
 
 using Clock = std::chrono::steady_clock;
 
@@ -111,8 +126,26 @@ struct Request {
   int lane = -1;
   bool done = false;
   int status = GLCM_OK;
+  int fused = 1;                  // requests in the launch that carried it
+  std::vector<Request*> group;    // the head of a fused launch: its other requests
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
+
+// A request the batch kernel can take in a fused launch: a small image, at
+// most four offsets, each with |dx|, |dy| <= 2, levels in one byte.
+bool fusable(const Request* q) {
+  if ((uint64_t)q->r.W * (uint64_t)q->r.H > kFusePixels || q->r.K > 4 || q->r.N > 255) return false;
+  for (int k = 0; k < q->r.K; ++k)
+    if (std::abs(q->offs[k].dx) > 2 || std::abs(q->offs[k].dy) > 2) return false;
+  return true;
+}
+
+// Same job: one plan binding and one quantizer serve both.
+bool same_job(const Request* a, const Request* b) {
+  return a->r.dtype == b->r.dtype && a->r.N == b->r.N && a->r.lo == b->r.lo && a->r.hi == b->r.hi &&
+         a->r.K == b->r.K && (a->r.features != 0) == (b->r.features != 0) &&
+         std::memcmp(a->offs, b->offs, sizeof(glcm_offset_t) * (size_t)a->r.K) == 0;
+}
 
 // Workspace a new plan for (N, kcap) reserves at creation: the per-XCD
 // accumulators (16 slices of kcap * N * N words) when they fit the cap.
@@ -143,6 +176,7 @@ struct glcm_server_s {
   std::deque<Request*> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   uint64_t next_id = 1, submitted = 0, completed = 0, failed = 0, admissions = 0;
+  uint64_t fused_launches = 0, fused_requests = 0;
   int inflight = 0, max_inflight = 0;
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -171,12 +205,63 @@ void finish_locked(glcm_server_s* s, Request* q, int status) {
   s->cv_done.notify_all();
 }
 
+// Finishes a launch's head request and the requests fused with it (lock held).
+void finish_group_locked(glcm_server_s* s, Request* q, int status) {
+  for (Request* m : q->group) finish_locked(s, m, status);
+  q->group.clear();
+  finish_locked(s, q, status);
+}
+
 // Runs on the HIP runtime's callback thread once the request's work is done.
 void on_done(void* arg) {
   Request* q = static_cast<Request*>(arg);
   glcm_server_s* s = q->srv;
   std::lock_guard<std::mutex> lk(s->mu);
-  finish_locked(s, q, GLCM_OK);
+  finish_group_locked(s, q, GLCM_OK);
+}
+
+// Points a request's missing result buffers into the pool block at `off`.
+void place_results(glcm_server_s* s, Request* q, uint64_t off) {
+  q->res_off = off;
+  if (!q->r.out) q->out = reinterpret_cast<uint32_t*>(s->pool_base + off);
+  if (q->r.features && !q->r.feat)
+    q->feat = reinterpret_cast<float*>(s->pool_base + off + (q->r.out ? 0 : round_up(q->out_bytes)));
+}
+
+// Admits queued requests of the head's job into its launch (lock held): small
+// ones, in arrival order, while their results fit the budget and the pool.
+void gather_locked(glcm_server_s* s, Request* head) {
+  if (!fusable(head)) return;
+  const size_t scan = std::min(s->queue.size(), (size_t)kFuseScan);
+  std::vector<char> taken(scan, 0);
+  size_t ntaken = 0;
+  for (size_t i = 0; i < scan && head->group.size() + 1 < (size_t)kFuseMax; ++i) {
+    Request* r = s->queue[i];
+    if (!same_job(head, r) || !fusable(r)) continue;
+    if (s->held + r->res_bytes > s->budget) break;
+    uint64_t off = 0;
+    if (r->res_bytes && !s->pool.alloc(r->res_bytes, &off)) break;
+    s->held += r->res_bytes;
+    place_results(s, r, off);
+    r->lane = head->lane;
+    r->t_admit = head->t_admit;
+    s->inflight++;
+    head->group.push_back(r);
+    taken[i] = 1;
+    ++ntaken;
+  }
+  if (!ntaken) return;
+  note_held(s);
+  s->max_inflight = std::max(s->max_inflight, s->inflight);
+  std::deque<Request*> rest;
+  for (size_t i = 0; i < s->queue.size(); ++i)
+    if (i >= scan || !taken[i]) rest.push_back(s->queue[i]);
+  s->queue.swap(rest);
+  const int n = (int)head->group.size() + 1;
+  head->fused = n;
+  for (Request* r : head->group) r->fused = n;
+  s->fused_launches++;
+  s->fused_requests += (uint64_t)n;
 }
 
 // Tries to admit the head of the queue (lock held).  Fills *a and returns
@@ -247,16 +332,14 @@ bool pick(glcm_server_s* s, Admission* a) {
   }
   s->held = s->held - freed + plan_bytes + q->res_bytes;
   note_held(s);
-  q->res_off = off;
-  if (!q->r.out) q->out = reinterpret_cast<uint32_t*>(s->pool_base + off);
-  if (q->r.features && !q->r.feat)
-    q->feat = reinterpret_cast<float*>(s->pool_base + off + (q->r.out ? 0 : round_up(q->out_bytes)));
+  place_results(s, q, off);
   q->lane = lane;
   q->t_admit = s->now_us();
   L.cur = q;
   s->inflight++;
   s->max_inflight = std::max(s->max_inflight, s->inflight);
   s->admissions++;
+  gather_locked(s, q);
   if (!need_plan) L.plans[plan_idx].last_use = s->admissions;
   a->q = q;
   a->lane = lane;
@@ -302,9 +385,37 @@ int launch(glcm_server_s* s, Admission& a) {
   if (!plan) return GLCM_EINVAL;
   int rc = glcm_plan_rebind(plan, q->offs, q->r.K);
   if (rc != GLCM_OK) return rc;
-  rc = glcm_compute(plan, q->r.img, q->r.W, q->r.H, q->r.stride, q->r.dtype, q->r.N, q->r.lo, q->r.hi, q->offs,
-                    q->r.K, q->out, L.stream);
-  if (rc == GLCM_OK && q->r.features) rc = glcm_features(q->out, q->r.K, q->r.N, q->feat, L.stream);
+  // (the group is fixed once admitted: only this thread reads it until the
+  // launch completes)
+  if (!q->group.empty()) {
+    // one fused batch launch for the whole group
+    const size_t n = q->group.size() + 1;
+    std::vector<glcm_tile_t> tiles(n);
+    std::vector<uint32_t*> outs(n);
+    std::vector<float*> feats(n);
+    for (size_t i = 0; i < n; ++i) {
+      const Request* m = i == 0 ? q : q->group[i - 1];
+      tiles[i] = glcm_tile_t{m->r.img, m->r.stride, m->r.W, m->r.H};
+      outs[i] = m->out;
+      feats[i] = m->feat;
+    }
+    rc = glcm::batch_compute_to(plan, tiles.data(), (int)n, q->r.lo, q->r.hi, outs.data(),
+                                q->r.features ? feats.data() : nullptr, L.stream);
+    if (rc == GLCM_EUNSUPPORTED) {
+      // a layout the batch kernel does not take (its LDS): one call each
+      rc = GLCM_OK;
+      for (size_t i = 0; i < n && rc == GLCM_OK; ++i) {
+        const Request* m = i == 0 ? q : q->group[i - 1];
+        rc = glcm_compute(plan, m->r.img, m->r.W, m->r.H, m->r.stride, m->r.dtype, m->r.N, m->r.lo, m->r.hi,
+                          m->offs, m->r.K, m->out, L.stream);
+        if (rc == GLCM_OK && m->r.features) rc = glcm_features(m->out, m->r.K, m->r.N, m->feat, L.stream);
+      }
+    }
+  } else {
+    rc = glcm_compute(plan, q->r.img, q->r.W, q->r.H, q->r.stride, q->r.dtype, q->r.N, q->r.lo, q->r.hi, q->offs,
+                      q->r.K, q->out, L.stream);
+    if (rc == GLCM_OK && q->r.features) rc = glcm_features(q->out, q->r.K, q->r.N, q->feat, L.stream);
+  }
   {
     // band partials or tile buffers the call allocated count from now on
     size_t wb = 0;
@@ -337,7 +448,7 @@ void scheduler(glcm_server_s* s) {
     lk.unlock();
     const int rc = launch(s, a);
     lk.lock();
-    if (rc != GLCM_OK) finish_locked(s, a.q, rc);
+    if (rc != GLCM_OK) finish_group_locked(s, a.q, rc);
   }
 }
 
@@ -351,6 +462,7 @@ void fill_info(const Request* q, glcm_request_info_t* info) {
   info->done = q->done ? 1 : 0;
   info->status = q->status;
   info->lane = q->lane;
+  info->fused = q->fused;
   info->submit_us = q->t_submit;
   info->admit_us = q->t_admit;
   info->done_us = q->t_done;
@@ -517,6 +629,8 @@ GLCM_API int glcm_server_stats(glcm_server_t s, glcm_server_stats_t* st) {
   st->budget_bytes = s->budget;
   st->bytes_in_use = s->held;
   st->max_bytes_in_use = s->max_held;
+  st->fused_launches = s->fused_launches;
+  st->fused_requests = s->fused_requests;
   return GLCM_OK;
 }
 

@@ -1,8 +1,10 @@
 """GPU tests of the request server (glcm_server_*, through the C ABI) and of
 plan re-targeting: every result of a mixed, concurrently served set of
 requests equals the same request computed alone (counts and statistics bit
-for bit), small ones also match the oracle; admission honours the HBM budget
-and the result pool; bad requests are rejected before anything is queued."""
+for bit), small ones also match the oracle; small requests of one job fused
+into one batch launch equal the same requests alone; admission honours the
+HBM budget and the result pool; bad requests are rejected before anything is
+queued."""
 
 import time
 
@@ -101,6 +103,66 @@ def test_small_requests_match_oracle(pool_images):
             assert np.all(fg[~nz] == 0)
             assert np.all(np.abs(fg[nz] - fw[nz]) / np.abs(fw[nz]) <= 1e-5)
             srv.release(t)
+    finally:
+        srv.close()
+
+
+D1 = [(1, 0), (-1, 1), (0, 1), (1, 1)]
+
+
+def test_fused_small_requests_equal_alone(pool_images):
+    """Continuous batching: while the only lane is busy, small requests queue
+    up; those of one job (dtype, N, range, offsets, statistics or not) run as
+    one fused batch launch.  Each result equals the request computed alone,
+    counts and statistics bit for bit, with server-owned or caller buffers and
+    misaligned image views; requests above 2^20 pixels run alone."""
+    smooth, noise = pool_images
+    rng = np.random.default_rng(17)
+    srv = G.Server(lanes=1, hbm_budget=8 << 30, result_pool_bytes=256 << 20)
+    try:
+        # a long first request holds the lane while the others are submitted
+        big = srv.submit(noise, 256, 0, 255, ALL12)
+        reqs = []
+        for i in range(64):
+            src = (smooth, noise)[i % 2]
+            h, w = (1100, 1000) if i % 16 == 15 else tuple(int(v) for v in rng.integers(1, 600, size=2))
+            y0 = int(rng.integers(0, src.shape[0] - h + 1))
+            x0 = int(rng.integers(0, src.shape[1] - w + 1))
+            N = 8 if i % 7 == 3 else 16
+            offs = D1 if i % 11 != 5 else [(2, 0), (-2, 2)]
+            feats = i % 3 != 0
+            caller = i % 5 == 0
+            out = torch.empty((len(offs), N, N), dtype=torch.uint32, device="cuda") if caller else None
+            feat = torch.empty((len(offs), 5), dtype=torch.float32, device="cuda") if caller and feats else None
+            img = src[y0:y0 + h, x0:x0 + w]
+            t = srv.submit(img, N, 0, 255, offs, features=feats, out=out, feat=feat)
+            reqs.append(dict(t=t, img=img, N=N, offsets=offs, features=feats, out=out, feat=feat, hw=(h, w)))
+        print(f"[server] submitted {len(reqs)} small requests behind one large one", flush=True)
+        srv.drain()
+        st = srv.stats()
+        print(f"[server] fused launches {st.fused_launches}, requests in them {st.fused_requests}", flush=True)
+        assert st.completed == len(reqs) + 1 and st.failed == 0
+        assert st.fused_launches >= 1 and st.fused_requests >= 2 * st.fused_launches
+        assert srv.wait(big).status == 0
+        fused_seen = 0
+        for r in reqs:
+            info = srv.query(r["t"])
+            assert info.done == 1 and info.status == 0 and info.fused >= 1
+            if r["hw"][0] * r["hw"][1] > (1 << 20):
+                assert info.fused == 1, "a large request was fused"
+            fused_seen += info.fused > 1
+            p_alone, f_alone = alone(r)
+            if r["out"] is not None:
+                assert info.out == r["out"].data_ptr()
+                P, F = r["out"], r["feat"]
+            else:
+                P, F = srv.fetch(r["t"])
+            assert np.array_equal(host(P), p_alone), f"counts differ from the request alone: {r['hw']} fused={info.fused}"
+            if r["features"]:
+                assert np.array_equal(host(F), f_alone), f"statistics differ from the request alone: fused={info.fused}"
+            srv.release(r["t"])
+        assert srv.query(big).fused == 1 and fused_seen == st.fused_requests
+        srv.release(big)
     finally:
         srv.close()
 
