@@ -212,8 +212,9 @@ __device__ __forceinline__ void batch_item(const BatchArgs& a, const BatchTile& 
                              : (a.feat ? a.feat + (size_t)t.index * K * 5 : nullptr);
   if (!fdst) return;  // (the same on every thread of the workgroup)
   __syncthreads();
-  // one wavefront per GLCM (K <= 4 = the workgroup's wavefronts)
-  if (wave < K) glcm_features_wave(merged + wave * NN, N, fdst + wave * 5);
+  // one wavefront per GLCM (a wavefront takes several when the workgroup has
+  // fewer wavefronts than K)
+  for (int k = wave; k < K; k += (int)(blockDim.x >> 6)) glcm_features_wave(merged + k * NN, N, fdst + k * 5);
 }
 
 // Persistent workgroups: each takes the next item from a counter (items are
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_fin(BatchArgs a) {
   if (!fdst) return;
   __syncthreads();
   const int wave = (int)(threadIdx.x >> 6);
-  if (wave < a.K) glcm_features_wave(lds + wave * NN, N, fdst + wave * 5);
+  for (int k = wave; k < a.K; k += (int)(blockDim.x >> 6)) glcm_features_wave(lds + k * NN, N, fdst + k * 5);
 }
 
 }  // namespace
