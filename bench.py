@@ -877,7 +877,7 @@ def bench_serving(args, G, torch, np, oracle, synth, dev):
             aligned = v.data_ptr() % 16 == 0 and v.stride(0) % 16 == 0
             path = G.PATH_NAMES.get(p.tuning.path, "?")
             if not aligned and path in ("strips", "slabs"):
-                path = (f"{path} (staged copy)" if v.shape[0] * v.shape[1] >= 1 << 16
+                path = (f"{path} (read in place)" if v.shape[0] * v.shape[1] >= 1 << 16
                         else "generic (misaligned)")
             evs.append((r["N"], path, e0, e1))
         torch.cuda.synchronize()

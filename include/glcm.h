@@ -188,7 +188,9 @@ GLCM_API int glcm_plan_autotune(glcm_plan_t plan, const void *img, int W, int H,
  * 16 MiB that each GPU the library runs on holds until the process ends
  * (found once per device with hipGetSymbolAddress on its first call there).
  * A misaligned image (base or row pitch not a multiple of 16 bytes) is read
- * by the per-pixel kernels instead of being copied.  Calls are queued on
+ * in place, never copied (from 2^16 pixels on, the strip and slab kernels
+ * assemble its rows from the dwords that hold them; smaller images and a
+ * block-code layout take the per-pixel kernels).  Calls are queued on
  * `stream` like glcm_compute; every call on one GPU shares that array, so
  * calls that overlap on one GPU (several streams, or host threads) race and
  * must be ordered by the caller.  The array is cleared at the start of each
@@ -254,7 +256,11 @@ GLCM_API int glcm_plan_cache_clear(void);
  *            pinned host memory or pageable host memory.  Host images are
  *            uploaded in row tiles (with the halo rows the offsets need) on the
  *            plan's upload stream while earlier tiles are counted on `stream`.
- *            Must be aligned to the pixel size.
+ *            Must be aligned to the pixel size; a device image of at least
+ *            2^16 pixels whose base or pitch is not 16-byte aligned is read
+ *            in place by the strip and slab kernels (the block-code kernel
+ *            copies it to an aligned plan buffer first); smaller ones take
+ *            the per-pixel kernels.
  *   stride   row pitch in ELEMENTS, >= W.
  *   dtype    GLCM_U8 or GLCM_U16.
  *   N, lo, hi  quantization (see above); lo <= hi <= max of dtype.

@@ -35,49 +35,6 @@ __device__ __forceinline__ void batch_vote(const uint32_t (&fa)[16], const TermR
   }
 }
 
-// Row loads of an image whose base or row pitch is not 16-byte aligned: the
-// lane's 16-pixel chunk and its 4-pixel halos are assembled from the aligned
-// dwords that span them (v_alignbyte_b32).  Only dwords that hold a byte of
-// the row are read; the others count as zero, and to_terms replaces every
-// pixel outside [0, W) by the sentinel anyway.
-template <typename Pix>
-__device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom& g, int y, int x0) {
-  constexpr int B = (int)sizeof(Pix);
-  constexpr int NC = 4 * B;  // chunk dwords (16 pixels)
-  constexpr int NH = B;      // halo dwords (4 pixels) on each side
-  const UnalignedRow u = unaligned_row<Pix>(g, y, x0);
-  const uint32_t* a0 = (const uint32_t*)u.a0;
-  const uint32_t sh = u.sh;
-  static_assert(NC + 2 * NH + 1 == unaligned_row_dwords<Pix>(), "dwords per unaligned row");
-  uint32_t d[NC + 2 * NH + 1];
-#pragma unroll
-  for (int k = 0; k < NC + 2 * NH + 1; ++k) {
-    const int j = u.j0 + k;
-    d[k] = unaligned_dword_in_row(j, u.lim) ? a0[j] : 0u;
-  }
-  // dword m of the halo-chunk-halo run covers row bytes [4 (j0 + m), +4)
-  uint32_t o[NC + 2 * NH];
-#pragma unroll
-  for (int m = 0; m < NC + 2 * NH; ++m) o[m] = __builtin_amdgcn_alignbyte(d[m + 1], d[m], sh);
-#pragma unroll
-  for (int h = 0; h < NH; ++h) {
-    rc.lh[h] = o[h];
-    rc.rh[h] = o[NH + NC + h];
-  }
-#pragma unroll
-  for (int v = 0; v < B; ++v) rc.v[v] = make_uint4(o[NH + 4 * v], o[NH + 4 * v + 1], o[NH + 4 * v + 2], o[NH + 4 * v + 3]);
-}
-
-// UNAL: the image is read by load_row_unaligned (cols unused), else by the
-// 16-byte loads of the strip machinery.
-template <typename Pix, bool UNAL>
-__device__ __forceinline__ void batch_load(RawChunk<Pix>& rc, const Geom& g, int y, int x0, const LaneCols& cols) {
-  if constexpr (UNAL)
-    load_row_unaligned<Pix>(rc, g, y, x0);
-  else
-    load_row<Pix>(rc, g, y, cols);
-}
-
 // BAND: the item is a band of an image's first-pixel rows; rows at or past
 // y_end (still read as second pixels) vote as the sentinel level (fsent).
 template <typename Pix, int MAXDY, int D, int CUR, bool UNAL, bool BAND>
@@ -93,7 +50,7 @@ __device__ __forceinline__ void batch_step(const BatchArgs& a, const Geom& geo, 
   for (int t = 0; t < 16; ++t) fa[t] = first ? mad_u24(ring[CUR].s[MAXDY + t], n1, C) : fsent;
   batch_vote<MAXDY, D, 0, CUR>(fa, ring, code, a.K, 1u);
   to_terms<Pix, MAXDY, true>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, true);
-  batch_load<Pix, UNAL>(raw[CUR], geo, y + 2 * NR, x0, cols);
+  row_load<Pix, UNAL>(raw[CUR], geo, y + 2 * NR, x0, cols);
 }
 
 // The votes of one item (first-pixel rows [t.y0, t.y1) of an image): lane ->
@@ -125,11 +82,11 @@ __device__ __forceinline__ void batch_votes(const BatchArgs& a, const BatchTile&
     LaneCols cols{};
     if constexpr (!UNAL) cols = lane_cols<Pix>(geo, x0);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) batch_load<Pix, UNAL>(raw[r], geo, ya + r, x0, cols);
+    for (int r = 0; r < NR; ++r) row_load<Pix, UNAL>(raw[r], geo, ya + r, x0, cols);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       to_terms<Pix, MAXDY, true>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb, true);
-      batch_load<Pix, UNAL>(raw[r], geo, ya + NR + r, x0, cols);
+      row_load<Pix, UNAL>(raw[r], geo, ya + NR + r, x0, cols);
     }
     // every lane takes h steps; rows past the image or the lane's segment
     // end carry the sentinel or belong to this segment's own run

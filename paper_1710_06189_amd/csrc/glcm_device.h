@@ -221,6 +221,49 @@ __device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y
   }
 }
 
+// Row loads of an image whose base or row pitch is not 16-byte aligned: the
+// lane's 16-pixel chunk and its 4-pixel halos are assembled from the aligned
+// dwords that span them (v_alignbyte_b32).  Only dwords that hold a byte of
+// the row are read; the others count as zero, and to_terms replaces every
+// pixel outside [0, W) by the sentinel anyway.
+template <typename Pix>
+__device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom& g, int y, int x0) {
+  constexpr int B = (int)sizeof(Pix);
+  constexpr int NC = 4 * B;  // chunk dwords (16 pixels)
+  constexpr int NH = B;      // halo dwords (4 pixels) on each side
+  const UnalignedRow u = unaligned_row<Pix>(g, y, x0);
+  const uint32_t* a0 = (const uint32_t*)u.a0;
+  const uint32_t sh = u.sh;
+  static_assert(NC + 2 * NH + 1 == unaligned_row_dwords<Pix>(), "dwords per unaligned row");
+  uint32_t d[NC + 2 * NH + 1];
+#pragma unroll
+  for (int k = 0; k < NC + 2 * NH + 1; ++k) {
+    const int j = u.j0 + k;
+    d[k] = unaligned_dword_in_row(j, u.lim) ? a0[j] : 0u;
+  }
+  // dword m of the halo-chunk-halo run covers row bytes [4 (j0 + m), +4)
+  uint32_t o[NC + 2 * NH];
+#pragma unroll
+  for (int m = 0; m < NC + 2 * NH; ++m) o[m] = __builtin_amdgcn_alignbyte(d[m + 1], d[m], sh);
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    rc.lh[h] = o[h];
+    rc.rh[h] = o[NH + NC + h];
+  }
+#pragma unroll
+  for (int v = 0; v < B; ++v) rc.v[v] = make_uint4(o[NH + 4 * v], o[NH + 4 * v + 1], o[NH + 4 * v + 2], o[NH + 4 * v + 3]);
+}
+
+// UNAL: the image is read by load_row_unaligned (cols unused), else by the
+// 16-byte loads of load_row.
+template <typename Pix, bool UNAL>
+__device__ __forceinline__ void row_load(RawChunk<Pix>& rc, const Geom& g, int y, int x0, const LaneCols& cols) {
+  if constexpr (UNAL)
+    load_row_unaligned<Pix>(rc, g, y, x0);
+  else
+    load_row<Pix>(rc, g, y, cols);
+}
+
 // Raw row -> per-pixel address terms (level * mb), sentinel level N outside
 // the image.  Halo pixels come from the neighbouring lanes; the wave-boundary
 // lanes use the halo dwords they loaded themselves.  SEG: a wavefront holds

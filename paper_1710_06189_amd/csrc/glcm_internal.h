@@ -33,6 +33,8 @@ struct VoteArgs {
   Quant q;
   int qfast;                  // 1: lo = 0, hi = dtype max, N = 2^n: level = pixel >> qfast_shift
   uint32_t qfast_shift, qfast_mask;  // shift and per-byte (u8) / per-halfword (u16) mask
+  int unaligned;              // strip and slab kernels: 1 = base or row pitch not 16-byte aligned
+                              // (rows assembled from the dwords that hold them), 0 = 16-byte loads
   int K;
   int32_t dx[kMaxK], dy[kMaxK];
   unsigned long long tmask;   // row kernel: bit k set = offset k was negated, vote (j, i)

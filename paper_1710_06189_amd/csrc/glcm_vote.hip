@@ -437,7 +437,10 @@ struct Ring {
   uint32_t w[6];  // [left halo (4 px) | 16 px chunk | right halo (4 px)], one level per byte
 };
 
-template <typename Pix>
+// UNAL: a row of an image whose base or pitch is not 16-byte aligned, read in
+// place as the dwords that hold it (load_row_unaligned: every lane takes its
+// halos too; finish_row uses those of the wave-boundary lanes only).
+template <typename Pix, bool UNAL>
 __device__ __forceinline__ void issue_row(RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0, int lane) {
 #pragma unroll
   for (int h = 0; h < (int)sizeof(Pix); ++h) {
@@ -446,6 +449,10 @@ __device__ __forceinline__ void issue_row(RawChunk<Pix>& rc, const VoteArgs& a, 
     rc.rh[h] = 0u;
   }
   if (y >= a.H) return;
+  if constexpr (UNAL) {
+    load_row_unaligned<Pix>(rc, Geom{a.img, a.stride, a.W, a.H}, y, x0);
+    return;
+  }
   const Pix* row = (const Pix*)a.img + (int64_t)y * a.stride;
   if (x0 < a.W) rc.v[0] = *(const uint4*)(row + x0);
   if (sizeof(Pix) == 2 && x0 + 8 < a.W) rc.v[sizeof(Pix) - 1] = *(const uint4*)(row + x0 + 8);
@@ -534,7 +541,7 @@ __device__ __forceinline__ void vote_offset(uint32_t* lds, const Ring (&rows)[NR
   }
 }
 
-template <typename Pix, int MAXDY, int RPW>
+template <typename Pix, int MAXDY, int RPW, bool UNAL>
 __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int2 rp = band_of_block(blockIdx.x, a.P, a.nregions);
@@ -579,7 +586,7 @@ __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
     {
       RawChunk<Pix> raw[NROWS];
 #pragma unroll
-      for (int i = 0; i < NROWS; ++i) issue_row<Pix>(raw[i], a, ys + i, x0, lane);
+      for (int i = 0; i < NROWS; ++i) issue_row<Pix, UNAL>(raw[i], a, ys + i, x0, lane);
 #pragma unroll
       for (int i = 0; i < NROWS; ++i) finish_row<Pix>(rows[i], raw[i], a, ys + i, x0, lane, sent4);
     }
@@ -604,7 +611,7 @@ __global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
 // One first-pixel row of a strip: bases, votes of every GLCM of the
 // partition, then the ring slot of this row takes the row NR below (from the
 // prefetched raw row) and the raw slot starts loading the row 2 NR below.
-template <typename Pix, int MAXDY, int D, bool PAIR, int CUR>
+template <typename Pix, int MAXDY, int D, bool PAIR, int CUR, bool UNAL>
 __device__ __forceinline__ void strip_step(const VoteArgs& a, const Geom& geo, TermRow<MAXDY> (&ring)[MAXDY + 1],
                                            RawChunk<Pix> (&raw)[MAXDY + 1], int y, int x0, const LaneCols& cols,
                                            bool edge, uint32_t C,
@@ -620,7 +627,7 @@ __device__ __forceinline__ void strip_step(const VoteArgs& a, const Geom& geo, T
   vote_glcm<MAXDY, D, 2, CUR, PAIR>(fa, ring, code[2], 1u);
   vote_glcm<MAXDY, D, 3, CUR, PAIR>(fa, ring, code[3], 1u);
   to_terms<Pix, MAXDY>(ring[CUR], raw[CUR], a, geo, y + NR, x0, sent4, mb, edge);
-  load_row<Pix>(raw[CUR], geo, y + 2 * NR, cols);
+  row_load<Pix, UNAL>(raw[CUR], geo, y + 2 * NR, x0, cols);
 }
 
 // Merge of the strip layout: one lane per (bin, dword group).  The lane reads
@@ -709,7 +716,9 @@ __device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int
 // (uint16 pixels with a reach of 2 need more than the 128 registers a
 // 1024-thread workgroup leaves a lane: that variant takes at most 512 threads,
 // as strip_max_threads tells the host)
-template <typename Pix, int MAXDY, int D, bool PAIR>
+// UNAL: rows of an image whose base or pitch is not 16-byte aligned, read in
+// place as the dwords that hold them (row_load).
+template <typename Pix, int MAXDY, int D, bool PAIR, bool UNAL>
 __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k_vote_strips(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   constexpr int NR = MAXDY + 1;
@@ -746,7 +755,7 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
     const int x0 = (((strip % spans) << 6) + lane) << 4, ya = y0 + (strip / spans) * a.strip_rows;
     const LaneCols cols = lane_cols<Pix>(geo, x0);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
+    for (int r = 0; r < NR; ++r) row_load<Pix, UNAL>(raw[r], geo, ya + r, x0, cols);
   }
   zero_lds(lds, n1 * n1 * (uint32_t)a.kg * D);
   // the quantizer's scalars are waited for here, once: a first use inside
@@ -764,20 +773,21 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
     const bool edge = ((span + 1) << 10) + 4 > a.W;  // chunks or right halos reach column W
     if (strip != wave) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) load_row<Pix>(raw[r], geo, ya + r, cols);
+      for (int r = 0; r < NR; ++r) row_load<Pix, UNAL>(raw[r], geo, ya + r, x0, cols);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       to_terms<Pix, MAXDY>(ring[r], raw[r], a, geo, ya + r, x0, sent4, mb, edge);
-      load_row<Pix>(raw[r], geo, ya + NR + r, cols);
+      row_load<Pix, UNAL>(raw[r], geo, ya + NR + r, x0, cols);
     }
     for (int y = ya; y < yb; y += NR) {
-      strip_step<Pix, MAXDY, D, PAIR, 0>(a, geo, ring, raw, y, x0, cols, edge, C, n1, mb, sent4, code, kp);
+      strip_step<Pix, MAXDY, D, PAIR, 0, UNAL>(a, geo, ring, raw, y, x0, cols, edge, C, n1, mb, sent4, code, kp);
       if (y + 1 >= yb) break;
-      strip_step<Pix, MAXDY, D, PAIR, 1>(a, geo, ring, raw, y + 1, x0, cols, edge, C, n1, mb, sent4, code, kp);
+      strip_step<Pix, MAXDY, D, PAIR, 1, UNAL>(a, geo, ring, raw, y + 1, x0, cols, edge, C, n1, mb, sent4, code, kp);
       if constexpr (NR > 2) {
         if (y + 2 >= yb) break;
-        strip_step<Pix, MAXDY, D, PAIR, 2>(a, geo, ring, raw, y + 2, x0, cols, edge, C, n1, mb, sent4, code, kp);
+        strip_step<Pix, MAXDY, D, PAIR, 2, UNAL>(a, geo, ring, raw, y + 2, x0, cols, edge, C, n1, mb, sent4, code,
+                                                 kp);
       }
     }
   }
@@ -801,16 +811,23 @@ hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_
   return launch(k_vote_generic<uint16_t>, a, grid, block, lds_bytes, stream, tm);
 }
 
+template <typename Pix, bool UNAL>
+static hipError_t launch_rows_u(const VoteArgs& a, int maxdy, int wg, size_t lds_bytes, hipStream_t stream,
+                                const LaunchTiming& tm) {
+  const dim3 grid(a.nregions * a.P), block(wg);
+  switch (maxdy) {
+    case 1: return launch(k_vote_rows<Pix, 1, 4, UNAL>, a, grid, block, lds_bytes, stream, tm);
+    case 2: return launch(k_vote_rows<Pix, 2, 4, UNAL>, a, grid, block, lds_bytes, stream, tm);
+    case 4: return launch(k_vote_rows<Pix, 4, 4, UNAL>, a, grid, block, lds_bytes, stream, tm);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename Pix>
 static hipError_t launch_rows_t(const VoteArgs& a, int maxdy, int wg, size_t lds_bytes, hipStream_t stream,
                                const LaunchTiming& tm) {
-  const dim3 grid(a.nregions * a.P), block(wg);
-  switch (maxdy) {
-    case 1: return launch(k_vote_rows<Pix, 1, 4>, a, grid, block, lds_bytes, stream, tm);
-    case 2: return launch(k_vote_rows<Pix, 2, 4>, a, grid, block, lds_bytes, stream, tm);
-    case 4: return launch(k_vote_rows<Pix, 4, 4>, a, grid, block, lds_bytes, stream, tm);
-    default: return hipErrorInvalidValue;
-  }
+  return a.unaligned ? launch_rows_u<Pix, true>(a, maxdy, wg, lds_bytes, stream, tm)
+                     : launch_rows_u<Pix, false>(a, maxdy, wg, lds_bytes, stream, tm);
 }
 
 hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
@@ -820,17 +837,24 @@ hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int r
                           : launch_rows_t<uint16_t>(a, maxdy, wg, lds_bytes, stream, tm);
 }
 
+template <typename Pix, int MAXDY, bool PAIR, bool UNAL>
+static hipError_t launch_strips_u(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream,
+                                  const LaunchTiming& tm) {
+  const dim3 grid(a.nregions * a.P), block(wg);
+  switch (D) {
+    case 4: return launch(k_vote_strips<Pix, MAXDY, 4, PAIR, UNAL>, a, grid, block, lds_bytes, stream, tm);
+    case 8: return launch(k_vote_strips<Pix, MAXDY, 8, PAIR, UNAL>, a, grid, block, lds_bytes, stream, tm);
+    case 16: return launch(k_vote_strips<Pix, MAXDY, 16, PAIR, UNAL>, a, grid, block, lds_bytes, stream, tm);
+    case 32: return launch(k_vote_strips<Pix, MAXDY, 32, PAIR, UNAL>, a, grid, block, lds_bytes, stream, tm);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename Pix, int MAXDY, bool PAIR>
 static hipError_t launch_strips_p(const VoteArgs& a, int D, int wg, size_t lds_bytes, hipStream_t stream,
                                  const LaunchTiming& tm) {
-  const dim3 grid(a.nregions * a.P), block(wg);
-  switch (D) {
-    case 4: return launch(k_vote_strips<Pix, MAXDY, 4, PAIR>, a, grid, block, lds_bytes, stream, tm);
-    case 8: return launch(k_vote_strips<Pix, MAXDY, 8, PAIR>, a, grid, block, lds_bytes, stream, tm);
-    case 16: return launch(k_vote_strips<Pix, MAXDY, 16, PAIR>, a, grid, block, lds_bytes, stream, tm);
-    case 32: return launch(k_vote_strips<Pix, MAXDY, 32, PAIR>, a, grid, block, lds_bytes, stream, tm);
-    default: return hipErrorInvalidValue;
-  }
+  return a.unaligned ? launch_strips_u<Pix, MAXDY, PAIR, true>(a, D, wg, lds_bytes, stream, tm)
+                     : launch_strips_u<Pix, MAXDY, PAIR, false>(a, D, wg, lds_bytes, stream, tm);
 }
 
 template <typename Pix, int MAXDY>

@@ -564,21 +564,45 @@ def test_kernel_timing_flag():
 
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 @pytest.mark.parametrize("offs", [synth.offsets_for([1]), synth.offsets_for([1, 2, 4])])
-def test_misaligned_large_views_staged(dtype, offs):
-    """Misaligned views of at least 2^16 pixels are copied to an aligned
-    staging buffer and counted by the strip / slab kernels: bit-exact, and the
-    plan's workspace grows by the staging buffer."""
+def test_misaligned_views_read_in_place(dtype, offs):
+    """Misaligned views (base or pitch not 16-byte aligned) of at least 2^16
+    pixels are read in place by the strip and slab kernels, smaller ones by
+    the per-pixel kernels: bit-exact whatever the byte offset of the rows,
+    and the plan's workspace does not grow (no staging copy)."""
     top = int(np.iinfo(dtype).max)
     base = synth.smooth(520, 1100, 4.0, 41, dtype)
     t = to_device(base)
     plan = G.glcm_plan_create(dtype, 32, offs, 1100, 520)
     try:
+        kernel = G.PATH_NAMES[plan.tuning.path]
+        assert kernel in ("strips", "slabs")
         before = G.glcm_plan_workspace(plan)
-        for y0, x0, h, w in ((1, 3, 500, 1001), (0, 1, 257, 1099), (7, 13, 300, 700)):
+        for y0, x0, h, w in ((1, 3, 500, 1001), (0, 1, 257, 1099), (7, 13, 300, 700), (2, 5, 40, 17),
+                             (0, 7, 3, 1093), (11, 2, 509, 1), (5, 1, 1, 1024), (3, 9, 200, 1040)):
             sub = base[y0:y0 + h, x0:x0 + w]
             check(sub, 32, 0, top, offs, plan=plan, t=t[y0:y0 + h, x0:x0 + w],
-                  label=f"staged view ({y0},{x0}) {h}x{w}")
-        assert G.glcm_plan_workspace(plan) >= before + 500 * ((1001 * base.itemsize + 15) // 16 * 16)
+                  label=f"{kernel} in place ({y0},{x0}) {h}x{w}")
+        assert G.glcm_plan_workspace(plan) == before
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("N,dists", [(8, [1]), (16, [1, 2]), (64, [2]), (32, [1, 2, 4])])
+def test_misaligned_views_every_layout(dtype, N, dists):
+    """In-place reads on both row kernels and several layouts (copies,
+    counter width), views starting at every byte offset of a dword."""
+    top = int(np.iinfo(dtype).max)
+    base = synth.smooth(300, 2100, 3.0, 42 + N, dtype)
+    t = to_device(base)
+    offs = synth.offsets_for(dists) + [(-dists[-1], 0), (0, -1)]
+    plan = G.glcm_plan_create(dtype, N, offs, 2100, 300)
+    try:
+        kernel = G.PATH_NAMES[plan.tuning.path]
+        for x0 in (1, 2, 3, 5, 6, 7):
+            w = 2100 - x0 - (x0 * 37) % 50
+            sub = base[x0:, x0:x0 + w]
+            check(sub, N, 0, top, offs, plan=plan, t=t[x0:, x0:x0 + w], label=f"{kernel} N={N} view x0={x0} w={w}")
     finally:
         plan.close()
 

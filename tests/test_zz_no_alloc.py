@@ -62,7 +62,7 @@ def test_static_equals_compute_twice(name, first, second, N, lo, hi, offs):
 
 def test_static_misaligned_view():
     t = to_device(synth.smooth(700, 901, 4.0, 12))
-    view = t[:, 1:]  # base + 1 byte, pitch 901: the per-pixel kernels, no staging copy
+    view = t[:, 1:]  # base + 1 byte, pitch 901: read in place, no staging copy
     got, ref = both(view, 32, 0, 255, D1)
     assert np.array_equal(got, ref)
     small = t[:50, 3:40]
