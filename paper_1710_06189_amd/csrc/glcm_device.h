@@ -176,6 +176,13 @@ __host__ __device__ inline UnalignedRow unaligned_row(const Geom& g, int y, int 
 }
 
 __host__ __device__ inline bool unaligned_dword_in_row(int j, int lim) { return j >= 0 && 4 * j < lim; }
+// Dword j clamped into the row: the nearest dword that holds a byte of it (the
+// bytes it brings in for positions outside the row are replaced by the
+// sentinel level afterwards, as every pixel outside [0, W) is).
+__host__ __device__ inline int unaligned_dword_clamped(int j, int lim) {
+  const int last = (lim - 1) >> 2;
+  return j < 0 ? 0 : (j > last ? last : j);
+}
 
 // Dwords load_row_unaligned reads per row: chunk (4 B), halos (B each side),
 // and one more for the byte shift.
@@ -224,8 +231,8 @@ __device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y
 // Row loads of an image whose base or row pitch is not 16-byte aligned: the
 // lane's 16-pixel chunk and its 4-pixel halos are assembled from the aligned
 // dwords that span them (v_alignbyte_b32).  Only dwords that hold a byte of
-// the row are read; the others count as zero, and to_terms replaces every
-// pixel outside [0, W) by the sentinel anyway.
+// the row are read (an index outside the row reads the nearest one), and
+// every pixel outside [0, W) is replaced by the sentinel afterwards.
 template <typename Pix>
 __device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom& g, int y, int x0) {
   constexpr int B = (int)sizeof(Pix);
@@ -239,7 +246,7 @@ __device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom
 #pragma unroll
   for (int k = 0; k < NC + 2 * NH + 1; ++k) {
     const int j = u.j0 + k;
-    d[k] = unaligned_dword_in_row(j, u.lim) ? a0[j] : 0u;
+    d[k] = a0[unaligned_dword_clamped(j, u.lim)];
   }
   // dword m of the halo-chunk-halo run covers row bytes [4 (j0 + m), +4)
   uint32_t o[NC + 2 * NH];

@@ -3,7 +3,7 @@
 // Built by tests/test_load_bounds_cpu.py with hipcc and run on the host (no
 // GPU): it calls the same __host__ __device__ address helpers the kernels use
 // (lane_cols, row_offset, next_span_offset, unaligned_row,
-// unaligned_dword_in_row, chunk_second_block, ChunkPos, hist_geometry) for every lane position a
+// unaligned_dword_clamped, chunk_second_block, ChunkPos, hist_geometry) for every lane position a
 // kernel can take, and checks each access:
 //  * 16-byte aligned rows (strip, slab-halo, block-code and batch loads,
 //    histogram chunks):
@@ -84,8 +84,8 @@ static void block_rows(int W, int H, int extra_blocks) {
   }
 }
 
-// Batch loads of rows that are not 16-byte aligned: base at byte `base`, row
-// pitch W + extra pixels.
+// Loads of rows that are not 16-byte aligned (batch, strip and slab kernels):
+// base at byte `base`, row pitch W + extra pixels.
 template <typename Pix>
 static void unaligned_rows(int W, int H, int base, int extra) {
   constexpr int B = (int)sizeof(Pix);
@@ -98,11 +98,11 @@ static void unaligned_rows(int W, int H, int base, int extra) {
       const long r0 = base + (long)yy * pitch, r1 = r0 + (long)W * B;
       const UnalignedRow u = unaligned_row<Pix>(g, y, x0);
       for (int k = 0; k < unaligned_row_dwords<Pix>(); ++k) {
-        const int j = u.j0 + k;
-        if (!unaligned_dword_in_row(j, u.lim)) continue;
+        const int j = unaligned_dword_clamped(u.j0 + k, u.lim);
         ++g_checked;
         const long a = (long)u.a0 + 4L * j;
         if (!(a < r1 && a + 4 > r0)) fail("unaligned dword", B, W, H, x0, y, a, 4);
+        if (unaligned_dword_in_row(u.j0 + k, u.lim) && j != u.j0 + k) fail("clamped in-row dword", B, W, H, x0, y, a, 4);
       }
     }
   }
