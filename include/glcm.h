@@ -514,7 +514,10 @@ GLCM_API int glcm_batch_autotune(glcm_plan_t plan, const glcm_tile_t *tiles, int
 typedef struct glcm_server_s *glcm_server_t;
 
 typedef struct glcm_request {
-    const void *img;                /* DEVICE image, row y at img + y*stride elements */
+    const void *img;                /* device image, or host memory (pinned or pageable: streamed to
+                                       the GPU in row tiles by the lane, never fused; the caller keeps
+                                       it unchanged until the request is done); row y at
+                                       img + y*stride elements */
     int32_t W, H;                   /* 1 .. 65535 each, W*H <= 2^32 - 1 */
     int64_t stride;                 /* elements, >= W */
     int32_t dtype;                  /* GLCM_U8 or GLCM_U16 */
@@ -565,7 +568,7 @@ GLCM_API int glcm_server_create(glcm_server_t *srv, int lanes, uint64_t hbm_budg
 
 /* Queues one request (validated here; nothing is queued on error) and returns
  * its ticket.  Errors: GLCM_EINVAL for a bad descriptor (as glcm_compute, plus
- * a host image, or a NULL out / feat without a result pool);
+ * a device image on another device, or a NULL out / feat without a result pool);
  * GLCM_EUNSUPPORTED when the request alone needs more than the budget. */
 GLCM_API int glcm_server_submit(glcm_server_t srv, const glcm_request_t *req, uint64_t *ticket);
 

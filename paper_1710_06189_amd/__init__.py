@@ -649,10 +649,12 @@ class Server:
     """Owner of a glcm_server_t: requests of mixed size, N and offsets admitted
     onto `lanes` HIP streams as lanes and the HBM budget allow.
 
-    submit() takes a 2-D device tensor (any row stride) and returns a ticket;
-    results go to the given `out` / `feat` tensors or, if omitted, to the
-    server's device pool (then read them with fetch() and free them with
-    release())."""
+    submit() takes a 2-D image (a device tensor of any row stride, or a host
+    numpy array or CPU tensor, pinned or pageable, which the lane streams to
+    the GPU) and returns a ticket; results go to the given `out` / `feat`
+    tensors or, if omitted, to the server's device pool (then read them with
+    fetch() and free them with release()).  A host image must stay unchanged
+    until its request is done (the server keeps a reference)."""
 
     def __init__(self, lanes=4, hbm_budget=32 << 30, result_pool_bytes=256 << 20):
         h = ctypes.c_void_p()
@@ -662,8 +664,6 @@ class Server:
         self._keep = {}  # ticket -> tensors the request reads or writes
 
     def submit(self, img, N, lo=0, hi=None, offsets=((1, 0),), features=False, out=None, feat=None) -> int:
-        if not (isinstance(img, torch.Tensor) and img.is_cuda):
-            raise ValueError("the server takes device images (CUDA tensors)")
         ptr, W, H, stride, dt, keep = _image_args(img)
         if hi is None:
             hi = 255 if dt == U8 else 65535

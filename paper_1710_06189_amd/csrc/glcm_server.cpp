@@ -12,6 +12,12 @@
 // scheduler for the next request.  Requests on different lanes overlap on the
 // GPU; results stay in device memory until fetched or released.
 //
+// Host images: a request may bring its image in host memory (pinned or
+// pageable); the lane's plan streams it to the GPU in row tiles (glcm_compute's
+// host path: a pageable image is first copied into pinned staging by the
+// scheduler thread), and the tile buffers the plan allocates count against the
+// budget from then on.
+//
 // Continuous batching: when the admitted request is small (at most
 // kFusePixels pixels, at most four offsets of reach <= 2), queued requests of
 // the same job (dtype, N, range, offsets, statistics or not) that are small
@@ -127,6 +133,7 @@ struct Request {
   bool done = false;
   int status = GLCM_OK;
   int fused = 1;                  // requests in the launch that carried it
+  bool host = false;              // image in host memory (streamed in row tiles; never fused)
   std::vector<Request*> group;    // the head of a fused launch: its other requests
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
@@ -134,7 +141,7 @@ struct Request {
 // A request the batch kernel can take in a fused launch: a small image, at
 // most four offsets, each with |dx|, |dy| <= 2, levels in one byte.
 bool fusable(const Request* q) {
-  if ((uint64_t)q->r.W * (uint64_t)q->r.H > kFusePixels || q->r.K > 4 || q->r.N > 255) return false;
+  if (q->host || (uint64_t)q->r.W * (uint64_t)q->r.H > kFusePixels || q->r.K > 4 || q->r.N > 255) return false;
   for (int k = 0; k < q->r.K; ++k)
     if (std::abs(q->offs[k].dx) > 2 || std::abs(q->offs[k].dy) > 2) return false;
   return true;
@@ -523,7 +530,8 @@ GLCM_API int glcm_server_submit(glcm_server_t s, const glcm_request_t* req, uint
   if (rc != GLCM_OK) return rc;
   if (r.W > kPlanMaxSide || r.H > kPlanMaxSide) return GLCM_EINVAL;
   int dev = -1;
-  if (glcm::memory_kind(r.img, &dev) != 2 || dev != s->device) return GLCM_EINVAL;
+  const int img_kind = glcm::memory_kind(r.img, &dev);
+  if (img_kind == 2 && dev != s->device) return GLCM_EINVAL;
   if (r.out && (glcm::memory_kind(r.out, &dev) != 2 || dev != s->device)) return GLCM_EINVAL;
   if (r.features && r.feat && (glcm::memory_kind(r.feat, &dev) != 2 || dev != s->device)) return GLCM_EINVAL;
   const uint64_t out_bytes = (uint64_t)r.K * (uint64_t)r.N * (uint64_t)r.N * 4ull;
@@ -541,6 +549,7 @@ GLCM_API int glcm_server_submit(glcm_server_t s, const glcm_request_t* req, uint
   q->res_bytes = res;
   q->out = r.out;
   q->feat = r.features ? r.feat : nullptr;
+  q->host = img_kind != 2;
   std::lock_guard<std::mutex> lk(s->mu);
   q->id = s->next_id++;
   q->t_submit = s->now_us();

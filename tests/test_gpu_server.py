@@ -167,6 +167,52 @@ def test_fused_small_requests_equal_alone(pool_images):
         srv.close()
 
 
+def test_host_images_equal_alone(pool_images):
+    """Requests whose images are in host memory (pinned CPU tensors, pageable
+    numpy arrays, strided views) are streamed to the GPU by their lane, mixed
+    with device requests: every result equals the request computed alone."""
+    smooth, noise = pool_images
+    rng = np.random.default_rng(23)
+    srv = G.Server(lanes=3, hbm_budget=8 << 30, result_pool_bytes=256 << 20)
+    try:
+        reqs = []
+        for i in range(18):
+            src = (smooth, noise)[i % 2]
+            h, w = (int(v) for v in rng.integers(1, 1400, size=2))
+            y0 = int(rng.integers(0, src.shape[0] - h + 1))
+            x0 = int(rng.integers(0, src.shape[1] - w + 1))
+            N = int(rng.choice([8, 32, 64, 256]))
+            mask = int(rng.integers(1, 1 << 12))
+            offs = [ALL12[b] for b in range(12) if mask >> b & 1]
+            dev_img = src[y0:y0 + h, x0:x0 + w]
+            kind = i % 3
+            if kind == 0:
+                img = dev_img.cpu().pin_memory()          # pinned, contiguous
+            elif kind == 1:
+                img = src.cpu().numpy()[y0:y0 + h, x0:x0 + w]  # pageable, strided view
+            else:
+                img = dev_img                              # device
+            t = srv.submit(img, N, 0, 255, offs, features=bool(i % 2))
+            reqs.append(dict(t=t, img=dev_img, N=N, offsets=offs, features=bool(i % 2), kind=kind))
+        print(f"[server] submitted {len(reqs)} requests, host and device images", flush=True)
+        srv.drain()
+        st = srv.stats()
+        assert st.completed == len(reqs) and st.failed == 0
+        for r in reqs:
+            info = srv.query(r["t"])
+            assert info.done == 1 and info.status == 0
+            if r["kind"] != 2:
+                assert info.fused == 1, "a host image was fused"
+            P, F = srv.fetch(r["t"])
+            p_alone, f_alone = alone(r)
+            assert np.array_equal(host(P), p_alone), f"counts differ (image kind {r['kind']}, N={r['N']})"
+            if r["features"]:
+                assert np.array_equal(host(F), f_alone), "statistics differ from the request alone"
+            srv.release(r["t"])
+    finally:
+        srv.close()
+
+
 def test_caller_owned_buffers(pool_images):
     reqs = mixed_requests(6, 3, pool_images, max_side=700)
     srv = G.Server(lanes=2, hbm_budget=2 << 30, result_pool_bytes=0)
@@ -240,7 +286,7 @@ def test_server_rejects_bad_requests(pool_images):
     srv = G.Server(lanes=1, hbm_budget=1 << 20, result_pool_bytes=1 << 20)
     try:
         with pytest.raises(ValueError):
-            srv.submit(torch.zeros((8, 8), dtype=torch.uint8), 8)  # host image
+            srv.submit(torch.zeros((8, 8), dtype=torch.int32), 8)  # not a uint8 / uint16 image
         with pytest.raises(G.GlcmError) as e:  # N = 256 needs a 50 MB plan: beyond the budget
             srv.submit(pool_images[0][:64, :64], 256, 0, 255, ALL12)
         assert e.value.status == -3
