@@ -11,13 +11,16 @@ before the timed loop: every step reads a copy last touched at least 496 MiB
 of traffic earlier, so from HBM rather than from the 256 MiB Infinity Cache.
 Every copy's result is checked bit-exact against the CPU oracle.  The plan is
 tuned first (untimed) by glcm_plan_autotune on one copy of the same image:
-it times the LDS layouts of the strip kernel and, the offsets being the d = 1
-directions, the block-code kernel, and keeps the fastest (--no-autotune keeps
-the default layout, --layout fixes one).  `extra.cache_hot_gpairs_s` repeats
-the timed loop on one image copy, which then stays in the Infinity Cache:
-labelled, never the headline value.  `extra.batch` carries the batch
-workload's ratio of one fused launch over per-tile calls and its graph-replay
-time (bench_batch).
+it times the LDS layouts of the strip and slab kernels and, the offsets being
+the d = 1 directions, the block-code kernel, and keeps the fastest
+(--no-autotune keeps the default layout, --layout fixes one).
+`extra.cache_hot_gpairs_s` repeats the timed loop on one image copy, which
+then stays in the Infinity Cache: labelled, never the headline value.
+`extra.batch` carries the batch workload's ratio of one fused launch over
+per-tile calls and its graph-replay time (bench_batch); `extra.tile_stream`
+the same tiles as one request each through the request server, which fuses
+queued requests of one job into batch launches, against one request at a
+time (serve_tile_stream).
 
 Prints one JSON line.  `value` is pairs per second over the timed steps
 (wall clock, both kernels of each call).  `roofline` prices the dominant
@@ -33,6 +36,7 @@ on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -310,6 +314,9 @@ def main():
                                             "per_image_ms", "per_image_device_ms", "batched_over_per_image",
                                             "graph_replay_ms", "graph_replay_gpairs_s", "autotuned_ms",
                                             "autotuned_layout", "check")}
+        # the same tiles as one request each through the request server, which
+        # fuses queued requests of one job into batch launches
+        extra["tile_stream"] = serve_tile_stream(args, G, torch, np, synth, dev)
     if args.others:
         for kind in ("uniform", "constant", "smooth"):
             if kind == args.kind:
@@ -1037,10 +1044,18 @@ def serve_tile_stream(args, G, torch, np, synth, dev):
 
     def served():
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tickets = [srv.submit(im, N, 0, 255, offs, features=True) for im in imgs]
-        srv.drain()
-        wall = time.perf_counter() - t0
+        # (the collector stays off while the requests are handed over: with
+        # the other legs' objects alive its passes would be what is timed)
+        gc.disable()
+        try:
+            t0 = time.perf_counter()
+            tickets = [srv.submit(im, N, 0, 255, offs, features=True) for im in imgs]
+            t_sub = time.perf_counter() - t0
+            srv.drain()
+            wall = time.perf_counter() - t0
+        finally:
+            gc.enable()
+        served.submit_s = t_sub
         infos = [srv.query(t) for t in tickets]
         for i, (t, info) in enumerate(zip(tickets, infos)):
             if info.status != 0:
@@ -1061,7 +1076,7 @@ def serve_tile_stream(args, G, torch, np, synth, dev):
     res = {"workload": f"{len(imgs)}-tile-requests-u8-32to512-N16-K4-features", "requests": len(imgs),
            "one_at_a_time_ms": t_sync * 1e3, "one_stream_ms": t_stream * 1e3, "served_ms": t_served * 1e3,
            "served_over_one_at_a_time": t_sync / t_served, "served_over_one_stream": t_stream / t_served,
-           "fused_launches": launches, "fused_requests": fused,
+           "submit_ms": served.submit_s * 1e3, "fused_launches": launches, "fused_requests": fused,
            "mean_requests_per_fused_launch": fused / launches if launches else 0.0,
            "largest_fused_launch": max(i.fused for i in infos)}
     print(f"[serving] tile stream: {json.dumps(res)}", file=sys.stderr, flush=True)
