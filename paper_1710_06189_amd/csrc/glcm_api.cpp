@@ -54,9 +54,10 @@ enum Path {
 // this many pixels: the strip and slab kernels read them in place (rows
 // assembled from the dwords that hold them); for the block-code kernel, which
 // needs 16-byte rows, they are copied into an aligned staging buffer.
-// Smaller ones take the per-pixel kernel, faster there (measured on MI355X:
-// 4096 images of 32-512 px, one call each, 138 ms per-pixel against 175 ms
-// in place; a 4096^2 image 30.9 us in place, about the same as copied).
+// Smaller ones take the per-pixel kernel, faster there.  Measured on MI355X:
+// 4096 uint8 images of 32-512 px, one call each, 138 ms per-pixel against
+// 175 ms in place; 4096^2 uint16 images 74-127 us per call in place against
+// 93-133 us copied first (the pitched copy alone costs 40-60 us).
 constexpr uint64_t kStageMinPixels = 1u << 16;
 
 
@@ -662,9 +663,10 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   if (path == kPathRows || path == kPathStrips || path == kPathBlocks) {
     const bool aligned = ((uintptr_t)img % 16 == 0) && (((uint64_t)stride * b) % 16 == 0);
     const bool large = (uint64_t)W * (uint64_t)H >= kStageMinPixels;
+    const bool can_stage = !p->no_alloc && y_begin == 0 && y_end == H;
     if (!aligned && path != kPathBlocks && large) {
       a.unaligned = 1;  // read in place
-    } else if (!aligned && path == kPathBlocks && !p->no_alloc && large && y_begin == 0 && y_end == H) {
+    } else if (!aligned && large && can_stage) {
       // one pitched copy into the plan's aligned buffer, then the fast kernels
       const size_t pitch = ((size_t)W * b + 15) & ~(size_t)15;
       GLCM_TRY_RC(ensure_stage(p, pitch * (size_t)H));
@@ -839,7 +841,9 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   // Row bands: as many workgroups per partition as the CUs hold at once
   // (limited by LDS and by 32 wavefronts per CU).
   const int rows = y_end - y_begin;
-  const int wg = path == kPathStrips ? std::min(t.wg_size, glcm::strip_max_threads(b, smd)) : t.wg_size;
+  const int wg = path == kPathStrips ? std::min(t.wg_size, glcm::strip_max_threads(b, smd))
+                 : path == kPathRows ? std::min(t.wg_size, glcm::rows_max_threads(b, c.maxdy, a.unaligned != 0))
+                                     : t.wg_size;
   const int nwaves = wg / 64;
   if (g16) a.c16 = 1;
   size_t lds_need = g16 ? (size_t)((a.part_words + 1u) / 2u) * 4u : ((size_t)a.part_words << log2R) * 4u;

@@ -14,6 +14,12 @@ constexpr uint32_t kXcdSlots = 16;
 constexpr int kStripMaxKp = 4;
 // Threads per workgroup the strip kernel accepts for a pixel size and reach.
 constexpr int strip_max_threads(int pixel_bytes, int maxdy) { return pixel_bytes == 2 && maxdy == 2 ? 512 : 1024; }
+// Threads per workgroup the slab kernel accepts: uint16 rows of reach 4 read in
+// place (eight rows of 13 dwords in flight) need more than a 1024-thread
+// workgroup's 128 registers per lane.
+constexpr int rows_max_threads(int pixel_bytes, int maxdy, bool unaligned) {
+  return unaligned && pixel_bytes == 2 && maxdy > 2 ? 512 : 1024;
+}
 
 // Gray-level reduction q(v): 0 below lo, N-1 above hi, otherwise
 // floor(x / D) with x = (v - lo) * N and D = hi - lo + 1, evaluated as

@@ -542,7 +542,7 @@ __device__ __forceinline__ void vote_offset(uint32_t* lds, const Ring (&rows)[NR
 }
 
 template <typename Pix, int MAXDY, int RPW, bool UNAL>
-__global__ __launch_bounds__(1024) void k_vote_rows(VoteArgs a) {
+__global__ __launch_bounds__(rows_max_threads(sizeof(Pix), MAXDY, UNAL)) void k_vote_rows(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int2 rp = band_of_block(blockIdx.x, a.P, a.nregions);
   const int region = rp.x, part = rp.y;

@@ -68,6 +68,11 @@ def test_static_misaligned_view():
     small = t[:50, 3:40]
     got, ref = both(small, 32, 0, 255, D1)
     assert np.array_equal(got, ref)
+    # uint16 views, read in place by both entry points
+    t16 = to_device(synth.smooth(600, 903, 4.0, 13, np.uint16))
+    for offs in (D1, synth.offsets_for([1, 2, 4])):
+        got, ref = both(t16[:, 3:], 64, 0, 65535, offs)
+        assert np.array_equal(got, ref)
 
 
 def test_static_rejects_beyond_its_array():
