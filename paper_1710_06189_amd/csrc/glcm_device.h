@@ -233,7 +233,10 @@ __device__ __forceinline__ void load_row(RawChunk<Pix>& rc, const Geom& a, int y
 // dwords that span them (v_alignbyte_b32).  Only dwords that hold a byte of
 // the row are read (an index outside the row reads the nearest one), and
 // every pixel outside [0, W) is replaced by the sentinel afterwards.
-template <typename Pix>
+// ALLHALO false: only the wave-boundary lanes read their halo dwords (the
+// others take their halo pixels from the neighbouring lanes; theirs read as
+// zero).
+template <typename Pix, bool ALLHALO = true>
 __device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom& g, int y, int x0) {
   constexpr int B = (int)sizeof(Pix);
   constexpr int NC = 4 * B;  // chunk dwords (16 pixels)
@@ -243,10 +246,13 @@ __device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom
   const uint32_t sh = u.sh;
   static_assert(NC + 2 * NH + 1 == unaligned_row_dwords<Pix>(), "dwords per unaligned row");
   uint32_t d[NC + 2 * NH + 1];
+  const int lane = (int)(threadIdx.x & 63u);
+  const bool lneed = ALLHALO || lane == 0, rneed = ALLHALO || lane == 63;
 #pragma unroll
   for (int k = 0; k < NC + 2 * NH + 1; ++k) {
     const int j = u.j0 + k;
-    d[k] = a0[unaligned_dword_clamped(j, u.lim)];
+    d[k] = 0u;
+    if (k < NH ? lneed : (k > NH + NC ? rneed : true)) d[k] = a0[unaligned_dword_clamped(j, u.lim)];
   }
   // dword m of the halo-chunk-halo run covers row bytes [4 (j0 + m), +4)
   uint32_t o[NC + 2 * NH];
@@ -266,7 +272,7 @@ __device__ __forceinline__ void load_row_unaligned(RawChunk<Pix>& rc, const Geom
 template <typename Pix, bool UNAL>
 __device__ __forceinline__ void row_load(RawChunk<Pix>& rc, const Geom& g, int y, int x0, const LaneCols& cols) {
   if constexpr (UNAL)
-    load_row_unaligned<Pix>(rc, g, y, x0);
+    load_row_unaligned<Pix, false>(rc, g, y, x0);
   else
     load_row<Pix>(rc, g, y, cols);
 }

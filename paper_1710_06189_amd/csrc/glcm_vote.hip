@@ -438,8 +438,8 @@ struct Ring {
 };
 
 // UNAL: a row of an image whose base or pitch is not 16-byte aligned, read in
-// place as the dwords that hold it (load_row_unaligned: every lane takes its
-// halos too; finish_row uses those of the wave-boundary lanes only).
+// place as the dwords that hold it (load_row_unaligned; only the wave-boundary
+// lanes read halo dwords, the only ones finish_row uses).
 template <typename Pix, bool UNAL>
 __device__ __forceinline__ void issue_row(RawChunk<Pix>& rc, const VoteArgs& a, int y, int x0, int lane) {
 #pragma unroll
@@ -450,7 +450,7 @@ __device__ __forceinline__ void issue_row(RawChunk<Pix>& rc, const VoteArgs& a, 
   }
   if (y >= a.H) return;
   if constexpr (UNAL) {
-    load_row_unaligned<Pix>(rc, Geom{a.img, a.stride, a.W, a.H}, y, x0);
+    load_row_unaligned<Pix, false>(rc, Geom{a.img, a.stride, a.W, a.H}, y, x0);
     return;
   }
   const Pix* row = (const Pix*)a.img + (int64_t)y * a.stride;
