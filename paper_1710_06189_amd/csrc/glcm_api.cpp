@@ -56,7 +56,7 @@ enum Path {
 // needs 16-byte rows, they are copied into an aligned staging buffer.
 // Smaller ones take the per-pixel kernel, faster there.  Measured on MI355X:
 // 4096 uint8 images of 32-512 px, one call each, 138 ms per-pixel against
-// 175 ms in place; 4096^2 uint16 images 74-127 us per call in place against
+// 175 ms in place; 4096^2 uint16 images 62-105 us per call in place against
 // 93-133 us copied first (the pitched copy alone costs 40-60 us).
 constexpr uint64_t kStageMinPixels = 1u << 16;
 
