@@ -154,7 +154,8 @@ def main():
                     help="keep the default layout instead of timing the candidates (glcm_plan_autotune)")
     ap.add_argument("--path", default="auto", choices=["auto", "strips", "blocks"],
                     help="auto: the autotuner's pick; strips / blocks: that kernel, untuned (for profiling runs, "
-                         "whose per-dispatch overhead would blur the autotuner's timing)")
+                         "whose per-dispatch overhead would blur the autotuner's timing); multispectral: strips "
+                         "moves the stack from the slab kernel onto the strip kernel's reach-4 variant")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload's figures in extra")
     ap.add_argument("--layout", default=None,
                     help="fixed layout replicas,counter_bits,wg_size (skips the autotuner)")
@@ -776,6 +777,14 @@ def bench_multispectral(args, G, torch, np, oracle, synth, dev):
     print("[multispectral] oracle for band 0 done", file=sys.stderr, flush=True)
     plan = G.glcm_plan_create(np.uint16, N, offs, size, size)
     plan_serial = G.glcm_plan_create(np.uint16, N, offs, size, size, G.FLAG_SERIAL_UPLOAD)
+    if args.path == "blocks":
+        raise SystemExit("bench: the block-code kernel takes the d = 1 offsets only")
+    if args.path == "strips":
+        # the strip kernel's reach-4 variant instead of the slab default
+        # (4 dwords per bin in 16-bit pairs, 512 threads unless --layout says)
+        R, bits, wg = (int(v) for v in args.layout.split(",")) if args.layout else (4, 16, 512)
+        for p in (plan, plan_serial):
+            p.set_tuning(path=4, replicas=R, counter_bits=bits, wg_size=wg)
     devs = [h.to(dev) for h in hosts]
     run(plan, devs)  # warm-up (workspace, code objects)
     _, t_dev = run(plan, devs)

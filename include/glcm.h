@@ -98,8 +98,9 @@ typedef struct glcm_plan_s *glcm_plan_t;
 /* Launch parameters of a plan, readable and (for tuning) overridable. */
 typedef struct glcm_tuning {
     int replicas;       /* R: LDS copies of each GLCM per workgroup (power of two) */
-    int wg_size;        /* threads per workgroup: 256, 512 or 1024 (the strip kernel on
-                           uint16 images with offsets reaching 2 pixels runs at most 512) */
+    int wg_size;        /* threads per workgroup: 256, 512 or 1024 (the strip kernel runs
+                           at most 512 on uint16 images with offsets reaching 2 pixels and
+                           on any image with offsets reaching 3 or 4) */
     int rows_per_wave;  /* slab kernel: first-pixel rows per wavefront slab (4); 0 elsewhere */
     int tile_rows;      /* host-image upload tile height (rows) */
     int counter_bits;   /* LDS counters: 16 or 32; 0 keeps the current value.  Slab kernel:
@@ -110,8 +111,13 @@ typedef struct glcm_tuning {
     int merge;          /* 0: workgroups add their counts into per-XCD accumulators in L2,
                            a small kernel sums the 8 slices; 1: per-band partial counts,
                            summed by a reduce kernel */
-    int path;           /* read-only: 0 generic, 1 slab kernel, 2 partitioned, 3 global,
-                           4 strip kernel, 5 L2 slices (large N), 6 block codes (d = 1) */
+    int path;           /* 0 generic, 1 slab kernel, 2 partitioned, 3 global, 4 strip
+                           kernel, 5 L2 slices (large N), 6 block codes (d = 1).  Read-only,
+                           except that a plan on the slab or strip kernel may be set to the
+                           other where its offsets allow it (GLCM_EINVAL otherwise): the
+                           strip kernel takes |dx|, |dy| <= 2, and 3 or 4 along the four
+                           directions of Eq.(2) (dx = 0, dy = 0 or |dx| = |dy|); the slab
+                           kernel any offset with |dx|, |dy| <= 4 */
     int partitions;     /* read-only: bin partitions per pass */
 } glcm_tuning_t;
 

@@ -415,12 +415,26 @@ constexpr int kPassesPerSliceGlcm = 13;
 constexpr int kBatchDefaultMinRows = 4;
 
 // Row kernels (strips, slabs, blocks) store a level and the sentinel N in one
-// byte; the strip kernel reaches |dx|, dy <= 2, the slab kernel 4.
+// byte; the strip kernel reaches |dx|, dy <= 2 for any offset and 4 along the
+// four directions of Eq.(2) (dx = 0, dy = 0 or |dx| = dy), the slab kernel 4
+// for any offset.
 bool row_kernels_ok(const glcm_plan_s* p) {
   return !(p->flags & (GLCM_FLAG_FORCE_GENERIC | GLCM_FLAG_FORCE_PARTITIONED)) && p->N <= 255;
 }
+bool strip_offsets_ok(const glcm_plan_s* p, const Canon& c) {
+  for (int k = 0; k < p->K; ++k) {
+    const int ax = std::abs(c.dx[k]), dy = c.dy[k], r = std::max(ax, dy);
+    if (r > 4 || (r > 2 && ax != 0 && dy != 0 && ax != dy)) return false;
+  }
+  return true;
+}
+// The strip kernel's template reach (ring of reach + 1 rows): 1, 2 or 4.
+int strip_reach(const Canon& c) {
+  const int r = std::max(c.maxdy, c.maxadx);
+  return r <= 1 ? 1 : (r <= 2 ? 2 : 4);
+}
 bool strips_eligible(const glcm_plan_s* p, const Canon& c) {
-  return row_kernels_ok(p) && !(p->flags & GLCM_FLAG_FORCE_SLABS) && c.maxadx <= 2 && c.maxdy <= 2 &&
+  return row_kernels_ok(p) && !(p->flags & GLCM_FLAG_FORCE_SLABS) && strip_offsets_ok(p, c) &&
          strip_partitions(p, 4, 16) > 0;
 }
 bool slabs_eligible(const glcm_plan_s* p, const Canon& c) {
@@ -433,7 +447,10 @@ bool slabs_eligible(const glcm_plan_s* p, const Canon& c) {
 // bin, and with 8 at a reach of 1, strips are 1.0-1.5x faster; with 8 at a
 // reach of 2, or 4, they tie on smooth images and are up to 1.5x slower on
 // noise and on 8192-pixel rows (the few copies concentrate same-bank votes).
-bool strips_beat_slabs(int R, int reach) { return R >= 16 || (R == 8 && reach <= 1); }
+// At a reach of 3 or 4 (five-row ring, half the waves) strips were 0.63-1.02x
+// the slab speed except on smooth images at N = 32 with 12 offsets (1.2x), so
+// they are left to the autotuner there.
+bool strips_beat_slabs(int R, int reach) { return reach <= 2 && (R >= 16 || (R == 8 && reach <= 1)); }
 
 int choose_tuning(glcm_plan_t p, glcm_tuning_t* t) {
   // Path and LDS layout for this plan's (dtype, N, K, offsets, flags).
@@ -800,9 +817,9 @@ int count_device(glcm_plan_t p, const void* img, int W, int H, int64_t stride, i
   while ((1 << log2R) < R) ++log2R;
   a.log2R = log2R;
   const int rpw = 4;
-  // strip kernel: layout, template reach (1 or 2) and workgroup size
+  // strip kernel: layout, template reach (1, 2 or 4) and workgroup size
   StripLayout sl;
-  const int smd = std::max(c.maxdy, c.maxadx) <= 1 ? 1 : 2;
+  const int smd = strip_reach(c);
   if (path == kPathStrips) {
     const int swg = std::min(t.wg_size, glcm::strip_max_threads(b, smd));
     if (!strip_layout(p, W, y_end - y_begin, R, t.counter_bits == 16, swg, &sl))
@@ -1210,38 +1227,55 @@ GLCM_API int glcm_plan_tuning(glcm_plan_t plan, glcm_tuning_t* tuning, int set) 
     glcm_tuning_t& t = plan->tuning;
     if (n.counter_bits != 0 && n.counter_bits != 16 && n.counter_bits != 32) return GLCM_EINVAL;
     int bits = n.counter_bits == 0 ? t.counter_bits : n.counter_bits;
-    if (t.path == kPathBlocks) {
+    // the two row-kernel families may be swapped where the offsets allow both
+    // (the slab height then takes its default, 4)
+    int path = t.path;
+    const bool row_family = t.path == kPathStrips || t.path == kPathRows;
+    if (row_family && n.path != t.path && (n.path == kPathStrips || n.path == kPathRows)) {
+      const Canon c = canonicalize(plan->offsets, plan->K);
+      if (!(n.path == kPathStrips ? strips_eligible(plan, c) : slabs_eligible(plan, c))) return GLCM_EINVAL;
+      path = n.path;
+    }
+    int parts = t.partitions, new_path = path;
+    const int rpw = path == t.path ? n.rows_per_wave : (path == kPathRows ? 4 : 0);
+    if (path == kPathBlocks) {
       // the block kernel's layout is fixed (32 copies, 16-bit halves, 1024
       // threads); only the upload tile height and the merge are tunable
       if (n.wg_size != 1024 || n.rows_per_wave != 0) return GLCM_EINVAL;
       if (n.replicas != 32 || bits != 16) return GLCM_EINVAL;
-    } else if (t.path == kPathStrips) {
-      if (n.rows_per_wave != 0) return GLCM_EINVAL;  // strips have no slab height
+    } else if (path == kPathStrips) {
+      if (rpw != 0) return GLCM_EINVAL;  // strips have no slab height
       const int P = strip_partitions(plan, n.replicas, bits);
       if (P == 0) return GLCM_EINVAL;
-      t.partitions = P;
-    } else if (t.path == kPathRows) {
+      parts = P;
+    } else if (path == kPathRows) {
       // partitions are groups of whole GLCMs; the copies must fit one
       if (bits == 16 && n.replicas < 2) return GLCM_EINVAL;
-      if (n.rows_per_wave != 0 && n.rows_per_wave != 4) return GLCM_EINVAL;
+      if (rpw != 0 && rpw != 4) return GLCM_EINVAL;
       const int P = row_partitions(plan, n.replicas, bits);
       if (P == 0) return GLCM_EINVAL;
-      t.partitions = P;
+      parts = P;
     } else if (t.path != kPathGlobal && t.path != kPathL2) {
       if (bits == 16 && n.replicas != 1) return GLCM_EINVAL;  // 16-bit bins: one copy
       const uint64_t words = (uint64_t)plan->K * NN;
       if ((uint64_t)n.replicas > (uint64_t)plan->lds_budget_words) return GLCM_EINVAL;
       const uint64_t cap = (uint64_t)plan->lds_budget_words / n.replicas;
-      t.partitions = (int)((words + cap - 1) / cap);
-      if (t.partitions > 1) t.path = kPathPartitioned;
+      parts = (int)((words + cap - 1) / cap);
+      if (parts > 1) new_path = kPathPartitioned;
     }
-    t.counter_bits = bits;
     if (n.merge != 0 && n.merge != 1) return GLCM_EINVAL;
     if (n.merge == 0 && !plan->xbuf && t.path != kPathGlobal) return GLCM_EINVAL;
+    t.counter_bits = bits;
     t.merge = n.merge;
     t.replicas = n.replicas;
     t.wg_size = n.wg_size;
-    if (t.path == kPathRows && n.rows_per_wave != 0) t.rows_per_wave = n.rows_per_wave;
+    t.partitions = parts;
+    if (path != t.path) {
+      t.rows_per_wave = rpw;
+    } else if (t.path == kPathRows && n.rows_per_wave != 0) {
+      t.rows_per_wave = n.rows_per_wave;
+    }
+    t.path = new_path;
     t.tile_rows = n.tile_rows;
     plan->user_tuned = true;
   }

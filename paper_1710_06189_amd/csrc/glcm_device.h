@@ -381,7 +381,17 @@ __device__ __forceinline__ void vote_glcm(const uint32_t (&fa)[16],
         switch (code) {
           GLCM_STRIP_CASE(0, 2) GLCM_STRIP_CASE(1, -2) GLCM_STRIP_CASE(1, 2)
           GLCM_STRIP_CASE(2, -2) GLCM_STRIP_CASE(2, -1) GLCM_STRIP_CASE(2, 0) GLCM_STRIP_CASE(2, 1) GLCM_STRIP_CASE(2, 2)
-          default: break;  // the host launches only canonical offsets within reach
+          default:
+            // reach 3 and 4: the four directions of Eq.(2) only (0, 45, 90
+            // and 135 degrees); the host sends other offsets to the slabs
+            if constexpr (MAXDY >= 4) {
+              switch (code) {
+                GLCM_STRIP_CASE(0, 3) GLCM_STRIP_CASE(3, -3) GLCM_STRIP_CASE(3, 0) GLCM_STRIP_CASE(3, 3)
+                GLCM_STRIP_CASE(0, 4) GLCM_STRIP_CASE(4, -4) GLCM_STRIP_CASE(4, 0) GLCM_STRIP_CASE(4, 4)
+                default: break;
+              }
+            }
+            break;  // the host launches only canonical offsets within reach
         }
       }
       break;

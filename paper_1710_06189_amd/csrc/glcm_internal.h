@@ -12,8 +12,13 @@ constexpr int kMaxK = 64;
 constexpr uint32_t kXcdSlots = 16;
 // GLCMs per partition of the strip kernel (its vote loop is unrolled over them).
 constexpr int kStripMaxKp = 4;
-// Threads per workgroup the strip kernel accepts for a pixel size and reach.
-constexpr int strip_max_threads(int pixel_bytes, int maxdy) { return pixel_bytes == 2 && maxdy == 2 ? 512 : 1024; }
+// Threads per workgroup the strip kernel accepts for a pixel size and template
+// reach (1, 2 or 4): a ring of five term rows (reach 4), or uint16 raw rows at
+// reach 2, need more than the 128 registers a 1024-thread workgroup leaves a
+// lane.
+constexpr int strip_max_threads(int pixel_bytes, int maxdy) {
+  return maxdy > 2 || (pixel_bytes == 2 && maxdy == 2) ? 512 : 1024;
+}
 // Threads per workgroup the slab kernel accepts: uint16 rows of reach 4 read in
 // place (eight rows of 13 dwords in flight) need more than a 1024-thread
 // workgroup's 128 registers per lane.
@@ -160,7 +165,7 @@ hipError_t launch_vote_generic(const VoteArgs& a, int dtype_bytes, int wg, size_
                                const LaunchTiming& tm = {});
 hipError_t launch_vote_rows(const VoteArgs& a, int dtype_bytes, int maxdy, int rpw, int wg, size_t lds_bytes,
                             hipStream_t stream, const LaunchTiming& tm = {});
-// D = dwords per bin (4, 8, 16 or 32), maxdy = 1 or 2.
+// D = dwords per bin (4, 8, 16 or 32), maxdy = 1, 2 or 4 (the ring holds maxdy + 1 rows).
 hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int D, int wg, size_t lds_bytes,
                               hipStream_t stream, const LaunchTiming& tm = {});
 // out[w] = (accumulate ? out[w] : 0) + sum_b partials[b * M + w] for w < M.

@@ -713,13 +713,13 @@ __device__ void store_partial_strips(const VoteArgs& a, const uint32_t* lds, int
   }
 }
 
-// (uint16 pixels with a reach of 2 need more than the 128 registers a
-// 1024-thread workgroup leaves a lane: that variant takes at most 512 threads,
-// as strip_max_threads tells the host)
+// (reach 4, and uint16 pixels with a reach of 2, need more than the 128
+// registers a 1024-thread workgroup leaves a lane: those variants take at most
+// 512 threads, as strip_max_threads tells the host)
 // UNAL: rows of an image whose base or pitch is not 16-byte aligned, read in
 // place as the dwords that hold them (row_load).
 template <typename Pix, int MAXDY, int D, bool PAIR, bool UNAL>
-__global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k_vote_strips(VoteArgs a) {
+__global__ __launch_bounds__(strip_max_threads(sizeof(Pix), MAXDY)) void k_vote_strips(VoteArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   constexpr int NR = MAXDY + 1;
   const int2 rp = band_of_block(blockIdx.x, a.P, a.nregions);
@@ -787,6 +787,14 @@ __global__ __launch_bounds__(sizeof(Pix) == 2 && MAXDY == 2 ? 512 : 1024) void k
       if constexpr (NR > 2) {
         if (y + 2 >= yb) break;
         strip_step<Pix, MAXDY, D, PAIR, 2, UNAL>(a, geo, ring, raw, y + 2, x0, cols, edge, C, n1, mb, sent4, code,
+                                                 kp);
+      }
+      if constexpr (NR > 4) {
+        if (y + 3 >= yb) break;
+        strip_step<Pix, MAXDY, D, PAIR, 3, UNAL>(a, geo, ring, raw, y + 3, x0, cols, edge, C, n1, mb, sent4, code,
+                                                 kp);
+        if (y + 4 >= yb) break;
+        strip_step<Pix, MAXDY, D, PAIR, 4, UNAL>(a, geo, ring, raw, y + 4, x0, cols, edge, C, n1, mb, sent4, code,
                                                  kp);
       }
     }
@@ -872,6 +880,9 @@ hipError_t launch_vote_strips(const VoteArgs& a, int dtype_bytes, int maxdy, int
   if (maxdy == 2)
     return dtype_bytes == 1 ? launch_strips_t<uint8_t, 2>(a, D, wg, lds_bytes, stream, tm)
                             : launch_strips_t<uint16_t, 2>(a, D, wg, lds_bytes, stream, tm);
+  if (maxdy == 4)
+    return dtype_bytes == 1 ? launch_strips_t<uint8_t, 4>(a, D, wg, lds_bytes, stream, tm)
+                            : launch_strips_t<uint16_t, 4>(a, D, wg, lds_bytes, stream, tm);
   return hipErrorInvalidValue;
 }
 

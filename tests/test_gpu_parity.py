@@ -223,6 +223,104 @@ def test_band_heights(kernel, dists, H):
         plan.close()
 
 
+def force_strips(plan, R, bits, wg=512):
+    """Moves a slab plan onto the strip kernel with R dwords per bin; None
+    when that layout does not fit the LDS."""
+    try:
+        return plan.set_tuning(path=4, replicas=R, counter_bits=bits, wg_size=wg)
+    except G.GlcmError:
+        return None
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("N,dists", [(16, [3]), (32, [4]), (8, [1, 2, 4]), (16, [3, 4])])
+@pytest.mark.parametrize("kind", ["smooth", "uniform"])
+def test_strips_reach_four(dtype, N, dists, kind):
+    """Offsets of reach 3 and 4 along the four directions, negated ones
+    included, on the strip kernel's five-row ring (forced over the slab
+    kernel): several layouts and workgroup sizes, a ragged image of several
+    bands and strips, and a misaligned view of it read in place."""
+    W, H = 1037, 301
+    top = int(np.iinfo(dtype).max)
+    img = synth.smooth(H, W, 3.0, 140 + N, dtype) if kind == "smooth" else synth.uniform(H, W, 141 + N, dtype)
+    t = to_device(img)
+    d = dists[-1]
+    offs = synth.offsets_for(dists) + [(-d, 0), (d, -d), (0, 0)]
+    plan = G.glcm_plan_create(dtype, N, offs, W, H)
+    try:
+        ran = 0
+        for R, bits, wg in [(32, 16, 512), (16, 32, 256), (8, 16, 512), (4, 32, 1024)]:
+            tu = force_strips(plan, R, bits, wg)
+            if tu is None:
+                continue
+            assert G.PATH_NAMES[tu.path] == "strips" and tu.rows_per_wave == 0
+            check(img, N, 0, top, offs, plan=plan, t=t, label=f"strips reach {d} R={R} bits={bits} wg={wg} {kind}")
+            sub = img[2:, 3:3 + 1001]
+            check(sub, N, 0, top, offs, plan=plan, t=t[2:, 3:3 + 1001], label=f"strips reach {d} R={R} in place")
+            ran += 1
+        assert ran >= 2
+        back = plan.set_tuning(path=1, replicas=4, counter_bits=32, wg_size=1024)
+        assert G.PATH_NAMES[back.path] == "slabs" and back.rows_per_wave == 4
+        check(img, N, 0, top, offs, plan=plan, t=t, label=f"back on slabs reach {d}")
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("H", [1, 2, 3, 4, 5, 6, 7, 9, 11, 255, 257, 1029])
+def test_strips_reach_four_band_heights(H):
+    """Heights that end a strip inside the five-row ring."""
+    img = synth.uniform(H, 1500, 23 + H)
+    offs = synth.offsets_for([1, 4])
+    plan = G.glcm_plan_create(np.uint8, 8, offs, 1500, H)
+    try:
+        assert force_strips(plan, 32, 16) is not None
+        check(img, 8, 0, 255, offs, plan=plan, label=f"strips reach 4 H={H}")
+    finally:
+        plan.close()
+
+
+def test_strip_reach_rules():
+    """Reach 3 and 4 stay on the slab kernel off the four directions; the
+    strip kernel refuses them, and a plan off the row kernels keeps its path."""
+    img = synth.smooth(200, 700, 3.0, 150)
+    offs = [(1, 3), (2, 0)]
+    plan = G.glcm_plan_create(np.uint8, 16, offs, 700, 200)
+    try:
+        assert G.PATH_NAMES[plan.tuning.path] == "slabs"
+        with pytest.raises(G.GlcmError):
+            plan.set_tuning(path=4, replicas=32, counter_bits=16, wg_size=512)
+        assert G.PATH_NAMES[plan.tuning.path] == "slabs"
+        check(img, 16, 0, 255, offs, plan=plan, label="reach 3 off the directions")
+    finally:
+        plan.close()
+    plan = G.glcm_plan_create(np.uint8, 300, [(4, 4)], 700, 200)
+    try:
+        before = plan.tuning.path
+        assert G.PATH_NAMES[before] not in ("strips", "slabs")
+        assert plan.set_tuning(path=4).path == before
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("kind", ["smooth", "uniform"])
+def test_autotune_reach_four(kind):
+    """The autotuner times strip layouts of reach 4 beside the slabs and keeps
+    one; the counts stay exact."""
+    W, H = 2048, 512
+    img = synth.smooth(H, W, 6.0, 155) if kind == "smooth" else synth.uniform(H, W, 156)
+    offs = synth.offsets_for([4])
+    t = to_device(img)
+    plan = G.glcm_plan_create(np.uint8, 16, offs, W, H)
+    try:
+        chosen = plan.autotune(t, 0, 255, repeats=2)
+        name = G.PATH_NAMES[chosen.path]
+        print(f"[autotune] reach 4 {kind}: {chosen.as_dict()}", flush=True)
+        assert name in ("strips", "slabs")
+        check(img, 16, 0, 255, offs, plan=plan, t=t, label=f"autotuned reach 4 {name} {kind}")
+    finally:
+        plan.close()
+
+
 @pytest.mark.parametrize("W", [1, 15, 16, 17, 1023, 1024, 1025, 2047, 3000])
 @pytest.mark.parametrize("dists", [[1], [2], [1, 2]])
 def test_strip_widths(W, dists):
